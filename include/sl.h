@@ -1,0 +1,190 @@
+/*
+ * sl.h -- C ABI of the MI355X semi-Lagrangian spectral transport library.
+ *
+ * The library advances u_t + a . grad u = 0 (advective form) or
+ * phi_t + div(a phi) = 0 (conservative form, paper section 2, eq. 2.3/2.4)
+ * on a uniform mesh of K quadrilateral (2D) or interval (1D) elements of
+ * order N (n = N + 1 nodes per direction) with the explicit semi-Lagrangian
+ * DSEM step of Natarajan & Jacobs (arXiv 1910.06476, section 4): particles
+ * seeded at the Gauss nodes (section 4.1), moved by one explicit Runge-Kutta
+ * step (section 4.2, eq. 4.4a / 4.8), remapped to the fixed nodes (section
+ * 4.3, eq. 4.9; 2D: eq. 5.4), and corrected by a least-squares fit
+ * constrained by the upwind interface values (eq. 4.12a) and optionally by
+ * local mass (eq. remap_mass) and energy (eq. remap_energy) targets
+ * (eq. matrix_a).
+ *
+ * Conventions
+ *   - Every entry point returns sl_status (0 = SL_OK); no C++ exception
+ *     crosses the ABI.
+ *   - Pointers documented "host" are ordinary host memory owned by the
+ *     caller; the library copies what it needs and keeps no reference.
+ *   - Field layout (u0, sl_read output, velocity components, divergence):
+ *     element-major, double, element index k = ix + kx * iy, node index
+ *     p = i + n * j with i along x (1D: p = i).  Element (ix, iy) covers
+ *     [x0 + ix dx, x0 + (ix+1) dx] x [y0 + iy dy, y0 + (iy+1) dy].
+ *   - Node positions inside an element are given by sl_node_coords.
+ *   - A mesh is used by one host thread at a time; distinct meshes are
+ *     independent.  All device work of a mesh runs on its stream.
+ */
+#ifndef SL_H
+#define SL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t sl_status;
+
+enum {
+    SL_OK = 0,
+    SL_E_INVALID = 1,   /* bad argument or descriptor; nothing changed          */
+    SL_E_NOMEM = 2,     /* device allocation failed; nothing left allocated      */
+    SL_E_DEVICE = 3,    /* a HIP runtime call failed                             */
+    SL_E_STATE = 4,     /* call not valid in the mesh's current state            */
+    SL_E_CFL = 5,       /* time step lets a particle leave its element           */
+    SL_E_NONFINITE = 6, /* NaN/Inf in inputs or produced by a step               */
+    SL_E_SINGULAR = 7,  /* a remap or constraint system had a zero pivot          */
+    SL_E_NOCONV = 8     /* energy Picard iteration hit its cap above tolerance   */
+};
+
+enum { SL_NODES_GL = 0, SL_NODES_CG = 1 };          /* Gauss-Legendre / Chebyshev-Gauss */
+enum { SL_BC_PERIODIC = 0, SL_BC_GHOST = 1 };
+enum { SL_FORM_ADVECTIVE = 0, SL_FORM_CONSERVATIVE = 1 };
+enum { SL_PREC_FP64 = 0, SL_PREC_FP32_REFINED = 1 };
+enum { SL_C_BOUNDARY = 1, SL_C_MASS = 2, SL_C_ENERGY = 4 };
+enum { SL_MODE_HARD = 0, SL_MODE_SOFT = 1 };
+
+/* Mesh descriptor (sl_create_mesh).
+ *   dim        1 or 2
+ *   kx, ky     elements per direction (ky = 1 in 1D); kx * ky <= 2^26
+ *   order      polynomial order N >= 1 (n = N + 1 nodes per direction);
+ *              1D: N <= 16, 2D: N <= 10
+ *   nodes      SL_NODES_GL (default) or SL_NODES_CG (paper, eq. gaussquad)
+ *   bc         SL_BC_PERIODIC, or SL_BC_GHOST (inflow values from sl_set_ghost)
+ *   form       SL_FORM_ADVECTIVE or SL_FORM_CONSERVATIVE
+ *   precision  SL_PREC_FP64, or SL_PREC_FP32_REFINED (2D only: remap solve
+ *              factored in FP32, corrected by FP64 residual refinement)
+ *   x0,x1,y0,y1 box (y ignored in 1D), x1 > x0, y1 > y0
+ *   u0         host, K * n^dim initial values (layout above)
+ *   stream     hipStream_t to run on, or NULL for a stream the mesh creates */
+typedef struct {
+    int32_t dim, kx, ky, order;
+    int32_t nodes, bc, form, precision;
+    double x0, x1, y0, y1;
+    const double* u0;
+    void* stream;
+} sl_mesh_desc;
+
+/* Step options (sl_step); a NULL pointer means all defaults.
+ *   rk            explicit Runge-Kutta order 1..4 (Euler, Heun, Kutta-3,
+ *                 classical RK4); default 4
+ *   constraints   mask of SL_C_*; default SL_C_BOUNDARY
+ *   mode          SL_MODE_HARD (KKT: rows hold exactly, default) or
+ *                 SL_MODE_SOFT (the paper's stacked least squares)
+ *   energy_maxit  Picard iterations cap for the energy row (default 50)
+ *   refine_steps  FP64 refinement sweeps in SL_PREC_FP32_REFINED (default 3)
+ *   energy_tol    Picard stop |phi^(k) - phi^(k-1)|_max < tol (default 1e-8, the
+ *                 paper's; 0 = always run energy_maxit iterations) */
+typedef struct {
+    int32_t rk, constraints, mode, energy_maxit, refine_steps;
+    double energy_tol;
+} sl_step_opts;
+
+/* Statistics returned by sl_read (accumulated since the last sl_read).
+ *   resid_*   largest |row . phi - target| seen (boundary: in the 2D
+ *             least-squares sense, the corner dependencies make it nonzero)
+ *   max_picard largest number of energy-row solves in one element and step
+ *   flags     bit0 non-finite, bit1 particle left element, bit2 singular
+ *             system, bit3 Picard not converged */
+typedef struct {
+    double t;
+    int64_t steps;
+    double mass, energy;
+    double resid_boundary, resid_mass, resid_energy;
+    double refine_resid;
+    int32_t max_picard;
+    int32_t flags;
+} sl_stats;
+
+typedef struct sl_mesh sl_mesh;
+
+/* Create a mesh: validates the descriptor, builds the reference-element
+ * tables, allocates device state and copies u0 (host) to the device.
+ * On error *out is NULL and nothing stays allocated.
+ * Errors: SL_E_INVALID, SL_E_NOMEM, SL_E_DEVICE, SL_E_NONFINITE (u0). */
+sl_status sl_create_mesh(const sl_mesh_desc* desc, sl_mesh** out);
+
+/* Set the (steady) velocity field.  a: host, dim * K * n^dim values,
+ * component-major (all x components, then all y components), given at the
+ * Gauss nodes as a DSEM solver supplies it (section 4.2); the velocity off
+ * the nodes is the element's Lagrange interpolant.  div_a: host, K * n^dim
+ * nodal values of div(a), or NULL to take the divergence of the interpolant.
+ * Copies both; derived tables (modal coefficients, face velocities) are
+ * built on the device.  Errors: SL_E_INVALID, SL_E_NONFINITE, SL_E_DEVICE. */
+sl_status sl_set_velocity(sl_mesh* m, const double* a, const double* div_a);
+
+/* Ghost (outside) values at the domain boundary for SL_BC_GHOST meshes.
+ * g: host, nrows rows of nghost values; row r holds the outside state at
+ * time t + r dt where t is the mesh time at this call, so the i-th following
+ * step reads rows i and i+1 (clamped to the last row; nrows = 1 is a steady
+ * ghost).  Row layout -- 1D: [left, right]; 2D: left edge (ky * n values,
+ * by iy then node j), right edge (ky * n), bottom edge (kx * n, by ix then
+ * node i), top edge (kx * n).  Errors: SL_E_STATE (periodic mesh),
+ * SL_E_INVALID, SL_E_NOMEM. */
+sl_status sl_set_ghost(sl_mesh* m, const double* g, int32_t nrows);
+
+/* Number of ghost values per row (see sl_set_ghost). */
+int32_t sl_ghost_count(const sl_mesh* m);
+
+/* Advance nsteps explicit SL steps of length dt, asynchronously on the
+ * mesh's stream.  Validated before any launch (state unchanged on error):
+ * SL_E_STATE (no velocity, or ghost mesh without ghost values),
+ * SL_E_INVALID (dt <= 0, nsteps < 0, bad options), SL_E_CFL (max |a_d| dt
+ * >= gap_d dx_d for some direction d, gap = distance from the element edge
+ * to the first node: the paper's time-step restriction, eq. 1d_delt_condition
+ * and eq. 2d_delt_condition). */
+sl_status sl_step(sl_mesh* m, double dt, int32_t nsteps, const sl_step_opts* opts);
+
+/* Synchronise the mesh's stream and copy the field to u_out (host, K * n^dim
+ * doubles, same layout as u0; may be NULL).  st (may be NULL) receives the
+ * statistics accumulated since the previous sl_read, which are then reset.
+ * Returns SL_E_NONFINITE / SL_E_SINGULAR / SL_E_NOCONV when the matching
+ * flag was raised (the copy has still been made), else SL_OK or
+ * SL_E_DEVICE. */
+sl_status sl_read(sl_mesh* m, double* u_out, sl_stats* st);
+
+/* Free the mesh's device memory and stream (if it created one). */
+sl_status sl_destroy_mesh(sl_mesh* m);
+
+/* Human-readable name of a status code (static string). */
+const char* sl_status_string(sl_status s);
+
+/* Largest dt allowed by the time-step restriction, times cfl (0 < cfl <= 1);
+ * 0 if no velocity is set, or the mesh is NULL. */
+double sl_max_dt(const sl_mesh* m, double cfl);
+
+/* Reference node positions xi[n] on [0,1] and quadrature weights w[n]
+ * (summing to 1) of a node family; both host arrays of n doubles.
+ * Errors: SL_E_INVALID (unknown family, n < 1 or n > 32). */
+sl_status sl_node_coords(int32_t nodes, int32_t n, double* xi, double* w);
+
+/* Device pointer of the mesh's field (K * n^dim doubles, layout above) and
+ * the mesh's stream, for callers that keep data on the device.  The pointer
+ * stays valid until sl_destroy_mesh; writes through it must be ordered on
+ * the mesh's stream. */
+sl_status sl_device_field(sl_mesh* m, double** d_phi, void** stream);
+
+/* Per-kernel timing with HIP events on the mesh's stream.  When enabled,
+ * every kernel launch of sl_step is bracketed by events; sl_kernel_time
+ * synchronises and returns the summed milliseconds and the launch count of
+ * kernel 'which' (0 = 1D advect, 1 = 1D constrain, 2 = 2D advect+solve,
+ * 3 = 2D constrain) since the last reset.  Errors: SL_E_INVALID. */
+sl_status sl_set_profiling(sl_mesh* m, int32_t enable);
+sl_status sl_kernel_time(sl_mesh* m, int32_t which, double* total_ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SL_H */

@@ -45,7 +45,7 @@ typedef struct {
     int32_t energy_maxit; /* Picard iterations cap */
     int32_t vel_kind;     /* 0 nodal arrays; >0 analytic field (paper pins only) */
     double x0, x1, y0, y1;
-    double energy_tol;    /* Picard stop: max |phi^(k) - phi^(k-1)| <= tol */
+    double energy_tol;    /* Picard stop: max |phi^(k) - phi^(k-1)| < tol */
     double vel_param[4];
 } ora_params;
 
@@ -307,6 +307,7 @@ typedef struct {
     double* div;           /* nodal divergence [K][nd] */
     tableau T;
     double dt;
+    double vzero;          /* face speeds with |v| <= vzero count as zero */
 } ctx;
 
 /* physical velocity and divergence at reference point (s, r) of element e */
@@ -689,8 +690,10 @@ static double face_velocity(const ctx* c, int e, int t)
     int nbe, nbt, gidx, high;
     face_partner(c, e, t, &nbe, &nbt, &gidx, &high);
     double mine = vel_normal(c, e, t);
-    if (nbe < 0) return mine;
-    return 0.5 * (mine + vel_normal(c, nbe, nbt));
+    double v = (nbe < 0) ? mine : 0.5 * (mine + vel_normal(c, nbe, nbt));
+    /* reading: a face speed at rounding level (a stagnation point) has no
+     * upwind side; it is treated as zero, i.e. the mean of both traces */
+    return fabs(v) <= c->vzero ? 0.0 : v;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -820,6 +823,21 @@ static int assemble_rows(const ctx* c, int e, const work* W, const double* prev,
                 C[m * nd + pidx] = c->dx * c->w[ii] * (d2 ? c->dy * c->w[jj] : 1.0) * prev[pidx];
             }
         d[m] = W->Et[e];
+        /* HARD with a mass row: represent the energy row by its part
+         * orthogonal to the mass row (same constraint set: subtract mu times
+         * the mass equation).  For smooth phi the two rows are nearly
+         * parallel, and this keeps the KKT system well conditioned. */
+        if (p->mode == 0 && (p->cmask & C_MASS)) {
+            int mr = m - 1;
+            double gw = 0, ww = 0;
+            for (int i = 0; i < nd; ++i) {
+                gw += C[m * nd + i] * C[mr * nd + i];
+                ww += C[mr * nd + i] * C[mr * nd + i];
+            }
+            double mu = gw / ww;
+            for (int i = 0; i < nd; ++i) C[m * nd + i] -= mu * C[mr * nd + i];
+            d[m] -= mu * d[mr];
+        }
         ++m;
     }
     return m;
@@ -921,7 +939,7 @@ static cls_out constrain(const ctx* c, int e, const work* W, const double* CB, c
             for (int i = 0; i < nd; ++i) diff = fmax(diff, fabs(cur[i] - prev[i]));
             memcpy(prev, cur, sizeof(double) * nd);
             o.picard = k;
-            if (diff <= p->energy_tol) { conv = 1; break; }
+            if (diff < p->energy_tol) { conv = 1; break; } /* strict, as printed */
         }
         if (!conv && p->energy_tol > 0) o.flags |= F_NOCONV;
     }
@@ -990,6 +1008,15 @@ int ora_step(const ora_params* p, const double* a, const double* div, const doub
     lag_basis(c.n, c.xi, 0.0, c.l0);
     lag_basis(c.n, c.xi, 1.0, c.l1);
     int n = c.n, nd = c.nd, K = c.K, nt = ntr(&c);
+
+    /* stagnation threshold: 1e-12 of the largest nodal speed (1e-12 for the
+     * analytic fields, whose speeds are of order one) */
+    c.vzero = 1e-12;
+    if (p->vel_kind == 0) {
+        double am = 0;
+        for (size_t i = 0; i < (size_t)p->dim * K * nd; ++i) am = fmax(am, fabs(a[i]));
+        c.vzero = 1e-12 * am;
+    }
 
     /* nodal divergence: given, or the derivative of the velocity interpolant */
     c.div = malloc(sizeof(double) * (size_t)K * nd);
