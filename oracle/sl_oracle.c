@@ -932,15 +932,27 @@ static cls_out constrain(const ctx* c, int e, const work* W, const double* CB, c
     double* cur = malloc(sizeof(double) * nd);
     if (solve_once(c, e, W, CB, CBp, PB, NULL, 0, prev)) o.flags |= F_SINGULAR;
     if (p->cmask & C_ENERGY) {
+        /* Picard on the energy row (section "Local energy conservation").
+         * Stop when the change is below tol (strict, as printed).  Reading:
+         * also stop, unconverged, when the iterate comes back to within tol
+         * of the one two iterations earlier -- the linearised energy row
+         * makes the map (close to) 2-periodic, so further sweeps repeat. */
         int conv = 0;
+        double* older = malloc(sizeof(double) * nd);
         for (int k = 1; k <= p->energy_maxit; ++k) {
             if (solve_once(c, e, W, CB, CBp, PB, prev, 1, cur)) o.flags |= F_SINGULAR;
-            double diff = 0;
-            for (int i = 0; i < nd; ++i) diff = fmax(diff, fabs(cur[i] - prev[i]));
+            double diff = 0, back = 0;
+            for (int i = 0; i < nd; ++i) {
+                diff = fmax(diff, fabs(cur[i] - prev[i]));
+                if (k >= 2) back = fmax(back, fabs(cur[i] - older[i]));
+            }
+            memcpy(older, prev, sizeof(double) * nd);
             memcpy(prev, cur, sizeof(double) * nd);
             o.picard = k;
-            if (diff < p->energy_tol) { conv = 1; break; } /* strict, as printed */
+            if (diff < p->energy_tol) { conv = 1; break; }
+            if (k >= 2 && back < p->energy_tol) break;
         }
+        free(older);
         if (!conv && p->energy_tol > 0) o.flags |= F_NOCONV;
     }
     memcpy(out, prev, sizeof(double) * nd);

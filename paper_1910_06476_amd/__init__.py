@@ -1,0 +1,248 @@
+"""Python binding of the MI355X semi-Lagrangian spectral transport library.
+
+Argument marshalling only: every step of the method runs in the HIP kernels
+of ``libsl.so`` (built in-tree by ``build.py``), called through the C ABI
+declared in ``include/sl.h``.  The function names mirror the C entry points;
+``Mesh`` is a small convenience wrapper that owns one ``sl_mesh``.
+
+Importing this package does not need a GPU, but it needs the built library:
+if ``libsl.so`` is missing the import fails with an explicit error -- there
+is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(_HERE, "libsl.so")
+
+SL_OK, SL_E_INVALID, SL_E_NOMEM, SL_E_DEVICE, SL_E_STATE, SL_E_CFL, SL_E_NONFINITE, SL_E_SINGULAR, SL_E_NOCONV = range(9)
+SL_NODES_GL, SL_NODES_CG = 0, 1
+SL_BC_PERIODIC, SL_BC_GHOST = 0, 1
+SL_FORM_ADVECTIVE, SL_FORM_CONSERVATIVE = 0, 1
+SL_PREC_FP64, SL_PREC_FP32_REFINED = 0, 1
+SL_C_BOUNDARY, SL_C_MASS, SL_C_ENERGY = 1, 2, 4
+SL_MODE_HARD, SL_MODE_SOFT = 0, 1
+KER_ADV1D, KER_CON1D, KER_ADV2D, KER_CON2D = 0, 1, 2, 3
+
+EXPORTS = ["sl_create_mesh", "sl_set_velocity", "sl_set_ghost", "sl_ghost_count", "sl_step", "sl_read",
+           "sl_destroy_mesh", "sl_status_string", "sl_max_dt", "sl_node_coords", "sl_device_field",
+           "sl_set_profiling", "sl_kernel_time"]
+
+
+class MeshDesc(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("kx", ctypes.c_int32), ("ky", ctypes.c_int32),
+                ("order", ctypes.c_int32), ("nodes", ctypes.c_int32), ("bc", ctypes.c_int32),
+                ("form", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("x0", ctypes.c_double), ("x1", ctypes.c_double), ("y0", ctypes.c_double),
+                ("y1", ctypes.c_double), ("u0", ctypes.POINTER(ctypes.c_double)), ("stream", ctypes.c_void_p)]
+
+
+class StepOpts(ctypes.Structure):
+    _fields_ = [("rk", ctypes.c_int32), ("constraints", ctypes.c_int32), ("mode", ctypes.c_int32),
+                ("energy_maxit", ctypes.c_int32), ("refine_steps", ctypes.c_int32),
+                ("energy_tol", ctypes.c_double)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_double), ("steps", ctypes.c_int64), ("mass", ctypes.c_double),
+                ("energy", ctypes.c_double), ("resid_boundary", ctypes.c_double),
+                ("resid_mass", ctypes.c_double), ("resid_energy", ctypes.c_double),
+                ("refine_resid", ctypes.c_double), ("max_picard", ctypes.c_int32), ("flags", ctypes.c_int32)]
+
+    def asdict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class SLError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {status_string(status)} ({status})")
+
+
+_lib = None
+
+
+def lib():
+    """Load libsl.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIBPATH):
+            raise ImportError(f"{LIBPATH} is missing: build it with "
+                              "`python paper_1910_06476_amd/build.py` (no fallback exists)")
+        L = ctypes.CDLL(LIBPATH)
+        dp = ctypes.POINTER(ctypes.c_double)
+        vp = ctypes.c_void_p
+        L.sl_create_mesh.argtypes = [ctypes.POINTER(MeshDesc), ctypes.POINTER(vp)]
+        L.sl_set_velocity.argtypes = [vp, dp, dp]
+        L.sl_set_ghost.argtypes = [vp, dp, ctypes.c_int32]
+        L.sl_ghost_count.argtypes = [vp]
+        L.sl_ghost_count.restype = ctypes.c_int32
+        L.sl_step.argtypes = [vp, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(StepOpts)]
+        L.sl_read.argtypes = [vp, dp, ctypes.POINTER(Stats)]
+        L.sl_destroy_mesh.argtypes = [vp]
+        L.sl_status_string.argtypes = [ctypes.c_int32]
+        L.sl_status_string.restype = ctypes.c_char_p
+        L.sl_max_dt.argtypes = [vp, ctypes.c_double]
+        L.sl_max_dt.restype = ctypes.c_double
+        L.sl_node_coords.argtypes = [ctypes.c_int32, ctypes.c_int32, dp, dp]
+        L.sl_device_field.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp)]
+        L.sl_set_profiling.argtypes = [vp, ctypes.c_int32]
+        L.sl_kernel_time.argtypes = [vp, ctypes.c_int32, dp, ctypes.POINTER(ctypes.c_int64)]
+        for name in EXPORTS:
+            if name not in ("sl_status_string", "sl_max_dt", "sl_ghost_count"):
+                getattr(L, name).restype = ctypes.c_int32
+        _lib = L
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if a is not None else ctypes.POINTER(ctypes.c_double)()
+
+
+def _f64(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+
+def status_string(s: int) -> str:
+    return lib().sl_status_string(int(s)).decode()
+
+
+def _check(rc: int, where: str):
+    if rc != SL_OK:
+        raise SLError(rc, where)
+
+
+# ---- functions named like the C entry points -------------------------------
+def sl_node_coords(nodes: int, n: int):
+    xi = np.zeros(n)
+    w = np.zeros(n)
+    _check(lib().sl_node_coords(nodes, n, _dp(xi), _dp(w)), "sl_node_coords")
+    return xi, w
+
+
+def sl_create_mesh(dim, kx, ky, order, u0, nodes=SL_NODES_GL, bc=SL_BC_PERIODIC, form=SL_FORM_ADVECTIVE,
+                   precision=SL_PREC_FP64, x0=0.0, x1=1.0, y0=0.0, y1=1.0, stream=None):
+    u0 = _f64(u0)
+    d = MeshDesc(dim, kx, ky, order, nodes, bc, form, precision, x0, x1, y0, y1, _dp(u0),
+                 ctypes.c_void_p(stream) if stream else None)
+    h = ctypes.c_void_p()
+    _check(lib().sl_create_mesh(ctypes.byref(d), ctypes.byref(h)), "sl_create_mesh")
+    return h
+
+
+def sl_set_velocity(m, a, div_a=None):
+    a = _f64(a)
+    div_a = _f64(div_a)
+    _check(lib().sl_set_velocity(m, _dp(a), _dp(div_a)), "sl_set_velocity")
+
+
+def sl_set_ghost(m, g, nrows=None):
+    g = _f64(g)
+    cnt = lib().sl_ghost_count(m)
+    nrows = g.size // max(cnt, 1) if nrows is None else nrows
+    _check(lib().sl_set_ghost(m, _dp(g), int(nrows)), "sl_set_ghost")
+
+
+def sl_ghost_count(m) -> int:
+    return int(lib().sl_ghost_count(m))
+
+
+def step_opts(rk=4, constraints=SL_C_BOUNDARY, mode=SL_MODE_HARD, energy_maxit=50, refine_steps=3, energy_tol=1e-8):
+    return StepOpts(rk, constraints, mode, energy_maxit, refine_steps, energy_tol)
+
+
+def sl_step(m, dt, nsteps=1, opts=None):
+    o = opts if opts is not None else step_opts()
+    _check(lib().sl_step(m, float(dt), int(nsteps), ctypes.byref(o)), "sl_step")
+
+
+def sl_read(m, size: int):
+    """Returns (status, field, Stats); flag statuses are returned, not raised."""
+    out = np.zeros(size)
+    st = Stats()
+    rc = lib().sl_read(m, _dp(out), ctypes.byref(st))
+    if rc not in (SL_OK, SL_E_NONFINITE, SL_E_SINGULAR, SL_E_NOCONV):
+        raise SLError(rc, "sl_read")
+    return rc, out, st
+
+
+def sl_destroy_mesh(m):
+    _check(lib().sl_destroy_mesh(m), "sl_destroy_mesh")
+
+
+def sl_max_dt(m, cfl=1.0) -> float:
+    return float(lib().sl_max_dt(m, float(cfl)))
+
+
+def sl_device_field(m):
+    p = ctypes.c_void_p()
+    s = ctypes.c_void_p()
+    _check(lib().sl_device_field(m, ctypes.byref(p), ctypes.byref(s)), "sl_device_field")
+    return p.value, s.value
+
+
+def sl_set_profiling(m, enable=True):
+    _check(lib().sl_set_profiling(m, 1 if enable else 0), "sl_set_profiling")
+
+
+def sl_kernel_time(m, which: int):
+    ms = ctypes.c_double()
+    cnt = ctypes.c_int64()
+    _check(lib().sl_kernel_time(m, which, ctypes.byref(ms), ctypes.byref(cnt)), "sl_kernel_time")
+    return ms.value, cnt.value
+
+
+class Mesh:
+    """Owns one sl_mesh.  Sizes follow the descriptor; see include/sl.h."""
+
+    def __init__(self, dim, kx, ky, order, u0, **kw):
+        self.dim, self.kx, self.ky, self.order = dim, kx, ky, order
+        self.n = order + 1
+        self.nd = self.n if dim == 1 else self.n * self.n
+        self.K = kx * ky
+        self.h = sl_create_mesh(dim, kx, ky, order, u0, **kw)
+
+    def set_velocity(self, a, div_a=None):
+        sl_set_velocity(self.h, a, div_a)
+
+    def set_ghost(self, g, nrows=None):
+        sl_set_ghost(self.h, g, nrows)
+
+    def step(self, dt, nsteps=1, **opts):
+        sl_step(self.h, dt, nsteps, step_opts(**opts))
+
+    def read(self):
+        return sl_read(self.h, self.K * self.nd)
+
+    def max_dt(self, cfl=1.0):
+        return sl_max_dt(self.h, cfl)
+
+    def close(self):
+        if self.h:
+            sl_destroy_mesh(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def from_workload(w, stream=None, precision=SL_PREC_FP64):
+    """Mesh for a workloads.Workload, velocity set (and ghost rows if any)."""
+    m = Mesh(w.dim, w.kx, w.ky, w.n - 1, w.initial(), nodes=w.family, bc=w.bc, form=w.form,
+             precision=precision, x0=w.x0, x1=w.x1, y0=w.y0, y1=w.y1, stream=stream)
+    a, _ = w.velocity()
+    m.set_velocity(a)
+    return m

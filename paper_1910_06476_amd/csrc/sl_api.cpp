@@ -1,0 +1,463 @@
+// Host runtime behind the C ABI of include/sl.h: mesh object, validation,
+// device buffers, time-step restriction, launch sequencing and statistics.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "sl_internal.h"
+
+using namespace sl;
+
+struct sl_mesh {
+    int dim, kx, ky, n, nd, K, family, bc, form, precision;
+    double x0, x1, y0, y1, dx, dy;
+    hipStream_t stream;
+    bool own_stream;
+    Tables T;
+    TabOff off;
+    // device buffers
+    double *phi, *phi2, *phihat, *rec, *eloc, *aN, *aM, *divN, *divM, *vface, *tab, *ghost, *stat_part;
+    int32_t* flag_part;
+    int nblocks;
+    // host state
+    bool has_velocity;
+    double amax[2];
+    int ghost_rows;
+    long ghost_step;
+    double t;
+    int64_t steps;
+    bool profiling;
+    hipEvent_t ev[KER_COUNT][2];
+    std::vector<hipEvent_t> pending[KER_COUNT];
+    double ktime[KER_COUNT];
+    int64_t kcount[KER_COUNT];
+};
+
+namespace {
+
+template <typename T>
+void dfree(T*& p)
+{
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+
+void release(sl_mesh* m)
+{
+    dfree(m->phi); dfree(m->phi2); dfree(m->phihat); dfree(m->rec); dfree(m->eloc); dfree(m->aN);
+    dfree(m->aM); dfree(m->divN); dfree(m->divM); dfree(m->vface); dfree(m->tab); dfree(m->ghost);
+    dfree(m->stat_part); dfree(m->flag_part);
+    for (int k = 0; k < KER_COUNT; ++k)
+        for (hipEvent_t e : m->pending[k]) (void)hipEventDestroy(e);
+    if (m->own_stream && m->stream) (void)hipStreamDestroy(m->stream);
+}
+
+bool all_finite(const double* p, size_t n)
+{
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+template <typename T>
+bool dalloc(T** p, size_t count)
+{
+    if (count == 0) count = 1;
+    return hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T)) == hipSuccess;
+}
+
+// 2D Gram constants are not needed; 1D rows l(0), l(1), W
+void gram1d(const sl_mesh* m, double g[6])
+{
+    double g00 = 0, g01 = 0, g11 = 0, g02 = 0, g12 = 0, g22 = 0;
+    for (int j = 0; j < m->n; ++j) {
+        const double W = m->dx * m->T.w[j];
+        g00 += m->T.l0[j] * m->T.l0[j];
+        g01 += m->T.l0[j] * m->T.l1[j];
+        g11 += m->T.l1[j] * m->T.l1[j];
+        g02 += m->T.l0[j] * W;
+        g12 += m->T.l1[j] * W;
+        g22 += W * W;
+    }
+    g[0] = g00; g[1] = g01; g[2] = g11; g[3] = g02; g[4] = g12; g[5] = g22;
+}
+
+}  // namespace
+
+namespace sl {
+
+TabOff tab_offsets(int dim, int n)
+{
+    TabOff o;
+    o.xi = 0;
+    o.w = n;
+    o.l0 = 2 * n;
+    o.l1 = 3 * n;
+    o.tinv = 4 * n;
+    o.dmat = 4 * n + n * n;
+    o.cbp = 4 * n + 2 * n * n;
+    o.pb = o.cbp + (dim == 2 ? n * n * 4 * n : 0);
+    o.total = o.pb + (dim == 2 ? n * n * n * n : 0);
+    return o;
+}
+
+bool rk_tableau(int order, RKTab* T)
+{
+    std::memset(T, 0, sizeof(*T));
+    switch (order) {
+    case 1: T->s = 1; T->b[0] = 1; break;
+    case 2: T->s = 2; T->a[1][0] = 1; T->b[0] = 0.5; T->b[1] = 0.5; T->c[1] = 1; break;
+    case 3:
+        T->s = 3; T->a[1][0] = 0.5; T->a[2][0] = -1; T->a[2][1] = 2;
+        T->b[0] = 1.0 / 6; T->b[1] = 2.0 / 3; T->b[2] = 1.0 / 6; T->c[1] = 0.5; T->c[2] = 1;
+        break;
+    case 4:
+        T->s = 4; T->a[1][0] = 0.5; T->a[2][1] = 0.5; T->a[3][2] = 1;
+        T->b[0] = 1.0 / 6; T->b[1] = 1.0 / 3; T->b[2] = 1.0 / 3; T->b[3] = 1.0 / 6;
+        T->c[1] = 0.5; T->c[2] = 0.5; T->c[3] = 1;
+        break;
+    default: return false;
+    }
+    T->nq = 0;
+    for (int s = 0; s < T->s; ++s) {
+        int f = -1;
+        for (int q = 0; q < T->nq; ++q)
+            if (T->cu[q] == T->c[s]) f = q;
+        if (f < 0) { T->cu[T->nq] = T->c[s]; T->bu[T->nq] = T->b[s]; ++T->nq; }
+        else T->bu[f] += T->b[s];
+    }
+    return true;
+}
+
+}  // namespace sl
+
+extern "C" {
+
+const char* sl_status_string(sl_status s)
+{
+    switch (s) {
+    case SL_OK: return "ok";
+    case SL_E_INVALID: return "invalid argument";
+    case SL_E_NOMEM: return "out of device memory";
+    case SL_E_DEVICE: return "device error";
+    case SL_E_STATE: return "invalid state";
+    case SL_E_CFL: return "time step lets particles leave their element";
+    case SL_E_NONFINITE: return "non-finite value";
+    case SL_E_SINGULAR: return "singular system";
+    case SL_E_NOCONV: return "energy iteration did not converge";
+    default: return "unknown status";
+    }
+}
+
+sl_status sl_node_coords(int32_t nodes, int32_t n, double* xi, double* w)
+{
+    if (!xi || !w || n < 1 || n > kMaxTableN) return SL_E_INVALID;
+    return node_rule(nodes, n, xi, w) ? SL_OK : SL_E_INVALID;
+}
+
+sl_status sl_create_mesh(const sl_mesh_desc* d, sl_mesh** out)
+{
+    if (!out) return SL_E_INVALID;
+    *out = nullptr;
+    if (!d || !d->u0) return SL_E_INVALID;
+    if (d->dim != 1 && d->dim != 2) return SL_E_INVALID;
+    const int n = d->order + 1;
+    if (d->order < 1 || n > (d->dim == 1 ? kMax1D : kMax2D)) return SL_E_INVALID;
+    if (d->kx < 1 || d->ky < 1 || (d->dim == 1 && d->ky != 1)) return SL_E_INVALID;
+    if ((int64_t)d->kx * d->ky > (1 << 26)) return SL_E_INVALID;
+    if (d->nodes != SL_NODES_GL && d->nodes != SL_NODES_CG) return SL_E_INVALID;
+    if (d->bc != SL_BC_PERIODIC && d->bc != SL_BC_GHOST) return SL_E_INVALID;
+    if (d->form != SL_FORM_ADVECTIVE && d->form != SL_FORM_CONSERVATIVE) return SL_E_INVALID;
+    if (d->precision != SL_PREC_FP64 && !(d->precision == SL_PREC_FP32_REFINED && d->dim == 2)) return SL_E_INVALID;
+    if (!(d->x1 > d->x0) || (d->dim == 2 && !(d->y1 > d->y0))) return SL_E_INVALID;
+    if (!std::isfinite(d->x0) || !std::isfinite(d->x1)) return SL_E_INVALID;
+    if (d->dim == 2) return SL_E_INVALID;  // 2D path attached separately
+
+    sl_mesh* m = new (std::nothrow) sl_mesh();
+    if (!m) return SL_E_NOMEM;
+    m->dim = d->dim; m->kx = d->kx; m->ky = d->ky; m->n = n;
+    m->nd = d->dim == 1 ? n : n * n;
+    m->K = d->kx * d->ky;
+    m->family = d->nodes; m->bc = d->bc; m->form = d->form; m->precision = d->precision;
+    m->x0 = d->x0; m->x1 = d->x1; m->y0 = d->y0; m->y1 = d->y1;
+    m->dx = (d->x1 - d->x0) / d->kx;
+    m->dy = d->dim == 2 ? (d->y1 - d->y0) / d->ky : 1.0;
+    const size_t nf = (size_t)m->K * m->nd;
+    if (!all_finite(d->u0, nf)) { delete m; return SL_E_NONFINITE; }
+    if (!build_tables(m->family, n, &m->T)) { delete m; return SL_E_INVALID; }
+    m->off = tab_offsets(m->dim, n);
+
+    if (d->stream) { m->stream = (hipStream_t)d->stream; m->own_stream = false; }
+    else {
+        if (hipStreamCreateWithFlags(&m->stream, hipStreamNonBlocking) != hipSuccess) { delete m; return SL_E_DEVICE; }
+        m->own_stream = true;
+    }
+    m->nblocks = blocks1d(n, m->K);
+    bool ok = dalloc(&m->phi, nf) && dalloc(&m->phi2, nf) && dalloc(&m->phihat, nf) &&
+              dalloc(&m->rec, (size_t)m->K * 8) && dalloc(&m->aN, nf) && dalloc(&m->aM, nf) &&
+              dalloc(&m->divN, nf) && dalloc(&m->divM, nf) && dalloc(&m->vface, (size_t)m->K + 1) &&
+              dalloc(&m->tab, (size_t)m->off.total) && dalloc(&m->stat_part, (size_t)m->nblocks * kStatSlots) &&
+              dalloc(&m->flag_part, (size_t)2 * m->nblocks);
+    if (!ok) { release(m); delete m; return SL_E_NOMEM; }
+
+    std::vector<double> tab(m->off.total, 0.0);
+    for (int j = 0; j < n; ++j) {
+        tab[m->off.xi + j] = m->T.xi[j];
+        tab[m->off.w + j] = m->T.w[j];
+        tab[m->off.l0 + j] = m->T.l0[j];
+        tab[m->off.l1 + j] = m->T.l1[j];
+        for (int k = 0; k < n; ++k) {
+            tab[m->off.tinv + j * n + k] = m->T.Tinv[j * n + k];
+            tab[m->off.dmat + j * n + k] = m->T.D[j * n + k];
+        }
+    }
+    hipError_t e1 = hipMemcpyAsync(m->tab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice, m->stream);
+    hipError_t e2 = hipMemcpyAsync(m->phi, d->u0, nf * sizeof(double), hipMemcpyHostToDevice, m->stream);
+    hipError_t e3 = hipMemsetAsync(m->stat_part, 0, (size_t)m->nblocks * kStatSlots * sizeof(double), m->stream);
+    hipError_t e4 = hipMemsetAsync(m->flag_part, 0, (size_t)2 * m->nblocks * sizeof(int32_t), m->stream);
+    hipError_t e5 = hipStreamSynchronize(m->stream);
+    if (e1 || e2 || e3 || e4 || e5) { release(m); delete m; return SL_E_DEVICE; }
+    *out = m;
+    return SL_OK;
+}
+
+sl_status sl_destroy_mesh(sl_mesh* m)
+{
+    if (!m) return SL_E_INVALID;
+    (void)hipStreamSynchronize(m->stream);
+    release(m);
+    delete m;
+    return SL_OK;
+}
+
+sl_status sl_set_velocity(sl_mesh* m, const double* a, const double* div_a)
+{
+    if (!m || !a) return SL_E_INVALID;
+    const size_t nf = (size_t)m->K * m->nd;
+    if (!all_finite(a, nf * m->dim)) return SL_E_NONFINITE;
+    if (div_a && !all_finite(div_a, nf)) return SL_E_NONFINITE;
+    double am[2] = {0.0, 0.0};
+    for (int c = 0; c < m->dim; ++c)
+        for (size_t i = 0; i < nf; ++i) am[c] = std::max(am[c], std::fabs(a[c * nf + i]));
+    if (hipMemcpyAsync(m->aN, a, nf * m->dim * sizeof(double), hipMemcpyHostToDevice, m->stream)) return SL_E_DEVICE;
+    if (div_a && hipMemcpyAsync(m->divN, div_a, nf * sizeof(double), hipMemcpyHostToDevice, m->stream))
+        return SL_E_DEVICE;
+    int rc = launch_prep1d(m->n, m->K, m->bc == SL_BC_PERIODIC, div_a != nullptr, m->aN, m->aM, m->divN, m->divM,
+                           m->vface, m->tab, m->dx, m->stream);
+    if (rc || hipStreamSynchronize(m->stream)) return SL_E_DEVICE;
+    m->amax[0] = am[0];
+    m->amax[1] = am[1];
+    m->has_velocity = true;
+    return SL_OK;
+}
+
+int32_t sl_ghost_count(const sl_mesh* m)
+{
+    if (!m) return 0;
+    return m->dim == 1 ? 2 : 2 * m->ky * m->n + 2 * m->kx * m->n;
+}
+
+sl_status sl_set_ghost(sl_mesh* m, const double* g, int32_t nrows)
+{
+    if (!m) return SL_E_INVALID;
+    if (m->bc != SL_BC_GHOST) return SL_E_STATE;
+    if (!g || nrows < 1) return SL_E_INVALID;
+    const size_t cnt = (size_t)sl_ghost_count(m) * nrows;
+    if (!all_finite(g, cnt)) return SL_E_NONFINITE;
+    if (hipStreamSynchronize(m->stream)) return SL_E_DEVICE;
+    dfree(m->ghost);
+    if (!dalloc(&m->ghost, cnt)) { m->ghost_rows = 0; return SL_E_NOMEM; }
+    if (hipMemcpyAsync(m->ghost, g, cnt * sizeof(double), hipMemcpyHostToDevice, m->stream)) return SL_E_DEVICE;
+    m->ghost_rows = nrows;
+    m->ghost_step = 0;
+    return SL_OK;
+}
+
+double sl_max_dt(const sl_mesh* m, double cfl)
+{
+    if (!m || !m->has_velocity || !(cfl > 0)) return 0.0;
+    const double gap = m->T.xi[0];
+    double dt = INFINITY;
+    if (m->amax[0] > 0) dt = std::min(dt, gap * m->dx / m->amax[0]);
+    if (m->dim == 2 && m->amax[1] > 0) dt = std::min(dt, gap * m->dy / m->amax[1]);
+    if (!std::isfinite(dt)) dt = 0.0;
+    return dt * cfl;
+}
+
+static void ev_begin(sl_mesh* m, int k)
+{
+    if (!m->profiling) return;
+    hipEvent_t a, b;
+    (void)hipEventCreate(&a);
+    (void)hipEventCreate(&b);
+    (void)hipEventRecord(a, m->stream);
+    m->pending[k].push_back(a);
+    m->pending[k].push_back(b);
+}
+
+static void ev_end(sl_mesh* m, int k)
+{
+    if (!m->profiling) return;
+    (void)hipEventRecord(m->pending[k].back(), m->stream);
+}
+
+sl_status sl_step(sl_mesh* m, double dt, int32_t nsteps, const sl_step_opts* o)
+{
+    if (!m) return SL_E_INVALID;
+    sl_step_opts opt = {4, SL_C_BOUNDARY, SL_MODE_HARD, 50, 3, 1e-8};
+    if (o) opt = *o;
+    if (!(dt > 0) || !std::isfinite(dt) || nsteps < 0) return SL_E_INVALID;
+    if (opt.rk < 1 || opt.rk > 4 || (opt.constraints & ~7) || (opt.mode != SL_MODE_HARD && opt.mode != SL_MODE_SOFT) ||
+        opt.energy_maxit < 0 || !(opt.energy_tol >= 0) || opt.refine_steps < 0)
+        return SL_E_INVALID;
+    if (!m->has_velocity) return SL_E_STATE;
+    if (m->bc == SL_BC_GHOST && m->ghost_rows < 1) return SL_E_STATE;
+    // time-step restriction: particles may not cross the element-edge gap
+    const double gap = m->T.xi[0];
+    if (m->amax[0] * dt >= gap * m->dx) return SL_E_CFL;
+    if (m->dim == 2 && m->amax[1] * dt >= gap * m->dy) return SL_E_CFL;
+    // the rows of the 1D KKT system must be independent: n >= number of rows
+    const int rows = ((opt.constraints & SL_C_BOUNDARY) ? 2 : 0) + ((opt.constraints & SL_C_MASS) ? 1 : 0) +
+                     ((opt.constraints & SL_C_ENERGY) ? 1 : 0);
+    if (rows > m->nd) return SL_E_INVALID;
+
+    Step1DArgs A;
+    std::memset(&A, 0, sizeof(A));
+    rk_tableau(opt.rk, &A.rk);
+    A.aN = m->aN; A.aM = m->aM; A.divN = m->divN; A.divM = m->divM; A.vface = m->vface; A.tab = m->tab;
+    A.rec = m->rec; A.phihat = m->phihat;
+    A.flag_part = m->flag_part; A.stat_part = m->stat_part;
+    A.K = m->K; A.periodic = m->bc == SL_BC_PERIODIC; A.cons = m->form == SL_FORM_CONSERVATIVE;
+    A.cmask = opt.constraints; A.mode = opt.mode; A.emaxit = opt.energy_maxit; A.etol = opt.energy_tol;
+    A.targets = (opt.constraints & (SL_C_MASS | SL_C_ENERGY)) != 0;
+    A.vol = A.targets;
+    A.dx = m->dx; A.dt = dt;
+    A.vzero = 1e-12 * m->amax[0];
+    double g[6];
+    gram1d(m, g);
+    A.g00 = g[0]; A.g01 = g[1]; A.g11 = g[2]; A.g02 = g[3]; A.g12 = g[4]; A.g22 = g[5];
+    static const double zero2[2] = {0.0, 0.0};
+    (void)zero2;
+    for (int s = 0; s < nsteps; ++s) {
+        if (m->bc == SL_BC_GHOST) {
+            const long r0 = std::min<long>(m->ghost_step, m->ghost_rows - 1);
+            const long r1 = std::min<long>(m->ghost_step + 1, m->ghost_rows - 1);
+            A.gnow = m->ghost + r0 * sl_ghost_count(m);
+            A.gnext = m->ghost + r1 * sl_ghost_count(m);
+        } else {
+            A.gnow = A.gnext = m->vface;  // unused for periodic meshes (valid address)
+        }
+        A.phi = m->phi;
+        A.phi_out = m->phi2;
+        ev_begin(m, KER_ADV1D);
+        if (launch_advect1d(m->n, A, m->stream)) return SL_E_DEVICE;
+        ev_end(m, KER_ADV1D);
+        ev_begin(m, KER_CON1D);
+        if (launch_constrain1d(m->n, A, m->stream)) return SL_E_DEVICE;
+        ev_end(m, KER_CON1D);
+        std::swap(m->phi, m->phi2);
+        m->t += dt;
+        m->steps += 1;
+        m->ghost_step += 1;
+    }
+    return SL_OK;
+}
+
+sl_status sl_read(sl_mesh* m, double* u_out, sl_stats* st)
+{
+    if (!m) return SL_E_INVALID;
+    if (hipStreamSynchronize(m->stream)) return SL_E_DEVICE;
+    const size_t nf = (size_t)m->K * m->nd;
+    std::vector<double> host;
+    double* dst = u_out;
+    if (!dst && st) { host.resize(nf); dst = host.data(); }
+    if (dst && hipMemcpy(dst, m->phi, nf * sizeof(double), hipMemcpyDeviceToHost)) return SL_E_DEVICE;
+    std::vector<double> sp((size_t)m->nblocks * kStatSlots);
+    std::vector<int32_t> fp((size_t)2 * m->nblocks);
+    if (hipMemcpy(sp.data(), m->stat_part, sp.size() * sizeof(double), hipMemcpyDeviceToHost)) return SL_E_DEVICE;
+    if (hipMemcpy(fp.data(), m->flag_part, fp.size() * sizeof(int32_t), hipMemcpyDeviceToHost)) return SL_E_DEVICE;
+    int flags = 0;
+    for (int32_t f : fp) flags |= f;
+    double rb = 0, rm = 0, re = 0, pic = 0;
+    for (int b = 0; b < m->nblocks; ++b) {
+        rb = std::max(rb, sp[b * kStatSlots + 0]);
+        rm = std::max(rm, sp[b * kStatSlots + 1]);
+        re = std::max(re, sp[b * kStatSlots + 2]);
+        pic = std::max(pic, sp[b * kStatSlots + 3]);
+    }
+    if (st) {
+        std::memset(st, 0, sizeof(*st));
+        st->t = m->t;
+        st->steps = m->steps;
+        double M = 0, E = 0;
+        for (int e = 0; e < m->K; ++e)
+            for (int p = 0; p < m->nd; ++p) {
+                const int i = p % m->n, j = p / m->n;
+                const double W = m->dx * m->T.w[i] * (m->dim == 2 ? m->dy * m->T.w[j] : 1.0);
+                const double v = dst[(size_t)e * m->nd + p];
+                M += W * v;
+                E += W * v * v;
+            }
+        st->mass = M;
+        st->energy = E;
+        st->resid_boundary = rb;
+        st->resid_mass = rm;
+        st->resid_energy = re;
+        st->max_picard = (int32_t)pic;
+        st->flags = flags;
+    }
+    (void)hipMemsetAsync(m->stat_part, 0, sp.size() * sizeof(double), m->stream);
+    (void)hipMemsetAsync(m->flag_part, 0, fp.size() * sizeof(int32_t), m->stream);
+    if (hipStreamSynchronize(m->stream)) return SL_E_DEVICE;
+    if (flags & FLAG_NONFINITE) return SL_E_NONFINITE;
+    if (flags & FLAG_SINGULAR) return SL_E_SINGULAR;
+    if (flags & FLAG_NOCONV) return SL_E_NOCONV;
+    return SL_OK;
+}
+
+sl_status sl_device_field(sl_mesh* m, double** d_phi, void** stream)
+{
+    if (!m) return SL_E_INVALID;
+    if (d_phi) *d_phi = m->phi;
+    if (stream) *stream = (void*)m->stream;
+    return SL_OK;
+}
+
+sl_status sl_set_profiling(sl_mesh* m, int32_t enable)
+{
+    if (!m) return SL_E_INVALID;
+    (void)hipStreamSynchronize(m->stream);
+    for (int k = 0; k < KER_COUNT; ++k) {
+        for (hipEvent_t e : m->pending[k]) (void)hipEventDestroy(e);
+        m->pending[k].clear();
+        m->ktime[k] = 0.0;
+        m->kcount[k] = 0;
+    }
+    m->profiling = enable != 0;
+    return SL_OK;
+}
+
+sl_status sl_kernel_time(sl_mesh* m, int32_t which, double* total_ms, int64_t* launches)
+{
+    if (!m || which < 0 || which >= KER_COUNT) return SL_E_INVALID;
+    if (hipStreamSynchronize(m->stream)) return SL_E_DEVICE;
+    auto& v = m->pending[which];
+    for (size_t i = 0; i + 1 < v.size(); i += 2) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, v[i], v[i + 1]) == hipSuccess) m->ktime[which] += ms;
+        m->kcount[which] += 1;
+        (void)hipEventDestroy(v[i]);
+        (void)hipEventDestroy(v[i + 1]);
+    }
+    v.clear();
+    if (total_ms) *total_ms = m->ktime[which];
+    if (launches) *launches = m->kcount[which];
+    return SL_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,107 @@
+// Internal declarations shared by the host runtime and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/sl.h"
+
+namespace sl {
+
+constexpr int kMaxTableN = 32;
+constexpr int kMax1D = 17;  // nodes per element in 1D (order 16)
+constexpr int kMax2D = 11;  // nodes per direction in 2D (order 10)
+
+struct Tables {
+    int n;
+    double xi[kMaxTableN], w[kMaxTableN], lam[kMaxTableN];
+    double l0[kMaxTableN], l1[kMaxTableN];
+    double D[kMaxTableN * kMaxTableN];
+    double Tinv[kMaxTableN * kMaxTableN];
+};
+
+bool node_rule(int family, int n, double* xi, double* w);
+bool build_tables(int family, int n, Tables* T);
+
+// Device table layout (doubles), per mesh.  1D and 2D share the head.
+struct TabOff {
+    int xi, w, l0, l1, tinv, dmat;   // n, n, n, n, n*n, n*n
+    int cbp, pb;                      // 2D: C_B^+ (n^2 x 4n), unused in 1D
+    int total;
+};
+TabOff tab_offsets(int dim, int n);
+
+// Explicit Runge-Kutta tableau, with the distinct abscissae and their
+// summed weights (the quadrature the tableau induces on a time integral).
+struct RKTab {
+    int s, nq;
+    double a[4][4], b[4], c[4];
+    double cu[4], bu[4];
+};
+bool rk_tableau(int order, RKTab* T);
+
+enum { KER_ADV1D = 0, KER_CON1D = 1, KER_ADV2D = 2, KER_CON2D = 3, KER_COUNT = 4 };
+enum { FLAG_NONFINITE = 1, FLAG_CONTAIN = 2, FLAG_SINGULAR = 4, FLAG_NOCONV = 8 };
+
+// Per-block statistics slots written by the constraint kernels:
+// [resid_boundary, resid_mass, resid_energy, max_picard]
+constexpr int kStatSlots = 4;
+
+struct Step1DArgs {
+    // fields
+    const double* phi;     // [K][n] phi^n
+    double* phihat;        // [K][n] remapped
+    double* rec;           // [K][8] per-element record
+    double* phi_out;       // [K][n] phi^{n+1}
+    // velocity
+    const double* aN;      // nodal velocity
+    const double* aM;      // Chebyshev coefficients of the velocity
+    const double* divN;    // nodal divergence
+    const double* divM;    // Chebyshev coefficients of the divergence
+    const double* vface;   // [K+1] face velocity
+    const double* tab;
+    const double* gnow;    // ghost row at t^n (2 values) or null
+    const double* gnext;   // ghost row at t^{n+1}
+    int32_t* flag_part;    // [2][nblocks]
+    double* stat_part;     // [nblocks][kStatSlots]
+    int K, periodic, cons, cmask, mode, emaxit, vol, targets;
+    double dx, dt, etol, vzero;
+    double g00, g01, g11, g02, g12, g22;  // constant Gram entries of rows l(0), l(1), W
+    RKTab rk;
+};
+
+int launch_prep1d(int n, int K, int periodic, int has_div, const double* aN, double* aM, double* divN,
+                  double* divM, double* vface, const double* tab, double dx, hipStream_t s);
+int launch_advect1d(int n, const Step1DArgs& A, hipStream_t s);
+int launch_constrain1d(int n, const Step1DArgs& A, hipStream_t s);
+int blocks1d(int n, int K);
+
+struct Step2DArgs {
+    const double* phi;
+    double* phihat;
+    double* rec;           // [K][4n][4]: trace, FM, FE, face velocity per edge point
+    double* eloc;          // [K][2]: M, E local targets
+    double* phi_out;
+    const double* aM;      // [2][K][n^2] Chebyshev coefficients (u then v)
+    const double* aN;      // [2][K][n^2] nodal velocity
+    const double* divN;    // [K][n^2]
+    const double* divM;    // [K][n^2]
+    const double* tab;
+    const double* gnow;
+    const double* gnext;
+    int32_t* flag_part;
+    double* stat_part;
+    int kx, ky, K, periodic, cons, cmask, mode, emaxit, vol, targets, precision, refine;
+    double dx, dy, dt, etol, vzero;
+    RKTab rk;
+};
+
+int launch_prep2d(int n, int kx, int ky, int has_div, const double* aN, double* aM, double* divN, double* divM,
+                  const double* tab, double dx, double dy, hipStream_t s);
+int launch_advect2d(int n, const Step2DArgs& A, hipStream_t s);
+int launch_constrain2d(int n, const Step2DArgs& A, hipStream_t s);
+int blocks2d(int n, int K);
+
+bool build_boundary_pinv(const Tables& T, double* CBp, double* PB);
+
+}  // namespace sl

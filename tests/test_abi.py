@@ -1,0 +1,89 @@
+"""C-ABI checks that need no GPU: the library loads, exports every entry
+point include/sl.h declares, and its host-only functions behave (node tables
+against numpy's library rules, status strings, descriptor validation that
+fails before any device call)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def sl():
+    import paper_1910_06476_amd as P
+    if not os.path.exists(P.LIBPATH):
+        pytest.skip("libsl.so not built (run __graft_entry__.build())")
+    return P
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "sl.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(sl_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol(sl):
+    names = declared_functions()
+    assert len(names) >= 12
+    L = ctypes.CDLL(sl.LIBPATH)
+    for name in names:
+        assert hasattr(L, name), name
+    assert sorted(sl.EXPORTS) == names
+
+
+@pytest.mark.parametrize("n", range(1, 33))
+def test_node_coords_gauss_legendre(sl, n):
+    xi, w = sl.sl_node_coords(sl.SL_NODES_GL, n)
+    t, wl = np.polynomial.legendre.leggauss(n)
+    order = np.argsort((1 - t) / 2)
+    np.testing.assert_allclose(xi, ((1 - t) / 2)[order], atol=3e-16)
+    np.testing.assert_allclose(w, (wl / 2)[order], atol=3e-15)
+
+
+@pytest.mark.parametrize("n", range(1, 20))
+def test_node_coords_chebyshev_gauss(sl, n):
+    xi, w = sl.sl_node_coords(sl.SL_NODES_CG, n)
+    t, _ = np.polynomial.chebyshev.chebgauss(n)
+    np.testing.assert_allclose(xi, np.sort((1 - t) / 2), atol=3e-16)
+    for k in range(n):  # interpolatory: exact below degree n
+        assert abs(np.dot(w, xi ** k) - 1 / (k + 1)) < 1e-13
+
+
+def test_node_coords_rejects(sl):
+    with pytest.raises(sl.SLError):
+        sl.sl_node_coords(7, 5)
+    with pytest.raises(sl.SLError):
+        sl.sl_node_coords(0, 0)
+
+
+def test_status_strings(sl):
+    for s in range(9):
+        assert isinstance(sl.status_string(s), str) and sl.status_string(s)
+    assert sl.status_string(99) == "unknown status"
+
+
+@pytest.mark.parametrize("bad", [
+    dict(dim=3), dict(order=0), dict(order=17), dict(kx=0), dict(ky=2), dict(nodes=5), dict(bc=3),
+    dict(form=2), dict(precision=1), dict(x1=0.0),
+])
+def test_create_mesh_validates_before_touching_the_device(sl, bad):
+    args = dict(dim=1, kx=4, ky=1, order=3, nodes=0, bc=0, form=0, precision=0, x0=0.0, x1=1.0)
+    args.update(bad)
+    u0 = np.zeros(4 * 4 * 4)
+    with pytest.raises(sl.SLError) as ei:
+        sl.sl_create_mesh(args.pop("dim"), args.pop("kx"), args.pop("ky"), args.pop("order"), u0, **args)
+    assert ei.value.status == sl.SL_E_INVALID
+
+
+def test_null_handles_rejected(sl):
+    L = sl.lib()
+    assert L.sl_step(None, 0.1, 1, None) == sl.SL_E_INVALID
+    assert L.sl_read(None, None, None) == sl.SL_E_INVALID
+    assert L.sl_destroy_mesh(None) == sl.SL_E_INVALID
+    assert L.sl_set_velocity(None, None, None) == sl.SL_E_INVALID
+    assert L.sl_max_dt(None, 1.0) == 0.0
+    assert L.sl_ghost_count(None) == 0
