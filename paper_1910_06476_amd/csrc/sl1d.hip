@@ -165,11 +165,17 @@ __global__ void k_prep1d(int K, int periodic, int has_div, const double* __restr
 
 // ---------------------------------------------------------------------------
 // advect + remap + element-local target parts
+//
+// n + 1 lanes per element: n node lanes and one edge lane.  The edge lane
+// runs the backtraces from the element's upwind edge(s) in the same
+// instruction stream as the node lanes' backtraces from the nodes, and the
+// edge traces of the remapped polynomial while the node lanes remap.
 // ---------------------------------------------------------------------------
 template <int N, bool CONS>
 __global__ __launch_bounds__(kBlock) void k_advect1d(Step1DArgs A)
 {
-    constexpr int E = kBlock / N;
+    constexpr int L = N + 1;
+    constexpr int E = kBlock / L;
     using O = Off<N>;
     __shared__ double s_a[E][N];
     __shared__ double s_d[E][N];
@@ -181,30 +187,33 @@ __global__ __launch_bounds__(kBlock) void k_advect1d(Step1DArgs A)
     __shared__ int s_flag;
 
     const int t = threadIdx.x;
-    const int slot = t / N, i = t - slot * N;
+    const int slot = t / L, i = t - slot * L;
     const bool inblk = slot < E;
     const int sl = inblk ? slot : 0;
+    const bool node = i < N;
+    const int in = node ? i : 0;
     const int e = blockIdx.x * E + slot;
     const bool live = inblk && e < A.K;
     const double* __restrict__ tab = A.tab;
-    const size_t g = (size_t)(live ? e : 0) * N + i;
+    const size_t g = (size_t)(live ? e : 0) * N + in;
     if (t == 0) s_flag = 0;
 
-    const double xi_i = tab[O::XI + i];
-    const double W_i = A.dx * tab[O::W + i];
+    const double xi_i = tab[O::XI + in];
+    const double W_i = A.dx * tab[O::W + in];
+    const double invdx = 1.0 / A.dx;
     double phi_i = 0.0, a_i = 0.0, dv_i = 0.0;
-    if (live) {
+    if (live && node) {
         phi_i = A.phi[g];
         a_i = A.aN[g];
         if (A.targets || CONS) dv_i = A.divN[g];
     }
-    if (inblk) {
+    if (inblk && node) {
         s_a[slot][i] = live ? A.aM[g] : 0.0;
         if (CONS) s_d[slot][i] = live ? A.divM[g] : 0.0;
         s_p[slot][i] = phi_i;
     }
     __syncthreads();
-    if (A.targets && inblk) {
+    if (A.targets && inblk && node) {
         double c = 0.0;
 #pragma unroll
         for (int j = 0; j < N; ++j) c = fma(tab[O::TINV + i * N + j], s_p[slot][j], c);
@@ -221,131 +230,122 @@ __global__ __launch_bounds__(kBlock) void k_advect1d(Step1DArgs A)
     bool out = false;
     // forward motion of particle i (section 4.2)
     double s = xi_i, q = phi_i;
-    rk_move<N, CONS>(A.rk, ca, cd, 1.0, A.dt, 1.0 / A.dx, s, q, out, true, a_i, dv_i);
+    if (node) rk_move<N, CONS>(A.rk, ca, cd, 1.0, A.dt, invdx, s, q, out, true, a_i, dv_i);
 
-    // element-local target parts (needs phi^n coefficients)
-    double m0 = 0.0, e0 = 0.0, vM = 0.0, vE = 0.0, FM = 0.0, FE = 0.0;
+    // element-local target parts: M^n, E^n, volume term at the RK abscissae
+    // (node lanes), edge values at the RK abscissae on the upwind edges (edge
+    // lane); backtracking as in eq. 4.11
+    double vM = 0.0, vE = 0.0, FM[2] = {0.0, 0.0}, FE[2] = {0.0, 0.0};
     if (A.targets) {
         double cp[N];
 #pragma unroll
         for (int k = 0; k < N; ++k) cp[k] = s_q[sl][k];
-        m0 = W_i * phi_i;
-        e0 = W_i * phi_i * phi_i;
-        if (A.vol) {
-            for (int qd = 0; qd < A.rk.nq; ++qd) {
-                const double cq = A.rk.cu[qd];
-                double val = phi_i;
-                if (cq != 0.0) {
-                    double sb = xi_i, hq = 1.0;
-                    rk_move<N, CONS>(A.rk, ca, cd, -1.0, cq * A.dt, 1.0 / A.dx, sb, hq, out, true, a_i, dv_i);
-                    val = hq * clenshaw<N>(cp, 2.0 * sb - 1.0);
-                }
-                vM += A.rk.bu[qd] * (W_i * dv_i * val);
-                vE += A.rk.bu[qd] * (W_i * dv_i * val * val);
-            }
+        int first = -1, second = -1;
+        if (!node && live) {
+            const double vL = A.vface[e];
+            const double vR = A.vface[(A.periodic && e == A.K - 1) ? 0 : e + 1];
+            const bool needL = !(vL > A.vzero), needR = !(vR < -A.vzero);
+            first = needL ? 0 : (needR ? 1 : -1);
+            second = (needL && needR) ? 1 : -1;
         }
-        // edge values are needed only where this element is the upwind side
-        // of the face (or the face is a stagnation point)
-        bool need_edge = false;
-        if (live && i == 0) {
-            double vL = A.vface[e];
-            need_edge = !(vL > A.vzero);
-        } else if (live && i == N - 1) {
-            double vR = A.vface[(A.periodic && e == A.K - 1) ? 0 : e + 1];
-            need_edge = !(vR < -A.vzero);
-        }
-        if (need_edge) {
-            const double xb = (i == 0) ? 0.0 : 1.0;
+        for (int r = 0; r < 2; ++r) {
+            const int edge = (r == 0) ? first : second;
+            const bool act = node ? (r == 0 && A.vol && live) : (edge >= 0);
+            if (!act) continue;
+            const double x0 = node ? xi_i : (double)edge;
             for (int qd = 0; qd < A.rk.nq; ++qd) {
                 const double cq = A.rk.cu[qd];
                 double val;
                 if (cq == 0.0) {
-                    val = clenshaw<N>(cp, 2.0 * xb - 1.0);
+                    val = node ? phi_i : clenshaw<N>(cp, 2.0 * x0 - 1.0);
                 } else {
-                    double sb = xb, hq = 1.0;
-                    rk_move<N, CONS>(A.rk, ca, cd, -1.0, cq * A.dt, 1.0 / A.dx, sb, hq, out, false, 0.0, 0.0);
+                    double sb = x0, hq = 1.0;
+                    rk_move<N, CONS>(A.rk, ca, cd, -1.0, cq * A.dt, invdx, sb, hq, out, node, a_i, dv_i);
                     val = hq * clenshaw<N>(cp, 2.0 * sb - 1.0);
                 }
-                FM += A.rk.bu[qd] * val;
-                FE += A.rk.bu[qd] * val * val;
+                const double bq = A.rk.bu[qd];
+                if (node) {
+                    vM += bq * (W_i * dv_i * val);
+                    vE += bq * (W_i * dv_i * val * val);
+                } else {
+                    FM[edge] += bq * val;
+                    FE[edge] += bq * val * val;
+                }
             }
         }
-        if (inblk) {
-            s_r[0][slot][i] = m0;
-            s_r[1][slot][i] = e0;
+        if (inblk && node) {
+            s_r[0][slot][i] = W_i * phi_i;
+            s_r[1][slot][i] = W_i * phi_i * phi_i;
             s_r[2][slot][i] = vM;
             s_r[3][slot][i] = vE;
         }
     }
 
     // remap (eq. 4.9): phihat_i = sum_j c_j prod_{m != j} (xi_i - s_m),
-    // c_j = phi*_j / prod_{m != j} (s_j - s_m)
-    if (inblk) s_x[slot][i] = s;
+    // c_j = phi*_j / prod_{m != j} (s_j - s_m); the edge lane evaluates the
+    // same polynomial at 0 and 1 (eq. remap_bnd)
+    if (inblk && node) s_x[slot][i] = s;
     __syncthreads();
     double xs[N];
 #pragma unroll
     for (int m = 0; m < N; ++m) xs[m] = s_x[sl][m];
-    double pr = 1.0;
+    if (node) {
+        double pr = 1.0;
 #pragma unroll
-    for (int m = 0; m < N; ++m)
-        if (m != i) pr *= (s - xs[m]);
-    if (inblk) s_c[slot][i] = q / pr;
+        for (int m = 0; m < N; ++m)
+            if (m != i) pr *= (s - xs[m]);
+        if (inblk) s_c[slot][i] = q / pr;
+    }
     __syncthreads();
     double cw[N];
 #pragma unroll
     for (int m = 0; m < N; ++m) cw[m] = s_c[sl][m];
+    const double xe = node ? xi_i : 0.0;
     double S = 0.0, P = 1.0;
 #pragma unroll
     for (int j = 0; j < N; ++j) {
-        const double d = xi_i - xs[j];
+        const double d = xe - xs[j];
         S = fma(S, d, cw[j] * P);
         P *= d;
     }
-    const double phat = S;
-    double tr = 0.0;
-    if (i == 0 || i == N - 1) {
-        const double xb = (i == 0) ? 0.0 : 1.0;
+    double T1 = 0.0;
+    if (!node) {
         double S2 = 0.0, P2 = 1.0;
 #pragma unroll
         for (int j = 0; j < N; ++j) {
-            const double d = xb - xs[j];
+            const double d = 1.0 - xs[j];
             S2 = fma(S2, d, cw[j] * P2);
             P2 *= d;
         }
-        tr = S2;
+        T1 = S2;
     }
 
     int fl = 0;
     if (live) {
         if (out) fl |= FLAG_CONTAIN;
-        if (!isfinite(phat)) fl |= FLAG_SINGULAR;
-        A.phihat[g] = phat;
-        double* r = A.rec + (size_t)e * 8;
-        if (i == 0) {
-            r[0] = tr;
-            r[2] = FM;
-            r[4] = FE;
-        }
-        if (i == N - 1) {
-            r[1] = tr;
-            r[3] = FM;
-            r[5] = FE;
-        }
-    }
-    if (A.targets) {
-        // s_r was written before the barriers above
-        if (live && i == 0) {
-            double M = 0.0, En = 0.0, sM = 0.0, sE = 0.0;
-#pragma unroll
-            for (int j = 0; j < N; ++j) {
-                M += s_r[0][slot][j];
-                En += s_r[1][slot][j];
-                sM += s_r[2][slot][j];
-                sE += s_r[3][slot][j];
-            }
+        if (node) {
+            if (!isfinite(S)) fl |= FLAG_SINGULAR;
+            A.phihat[g] = S;
+        } else {
             double* r = A.rec + (size_t)e * 8;
-            r[6] = CONS ? M : M + A.dt * sM;
-            r[7] = CONS ? En - A.dt * sE : En + A.dt * sE;
+            r[0] = S;
+            r[1] = T1;
+            r[2] = FM[0];
+            r[3] = FM[1];
+            r[4] = FE[0];
+            r[5] = FE[1];
+            if (A.targets) {
+                double M = 0.0, En = 0.0, sM = 0.0, sE = 0.0;
+#pragma unroll
+                for (int j = 0; j < N; ++j) {
+                    M += s_r[0][slot][j];
+                    En += s_r[1][slot][j];
+                    sM += s_r[2][slot][j];
+                    sE += s_r[3][slot][j];
+                }
+                r[6] = CONS ? M : M + A.dt * sM;
+                r[7] = CONS ? En - A.dt * sE : En + A.dt * sE;
+            }
         }
     }
     if (fl) atomicOr(&s_flag, fl);
@@ -354,7 +354,7 @@ __global__ __launch_bounds__(kBlock) void k_advect1d(Step1DArgs A)
 }
 
 // ---------------------------------------------------------------------------
-// constrained least squares
+// constrained least squares: one lane per element, values in registers
 // ---------------------------------------------------------------------------
 // Cholesky solve of a 4x4 SPD system (upper triangle used)
 __device__ __forceinline__ bool chol4(double G[4][4], double b[4])
@@ -394,35 +394,35 @@ __device__ __forceinline__ bool chol4(double G[4][4], double b[4])
     return ok;
 }
 
-template <int N>
-__global__ __launch_bounds__(kBlock) void k_constrain1d(Step1DArgs A)
-{
-    constexpr int E = kBlock / N;
-    using O = Off<N>;
-    __shared__ double s_r[5][E][N];
-    __shared__ int s_flag;
-    __shared__ unsigned long long s_stat[kStatSlots];
+constexpr int kConBlock = 64;
 
+template <int N>
+__global__ __launch_bounds__(kConBlock) void k_constrain1d(Step1DArgs A)
+{
+    using O = Off<N>;
+    __shared__ double s_buf[kConBlock * N];
     const int t = threadIdx.x;
-    const int slot = t / N, i = t - slot * N;
-    const bool inblk = slot < E;
-    const int sl = inblk ? slot : 0;
-    const int e = blockIdx.x * E + slot;
-    const bool live = inblk && e < A.K;
-    const int ee = live ? e : 0;
+    const int e0 = blockIdx.x * kConBlock;
+    const int K = A.K;
+    const int e = e0 + t;
+    const bool live = e < K;
+    const int ee = live ? e : K - 1;
     const double* __restrict__ tab = A.tab;
-    const size_t g = (size_t)ee * N + i;
-    if (t < kStatSlots) s_stat[t] = 0ull;
-    if (t == 0) s_flag = 0;
+
+    // coalesced staging of the block's phihat
+    const int cnt = (K - e0 < kConBlock ? K - e0 : kConBlock) * N;
+    for (int k = t; k < cnt; k += kConBlock) s_buf[k] = A.phihat[(size_t)e0 * N + k];
+    __syncthreads();
+    double ph[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) ph[j] = live ? s_buf[t * N + j] : 0.0;
+    __syncthreads();
 
     const bool bnd = (A.cmask & SL_C_BOUNDARY) != 0;
     const bool mass = (A.cmask & SL_C_MASS) != 0;
     const bool energy = (A.cmask & SL_C_ENERGY) != 0;
-    const double W_i = A.dx * tab[O::W + i];
-    const double ph = live ? A.phihat[g] : 0.0;
 
-    // neighbours and face values at t^{n+1}
-    const int K = A.K;
+    // neighbours and face values at t^{n+1} (eq. 4.12a)
     int em = ee - 1, ep = ee + 1;
     if (A.periodic) {
         if (em < 0) em = K - 1;
@@ -463,47 +463,37 @@ __global__ __launch_bounds__(kBlock) void k_constrain1d(Step1DArgs A)
         Et = Re[7] + A.dt * (vL * FEl - vR * FEr);
     }
 
-    // rows: l(0), l(1), W, W*psi (energy); inactive rows are zero
-    const double c0 = bnd ? tab[O::L0 + i] : 0.0;
-    const double c1 = bnd ? tab[O::L1 + i] : 0.0;
-    const double c2 = mass ? W_i : 0.0;
-    double d[4] = {bnd ? dB0 : 0.0, bnd ? dB1 : 0.0, mass ? Mt : 0.0, energy ? Et : 0.0};
-    double Gc[3][3] = {{bnd ? A.g00 : 0.0, bnd ? A.g01 : 0.0, (bnd && mass) ? A.g02 : 0.0},
-                       {0.0, bnd ? A.g11 : 0.0, (bnd && mass) ? A.g12 : 0.0},
-                       {0.0, 0.0, mass ? A.g22 : 0.0}};
-    const bool act[4] = {bnd, bnd, mass, false};
-
-    // C phihat for the constant rows
-    if (inblk) {
-        s_r[0][slot][i] = c0 * ph;
-        s_r[1][slot][i] = c1 * ph;
-        s_r[2][slot][i] = c2 * ph;
-    }
-    __syncthreads();
-    double Cph[4] = {0.0, 0.0, 0.0, 0.0};
+    // rows l(0), l(1), W (mass), W*psi (energy); inactive rows are zero.
+    // Tables are read with uniform indices (scalar loads).
+    double Cph[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int j = 0; j < N; ++j) {
-        Cph[0] += s_r[0][sl][j];
-        Cph[1] += s_r[1][sl][j];
-        Cph[2] += s_r[2][sl][j];
+        Cph[0] += tab[O::L0 + j] * ph[j];
+        Cph[1] += tab[O::L1 + j] * ph[j];
+        Cph[2] += (A.dx * tab[O::W + j]) * ph[j];
     }
-    __syncthreads();
-
+    const double dd0 = bnd ? dB0 : 0.0, dd1 = bnd ? dB1 : 0.0, dd2 = mass ? Mt : 0.0;
+    const double s0 = bnd ? 1.0 : 0.0, s1 = bnd ? 1.0 : 0.0, s2 = mass ? 1.0 : 0.0;
     bool singular = false;
-    // one constrained solve with energy row c3 (inactive if !use_e)
-    auto solve = [&](bool use_e, double c3, const double (&red)[5]) -> double {
+
+    // one constrained solve; energy row given by its Gram entries red[0..3]
+    // (against l0, l1, W, itself), its product with phihat red[4], target d3
+    auto solve = [&](bool use_e, const double (&red)[5], double d3, double (&y)[4]) {
         double G[4][4];
-        G[0][0] = Gc[0][0]; G[0][1] = Gc[0][1]; G[0][2] = Gc[0][2];
-        G[1][1] = Gc[1][1]; G[1][2] = Gc[1][2]; G[2][2] = Gc[2][2];
-        G[0][3] = use_e ? red[0] : 0.0;
-        G[1][3] = use_e ? red[1] : 0.0;
-        G[2][3] = use_e ? red[2] : 0.0;
+        G[0][0] = bnd ? A.g00 : 0.0;
+        G[0][1] = bnd ? A.g01 : 0.0;
+        G[0][2] = (bnd && mass) ? A.g02 : 0.0;
+        G[1][1] = bnd ? A.g11 : 0.0;
+        G[1][2] = (bnd && mass) ? A.g12 : 0.0;
+        G[2][2] = mass ? A.g22 : 0.0;
+        G[0][3] = use_e ? red[0] * s0 : 0.0;
+        G[1][3] = use_e ? red[1] * s1 : 0.0;
+        G[2][3] = use_e ? red[2] * s2 : 0.0;
         G[3][3] = use_e ? red[3] : 0.0;
-        const double cph3 = use_e ? red[4] : 0.0;
-        const double dd[4] = {d[0], d[1], d[2], use_e ? d[3] : 0.0};
-        const bool ac[4] = {act[0], act[1], act[2], use_e};
+        const double cp[4] = {Cph[0] * s0, Cph[1] * s1, Cph[2] * s2, use_e ? red[4] : 0.0};
+        const double dd[4] = {dd0, dd1, dd2, use_e ? d3 : 0.0};
+        const bool ac[4] = {bnd, bnd, mass, use_e};
         double rhs[4];
-        const double cp[4] = {Cph[0], Cph[1], Cph[2], cph3};
         if (A.mode == SL_MODE_HARD) {
 #pragma unroll
             for (int a = 0; a < 4; ++a) {
@@ -514,130 +504,127 @@ __global__ __launch_bounds__(kBlock) void k_constrain1d(Step1DArgs A)
             // (I + G) z = C phihat + G d ; y = z - d
 #pragma unroll
             for (int a = 0; a < 4; ++a) {
-                double s = cp[a];
+                double v = cp[a];
 #pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    const double gab = (a <= b) ? G[a][b] : G[b][a];
-                    s += gab * dd[b];
-                }
-                rhs[a] = s;
+                for (int b = 0; b < 4; ++b) v += ((a <= b) ? G[a][b] : G[b][a]) * dd[b];
+                rhs[a] = v;
             }
 #pragma unroll
             for (int a = 0; a < 4; ++a) G[a][a] += 1.0;
         }
         singular |= !chol4(G, rhs);
-        double y[4];
 #pragma unroll
         for (int a = 0; a < 4; ++a) y[a] = (A.mode == SL_MODE_HARD) ? rhs[a] : rhs[a] - dd[a];
-        return ph - (c0 * y[0] + c1 * y[1] + c2 * y[2] + (use_e ? c3 * y[3] : 0.0));
     };
 
-    const double zero5[5] = {0, 0, 0, 0, 0};
-    double phi = solve(false, 0.0, zero5);
+    double phi[N], y[4];
+    const double zero5[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    solve(false, zero5, 0.0, y);
+#pragma unroll
+    for (int j = 0; j < N; ++j)
+        phi[j] = ph[j] - (tab[O::L0 + j] * s0 * y[0] + tab[O::L1 + j] * s1 * y[1] +
+                          (A.dx * tab[O::W + j]) * s2 * y[2]);
+
     int iters = 0;
-    bool done = !(energy && live);
     bool conv = false;
-    if (energy) {
+    if (energy && live) {
+        // Picard on the energy row (section "Local energy conservation");
+        // HARD with a mass row: energy row orthogonalised against the mass
+        // row (same constraint set); stop below tol, or on a 2-cycle
         const bool center = (A.mode == SL_MODE_HARD) && mass;
-        double older = phi;
-        const double Et0 = d[3];
+        double older[N];
+#pragma unroll
+        for (int j = 0; j < N; ++j) older[j] = phi[j];
         for (int k = 1; k <= A.emaxit; ++k) {
-            if (__syncthreads_and(done)) break;
-            double c3 = W_i * phi;
+            double mu = 0.0;
             if (center) {
-                // energy row orthogonal to the mass row (same constraint set)
-                if (inblk) s_r[0][slot][i] = c3 * c2;
-                __syncthreads();
                 double gw = 0.0;
 #pragma unroll
-                for (int j = 0; j < N; ++j) gw += s_r[0][sl][j];
-                __syncthreads();
-                const double mu = gw / A.g22;
-                c3 -= mu * c2;
-                d[3] = Et0 - mu * Mt;
+                for (int j = 0; j < N; ++j) {
+                    const double Wj = A.dx * tab[O::W + j];
+                    gw += (Wj * phi[j]) * Wj;
+                }
+                mu = gw / A.g22;
             }
-            if (inblk) {
-                s_r[0][slot][i] = c3 * c0;
-                s_r[1][slot][i] = c3 * c1;
-                s_r[2][slot][i] = c3 * c2;
-                s_r[3][slot][i] = c3 * c3;
-                s_r[4][slot][i] = c3 * ph;
-            }
-            __syncthreads();
-            double red[5] = {0, 0, 0, 0, 0};
+            double red[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int j = 0; j < N; ++j) {
-#pragma unroll
-                for (int r = 0; r < 5; ++r) red[r] += s_r[r][sl][j];
+                const double Wj = A.dx * tab[O::W + j];
+                const double c3 = Wj * phi[j] - mu * Wj;
+                red[0] += c3 * tab[O::L0 + j];
+                red[1] += c3 * tab[O::L1 + j];
+                red[2] += c3 * Wj;
+                red[3] += c3 * c3;
+                red[4] += c3 * ph[j];
             }
-            __syncthreads();
-            const double nphi = solve(true, c3, red);
-            if (inblk) {
-                s_r[0][slot][i] = fabs(nphi - phi);
-                s_r[1][slot][i] = fabs(nphi - older);
-            }
-            __syncthreads();
+            solve(true, red, Et - mu * Mt, y);
             double diff = 0.0, back = 0.0;
 #pragma unroll
             for (int j = 0; j < N; ++j) {
-                diff = fmax(diff, s_r[0][sl][j]);
-                back = fmax(back, s_r[1][sl][j]);
+                const double Wj = A.dx * tab[O::W + j];
+                const double c3 = Wj * phi[j] - mu * Wj;
+                const double nv = ph[j] - (tab[O::L0 + j] * s0 * y[0] + tab[O::L1 + j] * s1 * y[1] +
+                                           Wj * s2 * y[2] + c3 * y[3]);
+                diff = fmax(diff, fabs(nv - phi[j]));
+                back = fmax(back, fabs(nv - older[j]));
+                older[j] = phi[j];
+                phi[j] = nv;
             }
-            __syncthreads();
-            if (!done) {
-                older = phi;
-                phi = nphi;
-                iters = k;
-                if (diff < A.etol) {
-                    done = true;
-                    conv = true;
-                } else if (k >= 2 && back < A.etol) {
-                    done = true;  // 2-cycle: further sweeps repeat
-                }
+            iters = k;
+            if (diff < A.etol) {
+                conv = true;
+                break;
             }
+            if (k >= 2 && back < A.etol) break;  // 2-cycle: further sweeps repeat
         }
     }
 
     // residuals of the rows actually imposed
-    if (inblk) {
-        s_r[0][slot][i] = tab[O::L0 + i] * phi;
-        s_r[1][slot][i] = tab[O::L1 + i] * phi;
-        s_r[2][slot][i] = W_i * phi;
-        s_r[3][slot][i] = W_i * phi * phi;
+    double r0 = 0.0, r1 = 0.0, r2 = 0.0, r3 = 0.0;
+    bool finite = true;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        const double Wj = A.dx * tab[O::W + j];
+        r0 += tab[O::L0 + j] * phi[j];
+        r1 += tab[O::L1 + j] * phi[j];
+        r2 += Wj * phi[j];
+        r3 += Wj * phi[j] * phi[j];
+        finite = finite && isfinite(phi[j]);
     }
-    __syncthreads();
+    double rb = (live && bnd) ? fmax(fabs(r0 - dB0), fabs(r1 - dB1)) : 0.0;
+    double rm = (live && mass) ? fabs(r2 - Mt) : 0.0;
+    double re = (live && energy) ? fabs(r3 - Et) : 0.0;
+    double pic = live ? (double)iters : 0.0;
     int fl = 0;
     if (live) {
-        double r0 = 0, r1 = 0, r2 = 0, r3 = 0;
-#pragma unroll
-        for (int j = 0; j < N; ++j) {
-            r0 += s_r[0][slot][j];
-            r1 += s_r[1][slot][j];
-            r2 += s_r[2][slot][j];
-            r3 += s_r[3][slot][j];
-        }
-        if (i == 0) {
-            const double rb = bnd ? fmax(fabs(r0 - dB0), fabs(r1 - dB1)) : 0.0;
-            const double rm = mass ? fabs(r2 - Mt) : 0.0;
-            const double re = energy ? fabs(r3 - Et) : 0.0;
-            atomicMax(&s_stat[0], (unsigned long long)__double_as_longlong(rb));
-            atomicMax(&s_stat[1], (unsigned long long)__double_as_longlong(rm));
-            atomicMax(&s_stat[2], (unsigned long long)__double_as_longlong(re));
-            atomicMax(&s_stat[3], (unsigned long long)iters);
-            if (energy && !conv && A.etol > 0.0) fl |= FLAG_NOCONV;
-        }
+        if (energy && !conv && A.etol > 0.0) fl |= FLAG_NOCONV;
         if (singular) fl |= FLAG_SINGULAR;
-        if (!isfinite(phi)) fl |= FLAG_NONFINITE;
-        A.phi_out[g] = phi;
+        if (!finite) fl |= FLAG_NONFINITE;
     }
-    if (fl) atomicOr(&s_flag, fl);
-    __syncthreads();
-    if (t == 0) {
-        if (s_flag) A.flag_part[gridDim.x + blockIdx.x] |= s_flag;
-        double* sp = A.stat_part + (size_t)blockIdx.x * kStatSlots;
+    // wave reductions (the block is one wave)
 #pragma unroll
-        for (int k = 0; k < 3; ++k) sp[k] = fmax(sp[k], __longlong_as_double((long long)s_stat[k]));
-        sp[3] = fmax(sp[3], (double)s_stat[3]);
+    for (int off = 32; off >= 1; off >>= 1) {
+        rb = fmax(rb, __shfl_xor(rb, off));
+        rm = fmax(rm, __shfl_xor(rm, off));
+        re = fmax(re, __shfl_xor(re, off));
+        pic = fmax(pic, __shfl_xor(pic, off));
+        fl |= __shfl_xor(fl, off);
+    }
+
+    // coalesced store of phi^{n+1}
+    if (live) {
+#pragma unroll
+        for (int j = 0; j < N; ++j) s_buf[t * N + j] = phi[j];
+    }
+    __syncthreads();
+    for (int k = t; k < cnt; k += kConBlock) A.phi_out[(size_t)e0 * N + k] = s_buf[k];
+    if (t == 0) {
+        if (fl) A.flag_part[A.nblk + blockIdx.x] |= fl;
+        double* sp = A.stat_part + (size_t)blockIdx.x * kStatSlots;
+        sp[0] = fmax(sp[0], rb);
+        sp[1] = fmax(sp[1], rm);
+        sp[2] = fmax(sp[2], re);
+        sp[3] = fmax(sp[3], pic);
     }
 }
 
@@ -654,7 +641,7 @@ int launch_prep_n(int K, int periodic, int has_div, const double* aN, double* aM
 template <int N>
 int launch_adv_n(const Step1DArgs& A, hipStream_t s)
 {
-    constexpr int E = kBlock / N;
+    constexpr int E = kBlock / (N + 1);
     dim3 grid((A.K + E - 1) / E);
     if (A.cons) hipLaunchKernelGGL((k_advect1d<N, true>), grid, dim3(kBlock), 0, s, A);
     else hipLaunchKernelGGL((k_advect1d<N, false>), grid, dim3(kBlock), 0, s, A);
@@ -664,28 +651,19 @@ int launch_adv_n(const Step1DArgs& A, hipStream_t s)
 template <int N>
 int launch_con_n(const Step1DArgs& A, hipStream_t s)
 {
-    constexpr int E = kBlock / N;
-    dim3 grid((A.K + E - 1) / E);
-    hipLaunchKernelGGL(k_constrain1d<N>, grid, dim3(kBlock), 0, s, A);
+    dim3 grid((A.K + kConBlock - 1) / kConBlock);
+    hipLaunchKernelGGL(k_constrain1d<N>, grid, dim3(kConBlock), 0, s, A);
     return hipGetLastError() == hipSuccess ? 0 : 1;
 }
-
-#define SL_DISPATCH_1D(n, CALL)                                                                                 \
-    switch (n) {                                                                                                \
-    case 2: return CALL<2>; case 3: return CALL<3>; case 4: return CALL<4>; case 5: return CALL<5>;             \
-    case 6: return CALL<6>; case 7: return CALL<7>; case 8: return CALL<8>; case 9: return CALL<9>;             \
-    case 10: return CALL<10>; case 11: return CALL<11>; case 12: return CALL<12>; case 13: return CALL<13>;     \
-    case 14: return CALL<14>; case 15: return CALL<15>; case 16: return CALL<16>; case 17: return CALL<17>;     \
-    default: return 1;                                                                                          \
-    }
 
 }  // namespace
 
 int blocks1d(int n, int K)
 {
     if (n < 2 || n > kMax1D) return 0;
-    const int E = kBlock / n;
-    return (K + E - 1) / E;
+    const int E = kBlock / (n + 1);
+    const int a = (K + E - 1) / E, c = (K + kConBlock - 1) / kConBlock;
+    return a > c ? a : c;
 }
 
 #define PREP_CALL(N) launch_prep_n<N>(K, periodic, has_div, aN, aM, divN, divM, vface, tab, dx, s)

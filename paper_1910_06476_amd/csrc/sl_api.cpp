@@ -331,7 +331,7 @@ sl_status sl_step(sl_mesh* m, double dt, int32_t nsteps, const sl_step_opts* o)
     rk_tableau(opt.rk, &A.rk);
     A.aN = m->aN; A.aM = m->aM; A.divN = m->divN; A.divM = m->divM; A.vface = m->vface; A.tab = m->tab;
     A.rec = m->rec; A.phihat = m->phihat;
-    A.flag_part = m->flag_part; A.stat_part = m->stat_part;
+    A.flag_part = m->flag_part; A.stat_part = m->stat_part; A.nblk = m->nblocks;
     A.K = m->K; A.periodic = m->bc == SL_BC_PERIODIC; A.cons = m->form == SL_FORM_CONSERVATIVE;
     A.cmask = opt.constraints; A.mode = opt.mode; A.emaxit = opt.energy_maxit; A.etol = opt.energy_tol;
     A.targets = (opt.constraints & (SL_C_MASS | SL_C_ENERGY)) != 0;

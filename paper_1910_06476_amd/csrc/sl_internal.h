@@ -62,8 +62,9 @@ struct Step1DArgs {
     const double* tab;
     const double* gnow;    // ghost row at t^n (2 values) or null
     const double* gnext;   // ghost row at t^{n+1}
-    int32_t* flag_part;    // [2][nblocks]
-    double* stat_part;     // [nblocks][kStatSlots]
+    int32_t* flag_part;    // [2][nblk]
+    double* stat_part;     // [nblk][kStatSlots]
+    int nblk;
     int K, periodic, cons, cmask, mode, emaxit, vol, targets;
     double dx, dt, etol, vzero;
     double g00, g01, g11, g02, g12, g22;  // constant Gram entries of rows l(0), l(1), W

@@ -88,10 +88,14 @@ def energy_kappa(w, phi):
     return np.linalg.norm(g, axis=1) / np.maximum(np.linalg.norm(gp, axis=1), 1e-300)
 
 
-def assert_parity(w, g, o, cmask=None, mode=None, tol=1e-12, elems=None):
+def assert_parity(w, g, o, cmask=None, mode=None, tol=1e-12, elems=None, solves=None):
     """GPU-vs-oracle parity.  Without a HARD energy row: relative L2 <= tol.
-    With one (and a mass row): element-wise
-    |g_e - o_e|_max <= max(tol, 64 eps kappa_e) |o_e|_max."""
+    With one (and a mass row) each energy-constrained solve is exact only to
+    about eps * kappa_e, and these errors add up over the Picard sweeps and
+    the steps (the sweep map has an eigenvalue near -1, so they are neither
+    damped nor amplified); element-wise bound
+    |g_e - o_e|_max <= max(tol, 64 eps kappa_e * solves) |o_e|_max,
+    solves = steps * sweeps (default from the workload)."""
     cmask = w.cmask if cmask is None else cmask
     mode = w.mode if mode is None else mode
     G = np.asarray(g).reshape(w.K, w.nd)
@@ -106,7 +110,9 @@ def assert_parity(w, g, o, cmask=None, mode=None, tol=1e-12, elems=None):
     k = energy_kappa(w, o)
     if elems is not None:
         k = k[elems]
-    bound = np.maximum(tol, 64 * EPS * k) * np.maximum(np.abs(O).max(1), 1e-300)
+    if solves is None:
+        solves = max(1, w.nsteps) * max(1, w.energy_maxit)
+    bound = np.maximum(tol, 64 * EPS * k * solves) * np.maximum(np.abs(O).max(1), 1e-300)
     e = np.abs(G - O).max(1)
     bad = np.nonzero(e > bound)[0]
     assert bad.size == 0, f"{bad.size} elements above the conditioning bound, worst ratio {np.max(e / bound):.2f}"
