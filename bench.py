@@ -30,11 +30,13 @@ FP64_VALU_PEAK = 78.6e12   # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz (FMA 
 HBM_PEAK = 8.0e12
 
 
-def advect_flops_per_element(n: int, s: int, nq: int, targets: bool) -> float:
+def advect_flops_per_element(n: int, s: int, nq: int, targets: bool, vel_terms: int) -> float:
     """Algorithmic FP64 flops of the 1D advect kernel for one element (FMA = 2):
-    Clenshaw evaluation 3 flops per term; RK stage update ~4 flops per stage."""
+    Clenshaw evaluation 3 flops per term (vel_terms terms for the velocity
+    series, n for phi^n); RK stage update ~4 flops per stage."""
     clen = 3.0 * n
-    rk_move = (s - 1) * clen + 4.0 * s
+    clen_v = 3.0 * vel_terms
+    rk_move = (s - 1) * clen_v + 4.0 * s
     f = n * rk_move                      # forward motion of the n particles
     f += n * (2.0 * n)                   # moved-point weights lambda*: n-1 (sub, mul) + div
     f += n * (5.0 * n) + 2 * 5.0 * n     # remap at n nodes + 2 edge traces (product form)
@@ -58,6 +60,22 @@ def constrain_bytes_per_element(n: int) -> float:
     """read phihat, the element record (neighbours' are cache hits), two face
     velocities; write phi."""
     return 8.0 * n + 64.0 + 8.0 + 8.0 * n
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    summary, or None if the kernel source changed since it was taken."""
+    import hashlib
+    src = os.path.join(ROOT, "paper_1910_06476_amd", "csrc", "sl1d.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    path = os.path.join(ROOT, "profiles", "sl1d_c2_K65536_n17.md")
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        parts = line.split()
+        if len(parts) == 4 and parts[0] == "traffic" and parts[1] == kernel and parts[3] == f"sl1d.hip:{sha}":
+            return float(parts[2])
+    return None
 
 
 def cpu_baseline(w, budget_s: float = 12.0):
@@ -137,21 +155,22 @@ def main():
     s_stages = 4
     nq = 3
     targets = True
-    fl = advect_flops_per_element(w.n, s_stages, nq, targets) * w.K
+    fl = advect_flops_per_element(w.n, s_stages, nq, targets, st.vel_terms) * w.K
     by = advect_bytes_per_element(w.n, targets) * w.K
     adv_avg = t_adv / max(c_adv, 1) * 1e-3
     con_avg = t_con / max(c_con, 1) * 1e-3
     if adv_avg >= con_avg:
         ach = fl / adv_avg
         roof = {"kernel": "sl1d_advect", "bound": "alu", "achieved": ach / 1e12, "peak": FP64_VALU_PEAK / 1e12,
-                "unit": "TFLOP/s", "frac": ach / FP64_VALU_PEAK, "traffic": None,
+                "unit": "TFLOP/s", "frac": ach / FP64_VALU_PEAK, "traffic": measured_traffic("k_advect1d"),
                 "avg_launch_us": adv_avg * 1e6, "algorithmic_flops_per_launch": fl,
-                "algorithmic_bytes_per_launch": by}
+                "algorithmic_bytes_per_launch": by, "velocity_series_terms": st.vel_terms}
     else:
         cb = constrain_bytes_per_element(w.n) * w.K
         ach = cb / con_avg
         roof = {"kernel": "sl1d_constrain", "bound": "hbm", "achieved": ach / 1e9, "peak": HBM_PEAK / 1e9,
-                "unit": "GB/s", "frac": ach / HBM_PEAK, "traffic": None, "avg_launch_us": con_avg * 1e6,
+                "unit": "GB/s", "frac": ach / HBM_PEAK, "traffic": measured_traffic("k_constrain1d"),
+                "avg_launch_us": con_avg * 1e6,
                 "algorithmic_bytes_per_launch": cb}
     roof["kernels_us"] = {"sl1d_advect": adv_avg * 1e6, "sl1d_constrain": con_avg * 1e6}
 

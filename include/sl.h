@@ -97,7 +97,11 @@ typedef struct {
  *             least-squares sense, the corner dependencies make it nonzero)
  *   max_picard largest number of energy-row solves in one element and step
  *   flags     bit0 non-finite, bit1 particle left element, bit2 singular
- *             system, bit3 Picard not converged */
+ *             system, bit3 Picard not converged
+ *   vel_terms number of Chebyshev terms of the velocity series the kernels
+ *             evaluate (trailing terms below 2^-46 of the series' absolute
+ *             sum -- the rounding noise of the nodal-to-modal transform --
+ *             are skipped) */
 typedef struct {
     double t;
     int64_t steps;
@@ -106,6 +110,8 @@ typedef struct {
     double refine_resid;
     int32_t max_picard;
     int32_t flags;
+    int32_t vel_terms;
+    int32_t reserved;
 } sl_stats;
 
 typedef struct sl_mesh sl_mesh;

@@ -51,7 +51,8 @@ class Stats(ctypes.Structure):
     _fields_ = [("t", ctypes.c_double), ("steps", ctypes.c_int64), ("mass", ctypes.c_double),
                 ("energy", ctypes.c_double), ("resid_boundary", ctypes.c_double),
                 ("resid_mass", ctypes.c_double), ("resid_energy", ctypes.c_double),
-                ("refine_resid", ctypes.c_double), ("max_picard", ctypes.c_int32), ("flags", ctypes.c_int32)]
+                ("refine_resid", ctypes.c_double), ("max_picard", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("vel_terms", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def asdict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

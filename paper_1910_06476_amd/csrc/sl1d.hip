@@ -27,6 +27,22 @@ constexpr int kBlock = 256;
 
 __device__ __forceinline__ bool outside(double s) { return s < -1e-10 || s > 1.0 + 1e-10; }
 
+// sum_{k < M} c_k T_k(x) by Clenshaw's recurrence (the first M of N terms)
+template <int N, int M>
+__device__ __forceinline__ double clenshaw_n(const double (&c)[N], double x)
+{
+    static_assert(M >= 1 && M <= N, "term count");
+    double b1 = 0.0, b2 = 0.0;
+    const double x2 = 2.0 * x;
+#pragma unroll
+    for (int k = M - 1; k >= 1; --k) {
+        double b0 = fma(x2, b1, c[k] - b2);
+        b2 = b1;
+        b1 = b0;
+    }
+    return fma(x, b1, c[0] - b2);
+}
+
 template <int N>
 __device__ __forceinline__ double clenshaw(const double (&c)[N], double x)
 {
@@ -41,10 +57,35 @@ __device__ __forceinline__ double clenshaw(const double (&c)[N], double x)
     return fma(x, b1, c[0] - b2);
 }
 
+// Effective degree of a Chebyshev series: the largest k whose tail
+// sum_{j >= k} |c_j| exceeds 2^-46 (1.4e-14) of sum_j |c_j|.  Coefficients
+// obtained from nodal values carry rounding noise of about 1e-16 sum|c|
+// each; a tail below this threshold is that noise, and skipping it moves
+// the evaluated series by no more than its own rounding error.
+template <int N>
+__device__ __forceinline__ int cheb_degree(const double (&c)[N])
+{
+    double tot = 0.0;
+#pragma unroll
+    for (int k = 0; k < N; ++k) tot += fabs(c[k]);
+    const double thr = tot * 0x1p-46;
+    double tail = 0.0;
+    int d = 0;
+#pragma unroll
+    for (int k = N - 1; k >= 1; --k) {
+        tail += fabs(c[k]);
+        if (d == 0 && tail > thr) d = k;
+    }
+    return d;
+}
+
 // One explicit RK step of length h for (s, q): ds/dt = dir * u(s) / dx and,
 // in the conservative form, dq/dt = -div(s) q.  When have_first is set the
 // first stage uses the given (nodal) values instead of an evaluation.
-template <int N, bool CONS>
+// (NA: number of leading Chebyshev coefficients of the velocity and
+// divergence series that are evaluated; the rest are negligible, see
+// cheb_degree)
+template <int N, bool CONS, int NA = N>
 __device__ __forceinline__ void rk_move(const RKTab& T, const double (&ca)[N], const double (&cd)[N], double dir,
                                         double h, double invdx, double& s, double& q, bool& out, bool have_first,
                                         double u_first, double dv_first)
@@ -68,8 +109,8 @@ __device__ __forceinline__ void rk_move(const RKTab& T, const double (&ca)[N], c
                 dv = dv_first;
             } else {
                 const double x = 2.0 * ss - 1.0;
-                u = clenshaw<N>(ca, x);
-                if (CONS) dv = clenshaw<N>(cd, x);
+                u = clenshaw_n<N, NA>(ca, x);
+                if (CONS) dv = clenshaw_n<N, NA>(cd, x);
                 out |= outside(ss);
             }
             ks[st] = dir * u * invdx;
@@ -107,7 +148,7 @@ template <int N> struct Off {
 template <int N>
 __global__ void k_prep1d(int K, int periodic, int has_div, const double* __restrict__ aN, double* __restrict__ aM,
                          double* __restrict__ divN, double* __restrict__ divM, double* __restrict__ vface,
-                         const double* __restrict__ tab, double invdx)
+                         const double* __restrict__ tab, double invdx, int cons, int* __restrict__ vdeg)
 {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= K) return;
@@ -141,6 +182,19 @@ __global__ void k_prep1d(int K, int periodic, int has_div, const double* __restr
         for (int j = 0; j < N; ++j) c = fma(tab[O::TINV + k * N + j], dv[j], c);
         divM[(size_t)e * N + k] = c;
     }
+    // effective degree of the velocity (and divergence) series
+    {
+        double c[N], cdv[N];
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            c[k] = aM[(size_t)e * N + k];
+            cdv[k] = divM[(size_t)e * N + k];
+        }
+        // the divergence series is evaluated off the nodes only in the
+        // conservative form
+        const int d = cons ? max(cheb_degree<N>(c), cheb_degree<N>(cdv)) : cheb_degree<N>(c);
+        atomicMax(vdeg, d);
+    }
     // face e sits between elements e-1 and e: mean of both sides' values
     double mine = 0.0;
 #pragma unroll
@@ -171,7 +225,7 @@ __global__ void k_prep1d(int K, int periodic, int has_div, const double* __restr
 // instruction stream as the node lanes' backtraces from the nodes, and the
 // edge traces of the remapped polynomial while the node lanes remap.
 // ---------------------------------------------------------------------------
-template <int N, bool CONS>
+template <int N, bool CONS, int NA>
 __global__ __launch_bounds__(kBlock) void k_advect1d(Step1DArgs A)
 {
     constexpr int L = N + 1;
@@ -200,7 +254,7 @@ __global__ __launch_bounds__(kBlock) void k_advect1d(Step1DArgs A)
 
     const double xi_i = tab[O::XI + in];
     const double W_i = A.dx * tab[O::W + in];
-    const double invdx = 1.0 / A.dx;
+    const double invdx = A.invdx;
     double phi_i = 0.0, a_i = 0.0, dv_i = 0.0;
     if (live && node) {
         phi_i = A.phi[g];
@@ -221,25 +275,23 @@ __global__ __launch_bounds__(kBlock) void k_advect1d(Step1DArgs A)
     }
     __syncthreads();
 
-    double ca[N], cd[N];
+    double ca[N], cd[N], cp[N];
 #pragma unroll
     for (int k = 0; k < N; ++k) {
         ca[k] = s_a[sl][k];
         cd[k] = CONS ? s_d[sl][k] : 0.0;
+        cp[k] = A.targets ? s_q[sl][k] : 0.0;
     }
     bool out = false;
     // forward motion of particle i (section 4.2)
     double s = xi_i, q = phi_i;
-    if (node) rk_move<N, CONS>(A.rk, ca, cd, 1.0, A.dt, invdx, s, q, out, true, a_i, dv_i);
+    if (node) rk_move<N, CONS, NA>(A.rk, ca, cd, 1.0, A.dt, invdx, s, q, out, true, a_i, dv_i);
 
     // element-local target parts: M^n, E^n, volume term at the RK abscissae
     // (node lanes), edge values at the RK abscissae on the upwind edges (edge
     // lane); backtracking as in eq. 4.11
     double vM = 0.0, vE = 0.0, FM[2] = {0.0, 0.0}, FE[2] = {0.0, 0.0};
     if (A.targets) {
-        double cp[N];
-#pragma unroll
-        for (int k = 0; k < N; ++k) cp[k] = s_q[sl][k];
         int first = -1, second = -1;
         if (!node && live) {
             const double vL = A.vface[e];
@@ -260,7 +312,7 @@ __global__ __launch_bounds__(kBlock) void k_advect1d(Step1DArgs A)
                     val = node ? phi_i : clenshaw<N>(cp, 2.0 * x0 - 1.0);
                 } else {
                     double sb = x0, hq = 1.0;
-                    rk_move<N, CONS>(A.rk, ca, cd, -1.0, cq * A.dt, invdx, sb, hq, out, node, a_i, dv_i);
+                    rk_move<N, CONS, NA>(A.rk, ca, cd, -1.0, cq * A.dt, invdx, sb, hq, out, node, a_i, dv_i);
                     val = hq * clenshaw<N>(cp, 2.0 * sb - 1.0);
                 }
                 const double bq = A.rk.bu[qd];
@@ -630,21 +682,32 @@ __global__ __launch_bounds__(kConBlock) void k_constrain1d(Step1DArgs A)
 
 template <int N>
 int launch_prep_n(int K, int periodic, int has_div, const double* aN, double* aM, double* divN, double* divM,
-                  double* vface, const double* tab, double dx, hipStream_t s)
+                  double* vface, const double* tab, double dx, int cons, int* vdeg, hipStream_t s)
 {
     const int bs = 128;
     hipLaunchKernelGGL(k_prep1d<N>, dim3((K + bs - 1) / bs), dim3(bs), 0, s, K, periodic, has_div, aN, aM, divN,
-                       divM, vface, tab, 1.0 / dx);
+                       divM, vface, tab, 1.0 / dx, cons, vdeg);
     return hipGetLastError() == hipSuccess ? 0 : 1;
 }
 
+template <int N, int NA>
+void launch_adv_na(const Step1DArgs& A, dim3 grid, hipStream_t s)
+{
+    if (A.cons) hipLaunchKernelGGL((k_advect1d<N, true, NA>), grid, dim3(kBlock), 0, s, A);
+    else hipLaunchKernelGGL((k_advect1d<N, false, NA>), grid, dim3(kBlock), 0, s, A);
+}
+
+// velocity series evaluated with 4, 8 or all n Chebyshev terms: the fewest
+// that cover the mesh-wide effective degree
 template <int N>
 int launch_adv_n(const Step1DArgs& A, hipStream_t s)
 {
     constexpr int E = kBlock / (N + 1);
     dim3 grid((A.K + E - 1) / E);
-    if (A.cons) hipLaunchKernelGGL((k_advect1d<N, true>), grid, dim3(kBlock), 0, s, A);
-    else hipLaunchKernelGGL((k_advect1d<N, false>), grid, dim3(kBlock), 0, s, A);
+    const int need = A.vdeg + 1;
+    if (N > 4 && need <= 4) launch_adv_na<N, (N > 4 ? 4 : N)>(A, grid, s);
+    else if (N > 8 && need <= 8) launch_adv_na<N, (N > 8 ? 8 : N)>(A, grid, s);
+    else launch_adv_na<N, N>(A, grid, s);
     return hipGetLastError() == hipSuccess ? 0 : 1;
 }
 
@@ -666,9 +729,9 @@ int blocks1d(int n, int K)
     return a > c ? a : c;
 }
 
-#define PREP_CALL(N) launch_prep_n<N>(K, periodic, has_div, aN, aM, divN, divM, vface, tab, dx, s)
+#define PREP_CALL(N) launch_prep_n<N>(K, periodic, has_div, aN, aM, divN, divM, vface, tab, dx, cons, vdeg, s)
 int launch_prep1d(int n, int K, int periodic, int has_div, const double* aN, double* aM, double* divN,
-                  double* divM, double* vface, const double* tab, double dx, hipStream_t s)
+                  double* divM, double* vface, const double* tab, double dx, int cons, int* vdeg, hipStream_t s)
 {
     switch (n) {
     case 2: return PREP_CALL(2); case 3: return PREP_CALL(3); case 4: return PREP_CALL(4);

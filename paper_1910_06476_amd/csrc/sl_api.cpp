@@ -23,7 +23,9 @@ struct sl_mesh {
     // device buffers
     double *phi, *phi2, *phihat, *rec, *eloc, *aN, *aM, *divN, *divM, *vface, *tab, *ghost, *stat_part;
     int32_t* flag_part;
+    int32_t* vdeg_d;
     int nblocks;
+    int vdeg;
     // host state
     bool has_velocity;
     double amax[2];
@@ -40,6 +42,16 @@ struct sl_mesh {
 
 namespace {
 
+// number of velocity series terms the 1D advect kernel evaluates (mirrors
+// the choice in launch_adv_n: 4, 8 or all n)
+int vel_terms_used(const sl_mesh* m)
+{
+    const int need = m->vdeg + 1, n = m->n;
+    if (n > 4 && need <= 4) return 4;
+    if (n > 8 && need <= 8) return 8;
+    return n;
+}
+
 template <typename T>
 void dfree(T*& p)
 {
@@ -51,7 +63,7 @@ void release(sl_mesh* m)
 {
     dfree(m->phi); dfree(m->phi2); dfree(m->phihat); dfree(m->rec); dfree(m->eloc); dfree(m->aN);
     dfree(m->aM); dfree(m->divN); dfree(m->divM); dfree(m->vface); dfree(m->tab); dfree(m->ghost);
-    dfree(m->stat_part); dfree(m->flag_part);
+    dfree(m->stat_part); dfree(m->flag_part); dfree(m->vdeg_d);
     for (int k = 0; k < KER_COUNT; ++k)
         for (hipEvent_t e : m->pending[k]) (void)hipEventDestroy(e);
     if (m->own_stream && m->stream) (void)hipStreamDestroy(m->stream);
@@ -202,7 +214,7 @@ sl_status sl_create_mesh(const sl_mesh_desc* d, sl_mesh** out)
               dalloc(&m->rec, (size_t)m->K * 8) && dalloc(&m->aN, nf) && dalloc(&m->aM, nf) &&
               dalloc(&m->divN, nf) && dalloc(&m->divM, nf) && dalloc(&m->vface, (size_t)m->K + 1) &&
               dalloc(&m->tab, (size_t)m->off.total) && dalloc(&m->stat_part, (size_t)m->nblocks * kStatSlots) &&
-              dalloc(&m->flag_part, (size_t)2 * m->nblocks);
+              dalloc(&m->flag_part, (size_t)2 * m->nblocks) && dalloc(&m->vdeg_d, 1);
     if (!ok) { release(m); delete m; return SL_E_NOMEM; }
 
     std::vector<double> tab(m->off.total, 0.0);
@@ -247,9 +259,14 @@ sl_status sl_set_velocity(sl_mesh* m, const double* a, const double* div_a)
     if (hipMemcpyAsync(m->aN, a, nf * m->dim * sizeof(double), hipMemcpyHostToDevice, m->stream)) return SL_E_DEVICE;
     if (div_a && hipMemcpyAsync(m->divN, div_a, nf * sizeof(double), hipMemcpyHostToDevice, m->stream))
         return SL_E_DEVICE;
+    if (hipMemsetAsync(m->vdeg_d, 0, sizeof(int32_t), m->stream)) return SL_E_DEVICE;
     int rc = launch_prep1d(m->n, m->K, m->bc == SL_BC_PERIODIC, div_a != nullptr, m->aN, m->aM, m->divN, m->divM,
-                           m->vface, m->tab, m->dx, m->stream);
-    if (rc || hipStreamSynchronize(m->stream)) return SL_E_DEVICE;
+                           m->vface, m->tab, m->dx, m->form == SL_FORM_CONSERVATIVE, m->vdeg_d, m->stream);
+    int32_t vdeg = m->n - 1;
+    if (rc || hipMemcpyAsync(&vdeg, m->vdeg_d, sizeof(int32_t), hipMemcpyDeviceToHost, m->stream) ||
+        hipStreamSynchronize(m->stream))
+        return SL_E_DEVICE;
+    m->vdeg = vdeg;
     m->amax[0] = am[0];
     m->amax[1] = am[1];
     m->has_velocity = true;
@@ -331,12 +348,12 @@ sl_status sl_step(sl_mesh* m, double dt, int32_t nsteps, const sl_step_opts* o)
     rk_tableau(opt.rk, &A.rk);
     A.aN = m->aN; A.aM = m->aM; A.divN = m->divN; A.divM = m->divM; A.vface = m->vface; A.tab = m->tab;
     A.rec = m->rec; A.phihat = m->phihat;
-    A.flag_part = m->flag_part; A.stat_part = m->stat_part; A.nblk = m->nblocks;
+    A.flag_part = m->flag_part; A.stat_part = m->stat_part; A.nblk = m->nblocks; A.vdeg = m->vdeg;
     A.K = m->K; A.periodic = m->bc == SL_BC_PERIODIC; A.cons = m->form == SL_FORM_CONSERVATIVE;
     A.cmask = opt.constraints; A.mode = opt.mode; A.emaxit = opt.energy_maxit; A.etol = opt.energy_tol;
     A.targets = (opt.constraints & (SL_C_MASS | SL_C_ENERGY)) != 0;
     A.vol = A.targets;
-    A.dx = m->dx; A.dt = dt;
+    A.dx = m->dx; A.invdx = 1.0 / m->dx; A.dt = dt;
     A.vzero = 1e-12 * m->amax[0];
     double g[6];
     gram1d(m, g);
@@ -410,6 +427,7 @@ sl_status sl_read(sl_mesh* m, double* u_out, sl_stats* st)
         st->resid_energy = re;
         st->max_picard = (int32_t)pic;
         st->flags = flags;
+        st->vel_terms = vel_terms_used(m);
     }
     (void)hipMemsetAsync(m->stat_part, 0, sp.size() * sizeof(double), m->stream);
     (void)hipMemsetAsync(m->flag_part, 0, fp.size() * sizeof(int32_t), m->stream);

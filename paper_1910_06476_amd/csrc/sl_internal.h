@@ -65,14 +65,15 @@ struct Step1DArgs {
     int32_t* flag_part;    // [2][nblk]
     double* stat_part;     // [nblk][kStatSlots]
     int nblk;
+    int vdeg;              // mesh-wide effective degree of the velocity series
     int K, periodic, cons, cmask, mode, emaxit, vol, targets;
-    double dx, dt, etol, vzero;
+    double dx, invdx, dt, etol, vzero;
     double g00, g01, g11, g02, g12, g22;  // constant Gram entries of rows l(0), l(1), W
     RKTab rk;
 };
 
 int launch_prep1d(int n, int K, int periodic, int has_div, const double* aN, double* aM, double* divN,
-                  double* divM, double* vface, const double* tab, double dx, hipStream_t s);
+                  double* divM, double* vface, const double* tab, double dx, int cons, int* vdeg, hipStream_t s);
 int launch_advect1d(int n, const Step1DArgs& A, hipStream_t s);
 int launch_constrain1d(int n, const Step1DArgs& A, hipStream_t s);
 int blocks1d(int n, int K);
