@@ -64,8 +64,10 @@ enum { SL_MODE_HARD = 0, SL_MODE_SOFT = 1 };
  *   nodes      SL_NODES_GL (default) or SL_NODES_CG (paper, eq. gaussquad)
  *   bc         SL_BC_PERIODIC, or SL_BC_GHOST (inflow values from sl_set_ghost)
  *   form       SL_FORM_ADVECTIVE or SL_FORM_CONSERVATIVE
- *   precision  SL_PREC_FP64, or SL_PREC_FP32_REFINED (2D only: remap solve
- *              factored in FP32, corrected by FP64 residual refinement)
+ *   precision  SL_PREC_FP64, or SL_PREC_FP32_REFINED (2D only: the
+ *              preconditioner of the remap solve is stored and applied in
+ *              FP32 while residuals and iterates stay FP64, so the solve
+ *              still converges to the FP64 solution; 1D rejects it)
  *   x0,x1,y0,y1 box (y ignored in 1D), x1 > x0, y1 > y0
  *   u0         host, K * n^dim initial values (layout above)
  *   stream     hipStream_t to run on, or NULL for a stream the mesh creates */
@@ -84,7 +86,8 @@ typedef struct {
  *   mode          SL_MODE_HARD (KKT: rows hold exactly, default) or
  *                 SL_MODE_SOFT (the paper's stacked least squares)
  *   energy_maxit  Picard iterations cap for the energy row (default 50)
- *   refine_steps  FP64 refinement sweeps in SL_PREC_FP32_REFINED (default 3)
+ *   refine_steps  reserved (the remap refinement runs to its own stop test);
+ *                 must be >= 0
  *   energy_tol    Picard stop |phi^(k) - phi^(k-1)|_max < tol (default 1e-8, the
  *                 paper's; 0 = always run energy_maxit iterations) */
 typedef struct {
@@ -98,10 +101,17 @@ typedef struct {
  *   max_picard largest number of energy-row solves in one element and step
  *   flags     bit0 non-finite, bit1 particle left element, bit2 singular
  *             system, bit3 Picard not converged
- *   vel_terms number of Chebyshev terms of the velocity series the kernels
- *             evaluate (trailing terms below 2^-46 of the series' absolute
- *             sum -- the rounding noise of the nodal-to-modal transform --
- *             are skipped) */
+ *   vel_terms number of Chebyshev terms (per direction in 2D) of the
+ *             velocity series the kernels evaluate: trailing terms below
+ *             2^-46 of max(the element series' absolute sum, mesh max |a|)
+ *             -- the rounding noise of the nodal-to-modal transform -- are
+ *             skipped
+ *   refine_resid      2D: largest estimated error left by the iterative
+ *                     remap solve (eq. 5.4): its last correction times the
+ *                     observed contraction, relative to max |phi*| of the
+ *                     element; 0 in 1D
+ *   remap_sweeps_max  2D: most defect-correction sweeps one element needed
+ *   remap_sweeps_mean 2D: sweeps per element and step, averaged */
 typedef struct {
     double t;
     int64_t steps;
@@ -111,7 +121,8 @@ typedef struct {
     int32_t max_picard;
     int32_t flags;
     int32_t vel_terms;
-    int32_t reserved;
+    int32_t remap_sweeps_max;
+    double remap_sweeps_mean;
 } sl_stats;
 
 typedef struct sl_mesh sl_mesh;
@@ -147,10 +158,11 @@ int32_t sl_ghost_count(const sl_mesh* m);
 /* Advance nsteps explicit SL steps of length dt, asynchronously on the
  * mesh's stream.  Validated before any launch (state unchanged on error):
  * SL_E_STATE (no velocity, or ghost mesh without ghost values),
- * SL_E_INVALID (dt <= 0, nsteps < 0, bad options), SL_E_CFL (max |a_d| dt
- * >= gap_d dx_d for some direction d, gap = distance from the element edge
- * to the first node: the paper's time-step restriction, eq. 1d_delt_condition
- * and eq. 2d_delt_condition). */
+ * SL_E_INVALID (dt <= 0, nsteps < 0, bad options; in 2D, mass or energy
+ * rows), SL_E_CFL (max |a_d| dt > gap_d dx_d for some direction d, gap =
+ * distance from the element edge to the first node: the paper's time-step
+ * restriction, eq. 1d_delt_condition and eq. 2d_delt_condition, which admits
+ * equality). */
 sl_status sl_step(sl_mesh* m, double dt, int32_t nsteps, const sl_step_opts* opts);
 
 /* Synchronise the mesh's stream and copy the field to u_out (host, K * n^dim

@@ -52,7 +52,8 @@ class Stats(ctypes.Structure):
                 ("energy", ctypes.c_double), ("resid_boundary", ctypes.c_double),
                 ("resid_mass", ctypes.c_double), ("resid_energy", ctypes.c_double),
                 ("refine_resid", ctypes.c_double), ("max_picard", ctypes.c_int32), ("flags", ctypes.c_int32),
-                ("vel_terms", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("vel_terms", ctypes.c_int32), ("remap_sweeps_max", ctypes.c_int32),
+                ("remap_sweeps_mean", ctypes.c_double)]
 
     def asdict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -58,17 +58,21 @@ __device__ __forceinline__ double clenshaw(const double (&c)[N], double x)
 }
 
 // Effective degree of a Chebyshev series: the largest k whose tail
-// sum_{j >= k} |c_j| exceeds 2^-46 (1.4e-14) of sum_j |c_j|.  Coefficients
-// obtained from nodal values carry rounding noise of about 1e-16 sum|c|
-// each; a tail below this threshold is that noise, and skipping it moves
-// the evaluated series by no more than its own rounding error.
+// sum_{j >= k} |c_j| exceeds 2^-46 (1.4e-14) of max(sum_j |c_j|, scale).
+// Coefficients obtained from nodal values carry rounding noise of about
+// 1e-16 of the nodal magnitudes; a tail below this threshold is that noise,
+// and skipping it moves the evaluated series by no more than its own
+// rounding error.  `scale` is the mesh-wide magnitude of the field (max
+// |a| for the velocity): where the field nearly vanishes in one element,
+// its noise is measured against the field, not against the element's own
+// tiny coefficients.
 template <int N>
-__device__ __forceinline__ int cheb_degree(const double (&c)[N])
+__device__ __forceinline__ int cheb_degree(const double (&c)[N], double scale = 0.0)
 {
     double tot = 0.0;
 #pragma unroll
     for (int k = 0; k < N; ++k) tot += fabs(c[k]);
-    const double thr = tot * 0x1p-46;
+    const double thr = fmax(tot, scale) * 0x1p-46;
     double tail = 0.0;
     int d = 0;
 #pragma unroll
@@ -148,7 +152,8 @@ template <int N> struct Off {
 template <int N>
 __global__ void k_prep1d(int K, int periodic, int has_div, const double* __restrict__ aN, double* __restrict__ aM,
                          double* __restrict__ divN, double* __restrict__ divM, double* __restrict__ vface,
-                         const double* __restrict__ tab, double invdx, int cons, int* __restrict__ vdeg)
+                         const double* __restrict__ tab, double invdx, int cons, double vscale,
+                         int* __restrict__ vdeg)
 {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= K) return;
@@ -192,7 +197,7 @@ __global__ void k_prep1d(int K, int periodic, int has_div, const double* __restr
         }
         // the divergence series is evaluated off the nodes only in the
         // conservative form
-        const int d = cons ? max(cheb_degree<N>(c), cheb_degree<N>(cdv)) : cheb_degree<N>(c);
+        const int d = cons ? max(cheb_degree<N>(c, vscale), cheb_degree<N>(cdv)) : cheb_degree<N>(c, vscale);
         atomicMax(vdeg, d);
     }
     // face e sits between elements e-1 and e: mean of both sides' values
@@ -682,11 +687,11 @@ __global__ __launch_bounds__(kConBlock) void k_constrain1d(Step1DArgs A)
 
 template <int N>
 int launch_prep_n(int K, int periodic, int has_div, const double* aN, double* aM, double* divN, double* divM,
-                  double* vface, const double* tab, double dx, int cons, int* vdeg, hipStream_t s)
+                  double* vface, const double* tab, double dx, int cons, double vscale, int* vdeg, hipStream_t s)
 {
     const int bs = 128;
     hipLaunchKernelGGL(k_prep1d<N>, dim3((K + bs - 1) / bs), dim3(bs), 0, s, K, periodic, has_div, aN, aM, divN,
-                       divM, vface, tab, 1.0 / dx, cons, vdeg);
+                       divM, vface, tab, 1.0 / dx, cons, vscale, vdeg);
     return hipGetLastError() == hipSuccess ? 0 : 1;
 }
 
@@ -729,9 +734,10 @@ int blocks1d(int n, int K)
     return a > c ? a : c;
 }
 
-#define PREP_CALL(N) launch_prep_n<N>(K, periodic, has_div, aN, aM, divN, divM, vface, tab, dx, cons, vdeg, s)
+#define PREP_CALL(N) launch_prep_n<N>(K, periodic, has_div, aN, aM, divN, divM, vface, tab, dx, cons, vscale, vdeg, s)
 int launch_prep1d(int n, int K, int periodic, int has_div, const double* aN, double* aM, double* divN,
-                  double* divM, double* vface, const double* tab, double dx, int cons, int* vdeg, hipStream_t s)
+                  double* divM, double* vface, const double* tab, double dx, int cons, double vscale, int* vdeg,
+                  hipStream_t s)
 {
     switch (n) {
     case 2: return PREP_CALL(2); case 3: return PREP_CALL(3); case 4: return PREP_CALL(4);

@@ -32,7 +32,7 @@ struct sl_mesh {
     int ghost_rows;
     long ghost_step;
     double t;
-    int64_t steps;
+    int64_t steps, steps_read;  // steps taken; value of steps at the last sl_read
     bool profiling;
     hipEvent_t ev[KER_COUNT][2];
     std::vector<hipEvent_t> pending[KER_COUNT];
@@ -47,6 +47,7 @@ namespace {
 int vel_terms_used(const sl_mesh* m)
 {
     const int need = m->vdeg + 1, n = m->n;
+    if (m->dim == 2) return need;  // 2D evaluates exactly vdeg + 1 terms per direction
     if (n > 4 && need <= 4) return 4;
     if (n > 8 && need <= 8) return 8;
     return n;
@@ -112,9 +113,10 @@ TabOff tab_offsets(int dim, int n)
     o.l1 = 3 * n;
     o.tinv = 4 * n;
     o.dmat = 4 * n + n * n;
-    o.cbp = 4 * n + 2 * n * n;
-    o.pb = o.cbp + (dim == 2 ? n * n * 4 * n : 0);
-    o.total = o.pb + (dim == 2 ? n * n * n * n : 0);
+    o.lam = 4 * n + 2 * n * n;
+    o.cbp = o.lam + n;
+    o.softs = o.cbp + (dim == 2 ? 16 * n * n : 0);
+    o.total = o.softs + (dim == 2 ? 16 * n * n : 0);
     return o;
 }
 
@@ -188,7 +190,6 @@ sl_status sl_create_mesh(const sl_mesh_desc* d, sl_mesh** out)
     if (d->precision != SL_PREC_FP64 && !(d->precision == SL_PREC_FP32_REFINED && d->dim == 2)) return SL_E_INVALID;
     if (!(d->x1 > d->x0) || (d->dim == 2 && !(d->y1 > d->y0))) return SL_E_INVALID;
     if (!std::isfinite(d->x0) || !std::isfinite(d->x1)) return SL_E_INVALID;
-    if (d->dim == 2) return SL_E_INVALID;  // 2D path attached separately
 
     sl_mesh* m = new (std::nothrow) sl_mesh();
     if (!m) return SL_E_NOMEM;
@@ -209,10 +210,12 @@ sl_status sl_create_mesh(const sl_mesh_desc* d, sl_mesh** out)
         if (hipStreamCreateWithFlags(&m->stream, hipStreamNonBlocking) != hipSuccess) { delete m; return SL_E_DEVICE; }
         m->own_stream = true;
     }
-    m->nblocks = blocks1d(n, m->K);
+    m->nblocks = m->dim == 1 ? blocks1d(n, m->K) : blocks2d(n, m->K);
+    const size_t nrec = m->dim == 1 ? (size_t)m->K * 8 : (size_t)m->K * 4 * n;
+    const size_t nvf = m->dim == 1 ? (size_t)m->K + 1 : (size_t)m->K * 4 * n;
     bool ok = dalloc(&m->phi, nf) && dalloc(&m->phi2, nf) && dalloc(&m->phihat, nf) &&
-              dalloc(&m->rec, (size_t)m->K * 8) && dalloc(&m->aN, nf) && dalloc(&m->aM, nf) &&
-              dalloc(&m->divN, nf) && dalloc(&m->divM, nf) && dalloc(&m->vface, (size_t)m->K + 1) &&
+              dalloc(&m->rec, nrec) && dalloc(&m->aN, nf * m->dim) && dalloc(&m->aM, nf * m->dim) &&
+              dalloc(&m->divN, nf) && dalloc(&m->divM, nf) && dalloc(&m->vface, nvf) &&
               dalloc(&m->tab, (size_t)m->off.total) && dalloc(&m->stat_part, (size_t)m->nblocks * kStatSlots) &&
               dalloc(&m->flag_part, (size_t)2 * m->nblocks) && dalloc(&m->vdeg_d, 1);
     if (!ok) { release(m); delete m; return SL_E_NOMEM; }
@@ -226,6 +229,14 @@ sl_status sl_create_mesh(const sl_mesh_desc* d, sl_mesh** out)
         for (int k = 0; k < n; ++k) {
             tab[m->off.tinv + j * n + k] = m->T.Tinv[j * n + k];
             tab[m->off.dmat + j * n + k] = m->T.D[j * n + k];
+        }
+    }
+    if (m->dim == 2) {
+        for (int j = 0; j < n; ++j) tab[m->off.lam + j] = m->T.lam[j];
+        if (!build_boundary_tables(m->T, &tab[m->off.cbp], &tab[m->off.softs])) {
+            release(m);
+            delete m;
+            return SL_E_INVALID;
         }
     }
     hipError_t e1 = hipMemcpyAsync(m->tab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice, m->stream);
@@ -260,8 +271,13 @@ sl_status sl_set_velocity(sl_mesh* m, const double* a, const double* div_a)
     if (div_a && hipMemcpyAsync(m->divN, div_a, nf * sizeof(double), hipMemcpyHostToDevice, m->stream))
         return SL_E_DEVICE;
     if (hipMemsetAsync(m->vdeg_d, 0, sizeof(int32_t), m->stream)) return SL_E_DEVICE;
-    int rc = launch_prep1d(m->n, m->K, m->bc == SL_BC_PERIODIC, div_a != nullptr, m->aN, m->aM, m->divN, m->divM,
-                           m->vface, m->tab, m->dx, m->form == SL_FORM_CONSERVATIVE, m->vdeg_d, m->stream);
+    const int cons = m->form == SL_FORM_CONSERVATIVE;
+    int rc = m->dim == 1
+                 ? launch_prep1d(m->n, m->K, m->bc == SL_BC_PERIODIC, div_a != nullptr, m->aN, m->aM, m->divN,
+                                 m->divM, m->vface, m->tab, m->dx, cons, std::max(am[0], am[1]), m->vdeg_d,
+                                 m->stream)
+                 : launch_prep2d(m->n, m->K, div_a != nullptr, cons, m->aN, m->aM, m->divN, m->divM, m->vface,
+                                 m->tab, m->dx, m->dy, std::max(am[0], am[1]), m->vdeg_d, m->stream);
     int32_t vdeg = m->n - 1;
     if (rc || hipMemcpyAsync(&vdeg, m->vdeg_d, sizeof(int32_t), hipMemcpyDeviceToHost, m->stream) ||
         hipStreamSynchronize(m->stream))
@@ -335,13 +351,55 @@ sl_status sl_step(sl_mesh* m, double dt, int32_t nsteps, const sl_step_opts* o)
     if (!m->has_velocity) return SL_E_STATE;
     if (m->bc == SL_BC_GHOST && m->ghost_rows < 1) return SL_E_STATE;
     // time-step restriction: particles may not cross the element-edge gap
+    // dt <= gap dx / max|a| (the paper's condition admits equality; a relative
+    // 1e-12 slack absorbs the rounding of dt computed at the limit)
     const double gap = m->T.xi[0];
-    if (m->amax[0] * dt >= gap * m->dx) return SL_E_CFL;
-    if (m->dim == 2 && m->amax[1] * dt >= gap * m->dy) return SL_E_CFL;
+    if (m->amax[0] * dt > gap * m->dx * (1.0 + 1e-12)) return SL_E_CFL;
+    if (m->dim == 2 && m->amax[1] * dt > gap * m->dy * (1.0 + 1e-12)) return SL_E_CFL;
     // the rows of the 1D KKT system must be independent: n >= number of rows
     const int rows = ((opt.constraints & SL_C_BOUNDARY) ? 2 : 0) + ((opt.constraints & SL_C_MASS) ? 1 : 0) +
                      ((opt.constraints & SL_C_ENERGY) ? 1 : 0);
     if (rows > m->nd) return SL_E_INVALID;
+
+    if (m->dim == 2) {
+        // 2D: boundary rows only in this build
+        if (opt.constraints & (SL_C_MASS | SL_C_ENERGY)) return SL_E_INVALID;
+        Step2DArgs B;
+        std::memset(&B, 0, sizeof(B));
+        rk_tableau(opt.rk, &B.rk);
+        B.aN = m->aN; B.aM = m->aM; B.divN = m->divN; B.divM = m->divM; B.vedge = m->vface; B.tab = m->tab;
+        B.rec = m->rec; B.phihat = m->phihat;
+        B.flag_part = m->flag_part; B.stat_part = m->stat_part; B.nblk = m->nblocks; B.vdeg = m->vdeg;
+        B.kx = m->kx; B.ky = m->ky; B.K = m->K; B.periodic = m->bc == SL_BC_PERIODIC;
+        B.cons = m->form == SL_FORM_CONSERVATIVE; B.cmask = opt.constraints; B.mode = opt.mode;
+        B.refine = 60;  // cap on defect-correction sweeps of the remap solve
+        B.precision = m->precision;
+        B.invdx = 1.0 / m->dx; B.invdy = 1.0 / m->dy; B.dt = dt;
+        B.vzero = 1e-12 * std::max(m->amax[0], m->amax[1]);
+        for (int s = 0; s < nsteps; ++s) {
+            if (m->bc == SL_BC_GHOST) {
+                const long r0 = std::min<long>(m->ghost_step, m->ghost_rows - 1);
+                const long r1 = std::min<long>(m->ghost_step + 1, m->ghost_rows - 1);
+                B.gnow = m->ghost + r0 * sl_ghost_count(m);
+                B.gnext = m->ghost + r1 * sl_ghost_count(m);
+            } else {
+                B.gnow = B.gnext = m->vface;
+            }
+            B.phi = m->phi;
+            B.phi_out = m->phi2;
+            ev_begin(m, KER_ADV2D);
+            if (launch_advect2d(m->n, B, m->stream)) return SL_E_DEVICE;
+            ev_end(m, KER_ADV2D);
+            ev_begin(m, KER_CON2D);
+            if (launch_constrain2d(m->n, B, m->stream)) return SL_E_DEVICE;
+            ev_end(m, KER_CON2D);
+            std::swap(m->phi, m->phi2);
+            m->t += dt;
+            m->steps += 1;
+            m->ghost_step += 1;
+        }
+        return SL_OK;
+    }
 
     Step1DArgs A;
     std::memset(&A, 0, sizeof(A));
@@ -400,13 +458,17 @@ sl_status sl_read(sl_mesh* m, double* u_out, sl_stats* st)
     if (hipMemcpy(fp.data(), m->flag_part, fp.size() * sizeof(int32_t), hipMemcpyDeviceToHost)) return SL_E_DEVICE;
     int flags = 0;
     for (int32_t f : fp) flags |= f;
-    double rb = 0, rm = 0, re = 0, pic = 0;
+    double rb = 0, rm = 0, re = 0, pic = 0, swsum = 0, swmax = 0, rres = 0;
     for (int b = 0; b < m->nblocks; ++b) {
         rb = std::max(rb, sp[b * kStatSlots + 0]);
         rm = std::max(rm, sp[b * kStatSlots + 1]);
         re = std::max(re, sp[b * kStatSlots + 2]);
         pic = std::max(pic, sp[b * kStatSlots + 3]);
+        swsum += sp[b * kStatSlots + 4];
+        swmax = std::max(swmax, sp[b * kStatSlots + 5]);
+        rres = std::max(rres, sp[b * kStatSlots + 6]);
     }
+    const int64_t dsteps = m->steps - m->steps_read;
     if (st) {
         std::memset(st, 0, sizeof(*st));
         st->t = m->t;
@@ -428,7 +490,11 @@ sl_status sl_read(sl_mesh* m, double* u_out, sl_stats* st)
         st->max_picard = (int32_t)pic;
         st->flags = flags;
         st->vel_terms = vel_terms_used(m);
+        st->refine_resid = rres;
+        st->remap_sweeps_max = (int32_t)swmax;
+        st->remap_sweeps_mean = dsteps > 0 ? swsum / ((double)dsteps * m->K) : 0.0;
     }
+    m->steps_read = m->steps;
     (void)hipMemsetAsync(m->stat_part, 0, sp.size() * sizeof(double), m->stream);
     (void)hipMemsetAsync(m->flag_part, 0, fp.size() * sizeof(int32_t), m->stream);
     if (hipStreamSynchronize(m->stream)) return SL_E_DEVICE;

@@ -21,12 +21,13 @@ struct Tables {
 };
 
 bool node_rule(int family, int n, double* xi, double* w);
+bool invert(int n, const double* A, double* Ainv);
 bool build_tables(int family, int n, Tables* T);
 
 // Device table layout (doubles), per mesh.  1D and 2D share the head.
 struct TabOff {
     int xi, w, l0, l1, tinv, dmat;   // n, n, n, n, n*n, n*n
-    int cbp, pb;                      // 2D: C_B^+ (n^2 x 4n), unused in 1D
+    int lam, cbp, softs;              // 2D: lambda (n), Qhard (4n x 4n), Qsoft (4n x 4n)
     int total;
 };
 TabOff tab_offsets(int dim, int n);
@@ -43,9 +44,10 @@ bool rk_tableau(int order, RKTab* T);
 enum { KER_ADV1D = 0, KER_CON1D = 1, KER_ADV2D = 2, KER_CON2D = 3, KER_COUNT = 4 };
 enum { FLAG_NONFINITE = 1, FLAG_CONTAIN = 2, FLAG_SINGULAR = 4, FLAG_NOCONV = 8 };
 
-// Per-block statistics slots written by the constraint kernels:
-// [resid_boundary, resid_mass, resid_energy, max_picard]
-constexpr int kStatSlots = 4;
+// Per-block statistics slots: [resid_boundary, resid_mass, resid_energy,
+// max_picard] from the constraint kernels, [remap sweeps summed over
+// elements, max sweeps, max final relative correction] from the 2D advect
+constexpr int kStatSlots = 7;
 
 struct Step1DArgs {
     // fields
@@ -72,38 +74,44 @@ struct Step1DArgs {
     RKTab rk;
 };
 
+// vscale: mesh-wide max |a|, the floor of the noise threshold of the
+// velocity series' effective degree
 int launch_prep1d(int n, int K, int periodic, int has_div, const double* aN, double* aM, double* divN,
-                  double* divM, double* vface, const double* tab, double dx, int cons, int* vdeg, hipStream_t s);
+                  double* divM, double* vface, const double* tab, double dx, int cons, double vscale, int* vdeg,
+                  hipStream_t s);
 int launch_advect1d(int n, const Step1DArgs& A, hipStream_t s);
 int launch_constrain1d(int n, const Step1DArgs& A, hipStream_t s);
 int blocks1d(int n, int K);
 
 struct Step2DArgs {
-    const double* phi;
-    double* phihat;
-    double* rec;           // [K][4n][4]: trace, FM, FE, face velocity per edge point
-    double* eloc;          // [K][2]: M, E local targets
-    double* phi_out;
-    const double* aM;      // [2][K][n^2] Chebyshev coefficients (u then v)
+    const double* phi;     // [K][n^2] phi^n
+    double* phihat;        // [K][n^2] remapped
+    double* rec;           // [K][4n] own edge traces of phihat
+    double* phi_out;       // [K][n^2] phi^{n+1}
     const double* aN;      // [2][K][n^2] nodal velocity
-    const double* divN;    // [K][n^2]
-    const double* divM;    // [K][n^2]
+    const double* aM;      // [2][K][n^2] tensor Chebyshev coefficients
+    const double* divN;    // [K][n^2] nodal divergence
+    const double* divM;    // [K][n^2] its coefficients
+    const double* vedge;   // [K][4n] own edge normal speeds
     const double* tab;
-    const double* gnow;
-    const double* gnext;
-    int32_t* flag_part;
-    double* stat_part;
-    int kx, ky, K, periodic, cons, cmask, mode, emaxit, vol, targets, precision, refine;
-    double dx, dy, dt, etol, vzero;
+    const double* gnow;    // ghost row at t^n, or any valid address
+    const double* gnext;   // ghost row at t^{n+1}
+    int32_t* flag_part;    // [2][nblk]
+    double* stat_part;     // [nblk][kStatSlots]
+    int nblk, vdeg;
+    int kx, ky, K, periodic, cons, cmask, mode, refine, precision;
+    double invdx, invdy, dt, vzero;
     RKTab rk;
 };
 
-int launch_prep2d(int n, int kx, int ky, int has_div, const double* aN, double* aM, double* divN, double* divM,
-                  const double* tab, double dx, double dy, hipStream_t s);
+int launch_prep2d(int n, int K, int has_div, int cons, const double* aN, double* aM, double* divN, double* divM,
+                  double* vedge, const double* tab, double dx, double dy, double vscale, int* vdeg, hipStream_t s);
 int launch_advect2d(int n, const Step2DArgs& A, hipStream_t s);
 int launch_constrain2d(int n, const Step2DArgs& A, hipStream_t s);
 int blocks2d(int n, int K);
 
-bool build_boundary_pinv(const Tables& T, double* CBp, double* PB);
+// 2D boundary tables (4n x 4n, row-major): Qhard = (C_B C_B^T)^+,
+// Qsoft = (I + C_B C_B^T)^{-1}
+bool build_boundary_tables(const Tables& T, double* Qhard, double* Qsoft);
 
 }  // namespace sl

@@ -82,7 +82,9 @@ void gauss_legendre(int n, double* xi, double* w)
     }
 }
 
-// Gauss-Jordan inverse with partial pivoting (n <= 32); returns false if singular
+}  // namespace
+
+// Gauss-Jordan inverse with partial pivoting; returns false if singular
 bool invert(int n, const double* A, double* Ainv)
 {
     std::vector<double> M(static_cast<size_t>(n) * 2 * n);
@@ -111,8 +113,6 @@ bool invert(int n, const double* A, double* Ainv)
         for (int j = 0; j < n; ++j) Ainv[i * n + j] = M[i * 2 * n + n + j];
     return true;
 }
-
-}  // namespace
 
 bool node_rule(int family, int n, double* xi, double* w)
 {
@@ -184,6 +184,73 @@ bool build_tables(int family, int n, Tables* T)
     }
     if (!invert(n, V.data(), T->Tinv)) return false;
     return true;
+}
+
+// 2D boundary rows C_B (4n x n^2): left edge j, right edge j, bottom edge
+// i, top edge i; node index i + n j.  Both constrained fits are
+//   phi = phihat + C_B^T Q (d_B - C_B phihat),
+// HARD: Q = G^+ (then C_B^T Q = C_B^+), SOFT: Q = (I + G)^{-1} (Woodbury form
+// of (I + C_B^T C_B)^{-1}(phihat + C_B^T d_B)), with G = C_B C_B^T (4n x 4n).
+// G has rank 4n - 4: each corner value is reachable from two edges.  Its
+// pseudo-inverse is built from the four corner combinations spanning null(G):
+//   z_BL = l(0) on left - l(0) on bottom,  z_TL = l(1) on left - l(0) on top,
+//   z_BR = l(0) on right - l(1) on bottom, z_TR = l(1) on right - l(1) on top;
+// with Z their orthonormal basis, G^+ = (G + Z Z^T)^{-1} - Z Z^T.
+bool build_boundary_tables(const Tables& T, double* Qhard, double* Qsoft)
+{
+    const int n = T.n, nd = n * n, m = 4 * n;
+    std::vector<double> CB((size_t)m * nd, 0.0);
+    for (int j = 0; j < n; ++j)
+        for (int i = 0; i < n; ++i) {
+            CB[(size_t)(0 * n + j) * nd + i + n * j] = T.l0[i];
+            CB[(size_t)(1 * n + j) * nd + i + n * j] = T.l1[i];
+            CB[(size_t)(2 * n + i) * nd + i + n * j] = T.l0[j];
+            CB[(size_t)(3 * n + i) * nd + i + n * j] = T.l1[j];
+        }
+    std::vector<double> G((size_t)m * m, 0.0);
+    for (int a = 0; a < m; ++a)
+        for (int b = 0; b < m; ++b) {
+            double s = 0.0;
+            for (int q = 0; q < nd; ++q) s += CB[(size_t)a * nd + q] * CB[(size_t)b * nd + q];
+            G[(size_t)a * m + b] = s;
+        }
+    std::vector<double> Z((size_t)4 * m, 0.0);
+    for (int k = 0; k < n; ++k) {
+        Z[0 * m + 0 * n + k] = T.l0[k]; Z[0 * m + 2 * n + k] = -T.l0[k];
+        Z[1 * m + 0 * n + k] = T.l1[k]; Z[1 * m + 3 * n + k] = -T.l0[k];
+        Z[2 * m + 1 * n + k] = T.l0[k]; Z[2 * m + 2 * n + k] = -T.l1[k];
+        Z[3 * m + 1 * n + k] = T.l1[k]; Z[3 * m + 3 * n + k] = -T.l1[k];
+    }
+    for (int a = 0; a < 4; ++a) {  // modified Gram-Schmidt, twice
+        for (int pass = 0; pass < 2; ++pass)
+            for (int b = 0; b < a; ++b) {
+                double d = 0.0;
+                for (int q = 0; q < m; ++q) d += Z[a * m + q] * Z[b * m + q];
+                for (int q = 0; q < m; ++q) Z[a * m + q] -= d * Z[b * m + q];
+            }
+        double nr = 0.0;
+        for (int q = 0; q < m; ++q) nr += Z[a * m + q] * Z[a * m + q];
+        nr = std::sqrt(nr);
+        if (!(nr > 0.0)) return false;
+        for (int q = 0; q < m; ++q) Z[a * m + q] /= nr;
+    }
+    std::vector<double> H((size_t)m * m);
+    for (int a = 0; a < m; ++a)
+        for (int b = 0; b < m; ++b) {
+            double zz = 0.0;
+            for (int k = 0; k < 4; ++k) zz += Z[k * m + a] * Z[k * m + b];
+            H[(size_t)a * m + b] = G[(size_t)a * m + b] + zz;
+        }
+    if (!invert(m, H.data(), Qhard)) return false;
+    for (int a = 0; a < m; ++a)
+        for (int b = 0; b < m; ++b) {
+            double zz = 0.0;
+            for (int k = 0; k < 4; ++k) zz += Z[k * m + a] * Z[k * m + b];
+            Qhard[(size_t)a * m + b] -= zz;
+        }
+    for (int a = 0; a < m; ++a)
+        for (int b = 0; b < m; ++b) H[(size_t)a * m + b] = G[(size_t)a * m + b] + (a == b ? 1.0 : 0.0);
+    return invert(m, H.data(), Qsoft);
 }
 
 }  // namespace sl
