@@ -62,18 +62,18 @@ def constrain_bytes_per_element(n: int) -> float:
     return 8.0 * n + 64.0 + 8.0 + 8.0 * n
 
 
-def measured_traffic(kernel: str):
+def measured_traffic(kernel: str, source: str = "sl1d.hip", profile: str = "sl1d_c2_K65536_n17.md"):
     """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
     summary, or None if the kernel source changed since it was taken."""
     import hashlib
-    src = os.path.join(ROOT, "paper_1910_06476_amd", "csrc", "sl1d.hip")
+    src = os.path.join(ROOT, "paper_1910_06476_amd", "csrc", source)
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    path = os.path.join(ROOT, "profiles", "sl1d_c2_K65536_n17.md")
+    path = os.path.join(ROOT, "profiles", profile)
     if not os.path.exists(path):
         return None
     for line in open(path):
         parts = line.split()
-        if len(parts) == 4 and parts[0] == "traffic" and parts[1] == kernel and parts[3] == f"sl1d.hip:{sha}":
+        if len(parts) == 4 and parts[0] == "traffic" and parts[1] == kernel and parts[3] == f"{source}:{sha}":
             return float(parts[2])
     return None
 
@@ -157,7 +157,9 @@ def bench_c3(args, torch, P, W, stream):
         "vel_terms": st.vel_terms,
         "roofline": {"kernel": "sl2d_advect", "bound": "alu", "achieved": ach / 1e12,
                      "peak": FP64_VALU_PEAK / 1e12, "unit": "TFLOP/s", "frac": ach / FP64_VALU_PEAK,
-                     "traffic": None, "avg_launch_us": adv_avg * 1e6, "algorithmic_flops_per_launch": fl,
+                     "traffic": measured_traffic("k_advect2d", "sl2d.hip", "sl2d_c3_256x256_n9.md")
+                     if args.precision == "fp64" else None,
+                     "avg_launch_us": adv_avg * 1e6, "algorithmic_flops_per_launch": fl,
                      "kernels_us": {"sl2d_advect": adv_avg * 1e6, "sl2d_constrain": con_avg * 1e6}},
     }
     print(json.dumps(out))
