@@ -158,8 +158,10 @@ int32_t sl_ghost_count(const sl_mesh* m);
 /* Advance nsteps explicit SL steps of length dt, asynchronously on the
  * mesh's stream.  Validated before any launch (state unchanged on error):
  * SL_E_STATE (no velocity, or ghost mesh without ghost values),
- * SL_E_INVALID (dt <= 0, nsteps < 0, bad options; in 2D, mass or energy
- * rows), SL_E_CFL (max |a_d| dt > gap_d dx_d for some direction d, gap =
+ * SL_E_INVALID (dt <= 0, nsteps < 0, bad options; 1D: more rows than n;
+ * 2D HARD with boundary rows: more mass/energy rows than (n-2)^2, the
+ * dimension of the null space of the 4n boundary rows of rank 4n-4),
+ * SL_E_CFL (max |a_d| dt > gap_d dx_d for some direction d, gap =
  * distance from the element edge to the first node: the paper's time-step
  * restriction, eq. 1d_delt_condition and eq. 2d_delt_condition, which admits
  * equality). */

@@ -1005,6 +1005,14 @@ int ora_step(const ora_params* p, const double* a, const double* div, const doub
     if (p->n < 1 || p->n > 16 * (p->dim == 1 ? 4 : 1)) return 1;
     if (p->kx < 1 || p->ky < 1 || (p->dim == 1 && p->ky != 1)) return 1;
     if (want && nsteps != 1) return 1;
+    /* 2D HARD: the rows after the boundary block are imposed inside
+     * null(C_B), of dimension (n-2)^2 since C_B has rank 4n-4; more rows
+     * than that cannot all hold, so the step is refused (SOFT stacks them
+     * and is always defined) */
+    if (p->dim == 2 && p->mode == 0 && (p->cmask & C_BOUND)) {
+        int extra = ((p->cmask & C_MASS) != 0) + ((p->cmask & C_ENERGY) != 0);
+        if (extra > (p->n - 2) * (p->n - 2)) return 1;
+    }
     ctx c;
     memset(&c, 0, sizeof(c));
     c.p = p;

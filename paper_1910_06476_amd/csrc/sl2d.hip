@@ -15,7 +15,10 @@
 //     displacements (M^{-1} is two 1D remaps from the shifted nodes);
 //   - the 4n edge traces of the remapped polynomial.
 // constrain (per element): upwind face values (eq. 4.12a) and the boundary
-// rows through C_B^+ (HARD) or (I + C_B^T C_B)^{-1} (SOFT).
+// rows through C_B^+ (HARD) or (I + C_B^T C_B)^{-1} (SOFT); with mass or
+// energy rows, their targets (eq. 4.14 and eq. remap_mass / remap_energy
+// generalised to the RK quadrature) and the rows imposed after the boundary
+// block, energy by Picard iteration.
 #include <type_traits>
 
 #include "sl_internal.h"
@@ -31,7 +34,7 @@ __device__ __forceinline__ bool outside2(double s) { return s < -1e-10 || s > 1.
 template <int N> struct Off2 {
     static constexpr int ND = N * N;
     static constexpr int XI = 0, W = N, L0 = 2 * N, L1 = 3 * N, TINV = 4 * N, DM = 4 * N + ND, LAM = 4 * N + 2 * ND,
-                         QH = 5 * N + 2 * ND, QS = QH + 16 * ND;
+                         QH = 5 * N + 2 * ND, QS = QH + 16 * ND, ZMH = QS + 16 * ND, ZMS = ZMH + ND;
 };
 
 __device__ __forceinline__ double upwind2(double vn, double lo, double hi)
@@ -73,8 +76,7 @@ __device__ __forceinline__ double cheb2(const double* __restrict__ C, double x, 
 // ---------------------------------------------------------------------------
 template <int N>
 __global__ void k_prep2d(int K, int has_div, int cons, const double* __restrict__ aN, double* __restrict__ aM,
-                         double* __restrict__ divN, double* __restrict__ divM, double* __restrict__ vedge,
-                         const double* __restrict__ tab, double invdx, double invdy, double vscale,
+                         double* __restrict__ divN, double* __restrict__ divM, const double* __restrict__ tab, double invdx, double invdy, double vscale,
                          int* __restrict__ vdeg)
 {
     using O = Off2<N>;
@@ -114,21 +116,6 @@ __global__ void k_prep2d(int K, int has_div, int cons, const double* __restrict_
             }
     }
     modal(dvn, divM + (size_t)e * ND);
-    // own edge normal speeds: left (xi=0, eta_j), right, bottom (xi_i, eta=0), top
-    double* ve = vedge + (size_t)e * 4 * N;
-    for (int k = 0; k < N; ++k) {
-        double l0 = 0.0, r0 = 0.0, b0 = 0.0, t0 = 0.0;
-        for (int q = 0; q < N; ++q) {
-            l0 = fma(tab[O::L0 + q], U[q + N * k], l0);
-            r0 = fma(tab[O::L1 + q], U[q + N * k], r0);
-            b0 = fma(tab[O::L0 + q], V[k + N * q], b0);
-            t0 = fma(tab[O::L1 + q], V[k + N * q], t0);
-        }
-        ve[k] = l0;
-        ve[N + k] = r0;
-        ve[2 * N + k] = b0;
-        ve[3 * N + k] = t0;
-    }
     // effective degree: the 1D rule applied to the row and column sums of
     // |C|, with the noise threshold taken against max(sum |C|, scale)
     auto degree = [&](const double* C, double scale) {
@@ -152,31 +139,173 @@ __global__ void k_prep2d(int K, int has_div, int cons, const double* __restrict_
 }
 
 // ---------------------------------------------------------------------------
-// advect + remap (eq. 5.4 by defect correction) + edge traces
-//
-// PPL particles per lane for n >= 5 (one by default: more cut the LDS reads
-// of the iterate in V x but the register growth costs more occupancy than
-// the reads save, measured at n = 9).  With P32 the separable
-// preconditioner is stored and applied in FP32 while the residual and the
-// iterate stay FP64 (iterative refinement).
+// For edge point tt of element e (layout: left j, right j, bottom i, top i):
+// the neighbour across that face (-1 outside the domain), the matching edge
+// point in the neighbour, the ghost index, and whether e is the high side of
+// the face (its left or bottom face)
 // ---------------------------------------------------------------------------
-#ifndef SL2D_PPL
-#define SL2D_PPL 1  // particles per lane of the 2D advect kernel for n >= 5
-#endif
-template <int N> struct Lanes2 {
-    static constexpr int ND = N * N;
-    static constexpr int PPL = N >= 5 ? SL2D_PPL : 1;
-    static constexpr int L = (ND + PPL - 1) / PPL;  // lanes per element
-    static constexpr int E = kBlock2 / L;           // elements per block
-};
+template <int N>
+__device__ __forceinline__ void face_partner2(int e, int tt, int kx, int ky, int periodic, int& nbe, int& nbt,
+                                              int& gidx, bool& high)
+{
+    const int side = tt / N, k = tt % N;
+    const int ex = e % kx, ey = e / kx;
+    const int KL = ky * N, KB = kx * N;
+    switch (side) {
+    case 0:
+        nbe = ex > 0 ? e - 1 : (periodic ? ey * kx + kx - 1 : -1);
+        nbt = N + k; gidx = ey * N + k; high = true;
+        break;
+    case 1:
+        nbe = ex < kx - 1 ? e + 1 : (periodic ? ey * kx : -1);
+        nbt = k; gidx = KL + ey * N + k; high = false;
+        break;
+    case 2:
+        nbe = ey > 0 ? e - kx : (periodic ? (ky - 1) * kx + ex : -1);
+        nbt = 3 * N + k; gidx = 2 * KL + ex * N + k; high = true;
+        break;
+    default:
+        nbe = ey < ky - 1 ? e + kx : (periodic ? ex : -1);
+        nbt = 2 * N + k; gidx = 2 * KL + KB + ex * N + k; high = false;
+        break;
+    }
+}
 
-template <int N, bool P32>
+// ---------------------------------------------------------------------------
+// face normal velocity at every element's own edge points: the mean of the
+// two sides' interpolated normal components (the interior side alone at a
+// ghost boundary); a speed at or below vzero has no upwind side and is
+// stored as zero.  Built once per velocity.
+// ---------------------------------------------------------------------------
+template <int N>
+__global__ void k_facevel2d(int kx, int ky, int periodic, const double* __restrict__ aN,
+                            const double* __restrict__ tab, double vzero, double* __restrict__ vface)
+{
+    using O = Off2<N>;
+    constexpr int ND = N * N, NB = 4 * N;
+    const int K = kx * ky;
+    const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= (long)K * NB) return;
+    const int e = (int)(gid / NB), tt = (int)(gid % NB);
+    auto normal = [&](int el, int t2) {
+        const int side = t2 / N, k = t2 % N;
+        const double* lv = tab + ((side & 1) ? O::L1 : O::L0);
+        double s = 0.0;
+        if (side < 2) {
+            const double* U = aN + (size_t)el * ND;
+            for (int c = 0; c < N; ++c) s = fma(lv[c], U[c + N * k], s);
+        } else {
+            const double* V = aN + (size_t)K * ND + (size_t)el * ND;
+            for (int c = 0; c < N; ++c) s = fma(lv[c], V[k + N * c], s);
+        }
+        return s;
+    };
+    int nbe, nbt, gidx;
+    bool high;
+    face_partner2<N>(e, tt, kx, ky, periodic, nbe, nbt, gidx, high);
+    double vn = normal(e, tt);
+    if (nbe >= 0) vn = 0.5 * (vn + normal(nbe, nbt));
+    if (fabs(vn) <= vzero) vn = 0.0;
+    vface[gid] = vn;
+}
+
+// ---------------------------------------------------------------------------
+// Lagrange basis row l_k(x), k < N, in product form:
+// l_k(x) = lambda_k prod_{j != k} (x - xi_j), from prefix and suffix products
+// (no division, exact at the nodes)
+// ---------------------------------------------------------------------------
+template <int N>
+__device__ __forceinline__ void lag_row(const double* __restrict__ tab, double x, double (&l)[N])
+{
+    using O = Off2<N>;
+    double pre[N];
+    double acc = 1.0;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        pre[k] = acc;
+        acc *= (x - tab[O::XI + k]);
+    }
+    acc = 1.0;
+#pragma unroll
+    for (int k = N - 1; k >= 0; --k) {
+        l[k] = tab[O::LAM + k] * pre[k] * acc;
+        acc *= (x - tab[O::XI + k]);
+    }
+}
+
+// phi^n (nodal values f of one element, in LDS) carried back along the
+// characteristic through reference point (s, r) over time h: the value of
+// phi^n at the foot, times the source factor of the conservative form.  The
+// trace uses the same explicit RK tableau as the particles (eq. 4.11 in 2D);
+// `out` is set when a stage position leaves the element.
+template <int N>
+__device__ double backtrace2(const Step2DArgs& A, const double* cu, const double* cv, const double* cd,
+                             const double* f, double h, double s, double r, bool& out)
+{
+    const RKTab& T = A.rk;
+    double qf = 1.0;
+    if (h > 0.0) {
+        double ks[4], kr[4], kq[4];
+#pragma unroll
+        for (int st = 0; st < 4; ++st) {
+            ks[st] = kr[st] = kq[st] = 0.0;
+            if (st < T.s) {
+                double ss = s, rr = r, qq = qf;
+                for (int m = 0; m < st; ++m) {
+                    ss += h * T.a[st][m] * ks[m];
+                    rr += h * T.a[st][m] * kr[m];
+                    qq += h * T.a[st][m] * kq[m];
+                }
+                out |= outside2(ss) || outside2(rr);
+                const double x = 2.0 * ss - 1.0, y = 2.0 * rr - 1.0;
+                ks[st] = -cheb2<N>(cu, x, y, A.vdeg) * A.invdx;
+                kr[st] = -cheb2<N>(cv, x, y, A.vdeg) * A.invdy;
+                kq[st] = A.cons ? -cheb2<N>(cd, x, y, A.vdeg) * qq : 0.0;
+            }
+        }
+#pragma unroll
+        for (int st = 0; st < 4; ++st)
+            if (st < T.s) {
+                s += h * T.b[st] * ks[st];
+                r += h * T.b[st] * kr[st];
+                qf += h * T.b[st] * kq[st];
+            }
+        out |= outside2(s) || outside2(r);
+    }
+    double ls[N], lr[N];
+    lag_row<N>(A.tab, s, ls);
+    lag_row<N>(A.tab, r, lr);
+    double acc = 0.0;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        double in = 0.0;
+#pragma unroll
+        for (int i = 0; i < N; ++i) in = fma(ls[i], f[i + N * j], in);
+        acc = fma(lr[j], in, acc);
+    }
+    return qf * acc;
+}
+
+// ---------------------------------------------------------------------------
+// advect + remap (eq. 5.4 by defect correction) + edge traces, and with TGT
+// the local parts of the mass and energy targets
+//
+// One lane per particle (n^2 lanes per element, floor(256/n^2) elements per
+// block).  With P32 the separable preconditioner is stored and applied in
+// FP32 while the residual and the iterate stay FP64 (iterative refinement).
+//
+// Record of element e (stride A.rstride): its 4n edge traces of phi-hat;
+// with TGT also, per edge point where e is upwind, sum_q bu_q v_q and
+// sum_q bu_q v_q^2 of the backtraced stage values v_q (4n each), and
+// M^n + dt sum_q bu_q V_q, E^n + dt sum_q bu_q V'_q with the volume terms
+// V of the balance laws (eq. 4.14 generalised to the RK quadrature).
+// ---------------------------------------------------------------------------
+template <int N, bool P32, bool TGT>
 __global__ __launch_bounds__(kBlock2) void k_advect2d(Step2DArgs A)
 {
     using O = Off2<N>;
-    using G = Lanes2<N>;
     using PT = typename std::conditional<P32, float, double>::type;
-    constexpr int ND = G::ND, PPL = G::PPL, L = G::L, E = G::E;
+    constexpr int ND = N * N, E = kBlock2 / ND, NB = 4 * N;
     __shared__ double s_cu[E][ND], s_cv[E][ND], s_cd[E][ND];
     __shared__ double s_x[E][ND], s_r[E][ND], s_f[E][ND];
     __shared__ PT s_z[E][ND];
@@ -185,16 +314,17 @@ __global__ __launch_bounds__(kBlock2) void k_advect2d(Step2DArgs A)
     __shared__ unsigned long long s_nrm[2][E];  // max |y| per element, double-buffered by sweep parity
     __shared__ int s_flag, s_sw_sum, s_sw_max;
     __shared__ unsigned long long s_res;
-    __shared__ unsigned long long s_ref[E];  // max |phi*| per element (FP32 scaling)
+    __shared__ unsigned long long s_ref[E];  // max |phi*| per element
 
     const int t = threadIdx.x;
-    const int slot = t / L, q = t - slot * L;
+    const int slot = t / ND, q = t - slot * ND;
     const bool inblk = slot < E;
     const int sl = inblk ? slot : 0;
     const int e = blockIdx.x * E + slot;
     const bool live = inblk && e < A.K;
     const double* __restrict__ tab = A.tab;
     const int K = A.K;
+    const int ii = q % N, jj = q / N;
     if (t == 0) {
         s_flag = 0;
         s_sw_sum = 0;
@@ -204,43 +334,94 @@ __global__ __launch_bounds__(kBlock2) void k_advect2d(Step2DArgs A)
     if (t < E * 2) s_nrm[t / E][t % E] = 0ull;
     if (t < E) s_ref[t] = 0ull;
 
-    // items of this lane: particle / node indices q, q + L, q + 2L (< n^2)
-    int idx[PPL];
-    bool has[PPL];
-#pragma unroll
-    for (int r = 0; r < PPL; ++r) {
-        idx[r] = q + r * L;
-        has[r] = inblk && idx[r] < ND;
-    }
-    double phi_p[PPL], u_p[PPL], v_p[PPL], dv_p[PPL];
-#pragma unroll
-    for (int r = 0; r < PPL; ++r) {
-        phi_p[r] = u_p[r] = v_p[r] = dv_p[r] = 0.0;
-        const size_t g = (size_t)(live ? e : 0) * ND + (has[r] ? idx[r] : 0);
-        if (live && has[r]) {
-            phi_p[r] = A.phi[g];
-            u_p[r] = A.aN[g];
-            v_p[r] = A.aN[(size_t)K * ND + g];
-            if (A.cons) dv_p[r] = A.divN[g];
+    const bool need_div = A.cons || (TGT && A.vol);
+    double phi_p = 0.0, u_p = 0.0, v_p = 0.0, dv_p = 0.0;
+    {
+        const size_t g = (size_t)(live ? e : 0) * ND + (inblk ? q : 0);
+        if (live) {
+            phi_p = A.phi[g];
+            u_p = A.aN[g];
+            v_p = A.aN[(size_t)K * ND + g];
+            if (need_div) dv_p = A.divN[g];
         }
-        if (has[r]) {
-            s_cu[slot][idx[r]] = live ? A.aM[g] : 0.0;
-            s_cv[slot][idx[r]] = live ? A.aM[(size_t)K * ND + g] : 0.0;
-            if (A.cons) s_cd[slot][idx[r]] = live ? A.divM[g] : 0.0;
+        if (inblk) {
+            s_cu[slot][q] = live ? A.aM[g] : 0.0;
+            s_cv[slot][q] = live ? A.aM[(size_t)K * ND + g] : 0.0;
+            if (A.cons) s_cd[slot][q] = live ? A.divM[g] : 0.0;
+            if (TGT) s_x[slot][q] = phi_p;  // phi^n for the backtraces
         }
     }
     __syncthreads();
 
-    // forward motion of each particle (eq. 5.1 tensor interpolant of the velocity)
     const RKTab& T = A.rk;
+    bool out = false;
+
+    if constexpr (TGT) {
+        double* rec = A.rec + (size_t)(live ? e : 0) * A.rstride;
+        // upwind edge points: stage sums of the backtraced values
+        for (int tt = q; live && tt < NB; tt += ND) {
+            const int side = tt / N, k = tt % N;
+            const double vn = A.vface[(size_t)e * NB + tt];
+            // e is upwind where the flow leaves it: left/bottom faces for
+            // vn < 0, right/top faces for vn > 0
+            const bool up = (side == 0 || side == 2) ? vn < 0.0 : vn > 0.0;
+            double fm = 0.0, fe = 0.0;
+            if (up) {
+                const double s = side == 0 ? 0.0 : side == 1 ? 1.0 : tab[O::XI + k];
+                const double r = side == 2 ? 0.0 : side == 3 ? 1.0 : tab[O::XI + k];
+                for (int c = 0; c < T.nq; ++c) {
+                    const double v =
+                        backtrace2<N>(A, s_cu[slot], s_cv[slot], s_cd[slot], s_x[slot], T.cu[c] * A.dt, s, r, out);
+                    fm = fma(T.bu[c], v, fm);
+                    fe = fma(T.bu[c], v * v, fe);
+                }
+            }
+            rec[NB + tt] = fm;
+            rec[2 * NB + tt] = fe;
+        }
+        // local mass and energy with the volume terms of the balance laws:
+        // advective form +div phi (mass) and +div phi^2 (energy),
+        // conservative form -div phi^2 (energy)
+        double cm = 0.0, ce = 0.0;
+        if (live) {
+            const double Wp = A.dx * A.dy * tab[O::W + ii] * tab[O::W + jj];
+            cm = Wp * phi_p;
+            ce = Wp * phi_p * phi_p;
+            if (A.vol && dv_p != 0.0) {
+                double vm = 0.0, ve = 0.0;
+                for (int c = 0; c < T.nq; ++c) {
+                    const double v = backtrace2<N>(A, s_cu[slot], s_cv[slot], s_cd[slot], s_x[slot],
+                                                   T.cu[c] * A.dt, tab[O::XI + ii], tab[O::XI + jj], out);
+                    vm = fma(T.bu[c], v, vm);
+                    ve = fma(T.bu[c], v * v, ve);
+                }
+                if (!A.cons) cm += A.dt * Wp * dv_p * vm;
+                ce += A.dt * Wp * dv_p * (A.cons ? -ve : ve);
+            }
+        }
+        if (inblk) {
+            s_r[slot][q] = cm;
+            s_f[slot][q] = ce;
+        }
+        __syncthreads();
+        if (live && q == 0) {
+            double M = 0.0, En = 0.0;
+            for (int p = 0; p < ND; ++p) {
+                M += s_r[slot][p];
+                En += s_f[slot][p];
+            }
+            rec[3 * NB] = M;
+            rec[3 * NB + 1] = En;
+        }
+        __syncthreads();  // s_x, s_r, s_f are reused below
+    }
+
+    // forward motion of the particle (eq. 5.1 tensor interpolant of the velocity)
     const int d = A.vdeg;
     const double h = A.dt;
-    bool out = false;
-    double sx[PPL], sy[PPL], sq[PPL];
-#pragma unroll
-    for (int r = 0; r < PPL; ++r) {
-        const int ii = idx[r] % N, jj = idx[r] / N;
-        double s = tab[O::XI + (has[r] ? ii : 0)], rr0 = tab[O::XI + (has[r] ? jj : 0)], qv = phi_p[r];
+    double sx, sy, sq;
+    {
+        const double s = tab[O::XI + ii], rr0 = tab[O::XI + jj], qv = phi_p;
         double ks[4], kr[4], kq[4];
 #pragma unroll
         for (int st = 0; st < 4; ++st) {
@@ -254,15 +435,15 @@ __global__ __launch_bounds__(kBlock2) void k_advect2d(Step2DArgs A)
                 }
                 double uu, vv, dd = 0.0;
                 if (st == 0) {
-                    uu = u_p[r];
-                    vv = v_p[r];
-                    dd = dv_p[r];
+                    uu = u_p;
+                    vv = v_p;
+                    dd = dv_p;
                 } else {
                     const double x = 2.0 * ss - 1.0, y = 2.0 * rr - 1.0;
                     uu = cheb2<N>(s_cu[sl], x, y, d);
                     vv = cheb2<N>(s_cv[sl], x, y, d);
                     if (A.cons) dd = cheb2<N>(s_cd[sl], x, y, d);
-                    out |= has[r] && (outside2(ss) || outside2(rr));
+                    out |= inblk && (outside2(ss) || outside2(rr));
                 }
                 ks[st] = uu * A.invdx;
                 kr[st] = vv * A.invdy;
@@ -277,124 +458,88 @@ __global__ __launch_bounds__(kBlock2) void k_advect2d(Step2DArgs A)
                 dr += T.b[st] * kr[st];
                 dq += T.b[st] * kq[st];
             }
-        sx[r] = s + h * ds;
-        sy[r] = rr0 + h * dr;
-        sq[r] = qv + h * dq;
-        out |= has[r] && (outside2(sx[r]) || outside2(sy[r]));
+        sx = s + h * ds;
+        sy = rr0 + h * dr;
+        sq = qv + h * dq;
+        out |= inblk && (outside2(sx) || outside2(sy));
     }
 
-    // rows of V: a_l = l_l(xi*_p), b_m = l_m(eta*_p) (eq. 5.4), product form
-    double a[PPL][N], b[PPL][N];
-#pragma unroll
-    for (int r = 0; r < PPL; ++r) {
-        double pa[N], pb[N];
-        double acc_a = 1.0, acc_b = 1.0;
-#pragma unroll
-        for (int l = 0; l < N; ++l) {
-            pa[l] = acc_a;
-            pb[l] = acc_b;
-            acc_a *= (sx[r] - tab[O::XI + l]);
-            acc_b *= (sy[r] - tab[O::XI + l]);
-        }
-        acc_a = 1.0;
-        acc_b = 1.0;
-#pragma unroll
-        for (int l = N - 1; l >= 0; --l) {
-            a[r][l] = tab[O::LAM + l] * pa[l] * acc_a;
-            b[r][l] = tab[O::LAM + l] * pb[l] * acc_b;
-            acc_a *= (sx[r] - tab[O::XI + l]);
-            acc_b *= (sy[r] - tab[O::XI + l]);
-        }
-    }
+    // row of V for this particle: a_l = l_l(xi*), b_m = l_m(eta*) (eq. 5.4)
+    double a[N], b[N];
+    lag_row<N>(tab, sx, a);
+    lag_row<N>(tab, sy, b);
 
     // separable preconditioner: mean displacement of each x-column i and of
     // each y-row j of particles
-#pragma unroll
-    for (int r = 0; r < PPL; ++r)
-        if (has[r]) {
-            const int ii = idx[r] % N, jj = idx[r] / N;
-            s_r[slot][idx[r]] = sx[r] - tab[O::XI + ii];
-            s_x[slot][idx[r]] = sy[r] - tab[O::XI + jj];
-            s_f[slot][idx[r]] = sq[r];  // phi*
-            atomicMax(&s_ref[slot], (unsigned long long)__double_as_longlong(fabs(sq[r])));
-        }
+    if (inblk) {
+        s_r[slot][q] = sx - tab[O::XI + ii];
+        s_x[slot][q] = sy - tab[O::XI + jj];
+        s_f[slot][q] = sq;  // phi*
+        atomicMax(&s_ref[slot], (unsigned long long)__double_as_longlong(fabs(sq)));
+    }
     __syncthreads();
-    for (int c = q; inblk && c < 2 * N; c += L) {
+    for (int c = q; inblk && c < 2 * N; c += ND) {
         double m = 0.0;
         if (c < N) {
-            for (int jj = 0; jj < N; ++jj) m += s_r[slot][c + N * jj];
+            for (int j = 0; j < N; ++j) m += s_r[slot][c + N * j];
             s_mx[slot][c] = m / N;
         } else {
-            for (int ii = 0; ii < N; ++ii) m += s_x[slot][ii + N * (c - N)];
+            for (int i = 0; i < N; ++i) m += s_x[slot][i + N * (c - N)];
             s_my[slot][c - N] = m / N;
         }
     }
     __syncthreads();
     // A0^{-1}[l][c]: interpolation from the shifted nodes xi_k + mx_k back to
     // node xi_l, prod_{k != c} (xi_l - s_k) / prod_{k != c} (s_c - s_k)
-#pragma unroll
-    for (int r = 0; r < PPL; ++r)
-        if (has[r]) {
-            const int l = idx[r] % N, c = idx[r] / N;
-            const double xl = tab[O::XI + l];
-            const double sc = tab[O::XI + c] + s_mx[slot][c], tc = tab[O::XI + c] + s_my[slot][c];
-            double na = 1.0, da = 1.0, nb = 1.0, db = 1.0;
-            for (int k = 0; k < N; ++k) {
-                if (k == c) continue;
-                const double sk = tab[O::XI + k] + s_mx[slot][k];
-                const double tk = tab[O::XI + k] + s_my[slot][k];
-                na *= (xl - sk);
-                da *= (sc - sk);
-                nb *= (xl - tk);
-                db *= (tc - tk);
-            }
-            s_ai[slot][idx[r]] = (PT)(na / da);
-            s_bi[slot][idx[r]] = (PT)(nb / db);
+    if (inblk) {
+        const int l = ii, c = jj;
+        const double xl = tab[O::XI + l];
+        const double sc = tab[O::XI + c] + s_mx[slot][c], tc = tab[O::XI + c] + s_my[slot][c];
+        double na = 1.0, da = 1.0, nb = 1.0, db = 1.0;
+        for (int k = 0; k < N; ++k) {
+            if (k == c) continue;
+            const double sk = tab[O::XI + k] + s_mx[slot][k];
+            const double tk = tab[O::XI + k] + s_my[slot][k];
+            na *= (xl - sk);
+            da *= (sc - sk);
+            nb *= (xl - tk);
+            db *= (tc - tk);
         }
+        s_ai[slot][q] = (PT)(na / da);
+        s_bi[slot][q] = (PT)(nb / db);
+    }
     __syncthreads();
 
-    // y = M^{-1} f (f in s_f or s_r, node c + N jj), per item:
+    // y = M^{-1} f (f in s_f or s_r, node c + N jj):
     //   stage 1: z[jj][l] = sum_c Ai[l][c] f[jj][c]
     //   stage 2: y[m][l] = sum_jj Bi[m][jj] z[jj][l]
     // In FP32 the operand is first scaled by 2^-e, e = exponent of a
     // reference magnitude of it (max |phi*| of the element, then the last
     // correction), so that it sits near 1 and never in the FP32 subnormal
     // range; M^{-1} is linear, so the result is scaled back exactly.
-    auto precond = [&](double (*src)[ND], double (&yy)[PPL], int e2) {
+    auto precond = [&](double (*src)[ND], int e2) -> double {
         const double sc = P32 ? ldexp(1.0, -e2) : 1.0;
-#pragma unroll
-        for (int r = 0; r < PPL; ++r)
-            if (has[r]) {
-                const int l = idx[r] % N, jj = idx[r] / N;
-                PT zz = 0;
-                for (int c = 0; c < N; ++c) {
-                    const double v = src[slot][c + N * jj];
-                    zz = fma(s_ai[slot][l + N * c], (PT)(P32 ? v * sc : v), zz);
-                }
-                s_z[slot][idx[r]] = zz;
+        if (inblk) {
+            PT zz = 0;
+            for (int c = 0; c < N; ++c) {
+                const double v = src[slot][c + N * jj];
+                zz = fma(s_ai[slot][ii + N * c], (PT)(P32 ? v * sc : v), zz);
             }
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < PPL; ++r) {
-            PT acc = 0;
-            if (has[r]) {
-                const int l = idx[r] % N, m = idx[r] / N;
-                for (int jj = 0; jj < N; ++jj) acc = fma(s_bi[slot][m + N * jj], s_z[slot][l + N * jj], acc);
-            }
-            yy[r] = P32 ? ldexp((double)acc, e2) : (double)acc;
+            s_z[slot][q] = zz;
         }
+        __syncthreads();
+        PT acc = 0;
+        if (inblk)
+            for (int j = 0; j < N; ++j) acc = fma(s_bi[slot][jj + N * j], s_z[slot][ii + N * j], acc);
+        return P32 ? ldexp((double)acc, e2) : (double)acc;
     };
     // exponent of a reference magnitude, clamped so 2^-e stays finite
     auto ref_exp = [](double ref) { return ref > 0.0 ? max(ilogb(ref), -1000) : 0; };
 
-    double x[PPL], y[PPL];
     const double ref = __longlong_as_double((long long)s_ref[sl]);  // max |phi*| of the element
-    int e2 = 0;
-    if (P32) e2 = ref_exp(ref);
-    precond(s_f, x, e2);
-#pragma unroll
-    for (int r = 0; r < PPL; ++r)
-        if (has[r]) s_x[slot][idx[r]] = x[r];
+    int e2 = P32 ? ref_exp(ref) : 0;
+    double x = precond(s_f, e2);
+    if (inblk) s_x[slot][q] = x;
     __syncthreads();
     bool conv = !live;
     int sweeps = A.refine;   // sweeps this element needed
@@ -402,39 +547,24 @@ __global__ __launch_bounds__(kBlock2) void k_advect2d(Step2DArgs A)
     double prev = 0.0;       // max |y| of the previous sweep
     for (int it = 0; it < A.refine; ++it) {
         // residual r_p = phi*_p - (V x)_p, (V x)_p = sum_m b_m sum_l a_l x[m][l]
-        double vx[PPL];
-#pragma unroll
-        for (int r = 0; r < PPL; ++r) vx[r] = 0.0;
+        double vx = 0.0;
 #pragma unroll
         for (int m = 0; m < N; ++m) {
-            double inner[PPL];
+            double inner = 0.0;
 #pragma unroll
-            for (int r = 0; r < PPL; ++r) inner[r] = 0.0;
-#pragma unroll
-            for (int l = 0; l < N; ++l) {
-                const double xml = s_x[sl][l + N * m];
-#pragma unroll
-                for (int r = 0; r < PPL; ++r) inner[r] = fma(a[r][l], xml, inner[r]);
-            }
-#pragma unroll
-            for (int r = 0; r < PPL; ++r) vx[r] = fma(b[r][m], inner[r], vx[r]);
+            for (int l = 0; l < N; ++l) inner = fma(a[l], s_x[sl][l + N * m], inner);
+            vx = fma(b[m], inner, vx);
         }
-#pragma unroll
-        for (int r = 0; r < PPL; ++r)
-            if (has[r]) s_r[slot][idx[r]] = sq[r] - vx[r];
+        if (inblk) s_r[slot][q] = sq - vx;
         __syncthreads();  // s_x is no longer read in this sweep
         // clear the other parity's slot, last read before this sweep's first barrier
         if (t < E) s_nrm[(it + 1) & 1][t] = 0ull;
-        precond(s_r, y, e2);
-        double ny = 0.0;
-#pragma unroll
-        for (int r = 0; r < PPL; ++r)
-            if (has[r]) {
-                if (!conv) x[r] += y[r];
-                ny = fmax(ny, fabs(y[r]));
-                s_x[slot][idx[r]] = x[r];
-            }
-        if (inblk) atomicMax(&s_nrm[it & 1][slot], (unsigned long long)__double_as_longlong(ny));
+        const double y = precond(s_r, e2);
+        if (inblk) {
+            if (!conv) x += y;
+            s_x[slot][q] = x;
+            atomicMax(&s_nrm[it & 1][slot], (unsigned long long)__double_as_longlong(fabs(y)));
+        }
         __syncthreads();
         if (inblk) {
             const double eny = __longlong_as_double((long long)s_nrm[it & 1][slot]);
@@ -465,19 +595,14 @@ __global__ __launch_bounds__(kBlock2) void k_advect2d(Step2DArgs A)
     int fl = 0;
     if (live) {
         if (out) fl |= FLAG_CONTAIN;
-        if (!conv) fl |= FLAG_SINGULAR;
+        if (!conv || !isfinite(x)) fl |= FLAG_SINGULAR;
         if (q == 0) {
             atomicAdd(&s_sw_sum, sweeps);
             atomicMax(&s_sw_max, sweeps);
             atomicMax(&s_res, (unsigned long long)__double_as_longlong(lastrel));
         }
-#pragma unroll
-        for (int r = 0; r < PPL; ++r)
-            if (has[r]) {
-                if (!isfinite(x[r])) fl |= FLAG_SINGULAR;
-                A.phihat[(size_t)e * ND + idx[r]] = x[r];
-            }
-        for (int tt = q; tt < 4 * N; tt += L) {
+        A.phihat[(size_t)e * ND + q] = x;
+        for (int tt = q; tt < NB; tt += ND) {
             const int side = tt / N, k = tt % N;
             const double* lv = tab + ((side & 1) ? O::L1 : O::L0);
             double tr = 0.0;
@@ -485,7 +610,7 @@ __global__ __launch_bounds__(kBlock2) void k_advect2d(Step2DArgs A)
                 for (int c = 0; c < N; ++c) tr = fma(lv[c], s_x[slot][c + N * k], tr);
             else
                 for (int c = 0; c < N; ++c) tr = fma(lv[c], s_x[slot][k + N * c], tr);
-            A.rec[(size_t)e * 4 * N + tt] = tr;
+            A.rec[(size_t)e * A.rstride + tt] = tr;
         }
     }
     if (fl) atomicOr(&s_flag, fl);
@@ -547,40 +672,12 @@ __global__ __launch_bounds__(kBlock2) void k_constrain2d(Step2DArgs A)
         // and the neighbour's matching trace (eq. 4.12a); ghost values at the
         // domain boundary
         for (int tt = p; inblk && tt < 4 * N; tt += ND) {
-            const int side = tt / N, k = tt % N;
-            const int ex = ee % kx, ey = ee / kx;
-            int nbe = -1, nbt = 0, gidx = 0;
-            bool high = false;
-            const int KL = ky * N, KB = kx * N;
-            switch (side) {
-            case 0:
-                nbe = ex > 0 ? ee - 1 : (A.periodic ? ey * kx + kx - 1 : -1);
-                nbt = N + k; gidx = ey * N + k; high = true;
-                break;
-            case 1:
-                nbe = ex < kx - 1 ? ee + 1 : (A.periodic ? ey * kx : -1);
-                nbt = k; gidx = KL + ey * N + k; high = false;
-                break;
-            case 2:
-                nbe = ey > 0 ? ee - kx : (A.periodic ? (ky - 1) * kx + ex : -1);
-                nbt = 3 * N + k; gidx = 2 * KL + ex * N + k; high = true;
-                break;
-            default:
-                nbe = ey < ky - 1 ? ee + kx : (A.periodic ? ex : -1);
-                nbt = 2 * N + k; gidx = 2 * KL + KB + ex * N + k; high = false;
-                break;
-            }
-            const double mine = A.rec[(size_t)ee * 4 * N + tt];
-            const double vmine = A.vedge[(size_t)ee * 4 * N + tt];
-            double other, vn;
-            if (nbe >= 0) {
-                other = A.rec[(size_t)nbe * 4 * N + nbt];
-                vn = 0.5 * (vmine + A.vedge[(size_t)nbe * 4 * N + nbt]);
-            } else {
-                other = A.gnext[gidx];
-                vn = vmine;
-            }
-            if (fabs(vn) <= A.vzero) vn = 0.0;
+            int nbe, nbt, gidx;
+            bool high;
+            face_partner2<N>(ee, tt, kx, ky, A.periodic, nbe, nbt, gidx, high);
+            const double mine = A.rec[(size_t)ee * A.rstride + tt];
+            const double other = nbe >= 0 ? A.rec[(size_t)nbe * A.rstride + nbt] : A.gnext[gidx];
+            const double vn = A.vface[(size_t)ee * 4 * N + tt];
             const double lo = high ? other : mine, hi = high ? mine : other;
             const double dv = upwind2(vn, lo, hi);
             s_fv[slot][tt] = dv;
@@ -630,23 +727,317 @@ __global__ __launch_bounds__(kBlock2) void k_constrain2d(Step2DArgs A)
     }
 }
 
+// ---------------------------------------------------------------------------
+// boundary-constrained least squares with mass and energy rows (2D)
+//
+// With the boundary rows' solution `base` (as in k_constrain2d) and the
+// extra rows G (mass W, energy W o phi linearised at the previous Picard
+// iterate), both modes take the form
+//   phi = base + Z S^{-1} (d_G - G base),  Z = P G^T,  S = G Z (+ I in SOFT),
+// with P = I - C_B^T Q C_B: the projector onto null(C_B) for HARD (Q =
+// (C_B C_B^T)^+, the prioritised reading), and (I + C_B^T C_B)^{-1} by
+// Woodbury for SOFT (Q = (I + C_B C_B^T)^{-1}), i.e. the paper's stacked
+// least squares.  Without boundary rows P = I and base = phi-hat.  HARD with
+// a mass row replaces the energy row by its part orthogonal to the mass row
+// (the same constraint set, better conditioned).  P W is a per-mesh table.
+// One block handles floor(256/n^2) elements, one lane per node.
+// ---------------------------------------------------------------------------
 template <int N>
-int prep_n(int K, int has_div, int cons, const double* aN, double* aM, double* divN, double* divM, double* vedge,
+__global__ __launch_bounds__(kBlock2) void k_constrain2d_me(Step2DArgs A)
+{
+    using O = Off2<N>;
+    constexpr int ND = N * N, E = kBlock2 / ND, NB = 4 * N, NQ = 16 * ND, NDOT = 5;
+    __shared__ double s_q[NQ];
+    __shared__ double s_fv[E][NB], s_tr[E][NB], s_w[E][NB];
+    __shared__ double s_v[E][ND];
+    __shared__ double s_red[E][NDOT][ND];
+    __shared__ double s_dot[E][NDOT];
+    __shared__ double s_tgt[E][2];
+    __shared__ unsigned long long s_mx[E][2];
+    __shared__ int s_flag, s_pic;
+    __shared__ unsigned long long s_stat[3];
+
+    const int t = threadIdx.x;
+    const int slot = t / ND, p = t - slot * ND;
+    const bool inblk = slot < E;
+    const int sl = inblk ? slot : 0;
+    const int e = blockIdx.x * E + slot;
+    const bool live = inblk && e < A.K;
+    const int ee = live ? e : 0;
+    const double* __restrict__ tab = A.tab;
+    const bool bnd = (A.cmask & SL_C_BOUNDARY) != 0;
+    const bool mass = (A.cmask & SL_C_MASS) != 0;
+    const bool energy = (A.cmask & SL_C_ENERGY) != 0;
+    const bool soft = A.mode == SL_MODE_SOFT;
+    const double* Qg = tab + (soft ? O::QS : O::QH);
+    for (int k = t; k < NQ; k += kBlock2) s_q[k] = Qg[k];
+    if (t == 0) {
+        s_flag = 0;
+        s_pic = 0;
+        s_stat[0] = s_stat[1] = s_stat[2] = 0ull;
+    }
+    if (t < 2 * E) s_mx[t / 2][t % 2] = 0ull;
+    const int i = p % N, j = p / N;
+    const double l0i = tab[O::L0 + i], l1i = tab[O::L1 + i], l0j = tab[O::L0 + j], l1j = tab[O::L1 + j];
+    const double Wp = A.dx * A.dy * tab[O::W + i] * tab[O::W + j];
+    const double* rec = A.rec + (size_t)ee * A.rstride;
+    const double ph = live ? A.phihat[(size_t)ee * ND + p] : 0.0;
+
+    // face values (eq. 4.12a) and the face terms of the targets: inflow
+    // positive, the upwind side's stage sums (own, neighbour's or ghost)
+    const RKTab& T = A.rk;
+    for (int tt = p; inblk && tt < NB; tt += ND) {
+        int nbe, nbt, gidx;
+        bool high;
+        face_partner2<N>(ee, tt, A.kx, A.ky, A.periodic, nbe, nbt, gidx, high);
+        const double vn = A.vface[(size_t)ee * NB + tt];
+        const double mine = rec[tt];
+        const double other = nbe >= 0 ? A.rec[(size_t)nbe * A.rstride + nbt] : A.gnext[gidx];
+        s_fv[slot][tt] = upwind2(vn, high ? other : mine, high ? mine : other);
+        double fm = 0.0, fe = 0.0;
+        if (vn != 0.0) {
+            const bool up = high ? vn < 0.0 : vn > 0.0;
+            double sm, se;
+            if (up) {
+                sm = rec[NB + tt];
+                se = rec[2 * NB + tt];
+            } else if (nbe >= 0) {
+                sm = A.rec[(size_t)nbe * A.rstride + NB + nbt];
+                se = A.rec[(size_t)nbe * A.rstride + 2 * NB + nbt];
+            } else {
+                // inflow from outside: ghost values, linear in time
+                sm = se = 0.0;
+                for (int c = 0; c < T.nq; ++c) {
+                    const double g = (1.0 - T.cu[c]) * A.gnow[gidx] + T.cu[c] * A.gnext[gidx];
+                    sm = fma(T.bu[c], g, sm);
+                    se = fma(T.bu[c], g * g, se);
+                }
+            }
+            const int side = tt / N, k = tt % N;
+            const double fw = (side < 2 ? A.dy : A.dx) * tab[O::W + k];
+            const double sg = high ? vn : -vn;
+            fm = sg * fw * sm;
+            fe = sg * fw * se;
+        }
+        s_tr[slot][tt] = fm;
+        s_w[slot][tt] = fe;
+    }
+    __syncthreads();
+    if (live && p == 0) {
+        double fm = 0.0, fe = 0.0;
+        for (int tt = 0; tt < NB; ++tt) {
+            fm += s_tr[slot][tt];
+            fe += s_w[slot][tt];
+        }
+        s_tgt[slot][0] = rec[3 * NB] + A.dt * fm;
+        s_tgt[slot][1] = rec[3 * NB + 1] + A.dt * fe;
+    }
+    __syncthreads();
+    const double Mt = s_tgt[sl][0], Et = s_tgt[sl][1];
+
+    // element-wise sums of up to NDOT per-node values, in a fixed order
+    auto dots = [&](int k, const double* vals) {
+        if (inblk)
+            for (int c = 0; c < k; ++c) s_red[slot][c][p] = vals[c];
+        __syncthreads();
+        for (int c = p; inblk && c < k; c += ND) {
+            double s = 0.0;
+            for (int r = 0; r < ND; ++r) s += s_red[slot][c][r];
+            s_dot[slot][c] = s;
+        }
+        __syncthreads();
+    };
+    // C_B^T Q (h - C_B v) at this node, v in s_v; h = d_B (face values) or 0
+    auto cbt_q = [&](bool with_data) -> double {
+        for (int tt = p; inblk && tt < NB; tt += ND) {
+            const int side = tt / N, k = tt % N;
+            const double* lv = tab + ((side & 1) ? O::L1 : O::L0);
+            double tr = 0.0;
+            if (side < 2)
+                for (int c = 0; c < N; ++c) tr = fma(lv[c], s_v[slot][c + N * k], tr);
+            else
+                for (int c = 0; c < N; ++c) tr = fma(lv[c], s_v[slot][k + N * c], tr);
+            s_tr[slot][tt] = (with_data ? s_fv[slot][tt] : 0.0) - tr;
+        }
+        __syncthreads();
+        for (int tt = p; inblk && tt < NB; tt += ND) {
+            double z = 0.0;
+            for (int c = 0; c < NB; ++c) z = fma(s_q[tt * NB + c], s_tr[slot][c], z);
+            s_w[slot][tt] = z;
+        }
+        __syncthreads();
+        const double r = l0i * s_w[sl][j] + l1i * s_w[sl][N + j] + l0j * s_w[sl][2 * N + i] +
+                         l1j * s_w[sl][3 * N + i];
+        __syncthreads();  // s_v, s_tr, s_w are rewritten by the next call
+        return r;
+    };
+
+    // boundary rows: base = phihat + C_B^T Q (d_B - C_B phihat)
+    double base = ph;
+    if (bnd) {
+        if (inblk) s_v[slot][p] = ph;
+        __syncthreads();
+        base = ph + cbt_q(true);
+    }
+    // mass row: Z_M = P W from the table (P W is W without boundary rows)
+    const double zm = bnd ? A.dx * A.dy * tab[(soft ? O::ZMS : O::ZMH) + p] : Wp;
+    const double shift = soft ? 1.0 : 0.0;
+    int fl = 0;
+    double gb = 0.0, gz = 0.0;
+    double cur = base;
+    if (mass) {
+        const double v[2] = {Wp * base, Wp * zm};
+        dots(2, v);
+        gb = s_dot[sl][0];
+        gz = s_dot[sl][1];
+        const double S = gz + shift;
+        if (!(S != 0.0) || !isfinite(S)) fl |= FLAG_SINGULAR;
+        cur = base + zm * ((Mt - gb) / S);
+    }
+    double prev = cur;
+    int picard = 0;
+    if (energy) {
+        // Picard on the energy row linearised at the previous iterate; stop
+        // when the change is below tol (strict), or, unconverged, when the
+        // iterate returns to within tol of the one two sweeps earlier
+        double older = prev;
+        bool done = !live, conv = false;
+        for (int k = 1; k <= A.emaxit; ++k) {
+            double gE = Wp * prev;
+            if (inblk) s_v[slot][p] = gE;
+            __syncthreads();
+            double zE = bnd ? gE + cbt_q(false) : gE;
+            double dE = Et;
+            if (!soft && mass) {
+                const double v[2] = {gE * Wp, Wp * Wp};
+                dots(2, v);
+                const double mu = s_dot[sl][0] / s_dot[sl][1];
+                gE -= mu * Wp;
+                zE -= mu * zm;
+                dE -= mu * Mt;
+            }
+            double sig_m = 0.0, sig_e = 0.0;
+            bool bad = false;
+            if (mass) {
+                const double v[4] = {Wp * zE, gE * zm, gE * zE, gE * base};
+                dots(4, v);
+                const double a11 = gz + shift, a12 = s_dot[sl][0], a21 = s_dot[sl][1], a22 = s_dot[sl][2] + shift;
+                const double r1 = Mt - gb, r2 = dE - s_dot[sl][3];
+                const double det = a11 * a22 - a12 * a21;
+                bad = !(det != 0.0) || !isfinite(det);
+                sig_m = (r1 * a22 - a12 * r2) / det;
+                sig_e = (a11 * r2 - a21 * r1) / det;
+            } else {
+                const double v[2] = {gE * zE, gE * base};
+                dots(2, v);
+                const double S = s_dot[sl][0] + shift;
+                bad = !(S != 0.0) || !isfinite(S);
+                sig_e = (dE - s_dot[sl][1]) / S;
+            }
+            const double nxt = base + zm * sig_m + zE * sig_e;
+            if (inblk && !done) {
+                if (bad) fl |= FLAG_SINGULAR;
+                atomicMax(&s_mx[slot][0], (unsigned long long)__double_as_longlong(fabs(nxt - prev)));
+                atomicMax(&s_mx[slot][1], (unsigned long long)__double_as_longlong(fabs(nxt - older)));
+            }
+            __syncthreads();
+            if (inblk && !done) {
+                const double diff = __longlong_as_double((long long)s_mx[slot][0]);
+                const double back = __longlong_as_double((long long)s_mx[slot][1]);
+                older = prev;
+                prev = nxt;
+                picard = k;
+                if (diff < A.etol) {
+                    conv = true;
+                    done = true;
+                } else if (k >= 2 && back < A.etol) {
+                    done = true;
+                }
+            }
+            const bool all = __syncthreads_and(done);
+            if (t < 2 * E) s_mx[t / 2][t % 2] = 0ull;
+            __syncthreads();
+            if (all) break;
+        }
+        if (live && !conv && A.etol > 0.0) fl |= FLAG_NOCONV;
+    }
+
+    // store, residuals: boundary (traces of phi vs the face values), mass,
+    // energy
+    const double phi = prev;
+    if (live) {
+        if (!isfinite(phi)) fl |= FLAG_NONFINITE;
+        A.phi_out[(size_t)e * ND + p] = phi;
+    }
+    if (inblk) s_v[slot][p] = phi;
+    {
+        const double v[2] = {Wp * phi, Wp * phi * phi};
+        dots(2, v);  // its first barrier also publishes s_v
+    }
+    if (live) {
+        for (int tt = p; bnd && tt < NB; tt += ND) {
+            const int side = tt / N, k = tt % N;
+            const double* lv = tab + ((side & 1) ? O::L1 : O::L0);
+            double tr = 0.0;
+            if (side < 2)
+                for (int c = 0; c < N; ++c) tr = fma(lv[c], s_v[slot][c + N * k], tr);
+            else
+                for (int c = 0; c < N; ++c) tr = fma(lv[c], s_v[slot][k + N * c], tr);
+            atomicMax(&s_stat[0], (unsigned long long)__double_as_longlong(fabs(tr - s_fv[slot][tt])));
+        }
+        if (p == 0) {
+            if (mass) atomicMax(&s_stat[1], (unsigned long long)__double_as_longlong(fabs(s_dot[slot][0] - Mt)));
+            if (energy) atomicMax(&s_stat[2], (unsigned long long)__double_as_longlong(fabs(s_dot[slot][1] - Et)));
+            atomicMax(&s_pic, picard);
+        }
+    }
+    if (fl) atomicOr(&s_flag, fl);
+    __syncthreads();
+    if (t == 0) {
+        if (s_flag) A.flag_part[A.nblk + blockIdx.x] |= s_flag;
+        double* sp = A.stat_part + (size_t)blockIdx.x * kStatSlots;
+        sp[0] = fmax(sp[0], __longlong_as_double((long long)s_stat[0]));
+        sp[1] = fmax(sp[1], __longlong_as_double((long long)s_stat[1]));
+        sp[2] = fmax(sp[2], __longlong_as_double((long long)s_stat[2]));
+        sp[3] = fmax(sp[3], (double)s_pic);
+    }
+}
+
+template <int N>
+int prep_n(int K, int has_div, int cons, const double* aN, double* aM, double* divN, double* divM,
            const double* tab, double dx, double dy, double vscale, int* vdeg, hipStream_t s)
 {
     const int bs = 64;
     hipLaunchKernelGGL(k_prep2d<N>, dim3((K + bs - 1) / bs), dim3(bs), 0, s, K, has_div, cons, aN, aM, divN, divM,
-                       vedge, tab, 1.0 / dx, 1.0 / dy, vscale, vdeg);
+                       tab, 1.0 / dx, 1.0 / dy, vscale, vdeg);
     return hipGetLastError() == hipSuccess ? 0 : 1;
+}
+
+template <int N>
+int facevel_n(int kx, int ky, int periodic, const double* aN, const double* tab, double vzero, double* vface,
+              hipStream_t s)
+{
+    const int bs = 256;
+    const long tot = (long)kx * ky * 4 * N;
+    hipLaunchKernelGGL(k_facevel2d<N>, dim3((unsigned)((tot + bs - 1) / bs)), dim3(bs), 0, s, kx, ky, periodic, aN,
+                       tab, vzero, vface);
+    return hipGetLastError() == hipSuccess ? 0 : 1;
+}
+
+template <int N, bool P32>
+void adv_launch(const Step2DArgs& A, dim3 grid, hipStream_t s)
+{
+    if (A.targets) hipLaunchKernelGGL((k_advect2d<N, P32, true>), grid, dim3(kBlock2), 0, s, A);
+    else hipLaunchKernelGGL((k_advect2d<N, P32, false>), grid, dim3(kBlock2), 0, s, A);
 }
 
 template <int N>
 int adv_n(const Step2DArgs& A, hipStream_t s)
 {
-    constexpr int E = Lanes2<N>::E;
+    constexpr int E = kBlock2 / (N * N);
     const dim3 grid((A.K + E - 1) / E);
-    if (A.precision == SL_PREC_FP32_REFINED) hipLaunchKernelGGL((k_advect2d<N, true>), grid, dim3(kBlock2), 0, s, A);
-    else hipLaunchKernelGGL((k_advect2d<N, false>), grid, dim3(kBlock2), 0, s, A);
+    if (A.precision == SL_PREC_FP32_REFINED) adv_launch<N, true>(A, grid, s);
+    else adv_launch<N, false>(A, grid, s);
     return hipGetLastError() == hipSuccess ? 0 : 1;
 }
 
@@ -655,7 +1046,10 @@ int con_n(const Step2DArgs& A, hipStream_t s)
 {
     constexpr int E = kBlock2 / (N * N);
     const int nchunk = (A.K + E - 1) / E;
-    hipLaunchKernelGGL(k_constrain2d<N>, dim3(nchunk < kConGrid ? nchunk : kConGrid), dim3(kBlock2), 0, s, A);
+    if (A.cmask & (SL_C_MASS | SL_C_ENERGY))
+        hipLaunchKernelGGL(k_constrain2d_me<N>, dim3(nchunk), dim3(kBlock2), 0, s, A);
+    else
+        hipLaunchKernelGGL(k_constrain2d<N>, dim3(nchunk < kConGrid ? nchunk : kConGrid), dim3(kBlock2), 0, s, A);
     return hipGetLastError() == hipSuccess ? 0 : 1;
 }
 
@@ -664,11 +1058,8 @@ int con_n(const Step2DArgs& A, hipStream_t s)
 int blocks2d(int n, int K)
 {
     if (n < 2 || n > kMax2D) return 0;
-    const int ppl = n >= 5 ? SL2D_PPL : 1;
-    const int Ea = kBlock2 / ((n * n + ppl - 1) / ppl);  // advect elements per block
-    const int Ec = kBlock2 / (n * n);                    // constrain elements per block
-    const int a = (K + Ea - 1) / Ea, c = (K + Ec - 1) / Ec;
-    return a > c ? a : c;
+    const int E = kBlock2 / (n * n);  // elements per block, both kernels
+    return (K + E - 1) / E;
 }
 
 #define SL2D_SWITCH(n, CALL)                                                                                   \
@@ -680,11 +1071,19 @@ int blocks2d(int n, int K)
     }
 
 int launch_prep2d(int n, int K, int has_div, int cons, const double* aN, double* aM, double* divN, double* divM,
-                  double* vedge, const double* tab, double dx, double dy, double vscale, int* vdeg, hipStream_t s)
+                  const double* tab, double dx, double dy, double vscale, int* vdeg, hipStream_t s)
 {
-#define PREP2(N) prep_n<N>(K, has_div, cons, aN, aM, divN, divM, vedge, tab, dx, dy, vscale, vdeg, s)
+#define PREP2(N) prep_n<N>(K, has_div, cons, aN, aM, divN, divM, tab, dx, dy, vscale, vdeg, s)
     SL2D_SWITCH(n, PREP2)
 #undef PREP2
+}
+
+int launch_facevel2d(int n, int kx, int ky, int periodic, const double* aN, const double* tab, double vzero,
+                     double* vface, hipStream_t s)
+{
+#define FV2(N) facevel_n<N>(kx, ky, periodic, aN, tab, vzero, vface, s)
+    SL2D_SWITCH(n, FV2)
+#undef FV2
 }
 
 int launch_advect2d(int n, const Step2DArgs& A, hipStream_t s)

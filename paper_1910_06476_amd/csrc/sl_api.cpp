@@ -116,7 +116,9 @@ TabOff tab_offsets(int dim, int n)
     o.lam = 4 * n + 2 * n * n;
     o.cbp = o.lam + n;
     o.softs = o.cbp + (dim == 2 ? 16 * n * n : 0);
-    o.total = o.softs + (dim == 2 ? 16 * n * n : 0);
+    o.zmh = o.softs + (dim == 2 ? 16 * n * n : 0);
+    o.zms = o.zmh + (dim == 2 ? n * n : 0);
+    o.total = o.zms + (dim == 2 ? n * n : 0);
     return o;
 }
 
@@ -211,7 +213,7 @@ sl_status sl_create_mesh(const sl_mesh_desc* d, sl_mesh** out)
         m->own_stream = true;
     }
     m->nblocks = m->dim == 1 ? blocks1d(n, m->K) : blocks2d(n, m->K);
-    const size_t nrec = m->dim == 1 ? (size_t)m->K * 8 : (size_t)m->K * 4 * n;
+    const size_t nrec = m->dim == 1 ? (size_t)m->K * 8 : (size_t)m->K * (12 * n + 2);
     const size_t nvf = m->dim == 1 ? (size_t)m->K + 1 : (size_t)m->K * 4 * n;
     bool ok = dalloc(&m->phi, nf) && dalloc(&m->phi2, nf) && dalloc(&m->phihat, nf) &&
               dalloc(&m->rec, nrec) && dalloc(&m->aN, nf * m->dim) && dalloc(&m->aM, nf * m->dim) &&
@@ -233,7 +235,8 @@ sl_status sl_create_mesh(const sl_mesh_desc* d, sl_mesh** out)
     }
     if (m->dim == 2) {
         for (int j = 0; j < n; ++j) tab[m->off.lam + j] = m->T.lam[j];
-        if (!build_boundary_tables(m->T, &tab[m->off.cbp], &tab[m->off.softs])) {
+        if (!build_boundary_tables(m->T, &tab[m->off.cbp], &tab[m->off.softs], &tab[m->off.zmh],
+                                   &tab[m->off.zms])) {
             release(m);
             delete m;
             return SL_E_INVALID;
@@ -276,8 +279,11 @@ sl_status sl_set_velocity(sl_mesh* m, const double* a, const double* div_a)
                  ? launch_prep1d(m->n, m->K, m->bc == SL_BC_PERIODIC, div_a != nullptr, m->aN, m->aM, m->divN,
                                  m->divM, m->vface, m->tab, m->dx, cons, std::max(am[0], am[1]), m->vdeg_d,
                                  m->stream)
-                 : launch_prep2d(m->n, m->K, div_a != nullptr, cons, m->aN, m->aM, m->divN, m->divM, m->vface,
-                                 m->tab, m->dx, m->dy, std::max(am[0], am[1]), m->vdeg_d, m->stream);
+                 : launch_prep2d(m->n, m->K, div_a != nullptr, cons, m->aN, m->aM, m->divN, m->divM, m->tab, m->dx,
+                                 m->dy, std::max(am[0], am[1]), m->vdeg_d, m->stream);
+    if (!rc && m->dim == 2)
+        rc = launch_facevel2d(m->n, m->kx, m->ky, m->bc == SL_BC_PERIODIC, m->aN, m->tab,
+                              1e-12 * std::max(am[0], am[1]), m->vface, m->stream);
     int32_t vdeg = m->n - 1;
     if (rc || hipMemcpyAsync(&vdeg, m->vdeg_d, sizeof(int32_t), hipMemcpyDeviceToHost, m->stream) ||
         hipStreamSynchronize(m->stream))
@@ -360,20 +366,31 @@ sl_status sl_step(sl_mesh* m, double dt, int32_t nsteps, const sl_step_opts* o)
     const int rows = ((opt.constraints & SL_C_BOUNDARY) ? 2 : 0) + ((opt.constraints & SL_C_MASS) ? 1 : 0) +
                      ((opt.constraints & SL_C_ENERGY) ? 1 : 0);
     if (rows > m->nd) return SL_E_INVALID;
+    // 2D HARD: the mass and energy rows are imposed inside null(C_B), of
+    // dimension n^2 - (4n - 4) = (n - 2)^2; more rows than that have no
+    // exact solution (SOFT, the stacked least squares, always has one)
+    if (m->dim == 2 && opt.mode == SL_MODE_HARD && (opt.constraints & SL_C_BOUNDARY) &&
+        rows - 2 > (m->n - 2) * (m->n - 2))
+        return SL_E_INVALID;
 
     if (m->dim == 2) {
-        // 2D: boundary rows only in this build
-        if (opt.constraints & (SL_C_MASS | SL_C_ENERGY)) return SL_E_INVALID;
         Step2DArgs B;
         std::memset(&B, 0, sizeof(B));
         rk_tableau(opt.rk, &B.rk);
-        B.aN = m->aN; B.aM = m->aM; B.divN = m->divN; B.divM = m->divM; B.vedge = m->vface; B.tab = m->tab;
+        B.aN = m->aN; B.aM = m->aM; B.divN = m->divN; B.divM = m->divM; B.vface = m->vface; B.tab = m->tab;
         B.rec = m->rec; B.phihat = m->phihat;
         B.flag_part = m->flag_part; B.stat_part = m->stat_part; B.nblk = m->nblocks; B.vdeg = m->vdeg;
         B.kx = m->kx; B.ky = m->ky; B.K = m->K; B.periodic = m->bc == SL_BC_PERIODIC;
         B.cons = m->form == SL_FORM_CONSERVATIVE; B.cmask = opt.constraints; B.mode = opt.mode;
         B.refine = 60;  // cap on defect-correction sweeps of the remap solve
         B.precision = m->precision;
+        B.targets = (opt.constraints & (SL_C_MASS | SL_C_ENERGY)) != 0;
+        // volume terms of the balance laws: advective form for mass and
+        // energy, conservative form for energy only
+        B.vol = B.targets && (B.cons ? (opt.constraints & SL_C_ENERGY) != 0 : 1);
+        B.rstride = B.targets ? 12 * m->n + 2 : 4 * m->n;
+        B.emaxit = opt.energy_maxit; B.etol = opt.energy_tol;
+        B.dx = m->dx; B.dy = m->dy;
         B.invdx = 1.0 / m->dx; B.invdy = 1.0 / m->dy; B.dt = dt;
         B.vzero = 1e-12 * std::max(m->amax[0], m->amax[1]);
         for (int s = 0; s < nsteps; ++s) {

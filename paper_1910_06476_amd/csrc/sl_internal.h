@@ -28,6 +28,7 @@ bool build_tables(int family, int n, Tables* T);
 struct TabOff {
     int xi, w, l0, l1, tinv, dmat;   // n, n, n, n, n*n, n*n
     int lam, cbp, softs;              // 2D: lambda (n), Qhard (4n x 4n), Qsoft (4n x 4n)
+    int zmh, zms;                     // 2D: projected mass rows (n^2 each)
     int total;
 };
 TabOff tab_offsets(int dim, int n);
@@ -86,32 +87,36 @@ int blocks1d(int n, int K);
 struct Step2DArgs {
     const double* phi;     // [K][n^2] phi^n
     double* phihat;        // [K][n^2] remapped
-    double* rec;           // [K][4n] own edge traces of phihat
+    double* rec;           // [K][rstride] edge traces of phihat (4n); with targets also the
+                           // upwind stage sums (2 x 4n) and the local mass and energy parts (2)
     double* phi_out;       // [K][n^2] phi^{n+1}
     const double* aN;      // [2][K][n^2] nodal velocity
     const double* aM;      // [2][K][n^2] tensor Chebyshev coefficients
     const double* divN;    // [K][n^2] nodal divergence
     const double* divM;    // [K][n^2] its coefficients
-    const double* vedge;   // [K][4n] own edge normal speeds
+    const double* vface;   // [K][4n] face normal velocity at the element's edge points
     const double* tab;
     const double* gnow;    // ghost row at t^n, or any valid address
     const double* gnext;   // ghost row at t^{n+1}
     int32_t* flag_part;    // [2][nblk]
     double* stat_part;     // [nblk][kStatSlots]
-    int nblk, vdeg;
-    int kx, ky, K, periodic, cons, cmask, mode, refine, precision;
-    double invdx, invdy, dt, vzero;
+    int nblk, vdeg, rstride;
+    int kx, ky, K, periodic, cons, cmask, mode, refine, precision, targets, vol, emaxit;
+    double dx, dy, invdx, invdy, dt, vzero, etol;
     RKTab rk;
 };
 
 int launch_prep2d(int n, int K, int has_div, int cons, const double* aN, double* aM, double* divN, double* divM,
-                  double* vedge, const double* tab, double dx, double dy, double vscale, int* vdeg, hipStream_t s);
+                  const double* tab, double dx, double dy, double vscale, int* vdeg, hipStream_t s);
+int launch_facevel2d(int n, int kx, int ky, int periodic, const double* aN, const double* tab, double vzero,
+                     double* vface, hipStream_t s);
 int launch_advect2d(int n, const Step2DArgs& A, hipStream_t s);
 int launch_constrain2d(int n, const Step2DArgs& A, hipStream_t s);
 int blocks2d(int n, int K);
 
 // 2D boundary tables (4n x 4n, row-major): Qhard = (C_B C_B^T)^+,
-// Qsoft = (I + C_B C_B^T)^{-1}
-bool build_boundary_tables(const Tables& T, double* Qhard, double* Qsoft);
+// Qsoft = (I + C_B C_B^T)^{-1}; and the reference mass row w (x) w (n^2)
+// projected by I - C_B^T Q C_B for each: Zhard, Zsoft
+bool build_boundary_tables(const Tables& T, double* Qhard, double* Qsoft, double* Zhard, double* Zsoft);
 
 }  // namespace sl

@@ -196,7 +196,7 @@ bool build_tables(int family, int n, Tables* T)
 //   z_BL = l(0) on left - l(0) on bottom,  z_TL = l(1) on left - l(0) on top,
 //   z_BR = l(0) on right - l(1) on bottom, z_TR = l(1) on right - l(1) on top;
 // with Z their orthonormal basis, G^+ = (G + Z Z^T)^{-1} - Z Z^T.
-bool build_boundary_tables(const Tables& T, double* Qhard, double* Qsoft)
+bool build_boundary_tables(const Tables& T, double* Qhard, double* Qsoft, double* Zhard, double* Zsoft)
 {
     const int n = T.n, nd = n * n, m = 4 * n;
     std::vector<double> CB((size_t)m * nd, 0.0);
@@ -250,7 +250,31 @@ bool build_boundary_tables(const Tables& T, double* Qhard, double* Qsoft)
         }
     for (int a = 0; a < m; ++a)
         for (int b = 0; b < m; ++b) H[(size_t)a * m + b] = G[(size_t)a * m + b] + (a == b ? 1.0 : 0.0);
-    return invert(m, H.data(), Qsoft);
+    if (!invert(m, H.data(), Qsoft)) return false;
+    // reference mass row g = w (x) w, projected: Z = g - C_B^T Q C_B g
+    std::vector<double> g(nd), cg(m), qcg(m);
+    for (int j = 0; j < n; ++j)
+        for (int i = 0; i < n; ++i) g[i + n * j] = T.w[i] * T.w[j];
+    for (int a = 0; a < m; ++a) {
+        double s = 0.0;
+        for (int q = 0; q < nd; ++q) s += CB[(size_t)a * nd + q] * g[q];
+        cg[a] = s;
+    }
+    for (int pass = 0; pass < 2; ++pass) {
+        const double* Q = pass == 0 ? Qhard : Qsoft;
+        double* Z = pass == 0 ? Zhard : Zsoft;
+        for (int a = 0; a < m; ++a) {
+            double s = 0.0;
+            for (int b = 0; b < m; ++b) s += Q[(size_t)a * m + b] * cg[b];
+            qcg[a] = s;
+        }
+        for (int q = 0; q < nd; ++q) {
+            double s = 0.0;
+            for (int a = 0; a < m; ++a) s += CB[(size_t)a * nd + q] * qcg[a];
+            Z[q] = g[q] - s;
+        }
+    }
+    return true;
 }
 
 }  // namespace sl

@@ -26,7 +26,8 @@ def _need_gpu():
     P.lib()
 
 
-def _swirl_case(kx, ky, n, bc=W.PERIODIC, form=W.ADVECTIVE, mode=W.HARD, rk=4, nsteps=3, family=W.GL, seed=0):
+def _swirl_case(kx, ky, n, bc=W.PERIODIC, form=W.ADVECTIVE, mode=W.HARD, rk=4, nsteps=3, family=W.GL, seed=0,
+                cmask=W.BOUNDARY, energy_maxit=50, energy_tol=1e-8):
     """Seeded smooth velocity with nonzero divergence and a random-mode field."""
     rng = np.random.default_rng(seed)
     ph = rng.uniform(0, 2 * math.pi, 4)
@@ -36,7 +37,8 @@ def _swirl_case(kx, ky, n, bc=W.PERIODIC, form=W.ADVECTIVE, mode=W.HARD, rk=4, n
     amax = 1.0
     dt = 0.2 * W.min_gap(family, n) * min(1.0 / kx, 1.0 / ky) / amax
     return W.Workload(name="swirl2", dim=2, kx=kx, ky=ky, n=n, family=family, x0=0.0, x1=1.0, y0=0.0, y1=1.0,
-                      bc=bc, form=form, rk=rk, cmask=W.BOUNDARY, mode=mode, dt=dt, nsteps=nsteps,
+                      bc=bc, form=form, rk=rk, cmask=cmask, mode=mode, dt=dt, nsteps=nsteps,
+                      energy_maxit=energy_maxit, energy_tol=energy_tol,
                       u0=f0, vel=lambda x, y: (u(x, y), v(x, y), 0.0),
                       exact=lambda x, y, t: f0(x - 0.6 * t, y + 0.4 * t))
 
@@ -164,15 +166,6 @@ def test_2d_bitwise_determinism():
     g1, _, _ = run_gpu(w)
     g2, _, _ = run_gpu(w)
     assert np.array_equal(g1, g2)
-
-
-def test_2d_mass_energy_rejected_for_now():
-    import paper_1910_06476_amd as P
-    w = _swirl_case(2, 2, 4)
-    announce("2d reject mass")
-    with pytest.raises(P.SLError) as e:
-        run_gpu(w, nsteps=1, constraints=W.BOUNDARY | W.MASS)
-    assert e.value.status == P.SL_E_INVALID
 
 
 def test_remap_solve_statistics():

@@ -331,3 +331,23 @@ def test_mass_telescopes_2d(ora):
     dt = 0.2 * W.min_gap(W.GL, n) * (1 / kx) / 0.7
     out, st = ora.step(p, phi0, a=a, dt=dt, nsteps=4)
     assert abs(np.dot(Wq, out) - np.dot(Wq, phi0)) < 1e-14
+
+
+@pytest.mark.parametrize("n,cmask,ok", [(2, W.BOUNDARY | W.MASS, False), (3, W.BOUNDARY | W.MASS, True),
+                                        (3, W.BOUNDARY | W.MASS | W.ENERGY, False),
+                                        (4, W.BOUNDARY | W.MASS | W.ENERGY, True)])
+def test_2d_hard_rows_beyond_boundary_null_space_refused(ora, n, cmask, ok):
+    """C_B has rank 4n-4, so null(C_B) has dimension (n-2)^2: HARD accepts
+    at most that many mass/energy rows after the boundary block; SOFT (the
+    stacked least squares) accepts any."""
+    w = W.c3(kx=2, ky=2, n=n, nsteps=1)
+    a, _ = w.velocity()
+    g = w.ghost_rows(0.0, 1)
+    for mode, expect in ((W.HARD, ok), (W.SOFT, True)):
+        p = ora.params_from(w, cmask=cmask, mode=mode)
+        if expect:
+            out, st = ora.step(p, w.initial(), a=a, ghost=g, dt=w.dt, nsteps=1)
+            assert np.all(np.isfinite(out))
+        else:
+            with pytest.raises(ValueError):
+                ora.step(p, w.initial(), a=a, ghost=g, dt=w.dt, nsteps=1)
