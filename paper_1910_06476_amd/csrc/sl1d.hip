@@ -89,23 +89,51 @@ __device__ __forceinline__ int cheb_degree(const double (&c)[N], double scale = 
 // (NA: number of leading Chebyshev coefficients of the velocity and
 // divergence series that are evaluated; the rest are negligible, see
 // cheb_degree)
-template <int N, bool CONS, int NA = N>
-__device__ __forceinline__ void rk_move(const RKTab& T, const double (&ca)[N], const double (&cd)[N], double dir,
+// Tableau access: RKS = 0 reads the runtime tableau, RKS = 4 is the
+// classical fourth-order tableau at compile time (its zero entries vanish
+// from the code; the distinct abscissae are 0, 1/2, 1 with weights
+// 1/6, 2/3, 1/6).
+template <int RKS> struct Tab {
+    const RKTab& T;
+    __device__ int s() const { return T.s; }
+    __device__ double a(int i, int j) const { return T.a[i][j]; }
+    __device__ double b(int i) const { return T.b[i]; }
+    __device__ int nq() const { return T.nq; }
+    __device__ double cu(int k) const { return T.cu[k]; }
+    __device__ double bu(int k) const { return T.bu[k]; }
+};
+template <> struct Tab<4> {
+    const RKTab& T;
+    __device__ constexpr int s() const { return 4; }
+    __device__ constexpr double a(int i, int j) const
+    {
+        return (i == 1 && j == 0) || (i == 2 && j == 1) ? 0.5 : (i == 3 && j == 2) ? 1.0 : 0.0;
+    }
+    __device__ constexpr double b(int i) const { return (i == 0 || i == 3) ? 1.0 / 6 : 1.0 / 3; }
+    __device__ constexpr int nq() const { return 3; }
+    __device__ constexpr double cu(int k) const { return k == 0 ? 0.0 : k == 1 ? 0.5 : 1.0; }
+    __device__ constexpr double bu(int k) const { return k == 1 ? 2.0 / 3 : 1.0 / 6; }
+};
+
+template <int N, bool CONS, int NA = N, int RKS = 0>
+__device__ __forceinline__ void rk_move(const RKTab& TT, const double (&ca)[N], const double (&cd)[N], double dir,
                                         double h, double invdx, double& s, double& q, bool& out, bool have_first,
                                         double u_first, double dv_first)
 {
+    const Tab<RKS> T{TT};
     double ks[4], kq[4];
     const double s0 = s, q0 = q;
 #pragma unroll
     for (int st = 0; st < 4; ++st) {
         ks[st] = 0.0;
         kq[st] = 0.0;
-        if (st < T.s) {
+        if (st < T.s()) {
             double ss = s0, qq = q0;
 #pragma unroll
             for (int j = 0; j < st; ++j) {
-                ss += h * T.a[st][j] * ks[j];
-                if (CONS) qq += h * T.a[st][j] * kq[j];
+                if (T.a(st, j) == 0.0) continue;
+                ss += h * T.a(st, j) * ks[j];
+                if (CONS) qq += h * T.a(st, j) * kq[j];
             }
             double u, dv = 0.0;
             if (st == 0 && have_first) {
@@ -124,9 +152,9 @@ __device__ __forceinline__ void rk_move(const RKTab& T, const double (&ca)[N], c
     double ds = 0.0, dq = 0.0;
 #pragma unroll
     for (int st = 0; st < 4; ++st) {
-        if (st < T.s) {
-            ds += T.b[st] * ks[st];
-            if (CONS) dq += T.b[st] * kq[st];
+        if (st < T.s()) {
+            ds += T.b(st) * ks[st];
+            if (CONS) dq += T.b(st) * kq[st];
         }
     }
     s = s0 + h * ds;
@@ -230,9 +258,10 @@ __global__ void k_prep1d(int K, int periodic, int has_div, const double* __restr
 // instruction stream as the node lanes' backtraces from the nodes, and the
 // edge traces of the remapped polynomial while the node lanes remap.
 // ---------------------------------------------------------------------------
-template <int N, bool CONS, int NA>
+template <int N, bool CONS, int NA, int RKS>
 __global__ __launch_bounds__(kBlock) void k_advect1d(Step1DArgs A)
 {
+    const Tab<RKS> RK{A.rk};
     constexpr int L = N + 1;
     constexpr int E = kBlock / L;
     using O = Off<N>;
@@ -290,7 +319,7 @@ __global__ __launch_bounds__(kBlock) void k_advect1d(Step1DArgs A)
     bool out = false;
     // forward motion of particle i (section 4.2)
     double s = xi_i, q = phi_i;
-    if (node) rk_move<N, CONS, NA>(A.rk, ca, cd, 1.0, A.dt, invdx, s, q, out, true, a_i, dv_i);
+    if (node) rk_move<N, CONS, NA, RKS>(A.rk, ca, cd, 1.0, A.dt, invdx, s, q, out, true, a_i, dv_i);
 
     // element-local target parts: M^n, E^n, volume term at the RK abscissae
     // (node lanes), edge values at the RK abscissae on the upwind edges (edge
@@ -310,17 +339,19 @@ __global__ __launch_bounds__(kBlock) void k_advect1d(Step1DArgs A)
             const bool act = node ? (r == 0 && A.vol && live) : (edge >= 0);
             if (!act) continue;
             const double x0 = node ? xi_i : (double)edge;
-            for (int qd = 0; qd < A.rk.nq; ++qd) {
-                const double cq = A.rk.cu[qd];
+#pragma unroll
+            for (int qd = 0; qd < 4; ++qd) {
+                if (qd >= RK.nq()) break;
+                const double cq = RK.cu(qd);
                 double val;
                 if (cq == 0.0) {
                     val = node ? phi_i : clenshaw<N>(cp, 2.0 * x0 - 1.0);
                 } else {
                     double sb = x0, hq = 1.0;
-                    rk_move<N, CONS, NA>(A.rk, ca, cd, -1.0, cq * A.dt, invdx, sb, hq, out, node, a_i, dv_i);
+                    rk_move<N, CONS, NA, RKS>(A.rk, ca, cd, -1.0, cq * A.dt, invdx, sb, hq, out, node, a_i, dv_i);
                     val = hq * clenshaw<N>(cp, 2.0 * sb - 1.0);
                 }
-                const double bq = A.rk.bu[qd];
+                const double bq = RK.bu(qd);
                 if (node) {
                     vM += bq * (W_i * dv_i * val);
                     vE += bq * (W_i * dv_i * val * val);
@@ -391,18 +422,19 @@ __global__ __launch_bounds__(kBlock) void k_advect1d(Step1DArgs A)
             r[3] = FM[1];
             r[4] = FE[0];
             r[5] = FE[1];
-            if (A.targets) {
-                double M = 0.0, En = 0.0, sM = 0.0, sE = 0.0;
+        }
+        // local mass (node lane 0) and energy (node lane 1) with their
+        // volume terms, summed in node order
+        if (A.targets && i < 2) {
+            double M = 0.0, V = 0.0;
 #pragma unroll
-                for (int j = 0; j < N; ++j) {
-                    M += s_r[0][slot][j];
-                    En += s_r[1][slot][j];
-                    sM += s_r[2][slot][j];
-                    sE += s_r[3][slot][j];
-                }
-                r[6] = CONS ? M : M + A.dt * sM;
-                r[7] = CONS ? En - A.dt * sE : En + A.dt * sE;
+            for (int j = 0; j < N; ++j) {
+                M += s_r[i][slot][j];
+                V += s_r[2 + i][slot][j];
             }
+            double* r = A.rec + (size_t)e * 8;
+            if (i == 0) r[6] = CONS ? M : M + A.dt * V;
+            else r[7] = CONS ? M - A.dt * V : M + A.dt * V;
         }
     }
     if (fl) atomicOr(&s_flag, fl);
@@ -413,66 +445,67 @@ __global__ __launch_bounds__(kBlock) void k_advect1d(Step1DArgs A)
 // ---------------------------------------------------------------------------
 // constrained least squares: one lane per element, values in registers
 // ---------------------------------------------------------------------------
-// Cholesky solve of a 4x4 SPD system (upper triangle used)
-__device__ __forceinline__ bool chol4(double G[4][4], double b[4])
+constexpr int kConBlock = 64;  // one wave
+constexpr int kConQ = 4;       // lanes per element (a quad)
+constexpr int kConElems = kConBlock / kConQ;
+
+// value of the lane whose index differs in bit 0 (CTRL 0xB1, quad_perm
+// [1,0,3,2]) or bit 1 (CTRL 0x4E, quad_perm [2,3,0,1]): a DPP move within
+// the quad, no LDS traffic
+template <int CTRL>
+__device__ __forceinline__ double quad_swap(double v)
 {
-    double L[4][4];
-    bool ok = true;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        double d = G[j][j];
-#pragma unroll
-        for (int k = 0; k < j; ++k) d -= L[j][k] * L[j][k];
-        ok = ok && (d > 0.0);
-        const double ljj = sqrt(d > 0.0 ? d : 1.0);
-        L[j][j] = ljj;
-#pragma unroll
-        for (int i = j + 1; i < 4; ++i) {
-            double v = G[j][i];
-#pragma unroll
-            for (int k = 0; k < j; ++k) v -= L[i][k] * L[j][k];
-            L[i][j] = v / ljj;
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        double v = b[i];
-#pragma unroll
-        for (int k = 0; k < i; ++k) v -= L[i][k] * b[k];
-        b[i] = v / L[i][i];
-    }
-#pragma unroll
-    for (int i = 3; i >= 0; --i) {
-        double v = b[i];
-#pragma unroll
-        for (int k = i + 1; k < 4; ++k) v -= L[k][i] * b[k];
-        b[i] = v / L[i][i];
-    }
-    return ok;
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+// sum over the element's quad (lanes 4k .. 4k+3), the same in every lane:
+// (v0 + v1) + (v2 + v3) in each
+__device__ __forceinline__ double quad_sum(double v)
+{
+    v += quad_swap<0xB1>(v);
+    return v + quad_swap<0x4E>(v);
+}
+__device__ __forceinline__ double quad_max(double v)
+{
+    v = fmax(v, quad_swap<0xB1>(v));
+    return fmax(v, quad_swap<0x4E>(v));
 }
 
-constexpr int kConBlock = 64;
-
+// Four lanes per element: lane r of the quad holds nodes r, r+4, r+8, ...
+// (NP of them); row products are quad sums, and the small KKT / least-squares
+// solve is repeated in the four lanes.
 template <int N>
 __global__ __launch_bounds__(kConBlock) void k_constrain1d(Step1DArgs A)
 {
     using O = Off<N>;
-    __shared__ double s_buf[kConBlock * N];
+    constexpr int NP = (N + kConQ - 1) / kConQ;
+    __shared__ double s_buf[kConElems * N];
     const int t = threadIdx.x;
-    const int e0 = blockIdx.x * kConBlock;
+    const int le = t / kConQ, r = t % kConQ;
+    const int e0 = blockIdx.x * kConElems;
     const int K = A.K;
-    const int e = e0 + t;
+    const int e = e0 + le;
     const bool live = e < K;
     const int ee = live ? e : K - 1;
     const double* __restrict__ tab = A.tab;
 
     // coalesced staging of the block's phihat
-    const int cnt = (K - e0 < kConBlock ? K - e0 : kConBlock) * N;
+    const int cnt = (K - e0 < kConElems ? K - e0 : kConElems) * N;
     for (int k = t; k < cnt; k += kConBlock) s_buf[k] = A.phihat[(size_t)e0 * N + k];
     __syncthreads();
-    double ph[N];
+    // this lane's nodes and their table entries (absent nodes are zero rows)
+    double ph[NP], l0[NP], l1[NP], Wn[NP];
 #pragma unroll
-    for (int j = 0; j < N; ++j) ph[j] = live ? s_buf[t * N + j] : 0.0;
+    for (int k = 0; k < NP; ++k) {
+        const int j = r + kConQ * k;
+        const bool on = j < N;
+        ph[k] = (live && on) ? s_buf[le * N + j] : 0.0;
+        l0[k] = on ? tab[O::L0 + j] : 0.0;
+        l1[k] = on ? tab[O::L1 + j] : 0.0;
+        Wn[k] = on ? A.dx * tab[O::W + j] : 0.0;
+    }
     __syncthreads();
 
     const bool bnd = (A.cmask & SL_C_BOUNDARY) != 0;
@@ -520,67 +553,70 @@ __global__ __launch_bounds__(kConBlock) void k_constrain1d(Step1DArgs A)
         Et = Re[7] + A.dt * (vL * FEl - vR * FEr);
     }
 
-    // rows l(0), l(1), W (mass), W*psi (energy); inactive rows are zero.
-    // Tables are read with uniform indices (scalar loads).
+    // rows l(0), l(1), W (mass), W*psi (energy); inactive rows are zero
     double Cph[3] = {0.0, 0.0, 0.0};
 #pragma unroll
-    for (int j = 0; j < N; ++j) {
-        Cph[0] += tab[O::L0 + j] * ph[j];
-        Cph[1] += tab[O::L1 + j] * ph[j];
-        Cph[2] += (A.dx * tab[O::W + j]) * ph[j];
+    for (int k = 0; k < NP; ++k) {
+        Cph[0] = fma(l0[k], ph[k], Cph[0]);
+        Cph[1] = fma(l1[k], ph[k], Cph[1]);
+        Cph[2] = fma(Wn[k], ph[k], Cph[2]);
     }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) Cph[a] = quad_sum(Cph[a]);
     const double dd0 = bnd ? dB0 : 0.0, dd1 = bnd ? dB1 : 0.0, dd2 = mass ? Mt : 0.0;
     const double s0 = bnd ? 1.0 : 0.0, s1 = bnd ? 1.0 : 0.0, s2 = mass ? 1.0 : 0.0;
     bool singular = false;
 
-    // one constrained solve; energy row given by its Gram entries red[0..3]
-    // (against l0, l1, W, itself), its product with phihat red[4], target d3
+    // one constrained solve.  The 3x3 block of rows l(0), l(1), W is the
+    // same for every element (its inverse g3i comes with the launch); the
+    // energy row borders it with its Gram entries red[0..3] (against l0,
+    // l1, W, itself), its product with phihat red[4] and target d3, and is
+    // eliminated through the Schur complement.  HARD: G y = C phihat - d;
+    // SOFT: (I + G) z = C phihat + G d, y = z - d.
     auto solve = [&](bool use_e, const double (&red)[5], double d3, double (&y)[4]) {
-        double G[4][4];
-        G[0][0] = bnd ? A.g00 : 0.0;
-        G[0][1] = bnd ? A.g01 : 0.0;
-        G[0][2] = (bnd && mass) ? A.g02 : 0.0;
-        G[1][1] = bnd ? A.g11 : 0.0;
-        G[1][2] = (bnd && mass) ? A.g12 : 0.0;
-        G[2][2] = mass ? A.g22 : 0.0;
-        G[0][3] = use_e ? red[0] * s0 : 0.0;
-        G[1][3] = use_e ? red[1] * s1 : 0.0;
-        G[2][3] = use_e ? red[2] * s2 : 0.0;
-        G[3][3] = use_e ? red[3] : 0.0;
-        const double cp[4] = {Cph[0] * s0, Cph[1] * s1, Cph[2] * s2, use_e ? red[4] : 0.0};
+        const double ge[3] = {use_e ? red[0] * s0 : 0.0, use_e ? red[1] * s1 : 0.0, use_e ? red[2] * s2 : 0.0};
+        const double gam = use_e ? red[3] : 0.0;
         const double dd[4] = {dd0, dd1, dd2, use_e ? d3 : 0.0};
-        const bool ac[4] = {bnd, bnd, mass, use_e};
-        double rhs[4];
-        if (A.mode == SL_MODE_HARD) {
+        double r3[3] = {Cph[0] * s0, Cph[1] * s1, Cph[2] * s2};
+        double r4 = use_e ? red[4] : 0.0;
+        const bool soft = A.mode == SL_MODE_SOFT;
+        if (soft) {
+            const double G3[3][3] = {{bnd ? A.g00 : 0.0, bnd ? A.g01 : 0.0, (bnd && mass) ? A.g02 : 0.0},
+                                     {bnd ? A.g01 : 0.0, bnd ? A.g11 : 0.0, (bnd && mass) ? A.g12 : 0.0},
+                                     {(bnd && mass) ? A.g02 : 0.0, (bnd && mass) ? A.g12 : 0.0, mass ? A.g22 : 0.0}};
 #pragma unroll
-            for (int a = 0; a < 4; ++a) {
-                rhs[a] = cp[a] - dd[a];
-                if (!ac[a]) G[a][a] = 1.0;
-            }
+            for (int a = 0; a < 3; ++a) r3[a] += G3[a][0] * dd[0] + G3[a][1] * dd[1] + G3[a][2] * dd[2] + ge[a] * dd[3];
+            r4 += ge[0] * dd[0] + ge[1] * dd[1] + ge[2] * dd[2] + gam * dd[3];
         } else {
-            // (I + G) z = C phihat + G d ; y = z - d
 #pragma unroll
-            for (int a = 0; a < 4; ++a) {
-                double v = cp[a];
-#pragma unroll
-                for (int b = 0; b < 4; ++b) v += ((a <= b) ? G[a][b] : G[b][a]) * dd[b];
-                rhs[a] = v;
-            }
-#pragma unroll
-            for (int a = 0; a < 4; ++a) G[a][a] += 1.0;
+            for (int a = 0; a < 3; ++a) r3[a] -= dd[a];
+            r4 -= dd[3];
         }
-        singular |= !chol4(G, rhs);
+        double z[3], w[3];
 #pragma unroll
-        for (int a = 0; a < 4; ++a) y[a] = (A.mode == SL_MODE_HARD) ? rhs[a] : rhs[a] - dd[a];
+        for (int a = 0; a < 3; ++a) {
+            z[a] = A.g3i[3 * a] * r3[0] + A.g3i[3 * a + 1] * r3[1] + A.g3i[3 * a + 2] * r3[2];
+            w[a] = A.g3i[3 * a] * ge[0] + A.g3i[3 * a + 1] * ge[1] + A.g3i[3 * a + 2] * ge[2];
+        }
+        double y4 = 0.0;
+        if (use_e) {
+            const double sch = (soft ? gam + 1.0 : gam) - (ge[0] * w[0] + ge[1] * w[1] + ge[2] * w[2]);
+            singular |= !(sch > 0.0);
+            y4 = (r4 - (ge[0] * z[0] + ge[1] * z[1] + ge[2] * z[2])) / sch;
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) y[a] = z[a] - w[a] * y4;
+        y[3] = y4;
+        if (soft)
+#pragma unroll
+            for (int a = 0; a < 4; ++a) y[a] -= dd[a];
     };
 
-    double phi[N], y[4];
+    double phi[NP], y[4];
     const double zero5[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     solve(false, zero5, 0.0, y);
 #pragma unroll
-    for (int j = 0; j < N; ++j)
-        phi[j] = ph[j] - (tab[O::L0 + j] * s0 * y[0] + tab[O::L1 + j] * s1 * y[1] +
-                          (A.dx * tab[O::W + j]) * s2 * y[2]);
+    for (int k = 0; k < NP; ++k) phi[k] = ph[k] - (l0[k] * s0 * y[0] + l1[k] * s1 * y[1] + Wn[k] * s2 * y[2]);
 
     int iters = 0;
     bool conv = false;
@@ -589,50 +625,48 @@ __global__ __launch_bounds__(kConBlock) void k_constrain1d(Step1DArgs A)
         // HARD with a mass row: energy row orthogonalised against the mass
         // row (same constraint set); stop below tol, or on a 2-cycle
         const bool center = (A.mode == SL_MODE_HARD) && mass;
-        double older[N];
+        double older[NP];
 #pragma unroll
-        for (int j = 0; j < N; ++j) older[j] = phi[j];
-        for (int k = 1; k <= A.emaxit; ++k) {
+        for (int k = 0; k < NP; ++k) older[k] = phi[k];
+        for (int it = 1; it <= A.emaxit; ++it) {
             double mu = 0.0;
             if (center) {
                 double gw = 0.0;
 #pragma unroll
-                for (int j = 0; j < N; ++j) {
-                    const double Wj = A.dx * tab[O::W + j];
-                    gw += (Wj * phi[j]) * Wj;
-                }
-                mu = gw / A.g22;
+                for (int k = 0; k < NP; ++k) gw += (Wn[k] * phi[k]) * Wn[k];
+                mu = quad_sum(gw) / A.g22;
             }
             double red[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int j = 0; j < N; ++j) {
-                const double Wj = A.dx * tab[O::W + j];
-                const double c3 = Wj * phi[j] - mu * Wj;
-                red[0] += c3 * tab[O::L0 + j];
-                red[1] += c3 * tab[O::L1 + j];
-                red[2] += c3 * Wj;
+            for (int k = 0; k < NP; ++k) {
+                const double c3 = Wn[k] * phi[k] - mu * Wn[k];
+                red[0] += c3 * l0[k];
+                red[1] += c3 * l1[k];
+                red[2] += c3 * Wn[k];
                 red[3] += c3 * c3;
-                red[4] += c3 * ph[j];
+                red[4] += c3 * ph[k];
             }
+#pragma unroll
+            for (int a = 0; a < 5; ++a) red[a] = quad_sum(red[a]);
             solve(true, red, Et - mu * Mt, y);
             double diff = 0.0, back = 0.0;
 #pragma unroll
-            for (int j = 0; j < N; ++j) {
-                const double Wj = A.dx * tab[O::W + j];
-                const double c3 = Wj * phi[j] - mu * Wj;
-                const double nv = ph[j] - (tab[O::L0 + j] * s0 * y[0] + tab[O::L1 + j] * s1 * y[1] +
-                                           Wj * s2 * y[2] + c3 * y[3]);
-                diff = fmax(diff, fabs(nv - phi[j]));
-                back = fmax(back, fabs(nv - older[j]));
-                older[j] = phi[j];
-                phi[j] = nv;
+            for (int k = 0; k < NP; ++k) {
+                const double c3 = Wn[k] * phi[k] - mu * Wn[k];
+                const double nv = ph[k] - (l0[k] * s0 * y[0] + l1[k] * s1 * y[1] + Wn[k] * s2 * y[2] + c3 * y[3]);
+                diff = fmax(diff, fabs(nv - phi[k]));
+                back = fmax(back, fabs(nv - older[k]));
+                older[k] = phi[k];
+                phi[k] = nv;
             }
-            iters = k;
+            diff = quad_max(diff);
+            back = quad_max(back);
+            iters = it;
             if (diff < A.etol) {
                 conv = true;
                 break;
             }
-            if (k >= 2 && back < A.etol) break;  // 2-cycle: further sweeps repeat
+            if (it >= 2 && back < A.etol) break;  // 2-cycle: further sweeps repeat
         }
     }
 
@@ -640,14 +674,17 @@ __global__ __launch_bounds__(kConBlock) void k_constrain1d(Step1DArgs A)
     double r0 = 0.0, r1 = 0.0, r2 = 0.0, r3 = 0.0;
     bool finite = true;
 #pragma unroll
-    for (int j = 0; j < N; ++j) {
-        const double Wj = A.dx * tab[O::W + j];
-        r0 += tab[O::L0 + j] * phi[j];
-        r1 += tab[O::L1 + j] * phi[j];
-        r2 += Wj * phi[j];
-        r3 += Wj * phi[j] * phi[j];
-        finite = finite && isfinite(phi[j]);
+    for (int k = 0; k < NP; ++k) {
+        r0 = fma(l0[k], phi[k], r0);
+        r1 = fma(l1[k], phi[k], r1);
+        r2 = fma(Wn[k], phi[k], r2);
+        r3 = fma(Wn[k] * phi[k], phi[k], r3);
+        finite = finite && isfinite(phi[k]);
     }
+    r0 = quad_sum(r0);
+    r1 = quad_sum(r1);
+    r2 = quad_sum(r2);
+    r3 = quad_sum(r3);
     double rb = (live && bnd) ? fmax(fabs(r0 - dB0), fabs(r1 - dB1)) : 0.0;
     double rm = (live && mass) ? fabs(r2 - Mt) : 0.0;
     double re = (live && energy) ? fabs(r3 - Et) : 0.0;
@@ -671,7 +708,10 @@ __global__ __launch_bounds__(kConBlock) void k_constrain1d(Step1DArgs A)
     // coalesced store of phi^{n+1}
     if (live) {
 #pragma unroll
-        for (int j = 0; j < N; ++j) s_buf[t * N + j] = phi[j];
+        for (int k = 0; k < NP; ++k) {
+            const int j = r + kConQ * k;
+            if (j < N) s_buf[le * N + j] = phi[k];
+        }
     }
     __syncthreads();
     for (int k = t; k < cnt; k += kConBlock) A.phi_out[(size_t)e0 * N + k] = s_buf[k];
@@ -698,8 +738,14 @@ int launch_prep_n(int K, int periodic, int has_div, const double* aN, double* aM
 template <int N, int NA>
 void launch_adv_na(const Step1DArgs& A, dim3 grid, hipStream_t s)
 {
-    if (A.cons) hipLaunchKernelGGL((k_advect1d<N, true, NA>), grid, dim3(kBlock), 0, s, A);
-    else hipLaunchKernelGGL((k_advect1d<N, false, NA>), grid, dim3(kBlock), 0, s, A);
+    const bool rk4 = A.rk.s == 4;  // the classical tableau, the only 4-stage one
+    if (A.cons) {
+        if (rk4) hipLaunchKernelGGL((k_advect1d<N, true, NA, 4>), grid, dim3(kBlock), 0, s, A);
+        else hipLaunchKernelGGL((k_advect1d<N, true, NA, 0>), grid, dim3(kBlock), 0, s, A);
+    } else {
+        if (rk4) hipLaunchKernelGGL((k_advect1d<N, false, NA, 4>), grid, dim3(kBlock), 0, s, A);
+        else hipLaunchKernelGGL((k_advect1d<N, false, NA, 0>), grid, dim3(kBlock), 0, s, A);
+    }
 }
 
 // velocity series evaluated with 4, 8 or all n Chebyshev terms: the fewest
@@ -719,7 +765,7 @@ int launch_adv_n(const Step1DArgs& A, hipStream_t s)
 template <int N>
 int launch_con_n(const Step1DArgs& A, hipStream_t s)
 {
-    dim3 grid((A.K + kConBlock - 1) / kConBlock);
+    dim3 grid((A.K + kConElems - 1) / kConElems);
     hipLaunchKernelGGL(k_constrain1d<N>, grid, dim3(kConBlock), 0, s, A);
     return hipGetLastError() == hipSuccess ? 0 : 1;
 }
@@ -730,7 +776,7 @@ int blocks1d(int n, int K)
 {
     if (n < 2 || n > kMax1D) return 0;
     const int E = kBlock / (n + 1);
-    const int a = (K + E - 1) / E, c = (K + kConBlock - 1) / kConBlock;
+    const int a = (K + E - 1) / E, c = (K + kConElems - 1) / kConElems;
     return a > c ? a : c;
 }
 

@@ -433,6 +433,21 @@ sl_status sl_step(sl_mesh* m, double dt, int32_t nsteps, const sl_step_opts* o)
     double g[6];
     gram1d(m, g);
     A.g00 = g[0]; A.g01 = g[1]; A.g11 = g[2]; A.g02 = g[3]; A.g12 = g[4]; A.g22 = g[5];
+    {
+        // the block of the constrained system that does not depend on the
+        // element: rows l(0), l(1) (boundary) and W (mass); an inactive row
+        // is an identity row, SOFT adds I
+        const bool bnd = (opt.constraints & SL_C_BOUNDARY) != 0, mass = (opt.constraints & SL_C_MASS) != 0;
+        const bool ac[3] = {bnd, bnd, mass};
+        double G3[9] = {bnd ? g[0] : 0.0, bnd ? g[1] : 0.0, (bnd && mass) ? g[3] : 0.0,
+                        bnd ? g[1] : 0.0, bnd ? g[2] : 0.0, (bnd && mass) ? g[4] : 0.0,
+                        (bnd && mass) ? g[3] : 0.0, (bnd && mass) ? g[4] : 0.0, mass ? g[5] : 0.0};
+        for (int a = 0; a < 3; ++a) {
+            if (opt.mode == SL_MODE_HARD && !ac[a]) G3[a * 3 + a] = 1.0;
+            if (opt.mode == SL_MODE_SOFT) G3[a * 3 + a] += 1.0;
+        }
+        if (!invert(3, G3, A.g3i)) return SL_E_INVALID;
+    }
     static const double zero2[2] = {0.0, 0.0};
     (void)zero2;
     for (int s = 0; s < nsteps; ++s) {

@@ -72,6 +72,8 @@ struct Step1DArgs {
     int K, periodic, cons, cmask, mode, emaxit, vol, targets;
     double dx, invdx, dt, etol, vzero;
     double g00, g01, g11, g02, g12, g22;  // constant Gram entries of rows l(0), l(1), W
+    double g3i[9];  // inverse of the constant 3x3 block of the launch's system (rows l(0), l(1), W;
+                    // inactive rows as identity; + I in SOFT), row-major
     RKTab rk;
 };
 
