@@ -301,10 +301,15 @@ __global__ __launch_bounds__(kBlock) void k_advect1d(Step1DArgs A)
         s_p[slot][i] = phi_i;
     }
     __syncthreads();
-    if (A.targets && inblk && node) {
+    // Chebyshev coefficients of phi^n (for its values at backtraced feet);
+    // zero without targets, so that the unconditional register copy below
+    // reads defined values
+    if (inblk && node) {
         double c = 0.0;
+        if (A.targets) {
 #pragma unroll
-        for (int j = 0; j < N; ++j) c = fma(tab[O::TINV + i * N + j], s_p[slot][j], c);
+            for (int j = 0; j < N; ++j) c = fma(tab[O::TINV + i * N + j], s_p[slot][j], c);
+        }
         s_q[slot][i] = c;
     }
     __syncthreads();
@@ -314,7 +319,7 @@ __global__ __launch_bounds__(kBlock) void k_advect1d(Step1DArgs A)
     for (int k = 0; k < N; ++k) {
         ca[k] = s_a[sl][k];
         cd[k] = CONS ? s_d[sl][k] : 0.0;
-        cp[k] = A.targets ? s_q[sl][k] : 0.0;
+        cp[k] = s_q[sl][k];
     }
     bool out = false;
     // forward motion of particle i (section 4.2)
