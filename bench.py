@@ -8,14 +8,18 @@ boundary + mass + energy constraints (HARD), dt = 0.2 * min node gap * dx /
 method).  Inputs are resident in HBM before the timed region.
 
 Prints one JSON line: DOF-updates/s over K timed steps, the L2 error against
-the closed-form solution at the final time, the roofline of the dominant
-kernel (HIP events on the mesh's stream, algorithmic flop count per element
-as stated in the design doc), and the CPU oracle timed on a bounded sample.
+the closed-form solution at the final time, the served per-step latency
+(p50/p99), the roofline of the dominant kernel (HIP events on the mesh's
+stream, algorithmic flop count per element from the functions below), and
+the CPU oracle timed on a bounded sample.  --workload c3 runs the 2D
+rotation configuration, --workload serve a Poisson stream of independent
+problems through the request loop.
 """
 from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -117,6 +121,21 @@ def advect2d_flops_per_element(n: int, s: int, sweeps: float, vel_terms: int) ->
     return f
 
 
+def step_latency(torch, m, dt, opts, samples=200):
+    """Served per-step latency: one sl_step submitted and waited for at a
+    time (host validation, both launches and the synchronisation), as a
+    request loop sees it; p50 and p99 over `samples` steps, microseconds."""
+    lat = []
+    for _ in range(samples):
+        t0 = time.perf_counter()
+        m.step(dt, 1, **opts)
+        torch.cuda.synchronize()
+        lat.append((time.perf_counter() - t0) * 1e6)
+    lat.sort()
+    pick = lambda q: lat[min(len(lat) - 1, int(q * len(lat)))]
+    return {"p50_us": pick(0.50), "p99_us": pick(0.99), "samples": samples}
+
+
 def bench_c3(args, torch, P, W, stream):
     """2D rotation workload (256x256, order 8, RK4, ghost inflow, boundary HARD)."""
     w = W.c3(nsteps=args.warmup + args.steps)
@@ -134,6 +153,7 @@ def bench_c3(args, torch, P, W, stream):
     T = (args.warmup + args.steps) * w.dt
     l2 = w.l2_error(phi, T)
     sweeps = st.remap_sweeps_mean  # defect-correction sweeps per element and step, measured
+    lat = step_latency(torch, m, w.dt, opts, samples=min(100, max(10, args.steps)))
     nprof = max(5, min(args.steps, 20))
     P.sl_set_profiling(m.h, True)
     m.step(w.dt, nprof, **opts)
@@ -153,6 +173,7 @@ def bench_c3(args, torch, P, W, stream):
                                "Gaussian hill, RK4, ghost inflow from the exact solution, boundary HARD",
                    "K": w.K, "n": w.n, "dofs": w.dofs, "dt": w.dt},
         "l2_error": l2, "l2_time": T, "status": P.status_string(rc), "precision": args.precision,
+        "step_latency": lat,
         "remap_sweeps_mean": sweeps, "remap_sweeps_max": st.remap_sweeps_max, "refine_resid": st.refine_resid,
         "vel_terms": st.vel_terms,
         "roofline": {"kernel": "sl2d_advect", "bound": "alu", "achieved": ach / 1e12,
@@ -165,14 +186,122 @@ def bench_c3(args, torch, P, W, stream):
     print(json.dumps(out))
 
 
+def serve_stream(W, count, seed):
+    """Seeded request mix of the serving configuration: dim 1 or 2 (p = 1/2);
+    K uniform in [64, 65536] (2D: kx = ky = round(sqrt K)); order N uniform in
+    {4..16} (2D: {4..10}, the 2D order limit); 1D u0 the C2 Gaussian or a
+    random sine field, 2D the C3 hill with its exact inflow; velocity of C2
+    (1D) or C3 (2D); 10..500 steps; 2D requests FP64 or FP32-refined
+    (p = 1/2).  Inputs are built only when a request is submitted."""
+    rng = np.random.default_rng(seed)
+    specs = []
+    for i in range(count):
+        dim = int(rng.integers(1, 3))
+        K = int(rng.integers(64, 65537))
+        steps = int(rng.integers(10, 501))
+        if dim == 1:
+            N = int(rng.integers(4, 17))
+            specs.append(dict(dim=1, K=K, n=N + 1, steps=steps, sine=bool(rng.integers(0, 2)), prec=0, seed=i))
+        else:
+            k = max(1, int(round(math.sqrt(K))))
+            N = int(rng.integers(4, 11))
+            specs.append(dict(dim=2, K=k * k, kx=k, n=N + 1, steps=steps, prec=int(rng.integers(0, 2)), seed=i))
+    return specs
+
+
+def serve_submit(S, W, sp):
+    if sp["dim"] == 1:
+        w = W.c2(K=sp["K"], n=sp["n"], nsteps=sp["steps"], cmask=W.BOUNDARY)
+        u0 = W.random_field_1d(w.K, w.n, sp["seed"], x0=w.x0, x1=w.x1) if sp["sine"] else w.initial()
+        a, _ = w.velocity()
+        ghost = None
+    else:
+        w = W.c3(kx=sp["kx"], n=sp["n"], nsteps=sp["steps"])
+        u0 = w.initial()
+        a, _ = w.velocity()
+        ghost = w.ghost_rows(0.0, w.nsteps)
+    rid = S.submit(w.dim, w.kx, w.ky, w.n - 1, u0, a, dt=w.dt, nsteps=w.nsteps, ghost=ghost, nodes=w.family,
+                   bc=w.bc, form=w.form, precision=sp["prec"], x0=w.x0, x1=w.x1, y0=w.y0, y1=w.y1, rk=w.rk,
+                   constraints=w.cmask, mode=w.mode)
+    return rid, w.K * w.nd * w.nsteps
+
+
+def bench_serve(args, torch, P, W):
+    """Serving: a seeded Poisson stream of independent problems through the
+    request loop (continuous batching).  First a closed-loop pass (all
+    submitted at once) measures the capacity; then the open-loop stream
+    arrives at 0.8x that capacity.  value = DOF-updates/s of the open loop,
+    with the per-step latency p50/p99 of its requests."""
+    count = args.requests
+    specs = serve_stream(W, count, seed=2024)
+    budget = int(args.budget_gib * (1 << 30))
+    # closed loop
+    with P.Server(max_active=args.slots, hbm_budget=budget) as S:
+        t0 = time.perf_counter()
+        ids, work = [], 0
+        for sp in specs:
+            rid, wk = serve_submit(S, W, sp)
+            ids.append(rid)
+            work += wk
+            S.progress()
+        S.drain()
+        closed = time.perf_counter() - t0
+        for rid in ids:
+            S.result(rid)
+    capacity = work / closed
+    # open loop: Poisson arrivals at 0.8x capacity (mean work per request / rate)
+    rng = np.random.default_rng(7)
+    rate = 0.8 * capacity / (work / count)          # requests per second
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=count))
+    statuses = []
+    with P.Server(max_active=args.slots, hbm_budget=budget) as S:
+        t0 = time.perf_counter()
+        ids, i = [], 0
+        while i < count or S.progress() != (0, 0):
+            now = time.perf_counter() - t0
+            while i < count and arrivals[i] <= now:
+                ids.append(serve_submit(S, W, specs[i])[0])
+                i += 1
+            S.progress()
+            if i < count and arrivals[i] > now:
+                time.sleep(min(5e-4, arrivals[i] - now))
+        wall = time.perf_counter() - t0
+        p50, p99, samples, dof = S.latency()
+        lat_req = []
+        for rid in ids:
+            rc, _, _, tm = S.result(rid)
+            statuses.append(rc)
+            lat_req.append(tm.total_us)
+    lat_req.sort()
+    out = {
+        "metric": METRIC, "value": dof / wall, "unit": "DOF-updates/s", "n_gpus": 1, "steps": int(samples),
+        "warmup": 0, "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64 (2D requests half FP32-refined)", "data": "synthetic",
+        "config": {"workload": f"serving: {count} seeded Poisson arrivals of 1D (C2 velocity) and 2D (C3 rotation) "
+                               "problems, K in [64,65536], N in 4..16 (2D 4..10), 10-500 steps, boundary rows",
+                   "slots": args.slots, "hbm_budget_gib": args.budget_gib, "arrival_rate_per_s": rate,
+                   "closed_loop_dof_per_s": capacity},
+        "step_latency": {"p50_ms": p50, "p99_ms": p99, "samples": samples},
+        "request_latency_ms": {"p50": lat_req[len(lat_req) // 2] / 1e3,
+                               "p99": lat_req[min(len(lat_req) - 1, int(0.99 * len(lat_req)))] / 1e3},
+        "failed_requests": int(sum(1 for r in statuses if r not in (P.SL_OK,))),
+        "wall_s": wall,
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--workload", choices=["c2", "c3"], default="c2",
-                    help="c2: the headline 1D configuration (default); c3: the 2D rotation configuration")
+    ap.add_argument("--workload", choices=["c2", "c3", "serve"], default="c2",
+                    help="c2: the headline 1D configuration (default); c3: the 2D rotation configuration; "
+                         "serve: a Poisson stream of independent problems through the request loop")
+    ap.add_argument("--requests", type=int, default=48, help="serve: number of requests")
+    ap.add_argument("--slots", type=int, default=8, help="serve: requests on the device at once")
+    ap.add_argument("--budget-gib", type=float, default=32.0, help="serve: device memory budget")
     ap.add_argument("--precision", choices=["fp64", "fp32r"], default="fp64",
                     help="c3 only: fp32r stores and applies the remap preconditioner in FP32 (FP64 residuals)")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -202,6 +331,8 @@ def main():
         del src, dst
     if args.workload == "c3":
         return bench_c3(args, torch, P, W, stream)
+    if args.workload == "serve":
+        return bench_serve(args, torch, P, W)
     w = W.c2()
     m = P.from_workload(w, stream=stream.cuda_stream)
     opts = dict(rk=w.rk, constraints=w.cmask, mode=w.mode, energy_maxit=w.energy_maxit, energy_tol=w.energy_tol)
@@ -215,6 +346,7 @@ def main():
     rc, phi, st = m.read()
     T = (args.warmup + args.steps) * w.dt
     l2 = w.l2_error(phi, T)
+    lat = step_latency(torch, m, w.dt, opts, samples=min(200, max(10, args.steps)))
 
     # per-kernel HIP-event timing on the mesh's stream (a second pass)
     nprof = max(10, min(args.steps, 200))
@@ -258,6 +390,7 @@ def main():
                    "K": w.K, "n": w.n, "dofs": w.dofs, "dt": w.dt, "rk": w.rk, "constraints": "B+M+E",
                    "energy_tol": w.energy_tol},
         "l2_error": l2, "l2_time": T, "status": P.status_string(rc), "max_picard": st.max_picard,
+        "step_latency": lat,
         "roofline": roof,
     }
     if not args.no_cpu:

@@ -29,6 +29,7 @@
 #ifndef SL_H
 #define SL_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -203,6 +204,87 @@ sl_status sl_device_field(sl_mesh* m, double** d_phi, void** stream);
  * 3 = 2D constrain) since the last reset.  Errors: SL_E_INVALID. */
 sl_status sl_set_profiling(sl_mesh* m, int32_t enable);
 sl_status sl_kernel_time(sl_mesh* m, int32_t which, double* total_ms, int64_t* launches);
+
+/* Device bytes a mesh with descriptor d holds (all its buffers, and
+ * ghost_rows rows of ghost values for a GHOST mesh), for admission by
+ * memory budget.  d->u0 is not read.  Errors: SL_E_INVALID. */
+sl_status sl_mesh_bytes(const sl_mesh_desc* d, int32_t ghost_rows, size_t* bytes);
+
+/* ------------------------------------------------------------------------
+ * Request loop (continuous batching of independent problems on one GPU).
+ *
+ * A request is a whole transport problem: mesh descriptor (with u0),
+ * velocity, optional divergence and ghost rows, dt, step count and options;
+ * all host arrays are copied at submission.  Requests wait in arrival order
+ * and are admitted while fewer than max_active run and the device memory
+ * they need (sl_mesh_bytes) fits within hbm_budget.  An admitted request
+ * gets its own mesh and stream, and all its steps are queued at once, so
+ * the work of the admitted requests overlaps on the device.  Results do not
+ * depend on what else runs: every kernel is deterministic and per mesh.
+ * One server is used from one host thread.
+ * ------------------------------------------------------------------------ */
+typedef struct sl_server sl_server;
+
+typedef struct {
+    int32_t max_active;   /* requests on the device at once, 1..64 */
+    int32_t reserved;     /* 0 */
+    size_t hbm_budget;    /* bytes of device memory admitted requests may hold */
+} sl_server_desc;
+
+typedef struct {
+    sl_mesh_desc mesh;    /* mesh.u0: host initial field; mesh.stream ignored */
+    const double* a;      /* host nodal velocity, layout of sl_set_velocity */
+    const double* div_a;  /* host nodal divergence or NULL */
+    const double* ghost;  /* host ghost rows (GHOST meshes), layout of sl_set_ghost */
+    int32_t ghost_rows;
+    int32_t nsteps;       /* steps of length dt */
+    double dt;
+    sl_step_opts opts;
+} sl_request;
+
+typedef struct {
+    double queue_us;      /* host time from submission to admission */
+    double total_us;      /* host time from submission to retirement */
+    double device_ms;     /* device time from before the first to after the last step */
+    size_t bytes;         /* device memory the request held */
+    int64_t admit_seq;    /* order of admission among the server's requests (0 first), -1 if never admitted */
+} sl_request_timing;
+
+/* Errors: SL_E_INVALID (max_active outside 1..64, zero budget), SL_E_NOMEM. */
+sl_status sl_server_create(const sl_server_desc* d, sl_server** out);
+
+/* Queue a request; *id names it in sl_server_result.  Errors: SL_E_INVALID
+ * (bad request or descriptor), SL_E_NOMEM (it could never fit the budget,
+ * or host memory). */
+sl_status sl_server_submit(sl_server* s, const sl_request* r, int64_t* id);
+
+/* Non-blocking: retire finished requests (field and statistics copied to
+ * host memory, mesh freed), then admit waiting ones in arrival order.  A
+ * request whose set-up or step validation fails is finished with that
+ * status.  *active / *waiting (may be NULL) receive the counts after the
+ * call.  Errors: SL_E_INVALID, SL_E_DEVICE. */
+sl_status sl_server_progress(sl_server* s, int32_t* active, int32_t* waiting);
+
+/* Run progress until nothing is active or waiting, blocking on the oldest
+ * active request in between.  Errors: those of sl_server_progress. */
+sl_status sl_server_drain(sl_server* s);
+
+/* Result of a finished request: the field (host, K * n^dim doubles; may be
+ * NULL), its statistics and timing (may be NULL); then the request is
+ * forgotten.  Returns the request's own status (that of its sl_read or of
+ * its failed set-up), SL_E_STATE if it is not finished, SL_E_INVALID for an
+ * unknown id. */
+sl_status sl_server_result(sl_server* s, int64_t id, double* u_out, sl_stats* st, sl_request_timing* tm);
+
+/* Per-step device latency over all retired requests' steps (the time
+ * between the events that bracket consecutive steps of one request, so it
+ * includes waiting behind the other requests' work): p50 and p99 in ms; the
+ * number of samples and the DOF-updates of the retired requests.  Errors:
+ * SL_E_INVALID. */
+sl_status sl_server_latency(sl_server* s, double p50_p99[2], int64_t* samples, int64_t* dof_updates);
+
+/* Wait for active requests, free everything.  Errors: SL_E_INVALID. */
+sl_status sl_server_destroy(sl_server* s);
 
 #ifdef __cplusplus
 }

@@ -30,7 +30,9 @@ KER_ADV1D, KER_CON1D, KER_ADV2D, KER_CON2D = 0, 1, 2, 3
 
 EXPORTS = ["sl_create_mesh", "sl_set_velocity", "sl_set_ghost", "sl_ghost_count", "sl_step", "sl_read",
            "sl_destroy_mesh", "sl_status_string", "sl_max_dt", "sl_node_coords", "sl_device_field",
-           "sl_set_profiling", "sl_kernel_time"]
+           "sl_set_profiling", "sl_kernel_time", "sl_mesh_bytes", "sl_server_create", "sl_server_submit",
+           "sl_server_progress", "sl_server_drain", "sl_server_result", "sl_server_latency",
+           "sl_server_destroy"]
 
 
 class MeshDesc(ctypes.Structure):
@@ -57,6 +59,22 @@ class Stats(ctypes.Structure):
 
     def asdict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class ServerDesc(ctypes.Structure):
+    _fields_ = [("max_active", ctypes.c_int32), ("reserved", ctypes.c_int32), ("hbm_budget", ctypes.c_size_t)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("mesh", MeshDesc), ("a", ctypes.POINTER(ctypes.c_double)),
+                ("div_a", ctypes.POINTER(ctypes.c_double)), ("ghost", ctypes.POINTER(ctypes.c_double)),
+                ("ghost_rows", ctypes.c_int32), ("nsteps", ctypes.c_int32), ("dt", ctypes.c_double),
+                ("opts", StepOpts)]
+
+
+class RequestTiming(ctypes.Structure):
+    _fields_ = [("queue_us", ctypes.c_double), ("total_us", ctypes.c_double), ("device_ms", ctypes.c_double),
+                ("bytes", ctypes.c_size_t), ("admit_seq", ctypes.c_int64)]
 
 
 class SLError(RuntimeError):
@@ -94,6 +112,14 @@ def lib():
         L.sl_device_field.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp)]
         L.sl_set_profiling.argtypes = [vp, ctypes.c_int32]
         L.sl_kernel_time.argtypes = [vp, ctypes.c_int32, dp, ctypes.POINTER(ctypes.c_int64)]
+        L.sl_mesh_bytes.argtypes = [ctypes.POINTER(MeshDesc), ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]
+        L.sl_server_create.argtypes = [ctypes.POINTER(ServerDesc), ctypes.POINTER(vp)]
+        L.sl_server_submit.argtypes = [vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_int64)]
+        L.sl_server_progress.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+        L.sl_server_drain.argtypes = [vp]
+        L.sl_server_result.argtypes = [vp, ctypes.c_int64, dp, ctypes.POINTER(Stats), ctypes.POINTER(RequestTiming)]
+        L.sl_server_latency.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
+        L.sl_server_destroy.argtypes = [vp]
         for name in EXPORTS:
             if name not in ("sl_status_string", "sl_max_dt", "sl_ghost_count"):
                 getattr(L, name).restype = ctypes.c_int32
@@ -248,3 +274,75 @@ def from_workload(w, stream=None, precision=SL_PREC_FP64):
     a, _ = w.velocity()
     m.set_velocity(a)
     return m
+
+
+def sl_mesh_bytes(dim, kx, ky, order, bc=SL_BC_PERIODIC, ghost_rows=0) -> int:
+    d = MeshDesc(dim, kx, ky, order, SL_NODES_GL, bc, SL_FORM_ADVECTIVE, SL_PREC_FP64, 0.0, 1.0, 0.0, 1.0,
+                 ctypes.POINTER(ctypes.c_double)(), None)
+    b = ctypes.c_size_t()
+    _check(lib().sl_mesh_bytes(ctypes.byref(d), int(ghost_rows), ctypes.byref(b)), "sl_mesh_bytes")
+    return int(b.value)
+
+
+class Server:
+    """Request loop over the sl_server_* entry points (continuous batching of
+    independent problems; see include/sl.h).  Host arrays are copied at
+    submission, so the caller's arrays may be reused at once."""
+
+    def __init__(self, max_active=8, hbm_budget=8 << 30):
+        h = ctypes.c_void_p()
+        _check(lib().sl_server_create(ctypes.byref(ServerDesc(int(max_active), 0, int(hbm_budget))),
+                                      ctypes.byref(h)), "sl_server_create")
+        self.h = h
+        self._sizes = {}
+
+    def submit(self, dim, kx, ky, order, u0, a, dt, nsteps, div_a=None, ghost=None, nodes=SL_NODES_GL,
+               bc=SL_BC_PERIODIC, form=SL_FORM_ADVECTIVE, precision=SL_PREC_FP64, x0=0.0, x1=1.0, y0=0.0, y1=1.0,
+               **opts):
+        u0, a, div_a, ghost = _f64(u0), _f64(a), _f64(div_a), _f64(ghost)
+        n = order + 1
+        nd = n if dim == 1 else n * n
+        ng = 2 if dim == 1 else 2 * n * (kx + ky)
+        rows = 0 if ghost is None else ghost.size // ng
+        mesh = MeshDesc(dim, kx, ky, order, nodes, bc, form, precision, x0, x1, y0, y1, _dp(u0), None)
+        req = Request(mesh, _dp(a), _dp(div_a), _dp(ghost), rows, int(nsteps), float(dt), step_opts(**opts))
+        rid = ctypes.c_int64()
+        _check(lib().sl_server_submit(self.h, ctypes.byref(req), ctypes.byref(rid)), "sl_server_submit")
+        self._sizes[rid.value] = kx * ky * nd
+        return rid.value
+
+    def progress(self):
+        a, w = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().sl_server_progress(self.h, ctypes.byref(a), ctypes.byref(w)), "sl_server_progress")
+        return a.value, w.value
+
+    def drain(self):
+        _check(lib().sl_server_drain(self.h), "sl_server_drain")
+
+    def result(self, rid):
+        """(status, field, Stats, RequestTiming) of a finished request."""
+        out = np.zeros(self._sizes.get(rid, 0))
+        st, tm = Stats(), RequestTiming()
+        rc = lib().sl_server_result(self.h, int(rid), _dp(out), ctypes.byref(st), ctypes.byref(tm))
+        if rc == SL_E_STATE or rc == SL_E_INVALID:
+            raise SLError(rc, "sl_server_result")
+        self._sizes.pop(rid, None)
+        return rc, out, st, tm
+
+    def latency(self):
+        """(p50 ms, p99 ms, samples, DOF-updates) over retired requests."""
+        pp = np.zeros(2)
+        n, dof = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().sl_server_latency(self.h, _dp(pp), ctypes.byref(n), ctypes.byref(dof)), "sl_server_latency")
+        return float(pp[0]), float(pp[1]), int(n.value), int(dof.value)
+
+    def close(self):
+        if self.h:
+            _check(lib().sl_server_destroy(self.h), "sl_server_destroy")
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

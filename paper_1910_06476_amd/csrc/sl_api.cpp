@@ -84,6 +84,25 @@ bool dalloc(T** p, size_t count)
     return hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T)) == hipSuccess;
 }
 
+// element counts of a mesh's device buffers (the single place that sizes them)
+struct BufSizes {
+    size_t nf, nrec, nvf, ntab, nstat, nflag;
+    int nblocks;
+};
+BufSizes buffer_sizes(int dim, int kx, int ky, int n)
+{
+    BufSizes z;
+    const size_t K = (size_t)kx * ky;
+    z.nf = K * (dim == 1 ? n : n * n);
+    z.nblocks = dim == 1 ? blocks1d(n, (int)K) : blocks2d(n, (int)K);
+    z.nrec = dim == 1 ? K * 8 : K * (12 * n + 2);
+    z.nvf = dim == 1 ? K + 1 : K * 4 * n;
+    z.ntab = (size_t)tab_offsets(dim, n).total;
+    z.nstat = (size_t)z.nblocks * kStatSlots;
+    z.nflag = (size_t)2 * z.nblocks;
+    return z;
+}
+
 // 2D Gram constants are not needed; 1D rows l(0), l(1), W
 void gram1d(const sl_mesh* m, double g[6])
 {
@@ -212,14 +231,13 @@ sl_status sl_create_mesh(const sl_mesh_desc* d, sl_mesh** out)
         if (hipStreamCreateWithFlags(&m->stream, hipStreamNonBlocking) != hipSuccess) { delete m; return SL_E_DEVICE; }
         m->own_stream = true;
     }
-    m->nblocks = m->dim == 1 ? blocks1d(n, m->K) : blocks2d(n, m->K);
-    const size_t nrec = m->dim == 1 ? (size_t)m->K * 8 : (size_t)m->K * (12 * n + 2);
-    const size_t nvf = m->dim == 1 ? (size_t)m->K + 1 : (size_t)m->K * 4 * n;
-    bool ok = dalloc(&m->phi, nf) && dalloc(&m->phi2, nf) && dalloc(&m->phihat, nf) &&
-              dalloc(&m->rec, nrec) && dalloc(&m->aN, nf * m->dim) && dalloc(&m->aM, nf * m->dim) &&
-              dalloc(&m->divN, nf) && dalloc(&m->divM, nf) && dalloc(&m->vface, nvf) &&
-              dalloc(&m->tab, (size_t)m->off.total) && dalloc(&m->stat_part, (size_t)m->nblocks * kStatSlots) &&
-              dalloc(&m->flag_part, (size_t)2 * m->nblocks) && dalloc(&m->vdeg_d, 1);
+    const BufSizes z = buffer_sizes(m->dim, m->kx, m->ky, n);
+    m->nblocks = z.nblocks;
+    bool ok = dalloc(&m->phi, z.nf) && dalloc(&m->phi2, z.nf) && dalloc(&m->phihat, z.nf) &&
+              dalloc(&m->rec, z.nrec) && dalloc(&m->aN, z.nf * m->dim) && dalloc(&m->aM, z.nf * m->dim) &&
+              dalloc(&m->divN, z.nf) && dalloc(&m->divM, z.nf) && dalloc(&m->vface, z.nvf) &&
+              dalloc(&m->tab, z.ntab) && dalloc(&m->stat_part, z.nstat) && dalloc(&m->flag_part, z.nflag) &&
+              dalloc(&m->vdeg_d, 1);
     if (!ok) { release(m); delete m; return SL_E_NOMEM; }
 
     std::vector<double> tab(m->off.total, 0.0);
@@ -258,6 +276,20 @@ sl_status sl_destroy_mesh(sl_mesh* m)
     (void)hipStreamSynchronize(m->stream);
     release(m);
     delete m;
+    return SL_OK;
+}
+
+sl_status sl_mesh_bytes(const sl_mesh_desc* d, int32_t ghost_rows, size_t* bytes)
+{
+    if (!d || !bytes || (d->dim != 1 && d->dim != 2) || d->kx < 1 || d->ky < 1 || ghost_rows < 0) return SL_E_INVALID;
+    const int n = d->order + 1;
+    if (d->order < 1 || n > (d->dim == 1 ? kMax1D : kMax2D) || (d->dim == 1 && d->ky != 1)) return SL_E_INVALID;
+    if ((int64_t)d->kx * d->ky > (1 << 26)) return SL_E_INVALID;
+    const BufSizes z = buffer_sizes(d->dim, d->kx, d->ky, n);
+    const size_t ng = d->dim == 1 ? 2 : (size_t)2 * n * (d->kx + d->ky);
+    const size_t dbl = 3 * z.nf + z.nrec + 2 * z.nf * d->dim + 2 * z.nf + z.nvf + z.ntab + z.nstat +
+                       (d->bc == SL_BC_GHOST ? ng * ghost_rows : 0);
+    *bytes = dbl * sizeof(double) + (z.nflag + 1) * sizeof(int32_t);
     return SL_OK;
 }
 

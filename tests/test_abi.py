@@ -87,3 +87,45 @@ def test_null_handles_rejected(sl):
     assert L.sl_set_velocity(None, None, None) == sl.SL_E_INVALID
     assert L.sl_max_dt(None, 1.0) == 0.0
     assert L.sl_ghost_count(None) == 0
+
+
+def test_mesh_bytes_host_only(sl):
+    b1 = sl.sl_mesh_bytes(1, 1000, 1, 8)
+    b2 = sl.sl_mesh_bytes(1, 2000, 1, 8)
+    assert 0 < b1 < b2 <= 2 * b1 + 4096
+    # 1D: three fields, two velocity arrays, two divergence arrays at least
+    assert b1 >= 7 * 1000 * 9 * 8
+    g0 = sl.sl_mesh_bytes(2, 16, 16, 4, bc=sl.SL_BC_GHOST, ghost_rows=0)
+    g3 = sl.sl_mesh_bytes(2, 16, 16, 4, bc=sl.SL_BC_GHOST, ghost_rows=3)
+    assert g3 - g0 == 3 * 2 * 5 * (16 + 16) * 8
+    with pytest.raises(sl.SLError):
+        sl.sl_mesh_bytes(2, 4, 4, 11)  # 12 nodes per direction: beyond the 2D limit
+    with pytest.raises(sl.SLError):
+        sl.sl_mesh_bytes(1, 4, 2, 4)   # 1D with ky != 1
+
+
+def test_server_host_side_validation(sl):
+    """Creation, submission and result lookup are host-only: descriptor
+    checks, the budget check and the request table."""
+    with pytest.raises(sl.SLError):
+        sl.Server(max_active=0)
+    with pytest.raises(sl.SLError):
+        sl.Server(max_active=65)
+    s = sl.Server(max_active=2, hbm_budget=1 << 20)
+    try:
+        n = 5
+        u0 = np.zeros(4096 * n)
+        a = np.ones(4096 * n)
+        with pytest.raises(sl.SLError) as e:  # needs more than the 1 MiB budget
+            s.submit(1, 4096, 1, n - 1, u0, a, dt=1e-4, nsteps=1)
+        assert e.value.status == sl.SL_E_NOMEM
+        rid = s.submit(1, 16, 1, n - 1, np.zeros(16 * n), np.ones(16 * n), dt=1e-4, nsteps=1)
+        with pytest.raises(sl.SLError) as e:  # waiting, not finished
+            s.result(rid)
+        assert e.value.status == sl.SL_E_STATE
+        with pytest.raises(sl.SLError):
+            s.result(rid + 100)
+        with pytest.raises(sl.SLError):  # ghost mesh without ghost rows
+            s.submit(1, 16, 1, n - 1, np.zeros(16 * n), np.ones(16 * n), dt=1e-4, nsteps=1, bc=sl.SL_BC_GHOST)
+    finally:
+        s.close()
