@@ -73,6 +73,8 @@ def lib():
         L.ora_nodes.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp]
         L.ora_lagrange.argtypes = [ctypes.c_int, dp, ctypes.c_double, dp]
         L.ora_ghost_count.argtypes = [ctypes.POINTER(Params)]
+        L.ora_step_mixed.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_int32), dp, ctypes.c_double,
+                                     ctypes.c_int, dp, ctypes.POINTER(Stats)]
         L.ora_step.argtypes = [ctypes.POINTER(Params), dp, dp, dp, ctypes.c_int, ctypes.c_double,
                                ctypes.c_int, dp, ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(Stats)]
         L.ora_rk_tableau.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_int), dp, dp, dp]
@@ -205,3 +207,23 @@ def run_workload(w, nsteps=None, analytic=False, ghost_t0=0.0, **over):
     a, _ = w.velocity()
     ghost = w.ghost_rows(ghost_t0, nsteps) if w.bc == 1 else None
     return step(p, w.initial(), a=a, ghost=ghost, dt=w.dt, nsteps=nsteps)
+
+
+def step_mixed(p: Params, orders, phi, a=None, dt=0.0, nsteps=1):
+    """Mixed-order 2D step (periodic, boundary rows): orders[K] nodes per
+    direction per element; phi and each velocity component concatenated
+    element by element (n_e^2 values each); a = u values then v values."""
+    orders = np.ascontiguousarray(orders, dtype=np.int32)
+    phi = np.array(phi, dtype=np.float64, copy=True)
+    if phi.size != int((orders.astype(np.int64) ** 2).sum()):
+        raise ValueError("phi has the wrong size")
+    nullp = ctypes.POINTER(ctypes.c_double)()
+    a_ = None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+    if p.vel_kind == 0 and (a_ is None or a_.size != 2 * phi.size):
+        raise ValueError("nodal velocity required")
+    st = Stats()
+    rc = lib().ora_step_mixed(ctypes.byref(p), orders.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                              _p(a_) if a_ is not None else nullp, float(dt), int(nsteps), _p(phi), ctypes.byref(st))
+    if rc:
+        raise ValueError("oracle rejected the parameters")
+    return phi, st

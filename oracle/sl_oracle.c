@@ -1160,6 +1160,205 @@ int ora_step(const ora_params* p, const double* a, const double* div, const doub
     return 0;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Mixed orders in 2D: every element has its own number of nodes n_e.       */
+/*                                                                          */
+/* Each element is handled as a one-element mesh with its own box and     */
+/* order (a "view"), so the element-local steps above apply unchanged: the */
+/* particle motion and the remap of eq. 5.4, the traces, and the boundary  */
+/* least squares.  What couples elements of different orders is the face  */
+/* value: the upwind side's remapped polynomial is evaluated at this        */
+/* element's own edge nodes (reading: the neighbour's edge polynomial       */
+/* evaluated at the element's edge points), and the face speed is the mean  */
+/* of the two sides' velocity interpolants at the same physical point.     */
+/* Periodic meshes, boundary rows only (HARD or SOFT).                      */
+/*                                                                          */
+/*   orders  [K] nodes per direction of each element, element e = ix+kx*iy  */
+/*   a       nodal velocity: all u values (element by element, n_e^2 each,  */
+/*           node i + n_e j), then all v values                             */
+/*   phi     in/out, element by element (n_e^2 values each)                 */
+/* Returns 0, or 1 on invalid parameters.                                    */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    ora_params p;   /* the element as a 1x1 mesh */
+    ctx c;
+    double* au;     /* [2][nd] velocity of the element (u then v) */
+    double* div;    /* [nd] */
+    double *CB, *CBp, *PB;
+} elem_view;
+
+static int view_init(const ora_params* p, int e, int n, const double* a_u, const double* a_v, double dt,
+                     double vzero, elem_view* v)
+{
+    memset(v, 0, sizeof(*v));
+    v->p = *p;
+    int ex = e % p->kx, ey = e / p->kx;
+    double dx = (p->x1 - p->x0) / p->kx, dy = (p->y1 - p->y0) / p->ky;
+    v->p.kx = v->p.ky = 1;
+    v->p.n = n;
+    v->p.x0 = p->x0 + ex * dx;
+    v->p.x1 = v->p.x0 + dx;
+    v->p.y0 = p->y0 + ey * dy;
+    v->p.y1 = v->p.y0 + dy;
+    ctx* c = &v->c;
+    c->p = &v->p;
+    c->n = n;
+    c->nd = n * n;
+    c->K = 1;
+    c->dx = dx;
+    c->dy = dy;
+    c->dt = dt;
+    c->vzero = vzero;
+    if (ora_nodes(p->family, n, c->xi, c->w)) return 1;
+    if (rk_tableau(p->rk, &c->T)) return 1;
+    lag_basis(n, c->xi, 0.0, c->l0);
+    lag_basis(n, c->xi, 1.0, c->l1);
+    int nd = n * n;
+    v->au = malloc(sizeof(double) * 2 * nd);
+    v->div = malloc(sizeof(double) * nd);
+    if (p->vel_kind == 0) {
+        memcpy(v->au, a_u, sizeof(double) * nd);
+        memcpy(v->au + nd, a_v, sizeof(double) * nd);
+        /* divergence of the velocity interpolant at the nodes */
+        double D[64 * 64];
+        for (int i = 0; i < n; ++i) lag_basis_deriv(n, c->xi, c->xi[i], D + i * n);
+        for (int jj = 0; jj < n; ++jj)
+            for (int ii = 0; ii < n; ++ii) {
+                double sx = 0, sy = 0;
+                for (int l = 0; l < n; ++l) sx += D[ii * n + l] * a_u[l + n * jj];
+                for (int m = 0; m < n; ++m) sy += D[jj * n + m] * a_v[ii + n * m];
+                v->div[ii + n * jj] = sx / dx + sy / dy;
+            }
+    } else {
+        memset(v->au, 0, sizeof(double) * 2 * nd);
+        memset(v->div, 0, sizeof(double) * nd);
+    }
+    c->a = v->au;
+    c->div = v->div;
+    v->CB = malloc(sizeof(double) * 4 * n * nd);
+    v->CBp = malloc(sizeof(double) * 4 * n * nd);
+    v->PB = malloc(sizeof(double) * nd * nd);
+    build_CB(c, v->CB);
+    build_CBpinv(c, v->CB, v->CBp);
+    for (int i = 0; i < nd; ++i)
+        for (int j = 0; j < nd; ++j) {
+            double sum = 0;
+            for (int t = 0; t < 4 * n; ++t) sum += v->CBp[i * 4 * n + t] * v->CB[t * nd + j];
+            v->PB[i * nd + j] = (i == j ? 1.0 : 0.0) - sum;
+        }
+    return 0;
+}
+
+static void view_free(elem_view* v)
+{
+    free(v->au); free(v->div); free(v->CB); free(v->CBp); free(v->PB);
+}
+
+/* normal velocity component of view v at its reference point (s, r):
+ * u on x-faces (sides 0, 1), v on y-faces */
+static double view_normal(const elem_view* v, int side, double s, double r)
+{
+    double u, w, dv;
+    vel_eval(&v->c, 0, s, r, &u, &w, &dv);
+    return side < 2 ? u : w;
+}
+
+int ora_step_mixed(const ora_params* p, const int32_t* orders, const double* a, double dt, int nsteps,
+                   double* phi, ora_stats* st)
+{
+    if (p->dim != 2 || p->bc != 0 || (p->cmask & ~C_BOUND) || p->kx < 1 || p->ky < 1) return 1;
+    int K = p->kx * p->ky;
+    size_t* off = malloc(sizeof(size_t) * (K + 1));
+    off[0] = 0;
+    for (int e = 0; e < K; ++e) {
+        if (orders[e] < 2 || orders[e] > 16) { free(off); return 1; }
+        off[e + 1] = off[e] + (size_t)orders[e] * orders[e];
+    }
+    size_t tot = off[K];
+    /* stagnation threshold: 1e-12 of the largest nodal speed */
+    double vzero = 1e-12;
+    if (p->vel_kind == 0) {
+        double am = 0;
+        for (size_t i = 0; i < 2 * tot; ++i) am = fmax(am, fabs(a[i]));
+        vzero = 1e-12 * am;
+    }
+    elem_view* V = calloc((size_t)K, sizeof(elem_view));
+    int bad = 0;
+    for (int e = 0; e < K && !bad; ++e)
+        bad = view_init(p, e, orders[e], a + off[e], a + tot + off[e], dt, vzero, &V[e]);
+    if (bad) {
+        for (int e = 0; e < K; ++e) view_free(&V[e]);
+        free(V); free(off);
+        return 1;
+    }
+    double* phihat = malloc(sizeof(double) * tot);
+    double* tr = malloc(sizeof(double) * 4 * 16 * (size_t)K);   /* each view's own traces */
+    double* fv = malloc(sizeof(double) * 4 * 16 * (size_t)K);
+    double* out = malloc(sizeof(double) * tot);
+    ora_stats S;
+    memset(&S, 0, sizeof(S));
+    for (int step = 0; step < nsteps; ++step) {
+        int flags = 0;
+        /* phase 1: seed, move and remap each element in its own view */
+#pragma omp parallel for schedule(dynamic, 16) reduction(| : flags)
+        for (int e = 0; e < K; ++e) {
+            work W;
+            memset(&W, 0, sizeof(W));
+            W.phihat = phihat + off[e];
+            W.tr = tr + (size_t)64 * e;
+            flags |= advect_remap(&V[e].c, 0, phi + off[e], &W);
+        }
+        /* phase 2: face values at each element's own edge points; phase 3:
+         * the element's boundary least squares */
+        double rb = 0;
+#pragma omp parallel for schedule(dynamic, 16) reduction(| : flags) reduction(max : rb)
+        for (int e = 0; e < K; ++e) {
+            const elem_view* me = &V[e];
+            int n = orders[e], ex = e % p->kx, ey = e / p->kx;
+            double* f = fv + (size_t)64 * e;
+            for (int t = 0; t < 4 * n; ++t) {
+                int side = t / n;
+                double s, r;
+                trace_point(&me->c, t, &s, &r);
+                /* neighbour across the face (periodic) and the same physical
+                 * point in its reference frame */
+                int nb;
+                double s2 = s, r2 = r;
+                switch (side) {
+                case 0: nb = ey * p->kx + (ex + p->kx - 1) % p->kx; s2 = 1.0; break;
+                case 1: nb = ey * p->kx + (ex + 1) % p->kx; s2 = 0.0; break;
+                case 2: nb = ((ey + p->ky - 1) % p->ky) * p->kx + ex; r2 = 1.0; break;
+                default: nb = ((ey + 1) % p->ky) * p->kx + ex; r2 = 0.0; break;
+                }
+                const elem_view* ot = &V[nb];
+                double v = 0.5 * (view_normal(me, side, s, r) + view_normal(ot, side, s2, r2));
+                if (fabs(v) <= vzero) v = 0.0;
+                double mine = field_eval(&me->c, phihat + off[e], s, r);
+                double other = field_eval(&ot->c, phihat + off[nb], s2, r2);
+                int high = (side == 0 || side == 2);
+                f[t] = upwind(v, high ? other : mine, high ? mine : other);
+            }
+            work W;
+            memset(&W, 0, sizeof(W));
+            W.phihat = phihat + off[e];
+            W.fv = f;
+            cls_out o = constrain(&me->c, 0, &W, me->CB, me->CBp, me->PB, out + off[e]);
+            flags |= o.flags;
+            rb = fmax(rb, o.rb);
+        }
+        for (size_t i = 0; i < tot; ++i) {
+            if (!isfinite(out[i])) flags |= F_NONFINITE;
+            phi[i] = out[i];
+        }
+        S.flags |= flags;
+        S.resid_boundary = fmax(S.resid_boundary, rb);
+    }
+    if (st) *st = S;
+    for (int e = 0; e < K; ++e) view_free(&V[e]);
+    free(V); free(off); free(phihat); free(tr); free(fv); free(out);
+    return 0;
+}
+
 /* Exposed pieces for unit tests of the oracle itself. */
 int ora_rk_tableau(int id, int* s, double* a16, double* b4, double* c4)
 {

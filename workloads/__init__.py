@@ -362,3 +362,126 @@ def random_field_2d(kx: int, ky: int, n: int, seed: int, modes: int = 8, family:
                 break
         f += np.sin(2 * math.pi * (p * x + q * y) + rng.uniform(0, 2 * math.pi))
     return np.ascontiguousarray(f.ravel())
+
+
+# ---------------------------------------------------------------------------
+# Mixed orders in 2D: every element has its own number of nodes n_e per
+# direction.  Arrays are concatenated element by element (e = ix + kx*iy),
+# n_e^2 values each, node i + n_e j with i along x; a velocity array holds
+# all u values, then all v values.
+# ---------------------------------------------------------------------------
+@dataclasses.dataclass
+class MixedWorkload:
+    name: str
+    kx: int
+    ky: int
+    orders: np.ndarray              # [K] nodes per direction per element
+    family: int
+    dt: float
+    nsteps: int
+    u0: Callable                    # (x, y) -> phi
+    vel: Callable                   # (x, y) -> (u, v)
+    mode: int = HARD
+    form: int = ADVECTIVE
+    rk: int = 4
+    x0: float = 0.0
+    x1: float = 1.0
+    y0: float = 0.0
+    y1: float = 1.0
+    exact: Optional[Callable] = None  # (x, y, t) -> phi
+
+    @property
+    def K(self) -> int:
+        return self.kx * self.ky
+
+    @property
+    def dofs(self) -> int:
+        return int((self.orders.astype(np.int64) ** 2).sum())
+
+    @property
+    def offsets(self) -> np.ndarray:
+        return np.concatenate([[0], np.cumsum(self.orders.astype(np.int64) ** 2)])
+
+    def coords(self):
+        dx = (self.x1 - self.x0) / self.kx
+        dy = (self.y1 - self.y0) / self.ky
+        xs, ys = [], []
+        cache = {}
+        for e, n in enumerate(self.orders):
+            n = int(n)
+            if n not in cache:
+                xi = nodes(self.family, n)
+                ii, jj = np.meshgrid(np.arange(n), np.arange(n), indexing="xy")
+                cache[n] = (xi[ii.ravel()], xi[jj.ravel()])
+            sx, sy = cache[n]
+            xs.append(self.x0 + (e % self.kx + sx) * dx)
+            ys.append(self.y0 + (e // self.kx + sy) * dy)
+        return np.concatenate(xs), np.concatenate(ys)
+
+    def initial(self):
+        x, y = self.coords()
+        return np.ascontiguousarray(self.u0(x, y), dtype=np.float64)
+
+    def velocity(self):
+        x, y = self.coords()
+        u, v = self.vel(x, y)
+        return np.ascontiguousarray(np.concatenate([np.broadcast_to(u, x.shape), np.broadcast_to(v, x.shape)]))
+
+    def exact_at(self, t):
+        x, y = self.coords()
+        return self.exact(x, y, t)
+
+    def l2_error(self, phi, t):
+        """Sum over elements of each element's physical L2 error (the paper's
+        norm, eq. 5.2), element by element with its own quadrature."""
+        x, y = self.coords()
+        err = np.asarray(phi) - self.exact(x, y, t)
+        dx = (self.x1 - self.x0) / self.kx
+        dy = (self.y1 - self.y0) / self.ky
+        off = self.offsets
+        tot = 0.0
+        wcache = {}
+        for e, n in enumerate(self.orders):
+            n = int(n)
+            if n not in wcache:
+                wq = gl_weights(n) if self.family == GL else np.full(n, 1.0 / n)
+                wcache[n] = np.outer(wq, wq).ravel()
+            d = err[off[e]:off[e + 1]]
+            tot += math.sqrt(dx * dy * float(np.dot(wcache[n], d * d)))
+        return tot
+
+
+def swirl_velocity(x, y):
+    """a = (sin^2(pi x) sin(2 pi y), -sin^2(pi y) sin(2 pi x)): divergence
+    free, zero normal component on the walls of [0,1]^2, periodic."""
+    sx, sy = np.sin(math.pi * x), np.sin(math.pi * y)
+    return sx * sx * np.sin(2 * math.pi * y), -sy * sy * np.sin(2 * math.pi * x)
+
+
+def fourier_modes(seed: int, modes: int = 8):
+    """u0 = sum of `modes` unit-amplitude sin(2 pi (p x + q y) + theta), with
+    integers (p, q) in [-4, 4]^2 minus the origin and theta uniform, by seed."""
+    rng = np.random.default_rng(seed)
+    terms = []
+    for _ in range(modes):
+        while True:
+            p, q = rng.integers(-4, 5, size=2)
+            if p or q:
+                break
+        terms.append((int(p), int(q), float(rng.uniform(0, 2 * math.pi))))
+    return lambda x, y: sum(np.sin(2 * math.pi * (p * x + q * y) + th) for p, q, th in terms)
+
+
+def c4(kx: int = 316, ky: Optional[int] = None, nsteps: int = 100, seed: int = 0,
+       orders=(4, 6, 8, 12)) -> MixedWorkload:
+    """Mixed-order batch: kx x ky quads on [0,1]^2 (316 x 316 = 99,856 by
+    default), per-element order drawn from `orders` by seed, swirl velocity,
+    eight random Fourier modes, periodic, boundary rows (HARD), RK4,
+    dt = 0.2 * (min node spacing of the largest order) * dx / max |a|."""
+    ky = kx if ky is None else ky
+    rng = np.random.default_rng(seed)
+    n_e = np.asarray(orders)[rng.integers(0, len(orders), size=kx * ky)] + 1
+    nmax = int(max(orders)) + 1
+    dt = 0.2 * min_gap(GL, nmax) * (1.0 / max(kx, ky)) / 1.0
+    return MixedWorkload(name="c4", kx=kx, ky=ky, orders=n_e.astype(np.int32), family=GL, dt=dt, nsteps=nsteps,
+                         u0=fourier_modes(seed + 1), vel=swirl_velocity)
