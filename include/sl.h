@@ -61,7 +61,7 @@ enum { SL_MODE_HARD = 0, SL_MODE_SOFT = 1 };
  *   dim        1 or 2
  *   kx, ky     elements per direction (ky = 1 in 1D); kx * ky <= 2^26
  *   order      polynomial order N >= 1 (n = N + 1 nodes per direction);
- *              1D: N <= 16, 2D: N <= 10
+ *              1D: N <= 16, 2D: N <= 12
  *   nodes      SL_NODES_GL (default) or SL_NODES_CG (paper, eq. gaussquad)
  *   bc         SL_BC_PERIODIC, or SL_BC_GHOST (inflow values from sl_set_ghost)
  *   form       SL_FORM_ADVECTIVE or SL_FORM_CONSERVATIVE
@@ -71,13 +71,24 @@ enum { SL_MODE_HARD = 0, SL_MODE_SOFT = 1 };
  *              still converges to the FP64 solution; 1D rejects it)
  *   x0,x1,y0,y1 box (y ignored in 1D), x1 > x0, y1 > y0
  *   u0         host, K * n^dim initial values (layout above)
- *   stream     hipStream_t to run on, or NULL for a stream the mesh creates */
+ *   stream     hipStream_t to run on, or NULL for a stream the mesh creates
+ *   orders     NULL, or (2D, periodic) host array of K per-element orders
+ *              N_e in 1..12 for a mixed-order mesh: element e then has
+ *              n_e = N_e + 1 nodes per direction, `order` is ignored, and
+ *              every per-node array (u0, velocity components, the field of
+ *              sl_read) holds the elements one after another, n_e^2 values
+ *              each, node i + n_e j.  Elements of different orders are
+ *              coupled through the face values: the upwind side's edge
+ *              polynomial is evaluated at the element's own edge nodes.
+ *              Mixed-order meshes take boundary rows only (HARD or SOFT);
+ *              their steps run as a captured HIP graph. */
 typedef struct {
     int32_t dim, kx, ky, order;
     int32_t nodes, bc, form, precision;
     double x0, x1, y0, y1;
     const double* u0;
     void* stream;
+    const int32_t* orders;
 } sl_mesh_desc;
 
 /* Step options (sl_step); a NULL pointer means all defaults.

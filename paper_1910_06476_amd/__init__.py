@@ -40,7 +40,8 @@ class MeshDesc(ctypes.Structure):
                 ("order", ctypes.c_int32), ("nodes", ctypes.c_int32), ("bc", ctypes.c_int32),
                 ("form", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("x0", ctypes.c_double), ("x1", ctypes.c_double), ("y0", ctypes.c_double),
-                ("y1", ctypes.c_double), ("u0", ctypes.POINTER(ctypes.c_double)), ("stream", ctypes.c_void_p)]
+                ("y1", ctypes.c_double), ("u0", ctypes.POINTER(ctypes.c_double)), ("stream", ctypes.c_void_p),
+                ("orders", ctypes.POINTER(ctypes.c_int32))]
 
 
 class StepOpts(ctypes.Structure):
@@ -153,10 +154,13 @@ def sl_node_coords(nodes: int, n: int):
 
 
 def sl_create_mesh(dim, kx, ky, order, u0, nodes=SL_NODES_GL, bc=SL_BC_PERIODIC, form=SL_FORM_ADVECTIVE,
-                   precision=SL_PREC_FP64, x0=0.0, x1=1.0, y0=0.0, y1=1.0, stream=None):
+                   precision=SL_PREC_FP64, x0=0.0, x1=1.0, y0=0.0, y1=1.0, stream=None, orders=None):
+    """orders: None, or per-element orders N_e (mixed-order 2D mesh)."""
     u0 = _f64(u0)
+    od = None if orders is None else np.ascontiguousarray(orders, dtype=np.int32)
     d = MeshDesc(dim, kx, ky, order, nodes, bc, form, precision, x0, x1, y0, y1, _dp(u0),
-                 ctypes.c_void_p(stream) if stream else None)
+                 ctypes.c_void_p(stream) if stream else None,
+                 od.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)) if od is not None else None)
     h = ctypes.c_void_p()
     _check(lib().sl_create_mesh(ctypes.byref(d), ctypes.byref(h)), "sl_create_mesh")
     return h
@@ -232,6 +236,8 @@ class Mesh:
         self.n = order + 1
         self.nd = self.n if dim == 1 else self.n * self.n
         self.K = kx * ky
+        orders = kw.get("orders")
+        self.size = self.K * self.nd if orders is None else int(((np.asarray(orders, dtype=np.int64) + 1) ** 2).sum())
         self.h = sl_create_mesh(dim, kx, ky, order, u0, **kw)
 
     def set_velocity(self, a, div_a=None):
@@ -244,7 +250,7 @@ class Mesh:
         sl_step(self.h, dt, nsteps, step_opts(**opts))
 
     def read(self):
-        return sl_read(self.h, self.K * self.nd)
+        return sl_read(self.h, self.size)
 
     def max_dt(self, cfl=1.0):
         return sl_max_dt(self.h, cfl)
@@ -265,6 +271,15 @@ class Mesh:
             self.close()
         except Exception:
             pass
+
+
+def from_mixed_workload(w, stream=None, precision=SL_PREC_FP64):
+    """Mixed-order mesh for a workloads.MixedWorkload, velocity set."""
+    m = Mesh(2, w.kx, w.ky, int(w.orders[0]) - 1, w.initial(), nodes=w.family, bc=SL_BC_PERIODIC, form=w.form,
+             precision=precision, x0=w.x0, x1=w.x1, y0=w.y0, y1=w.y1, stream=stream,
+             orders=np.asarray(w.orders, dtype=np.int32) - 1)
+    m.set_velocity(w.velocity())
+    return m
 
 
 def from_workload(w, stream=None, precision=SL_PREC_FP64):

@@ -300,12 +300,20 @@ __device__ double backtrace2(const Step2DArgs& A, const double* cu, const double
 // M^n + dt sum_q bu_q V_q, E^n + dt sum_q bu_q V'_q with the volume terms
 // V of the balance laws (eq. 4.14 generalised to the RK quadrature).
 // ---------------------------------------------------------------------------
-template <int N, bool P32, bool TGT>
-__global__ __launch_bounds__(kBlock2) void k_advect2d(Step2DArgs A)
+// block shapes of the advect kernel: 0 = 256 lanes, 1 = the fewest whole
+// waves that hold one element, 2 = 512 lanes
+template <int N, int BSEL> struct Shape2 {
+    static constexpr int ND = N * N;
+    static constexpr int BS = BSEL == 0 ? kBlock2 : BSEL == 1 ? ((ND + 63) / 64) * 64 : 2 * kBlock2;
+    static constexpr int E = BS / ND;
+};
+
+template <int N, bool P32, bool TGT, int BSEL = 0>
+__global__ __launch_bounds__((Shape2<N, BSEL>::BS)) void k_advect2d(Step2DArgs A)
 {
     using O = Off2<N>;
     using PT = typename std::conditional<P32, float, double>::type;
-    constexpr int ND = N * N, E = kBlock2 / ND, NB = 4 * N;
+    constexpr int ND = N * N, E = Shape2<N, BSEL>::E, NB = 4 * N;
     __shared__ double s_cu[E][ND], s_cv[E][ND], s_cd[E][ND];
     __shared__ double s_x[E][ND], s_r[E][ND], s_f[E][ND];
     __shared__ PT s_z[E][ND];
@@ -1003,6 +1011,178 @@ __global__ __launch_bounds__(kBlock2) void k_constrain2d_me(Step2DArgs A)
     }
 }
 
+// ---------------------------------------------------------------------------
+// mixed-order meshes (periodic, boundary rows): elements are grouped in
+// buckets of one order; each launch covers one bucket.  The face value at an
+// element's own edge point comes from the upwind side; when the neighbour
+// has another order its edge polynomial (its n' traces along the shared
+// edge) is interpolated to this element's edge nodes by a precomputed
+// n x n' Lagrange matrix, which is exact for that polynomial.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void periodic_partner(int e, int side, int kx, int ky, int& nbe, bool& high)
+{
+    const int ex = e % kx, ey = e / kx;
+    switch (side) {
+    case 0: nbe = ey * kx + (ex + kx - 1) % kx; high = true; break;
+    case 1: nbe = ey * kx + (ex + 1) % kx; high = false; break;
+    case 2: nbe = ((ey + ky - 1) % ky) * kx + ex; high = true; break;
+    default: nbe = ((ey + 1) % ky) * kx + ex; high = false; break;
+    }
+}
+
+// normal velocity of element j of bucket b (order n) at its own edge point
+// q of side sd: the u (x-faces) or v (y-faces) interpolant on that edge
+__device__ double edge_speed_mixed(const int* meta, const double* __restrict__ aN_all,
+                                   const double* __restrict__ tab_all, int b, int j, int sd, int q)
+{
+    const int n = meta[MixMeta::kN + b], nd = n * n;
+    const double* lv = tab_all + meta[MixMeta::kTab + b] + ((sd & 1) ? 3 * n : 2 * n);  // l(1) or l(0)
+    const double* base = aN_all + meta[MixMeta::kVel + b];
+    double s = 0.0;
+    if (sd < 2) {
+        const double* U = base + (size_t)j * nd;
+        for (int c = 0; c < n; ++c) s = fma(lv[c], U[c + n * q], s);
+    } else {
+        const double* V = base + ((size_t)meta[MixMeta::kK + b] + j) * nd;
+        for (int c = 0; c < n; ++c) s = fma(lv[c], V[q + n * c], s);
+    }
+    return s;
+}
+
+// face normal velocity at the own edge points of one bucket's elements: the
+// mean of this element's normal velocity interpolant and the neighbour's,
+// both at this element's edge node (the neighbour's edge values
+// interpolated when its order differs); at or below vzero it is zero
+template <int N>
+__global__ void k_facevel2d_mixed(int K_b, int bucket, int kx, int ky, const int32_t* __restrict__ elems,
+                                  const int32_t* __restrict__ mix, const double* __restrict__ aN_all,
+                                  const double* __restrict__ tab_all, const double* __restrict__ interp,
+                                  double vzero, double* __restrict__ vface)
+{
+    constexpr int NB = 4 * N;
+    const int K = kx * ky;
+    const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= (long)K_b * NB) return;
+    const int i = (int)(gid / NB), tt = (int)(gid % NB);
+    const int side = tt / N, k = tt % N;
+    const int e = elems[i];
+    const int* meta = mix + 2 * K;
+    double vn = edge_speed_mixed(meta, aN_all, tab_all, bucket, i, side, k);
+    int nbe;
+    bool high;
+    periodic_partner(e, side, kx, ky, nbe, high);
+    const int b2 = mix[nbe], j2 = mix[K + nbe];
+    const int n2 = meta[MixMeta::kN + b2];
+    const int s2 = side ^ 1;  // the neighbour's side on the shared face
+    double other = 0.0;
+    if (n2 == N) {
+        other = edge_speed_mixed(meta, aN_all, tab_all, b2, j2, s2, k);
+    } else {
+        const double* M = interp + meta[MixMeta::kInterp + kMaxBuckets * bucket + b2];
+        for (int q = 0; q < n2; ++q) other = fma(M[k * n2 + q], edge_speed_mixed(meta, aN_all, tab_all, b2, j2, s2, q), other);
+    }
+    vn = 0.5 * (vn + other);
+    if (fabs(vn) <= vzero) vn = 0.0;
+    vface[(size_t)i * NB + tt] = vn;
+}
+
+// boundary least squares of one bucket's elements (as k_constrain2d), with
+// the neighbour's trace taken from its bucket and interpolated to this
+// element's edge nodes when the orders differ
+template <int N>
+__global__ __launch_bounds__(kBlock2) void k_constrain2d_mixed(Step2DArgs A)
+{
+    using O = Off2<N>;
+    constexpr int ND = N * N, E = kBlock2 / ND, NB = 4 * N, NQ = 16 * ND;
+    __shared__ double s_q[NQ];
+    __shared__ double s_d[E][NB], s_rb[E][NB], s_fv[E][NB], s_y[E][ND];
+    __shared__ int s_flag;
+    __shared__ unsigned long long s_stat;
+
+    const int t = threadIdx.x;
+    const int slot = t / ND, p = t - slot * ND;
+    const bool inblk = slot < E;
+    const double* __restrict__ tab = A.tab;
+    const int K_b = A.K, Kall = A.kx * A.ky;
+    const int* meta = A.mix + 2 * Kall;
+    const double* Qg = tab + (A.mode == SL_MODE_HARD ? O::QH : O::QS);
+    for (int k = t; k < NQ; k += kBlock2) s_q[k] = Qg[k];
+    if (t == 0) {
+        s_flag = 0;
+        s_stat = 0ull;
+    }
+    const int i = p % N, j = p / N;
+    const double l0i = tab[O::L0 + i], l1i = tab[O::L1 + i], l0j = tab[O::L0 + j], l1j = tab[O::L1 + j];
+    const int nchunk = (K_b + E - 1) / E;
+
+    for (int chunk = blockIdx.x; chunk < nchunk; chunk += gridDim.x) {
+        const int li = chunk * E + slot;  // index within the bucket
+        const bool live = inblk && li < K_b;
+        const int ll = live ? li : 0;
+        const size_t g = (size_t)ll * ND + p;
+        const double ph = live ? A.phihat[g] : 0.0;
+        const double* myrec = A.rec + (size_t)ll * NB;
+
+        for (int tt = p; inblk && tt < NB; tt += ND) {
+            const int side = tt / N, k = tt % N;
+            int nbe;
+            bool high;
+            periodic_partner(A.elems[ll], side, A.kx, A.ky, nbe, high);
+            const int b2 = A.mix[nbe], j2 = A.mix[Kall + nbe];
+            const int n2 = meta[MixMeta::kN + b2];
+            const double* tr2 = A.rec_all + meta[MixMeta::kRec + b2] + (size_t)j2 * 4 * n2 + (side ^ 1) * n2;
+            double other = 0.0;
+            if (n2 == N) {
+                other = tr2[k];
+            } else {
+                const double* M = A.interp + meta[MixMeta::kInterp + kMaxBuckets * A.bucket + b2];
+                for (int q = 0; q < n2; ++q) other = fma(M[k * n2 + q], tr2[q], other);
+            }
+            const double mine = myrec[tt];
+            const double vn = A.vface[(size_t)ll * NB + tt];
+            const double dv = upwind2(vn, high ? other : mine, high ? mine : other);
+            s_fv[slot][tt] = dv;
+            s_rb[slot][tt] = dv - mine;
+        }
+        __syncthreads();
+
+        double phi = ph;
+        for (int tt = p; inblk && tt < NB; tt += ND) {
+            double z = 0.0;
+            for (int q = 0; q < NB; ++q) z = fma(s_q[tt * NB + q], s_rb[slot][q], z);
+            s_d[slot][tt] = z;
+        }
+        __syncthreads();
+        if (inblk)
+            phi = ph + l0i * s_d[slot][j] + l1i * s_d[slot][N + j] + l0j * s_d[slot][2 * N + i] +
+                  l1j * s_d[slot][3 * N + i];
+        if (inblk) s_y[slot][p] = phi;
+        __syncthreads();
+        int fl = 0;
+        if (live) {
+            if (!isfinite(phi)) fl |= FLAG_NONFINITE;
+            A.phi_out[g] = phi;
+            for (int tt = p; tt < NB; tt += ND) {
+                const int side = tt / N, k = tt % N;
+                const double* lv = tab + ((side & 1) ? O::L1 : O::L0);
+                double tr = 0.0;
+                if (side < 2)
+                    for (int c = 0; c < N; ++c) tr = fma(lv[c], s_y[slot][c + N * k], tr);
+                else
+                    for (int c = 0; c < N; ++c) tr = fma(lv[c], s_y[slot][k + N * c], tr);
+                atomicMax(&s_stat, (unsigned long long)__double_as_longlong(fabs(tr - s_fv[slot][tt])));
+            }
+        }
+        if (fl) atomicOr(&s_flag, fl);
+        __syncthreads();  // s_fv, s_rb, s_d, s_y are rewritten by the next chunk
+    }
+    if (t == 0) {
+        if (s_flag) A.flag_part[A.nblk + blockIdx.x] |= s_flag;
+        double* sp = A.stat_part + (size_t)blockIdx.x * kStatSlots;
+        sp[0] = fmax(sp[0], __longlong_as_double((long long)s_stat));
+    }
+}
+
 template <int N>
 int prep_n(int K, int has_div, int cons, const double* aN, double* aM, double* divN, double* divM,
            const double* tab, double dx, double dy, double vscale, int* vdeg, hipStream_t s)
@@ -1031,9 +1211,22 @@ void adv_launch(const Step2DArgs& A, dim3 grid, hipStream_t s)
     else hipLaunchKernelGGL((k_advect2d<N, P32, false>), grid, dim3(kBlock2), 0, s, A);
 }
 
+template <int N, int BSEL>
+void adv_shape(const Step2DArgs& A, hipStream_t s)
+{
+    using S = Shape2<N, BSEL>;
+    hipLaunchKernelGGL((k_advect2d<N, false, false, BSEL>), dim3((A.K + S::E - 1) / S::E), dim3(S::BS), 0, s, A);
+}
+
 template <int N>
 int adv_n(const Step2DArgs& A, hipStream_t s)
 {
+    // the alternative block shapes exist for the FP64 boundary-rows kernel
+    if (A.bs != 0 && A.precision != SL_PREC_FP32_REFINED && !A.targets) {
+        if (A.bs == 1) adv_shape<N, 1>(A, s);
+        else adv_shape<N, 2>(A, s);
+        return hipGetLastError() == hipSuccess ? 0 : 1;
+    }
     constexpr int E = kBlock2 / (N * N);
     const dim3 grid((A.K + E - 1) / E);
     if (A.precision == SL_PREC_FP32_REFINED) adv_launch<N, true>(A, grid, s);
@@ -1053,7 +1246,37 @@ int con_n(const Step2DArgs& A, hipStream_t s)
     return hipGetLastError() == hipSuccess ? 0 : 1;
 }
 
+template <int N>
+int facevel_mixed_n(int K_b, int bucket, int kx, int ky, const int32_t* elems, const int32_t* mix,
+                    const double* aN_all, const double* tab_all, const double* interp, double vzero, double* vface,
+                    hipStream_t s)
+{
+    const int bs = 256;
+    const long tot = (long)K_b * 4 * N;
+    hipLaunchKernelGGL(k_facevel2d_mixed<N>, dim3((unsigned)((tot + bs - 1) / bs)), dim3(bs), 0, s, K_b, bucket, kx, ky,
+                       elems, mix, aN_all, tab_all, interp, vzero, vface);
+    return hipGetLastError() == hipSuccess ? 0 : 1;
+}
+
+template <int N>
+int con_mixed_n(const Step2DArgs& A, hipStream_t s)
+{
+    constexpr int E = kBlock2 / (N * N);
+    const int nchunk = (A.K + E - 1) / E;
+    hipLaunchKernelGGL(k_constrain2d_mixed<N>, dim3(nchunk < kConGrid ? nchunk : kConGrid), dim3(kBlock2), 0, s, A);
+    return hipGetLastError() == hipSuccess ? 0 : 1;
+}
+
 }  // namespace
+
+int advect2d_shapes(int n) { return n >= 2 && n <= kMax2D ? 3 : 0; }
+
+int advect2d_elems(int n, int bs)
+{
+    const int nd = n * n;
+    const int BS = bs == 0 ? kBlock2 : bs == 1 ? ((nd + 63) / 64) * 64 : 2 * kBlock2;
+    return BS / nd;
+}
 
 int blocks2d(int n, int K)
 {
@@ -1066,7 +1289,7 @@ int blocks2d(int n, int K)
     switch (n) {                                                                                               \
     case 2: return CALL(2); case 3: return CALL(3); case 4: return CALL(4); case 5: return CALL(5);            \
     case 6: return CALL(6); case 7: return CALL(7); case 8: return CALL(8); case 9: return CALL(9);            \
-    case 10: return CALL(10); case 11: return CALL(11);                                                        \
+    case 10: return CALL(10); case 11: return CALL(11); case 12: return CALL(12); case 13: return CALL(13);    \
     default: return 1;                                                                                         \
     }
 
@@ -1084,6 +1307,22 @@ int launch_facevel2d(int n, int kx, int ky, int periodic, const double* aN, cons
 #define FV2(N) facevel_n<N>(kx, ky, periodic, aN, tab, vzero, vface, s)
     SL2D_SWITCH(n, FV2)
 #undef FV2
+}
+
+int launch_facevel2d_mixed(int n, int K_b, int bucket, int kx, int ky, const int32_t* elems, const int32_t* mix,
+                           const double* aN_all, const double* tab_all, const double* interp, double vzero,
+                           double* vface, hipStream_t s)
+{
+#define FVM(N) facevel_mixed_n<N>(K_b, bucket, kx, ky, elems, mix, aN_all, tab_all, interp, vzero, vface, s)
+    SL2D_SWITCH(n, FVM)
+#undef FVM
+}
+
+int launch_constrain2d_mixed(int n, const Step2DArgs& A, hipStream_t s)
+{
+#define CONM(N) con_mixed_n<N>(A, s)
+    SL2D_SWITCH(n, CONM)
+#undef CONM
 }
 
 int launch_advect2d(int n, const Step2DArgs& A, hipStream_t s)

@@ -38,6 +38,23 @@ struct sl_mesh {
     std::vector<hipEvent_t> pending[KER_COUNT];
     double ktime[KER_COUNT];
     int64_t kcount[KER_COUNT];
+    // mixed-order meshes: elements grouped by order in buckets b (ascending
+    // n); per-node arrays on the device are bucket after bucket
+    bool mixed;
+    int nbk;
+    int bn[kMaxBuckets], bK[kMaxBuckets], bs[kMaxBuckets], bdeg[kMaxBuckets];
+    size_t bOff[kMaxBuckets], aOff[kMaxBuckets], recOff[kMaxBuckets], tabOff[kMaxBuckets], elemOff[kMaxBuckets];
+    std::vector<int32_t> orders;       // n_e per global element
+    std::vector<size_t> uoff;          // caller layout offset of element e (n_e^2 values each)
+    std::vector<size_t> doff;          // device (bucket) layout offset of element e
+    int32_t *elems_d, *mix_d;
+    double *interp_d;
+    size_t dofs;
+    hipGraph_t graph;
+    hipGraphExec_t gexec;
+    bool graph_ok;
+    double graph_dt;
+    sl_step_opts graph_opts;
 };
 
 namespace {
@@ -65,6 +82,11 @@ void release(sl_mesh* m)
     dfree(m->phi); dfree(m->phi2); dfree(m->phihat); dfree(m->rec); dfree(m->eloc); dfree(m->aN);
     dfree(m->aM); dfree(m->divN); dfree(m->divM); dfree(m->vface); dfree(m->tab); dfree(m->ghost);
     dfree(m->stat_part); dfree(m->flag_part); dfree(m->vdeg_d);
+    dfree(m->elems_d); dfree(m->mix_d); dfree(m->interp_d);
+    if (m->gexec) (void)hipGraphExecDestroy(m->gexec);
+    if (m->graph) (void)hipGraphDestroy(m->graph);
+    m->gexec = nullptr;
+    m->graph = nullptr;
     for (int k = 0; k < KER_COUNT; ++k)
         for (hipEvent_t e : m->pending[k]) (void)hipEventDestroy(e);
     if (m->own_stream && m->stream) (void)hipStreamDestroy(m->stream);
@@ -171,6 +193,163 @@ bool rk_tableau(int order, RKTab* T)
 
 }  // namespace sl
 
+
+// ===========================================================================
+// mixed-order meshes
+// ===========================================================================
+namespace {
+
+// Lagrange basis of nodes xf[0..nf) at x, product form (exact at the nodes)
+double lag_at(const double* xf, int nf, int j, double x)
+{
+    double v = 1.0;
+    for (int i = 0; i < nf; ++i)
+        if (i != j) v *= (x - xf[i]) / (xf[j] - xf[i]);
+    return v;
+}
+
+struct MixedPlan {
+    int nbk = 0;
+    int bn[kMaxBuckets] = {}, bK[kMaxBuckets] = {};
+    size_t dofs = 0, nrec = 0, ntab = 0, ninterp = 0;
+    int nblocks = 1;
+};
+
+// buckets and buffer sizes of a mixed-order descriptor (validated)
+bool mixed_plan(const sl_mesh_desc* d, MixedPlan* P)
+{
+    if (d->dim != 2 || d->bc != SL_BC_PERIODIC || d->kx < 1 || d->ky < 1) return false;
+    if ((int64_t)d->kx * d->ky > (1 << 26)) return false;
+    const int K = d->kx * d->ky;
+    int count[kMax2D + 1] = {};
+    for (int e = 0; e < K; ++e) {
+        const int n = d->orders[e] + 1;
+        if (d->orders[e] < 1 || n > kMax2D) return false;
+        ++count[n];
+    }
+    for (int n = 2; n <= kMax2D; ++n)
+        if (count[n]) {
+            const int b = P->nbk++;
+            P->bn[b] = n;
+            P->bK[b] = count[n];
+            P->dofs += (size_t)count[n] * n * n;
+            P->nrec += (size_t)count[n] * 4 * n;
+            P->ntab += (size_t)tab_offsets(2, n).total;
+            P->nblocks = std::max(P->nblocks, count[n]);
+        }
+    for (int a = 0; a < P->nbk; ++a)
+        for (int b = 0; b < P->nbk; ++b)
+            if (a != b) P->ninterp += (size_t)P->bn[a] * P->bn[b];
+    return true;
+}
+
+size_t mixed_bytes(const sl_mesh_desc* d, const MixedPlan& P)
+{
+    const size_t K = (size_t)d->kx * d->ky;
+    const size_t dbl = 3 * P.dofs + 2 * 2 * P.dofs + 2 * P.dofs + 2 * P.nrec + P.ntab + P.ninterp +
+                       (size_t)P.nblocks * kStatSlots;
+    const size_t ints = 2 * (size_t)P.nblocks + 1 + K + (size_t)MixMeta::size((int)K);
+    return dbl * sizeof(double) + ints * sizeof(int32_t);
+}
+
+// per-bucket arguments of one launch; phi pointers are set per step
+Step2DArgs bucket_args(const sl_mesh* m, int b, double dt, const sl_step_opts& opt)
+{
+    Step2DArgs B;
+    std::memset(&B, 0, sizeof(B));
+    rk_tableau(opt.rk, &B.rk);
+    const int n = m->bn[b];
+    B.phihat = m->phihat + m->bOff[b];
+    B.rec = m->rec + m->recOff[b];
+    B.aN = m->aN + m->aOff[b];
+    B.aM = m->aM + m->aOff[b];
+    B.divN = m->divN + m->bOff[b];
+    B.divM = m->divM + m->bOff[b];
+    B.vface = m->vface + m->recOff[b];
+    B.tab = m->tab + m->tabOff[b];
+    B.gnow = B.gnext = m->vface;
+    B.flag_part = m->flag_part;
+    B.stat_part = m->stat_part;
+    B.nblk = m->nblocks;
+    B.vdeg = m->bdeg[b];
+    B.rstride = 4 * n;
+    B.kx = m->kx;
+    B.ky = m->ky;
+    B.K = m->bK[b];
+    B.periodic = 1;
+    B.cons = m->form == SL_FORM_CONSERVATIVE;
+    B.cmask = opt.constraints;
+    B.mode = opt.mode;
+    B.refine = 60;
+    B.precision = m->precision;
+    B.dx = m->dx;
+    B.dy = m->dy;
+    B.invdx = 1.0 / m->dx;
+    B.invdy = 1.0 / m->dy;
+    B.dt = dt;
+    B.vzero = 1e-12 * std::max(m->amax[0], m->amax[1]);
+    B.bs = m->bs[b] > 0 ? m->bs[b] : 0;
+    B.elems = m->elems_d + m->elemOff[b];
+    B.mix = m->mix_d;
+    B.rec_all = m->rec;
+    B.interp = m->interp_d;
+    B.bucket = b;
+    return B;
+}
+
+// one step of every bucket: all advects (each writes its records), then all
+// constraints (each reads the neighbours' records)
+int mixed_launch_step(const sl_mesh* m, std::vector<Step2DArgs>& B, double* src, double* dst)
+{
+    for (int b = 0; b < m->nbk; ++b) {
+        B[b].phi = src + m->bOff[b];
+        B[b].phi_out = dst + m->bOff[b];
+        if (launch_advect2d(m->bn[b], B[b], m->stream)) return 1;
+    }
+    for (int b = 0; b < m->nbk; ++b)
+        if (launch_constrain2d_mixed(m->bn[b], B[b], m->stream)) return 1;
+    return 0;
+}
+
+// pick, per bucket, the fastest block shape of the advect kernel on the
+// mesh's own data (three timed launches per shape); the statistics the
+// trial launches accumulate are cleared afterwards
+sl_status mixed_autotune(sl_mesh* m, double dt, const sl_step_opts& opt)
+{
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) || hipEventCreate(&e1)) return SL_E_DEVICE;
+    sl_status rc = SL_OK;
+    for (int b = 0; b < m->nbk && rc == SL_OK; ++b) {
+        Step2DArgs B = bucket_args(m, b, dt, opt);
+        B.phi = m->phi + m->bOff[b];
+        B.phi_out = m->phi2 + m->bOff[b];
+        float best = 1e30f;
+        int pick = 0;
+        for (int sh = 0; sh < advect2d_shapes(m->bn[b]) && rc == SL_OK; ++sh) {
+            if (advect2d_elems(m->bn[b], sh) < 1) continue;
+            B.bs = sh;
+            if (launch_advect2d(m->bn[b], B, m->stream)) { rc = SL_E_DEVICE; break; }
+            (void)hipEventRecord(e0, m->stream);
+            for (int r = 0; r < 3; ++r)
+                if (launch_advect2d(m->bn[b], B, m->stream)) rc = SL_E_DEVICE;
+            (void)hipEventRecord(e1, m->stream);
+            float ms = 0.0f;
+            if (hipEventSynchronize(e1) || hipEventElapsedTime(&ms, e0, e1)) rc = SL_E_DEVICE;
+            if (rc == SL_OK && ms < best) { best = ms; pick = sh; }
+        }
+        m->bs[b] = pick;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != SL_OK) return rc;
+    if (hipMemsetAsync(m->stat_part, 0, (size_t)m->nblocks * kStatSlots * sizeof(double), m->stream) ||
+        hipMemsetAsync(m->flag_part, 0, (size_t)2 * m->nblocks * sizeof(int32_t), m->stream))
+        return SL_E_DEVICE;
+    return SL_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* sl_status_string(sl_status s)
@@ -195,11 +374,256 @@ sl_status sl_node_coords(int32_t nodes, int32_t n, double* xi, double* w)
     return node_rule(nodes, n, xi, w) ? SL_OK : SL_E_INVALID;
 }
 
+static void ev_begin(sl_mesh* m, int k);
+static void ev_end(sl_mesh* m, int k);
+
+// mixed-order mesh: buckets, tables, interpolation matrices, meta data and
+// the initial field in bucket layout (validated by mixed_plan)
+static sl_status create_mixed(const sl_mesh_desc* d, sl_mesh** out)
+{
+    MixedPlan P;
+    if (!mixed_plan(d, &P)) return SL_E_INVALID;
+    if (d->nodes != SL_NODES_GL && d->nodes != SL_NODES_CG) return SL_E_INVALID;
+    if (d->form != SL_FORM_ADVECTIVE && d->form != SL_FORM_CONSERVATIVE) return SL_E_INVALID;
+    if (d->precision != SL_PREC_FP64 && d->precision != SL_PREC_FP32_REFINED) return SL_E_INVALID;
+    if (!(d->x1 > d->x0) || !(d->y1 > d->y0) || !std::isfinite(d->x0) || !std::isfinite(d->x1) ||
+        !std::isfinite(d->y0) || !std::isfinite(d->y1))
+        return SL_E_INVALID;
+    const int K = d->kx * d->ky;
+    if (!all_finite(d->u0, P.dofs)) return SL_E_NONFINITE;
+    sl_mesh* m = new (std::nothrow) sl_mesh();
+    if (!m) return SL_E_NOMEM;
+    m->mixed = true;
+    m->dim = 2; m->kx = d->kx; m->ky = d->ky; m->K = K;
+    m->family = d->nodes; m->bc = d->bc; m->form = d->form; m->precision = d->precision;
+    m->x0 = d->x0; m->x1 = d->x1; m->y0 = d->y0; m->y1 = d->y1;
+    m->dx = (d->x1 - d->x0) / d->kx;
+    m->dy = (d->y1 - d->y0) / d->ky;
+    m->nbk = P.nbk;
+    m->n = P.bn[P.nbk - 1];  // largest order: its edge gap is the smallest
+    m->nd = m->n * m->n;
+    m->dofs = P.dofs;
+    if (!build_tables(m->family, m->n, &m->T)) { delete m; return SL_E_INVALID; }
+    m->off = tab_offsets(2, m->n);
+    // bucket offsets
+    size_t bo = 0, ro = 0, to = 0, eo = 0;
+    for (int b = 0; b < P.nbk; ++b) {
+        const int n = P.bn[b];
+        m->bn[b] = n;
+        m->bK[b] = P.bK[b];
+        m->bs[b] = -1;
+        m->bOff[b] = bo;
+        m->aOff[b] = 2 * bo;
+        m->recOff[b] = ro;
+        m->tabOff[b] = to;
+        m->elemOff[b] = eo;
+        bo += (size_t)P.bK[b] * n * n;
+        ro += (size_t)P.bK[b] * 4 * n;
+        to += (size_t)tab_offsets(2, n).total;
+        eo += (size_t)P.bK[b];
+    }
+    // element placement: caller layout (element order) and bucket layout
+    int bucket_of[kMax2D + 1];
+    for (int b = 0; b < P.nbk; ++b) bucket_of[P.bn[b]] = b;
+    std::vector<int32_t> meta((size_t)MixMeta::size(K), 0), elems((size_t)K);
+    m->orders.resize(K);
+    m->uoff.resize(K);
+    m->doff.resize(K);
+    int fill[kMaxBuckets] = {};
+    size_t uo = 0;
+    for (int e = 0; e < K; ++e) {
+        const int n = d->orders[e] + 1, b = bucket_of[n], idx = fill[b]++;
+        m->orders[e] = n;
+        m->uoff[e] = uo;
+        uo += (size_t)n * n;
+        m->doff[e] = m->bOff[b] + (size_t)idx * n * n;
+        meta[e] = b;
+        meta[(size_t)K + e] = idx;
+        elems[m->elemOff[b] + idx] = e;
+    }
+    int32_t* mm = meta.data() + 2 * (size_t)K;
+    for (int b = 0; b < P.nbk; ++b) {
+        mm[MixMeta::kN + b] = P.bn[b];
+        mm[MixMeta::kRec + b] = (int32_t)m->recOff[b];
+        mm[MixMeta::kVel + b] = (int32_t)m->aOff[b];
+        mm[MixMeta::kTab + b] = (int32_t)m->tabOff[b];
+        mm[MixMeta::kK + b] = P.bK[b];
+    }
+    // tables per bucket, interpolation matrices between bucket orders
+    std::vector<double> tab(P.ntab, 0.0), interp(std::max<size_t>(P.ninterp, 1), 0.0);
+    std::vector<Tables> T(P.nbk);
+    bool ok = true;
+    for (int b = 0; b < P.nbk && ok; ++b) {
+        const int n = P.bn[b];
+        ok = build_tables(m->family, n, &T[b]);
+        if (!ok) break;
+        const TabOff o = tab_offsets(2, n);
+        double* tb = tab.data() + m->tabOff[b];
+        for (int j = 0; j < n; ++j) {
+            tb[o.xi + j] = T[b].xi[j];
+            tb[o.w + j] = T[b].w[j];
+            tb[o.l0 + j] = T[b].l0[j];
+            tb[o.l1 + j] = T[b].l1[j];
+            tb[o.lam + j] = T[b].lam[j];
+            for (int k = 0; k < n; ++k) {
+                tb[o.tinv + j * n + k] = T[b].Tinv[j * n + k];
+                tb[o.dmat + j * n + k] = T[b].D[j * n + k];
+            }
+        }
+        ok = build_boundary_tables(T[b], tb + o.cbp, tb + o.softs, tb + o.zmh, tb + o.zms);
+    }
+    size_t io = 0;
+    for (int a = 0; a < P.nbk && ok; ++a)
+        for (int b = 0; b < P.nbk; ++b) {
+            if (a == b) continue;
+            mm[MixMeta::kInterp + kMaxBuckets * a + b] = (int32_t)io;
+            for (int k = 0; k < P.bn[a]; ++k)
+                for (int j = 0; j < P.bn[b]; ++j)
+                    interp[io + (size_t)k * P.bn[b] + j] = lag_at(T[b].xi, P.bn[b], j, T[a].xi[k]);
+            io += (size_t)P.bn[a] * P.bn[b];
+        }
+    if (!ok) { delete m; return SL_E_INVALID; }
+    if (d->stream) { m->stream = (hipStream_t)d->stream; m->own_stream = false; }
+    else {
+        if (hipStreamCreateWithFlags(&m->stream, hipStreamNonBlocking) != hipSuccess) { delete m; return SL_E_DEVICE; }
+        m->own_stream = true;
+    }
+    m->nblocks = P.nblocks;
+    ok = dalloc(&m->phi, P.dofs) && dalloc(&m->phi2, P.dofs) && dalloc(&m->phihat, P.dofs) &&
+         dalloc(&m->rec, P.nrec) && dalloc(&m->aN, 2 * P.dofs) && dalloc(&m->aM, 2 * P.dofs) &&
+         dalloc(&m->divN, P.dofs) && dalloc(&m->divM, P.dofs) && dalloc(&m->vface, P.nrec) &&
+         dalloc(&m->tab, P.ntab) && dalloc(&m->stat_part, (size_t)m->nblocks * kStatSlots) &&
+         dalloc(&m->flag_part, (size_t)2 * m->nblocks) && dalloc(&m->vdeg_d, 1) && dalloc(&m->elems_d, (size_t)K) &&
+         dalloc(&m->mix_d, meta.size()) && dalloc(&m->interp_d, interp.size());
+    if (!ok) { release(m); delete m; return SL_E_NOMEM; }
+    std::vector<double> u((size_t)P.dofs);
+    for (int e = 0; e < K; ++e)
+        std::memcpy(&u[m->doff[e]], d->u0 + m->uoff[e], sizeof(double) * m->orders[e] * m->orders[e]);
+    hipError_t r[8] = {
+        hipMemcpyAsync(m->tab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice, m->stream),
+        hipMemcpyAsync(m->phi, u.data(), u.size() * sizeof(double), hipMemcpyHostToDevice, m->stream),
+        hipMemcpyAsync(m->elems_d, elems.data(), elems.size() * sizeof(int32_t), hipMemcpyHostToDevice, m->stream),
+        hipMemcpyAsync(m->mix_d, meta.data(), meta.size() * sizeof(int32_t), hipMemcpyHostToDevice, m->stream),
+        hipMemcpyAsync(m->interp_d, interp.data(), interp.size() * sizeof(double), hipMemcpyHostToDevice, m->stream),
+        hipMemsetAsync(m->stat_part, 0, (size_t)m->nblocks * kStatSlots * sizeof(double), m->stream),
+        hipMemsetAsync(m->flag_part, 0, (size_t)2 * m->nblocks * sizeof(int32_t), m->stream),
+        hipStreamSynchronize(m->stream)};
+    for (hipError_t x : r)
+        if (x != hipSuccess) { release(m); delete m; return SL_E_DEVICE; }
+    *out = m;
+    return SL_OK;
+}
+
+// velocity of a mixed-order mesh: to bucket layout, then per bucket the
+// series coefficients and effective degree, then the face speeds
+static sl_status set_velocity_mixed(sl_mesh* m, const double* a, const double* div_a)
+{
+    const size_t nf = m->dofs;
+    if (!all_finite(a, 2 * nf)) return SL_E_NONFINITE;
+    if (div_a && !all_finite(div_a, nf)) return SL_E_NONFINITE;
+    double am[2] = {0.0, 0.0};
+    for (int c = 0; c < 2; ++c)
+        for (size_t i = 0; i < nf; ++i) am[c] = std::max(am[c], std::fabs(a[c * nf + i]));
+    std::vector<double> da(2 * nf), dd(div_a ? nf : 0);
+    for (int e = 0; e < m->K; ++e) {
+        const int n = m->orders[e], nd = n * n;
+        int b = 0;
+        while (m->bn[b] != n) ++b;
+        const size_t idx = (m->doff[e] - m->bOff[b]) / nd;
+        std::memcpy(&da[m->aOff[b] + idx * nd], a + m->uoff[e], sizeof(double) * nd);
+        std::memcpy(&da[m->aOff[b] + ((size_t)m->bK[b] + idx) * nd], a + nf + m->uoff[e], sizeof(double) * nd);
+        if (div_a) std::memcpy(&dd[m->doff[e]], div_a + m->uoff[e], sizeof(double) * nd);
+    }
+    if (hipMemcpy(m->aN, da.data(), da.size() * sizeof(double), hipMemcpyHostToDevice)) return SL_E_DEVICE;
+    if (div_a && hipMemcpy(m->divN, dd.data(), dd.size() * sizeof(double), hipMemcpyHostToDevice)) return SL_E_DEVICE;
+    const int cons = m->form == SL_FORM_CONSERVATIVE;
+    int vmax = 0;
+    for (int b = 0; b < m->nbk; ++b) {
+        int32_t deg = m->bn[b] - 1;
+        if (hipMemsetAsync(m->vdeg_d, 0, sizeof(int32_t), m->stream) ||
+            launch_prep2d(m->bn[b], m->bK[b], div_a != nullptr, cons, m->aN + m->aOff[b], m->aM + m->aOff[b],
+                          m->divN + m->bOff[b], m->divM + m->bOff[b], m->tab + m->tabOff[b], m->dx, m->dy,
+                          std::max(am[0], am[1]), m->vdeg_d, m->stream) ||
+            hipMemcpyAsync(&deg, m->vdeg_d, sizeof(int32_t), hipMemcpyDeviceToHost, m->stream) ||
+            hipStreamSynchronize(m->stream))
+            return SL_E_DEVICE;
+        m->bdeg[b] = deg;
+        vmax = std::max(vmax, deg);
+    }
+    const double vzero = 1e-12 * std::max(am[0], am[1]);
+    for (int b = 0; b < m->nbk; ++b)
+        if (launch_facevel2d_mixed(m->bn[b], m->bK[b], b, m->kx, m->ky, m->elems_d + m->elemOff[b], m->mix_d, m->aN,
+                                   m->tab, m->interp_d, vzero, m->vface + m->recOff[b], m->stream))
+            return SL_E_DEVICE;
+    if (hipStreamSynchronize(m->stream)) return SL_E_DEVICE;
+    m->vdeg = vmax;
+    m->amax[0] = am[0];
+    m->amax[1] = am[1];
+    m->has_velocity = true;
+    m->graph_ok = false;  // the captured launches carry the degrees
+    return SL_OK;
+}
+
+// steps of a mixed-order mesh (validated by sl_step): autotune once, then
+// replay a captured two-step graph; an odd last step runs eagerly
+static sl_status step_mixed(sl_mesh* m, double dt, int32_t nsteps, const sl_step_opts& opt)
+{
+    if (opt.constraints & (SL_C_MASS | SL_C_ENERGY)) return SL_E_INVALID;
+    bool tuned = true;
+    for (int b = 0; b < m->nbk; ++b) tuned = tuned && m->bs[b] >= 0;
+    if (!tuned) {
+        const sl_status rc = mixed_autotune(m, dt, opt);
+        if (rc != SL_OK) return rc;
+        m->graph_ok = false;
+    }
+    std::vector<Step2DArgs> B(m->nbk);
+    for (int b = 0; b < m->nbk; ++b) B[b] = bucket_args(m, b, dt, opt);
+    int32_t done = 0;
+    if (!m->profiling && nsteps >= 2) {
+        const bool same = m->graph_ok && m->graph_dt == dt && !std::memcmp(&m->graph_opts, &opt, sizeof(opt));
+        if (!same) {
+            if (m->gexec) (void)hipGraphExecDestroy(m->gexec);
+            if (m->graph) (void)hipGraphDestroy(m->graph);
+            m->gexec = nullptr;
+            m->graph = nullptr;
+            m->graph_ok = false;
+            if (hipStreamBeginCapture(m->stream, hipStreamCaptureModeThreadLocal)) return SL_E_DEVICE;
+            const int bad = mixed_launch_step(m, B, m->phi, m->phi2) | mixed_launch_step(m, B, m->phi2, m->phi);
+            hipGraph_t g = nullptr;
+            const hipError_t ec = hipStreamEndCapture(m->stream, &g);
+            if (bad || ec != hipSuccess || !g) {
+                if (g) (void)hipGraphDestroy(g);
+                return SL_E_DEVICE;
+            }
+            m->graph = g;
+            if (hipGraphInstantiate(&m->gexec, m->graph, nullptr, nullptr, 0)) return SL_E_DEVICE;
+            m->graph_ok = true;
+            m->graph_dt = dt;
+            m->graph_opts = opt;
+        }
+        // the graph reads the field from m->phi and leaves it there
+        for (; done + 2 <= nsteps; done += 2)
+            if (hipGraphLaunch(m->gexec, m->stream)) return SL_E_DEVICE;
+    }
+    for (; done < nsteps; ++done) {
+        ev_begin(m, KER_ADV2D);
+        if (mixed_launch_step(m, B, m->phi, m->phi2)) return SL_E_DEVICE;
+        ev_end(m, KER_ADV2D);
+        // the graph captured m->phi as its input: bring the field back there
+        if (hipMemcpyAsync(m->phi, m->phi2, m->dofs * sizeof(double), hipMemcpyDeviceToDevice, m->stream))
+            return SL_E_DEVICE;
+    }
+    m->t += dt * nsteps;
+    m->steps += nsteps;
+    return SL_OK;
+}
+
 sl_status sl_create_mesh(const sl_mesh_desc* d, sl_mesh** out)
 {
     if (!out) return SL_E_INVALID;
     *out = nullptr;
     if (!d || !d->u0) return SL_E_INVALID;
+    if (d->orders) return create_mixed(d, out);
     if (d->dim != 1 && d->dim != 2) return SL_E_INVALID;
     const int n = d->order + 1;
     if (d->order < 1 || n > (d->dim == 1 ? kMax1D : kMax2D)) return SL_E_INVALID;
@@ -282,6 +706,12 @@ sl_status sl_destroy_mesh(sl_mesh* m)
 sl_status sl_mesh_bytes(const sl_mesh_desc* d, int32_t ghost_rows, size_t* bytes)
 {
     if (!d || !bytes || (d->dim != 1 && d->dim != 2) || d->kx < 1 || d->ky < 1 || ghost_rows < 0) return SL_E_INVALID;
+    if (d->orders) {
+        MixedPlan P;
+        if (!mixed_plan(d, &P)) return SL_E_INVALID;
+        *bytes = mixed_bytes(d, P);
+        return SL_OK;
+    }
     const int n = d->order + 1;
     if (d->order < 1 || n > (d->dim == 1 ? kMax1D : kMax2D) || (d->dim == 1 && d->ky != 1)) return SL_E_INVALID;
     if ((int64_t)d->kx * d->ky > (1 << 26)) return SL_E_INVALID;
@@ -296,6 +726,7 @@ sl_status sl_mesh_bytes(const sl_mesh_desc* d, int32_t ghost_rows, size_t* bytes
 sl_status sl_set_velocity(sl_mesh* m, const double* a, const double* div_a)
 {
     if (!m || !a) return SL_E_INVALID;
+    if (m->mixed) return set_velocity_mixed(m, a, div_a);
     const size_t nf = (size_t)m->K * m->nd;
     if (!all_finite(a, nf * m->dim)) return SL_E_NONFINITE;
     if (div_a && !all_finite(div_a, nf)) return SL_E_NONFINITE;
@@ -405,6 +836,7 @@ sl_status sl_step(sl_mesh* m, double dt, int32_t nsteps, const sl_step_opts* o)
         rows - 2 > (m->n - 2) * (m->n - 2))
         return SL_E_INVALID;
 
+    if (m->mixed) return step_mixed(m, dt, nsteps, opt);
     if (m->dim == 2) {
         Step2DArgs B;
         std::memset(&B, 0, sizeof(B));
@@ -511,11 +943,18 @@ sl_status sl_read(sl_mesh* m, double* u_out, sl_stats* st)
 {
     if (!m) return SL_E_INVALID;
     if (hipStreamSynchronize(m->stream)) return SL_E_DEVICE;
-    const size_t nf = (size_t)m->K * m->nd;
+    const size_t nf = m->mixed ? m->dofs : (size_t)m->K * m->nd;
     std::vector<double> host;
     double* dst = u_out;
     if (!dst && st) { host.resize(nf); dst = host.data(); }
-    if (dst && hipMemcpy(dst, m->phi, nf * sizeof(double), hipMemcpyDeviceToHost)) return SL_E_DEVICE;
+    if (dst && m->mixed) {
+        std::vector<double> dev(nf);
+        if (hipMemcpy(dev.data(), m->phi, nf * sizeof(double), hipMemcpyDeviceToHost)) return SL_E_DEVICE;
+        for (int e = 0; e < m->K; ++e)
+            std::memcpy(dst + m->uoff[e], &dev[m->doff[e]], sizeof(double) * m->orders[e] * m->orders[e]);
+    } else if (dst && hipMemcpy(dst, m->phi, nf * sizeof(double), hipMemcpyDeviceToHost)) {
+        return SL_E_DEVICE;
+    }
     std::vector<double> sp((size_t)m->nblocks * kStatSlots);
     std::vector<int32_t> fp((size_t)2 * m->nblocks);
     if (hipMemcpy(sp.data(), m->stat_part, sp.size() * sizeof(double), hipMemcpyDeviceToHost)) return SL_E_DEVICE;
@@ -538,14 +977,29 @@ sl_status sl_read(sl_mesh* m, double* u_out, sl_stats* st)
         st->t = m->t;
         st->steps = m->steps;
         double M = 0, E = 0;
-        for (int e = 0; e < m->K; ++e)
-            for (int p = 0; p < m->nd; ++p) {
-                const int i = p % m->n, j = p / m->n;
-                const double W = m->dx * m->T.w[i] * (m->dim == 2 ? m->dy * m->T.w[j] : 1.0);
-                const double v = dst[(size_t)e * m->nd + p];
-                M += W * v;
-                E += W * v * v;
+        if (m->mixed) {
+            double wq[kMax2D + 1][kMaxTableN] = {};
+            double xq[kMaxTableN];
+            for (int b = 0; b < m->nbk; ++b) node_rule(m->family, m->bn[b], xq, wq[m->bn[b]]);
+            for (int e = 0; e < m->K; ++e) {
+                const int n = m->orders[e];
+                for (int p = 0; p < n * n; ++p) {
+                    const double W = m->dx * m->dy * wq[n][p % n] * wq[n][p / n];
+                    const double v = dst[m->uoff[e] + p];
+                    M += W * v;
+                    E += W * v * v;
+                }
             }
+        } else {
+            for (int e = 0; e < m->K; ++e)
+                for (int p = 0; p < m->nd; ++p) {
+                    const int i = p % m->n, j = p / m->n;
+                    const double W = m->dx * m->T.w[i] * (m->dim == 2 ? m->dy * m->T.w[j] : 1.0);
+                    const double v = dst[(size_t)e * m->nd + p];
+                    M += W * v;
+                    E += W * v * v;
+                }
+        }
         st->mass = M;
         st->energy = E;
         st->resid_boundary = rb;

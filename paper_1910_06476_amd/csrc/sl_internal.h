@@ -10,7 +10,8 @@ namespace sl {
 
 constexpr int kMaxTableN = 32;
 constexpr int kMax1D = 17;  // nodes per element in 1D (order 16)
-constexpr int kMax2D = 11;  // nodes per direction in 2D (order 10)
+constexpr int kMax2D = 13;  // nodes per direction in 2D (order 12)
+constexpr int kMaxBuckets = 16;  // distinct orders of a mixed-order mesh
 
 struct Tables {
     int n;
@@ -106,7 +107,41 @@ struct Step2DArgs {
     int kx, ky, K, periodic, cons, cmask, mode, refine, precision, targets, vol, emaxit;
     double dx, dy, invdx, invdy, dt, vzero, etol;
     RKTab rk;
+    int bs;                // advect block shape: 0 = 256 lanes, 1 = fewest whole waves, 2 = 512 lanes
+    // mixed-order meshes (elements grouped in buckets of one order; this
+    // launch covers one bucket, K above is its element count)
+    const int32_t* elems;  // [K] global element index of the bucket's elements
+    const int32_t* mix;    // device meta data, see MixMeta
+    const double* rec_all; // records of all buckets
+    const double* interp;  // interpolation matrices between the orders
+    int bucket;            // this launch's bucket
 };
+
+// Layout of the int32 meta data of a mixed-order mesh on the device:
+//   [0, K)               bucket of each global element
+//   [K, 2K)              index of each global element within its bucket
+//   [2K + kN + b]        nodes per direction of bucket b (b < kMaxBuckets)
+//   [2K + kRec + b]      offset of bucket b's records in rec_all (doubles)
+//   [2K + kVel + b]      offset of bucket b's nodal velocity in aN_all
+//   [2K + kTab + b]      offset of bucket b's tables in tab_all
+//   [2K + kK + b]        number of elements of bucket b
+//   [2K + kInterp + 16 b_to + b_from]  offset in interp of the n_to x n_from
+//                        matrix taking values at b_from's nodes to b_to's
+// Bucket b's velocity slice is [2][K_b][n_b^2] (u, then v).
+struct MixMeta {
+    static constexpr int kN = 0, kRec = kMaxBuckets, kVel = 2 * kMaxBuckets, kTab = 3 * kMaxBuckets,
+                         kK = 4 * kMaxBuckets, kInterp = 5 * kMaxBuckets;
+    static constexpr int size(int K) { return 2 * K + 5 * kMaxBuckets + kMaxBuckets * kMaxBuckets; }
+};
+
+// face normal velocity of one bucket's elements (aN_all, tab_all: all
+// buckets' velocity and tables, located through mix)
+int launch_facevel2d_mixed(int n, int K_b, int bucket, int kx, int ky, const int32_t* elems, const int32_t* mix,
+                           const double* aN_all, const double* tab_all, const double* interp, double vzero,
+                           double* vface, hipStream_t s);
+int launch_constrain2d_mixed(int n, const Step2DArgs& A, hipStream_t s);
+int advect2d_shapes(int n);            // number of block shapes the advect kernel offers for n
+int advect2d_elems(int n, int bs);     // elements per block of shape bs
 
 int launch_prep2d(int n, int K, int has_div, int cons, const double* aN, double* aM, double* divN, double* divM,
                   const double* tab, double dx, double dy, double vscale, int* vdeg, hipStream_t s);

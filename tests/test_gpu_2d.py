@@ -100,7 +100,7 @@ def test_rk_orders_parity(rk):
     assert rel_l2(g, o) <= TOL, rel_l2(g, o)
 
 
-@pytest.mark.parametrize("n", list(range(2, 12)))
+@pytest.mark.parametrize("n", list(range(2, 14)))
 def test_orders_parity(n):
     w = _swirl_case(4, 5, n, bc=W.GHOST)
     announce(f"2d n={n}")

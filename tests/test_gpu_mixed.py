@@ -1,0 +1,136 @@
+"""GPU parity of mixed-order 2D meshes (per-element orders, periodic,
+boundary rows) against the oracle's mixed-order step, through the C-ABI.
+The device runs the order buckets as separate launches, captured in a HIP
+graph, with block shapes picked by the autotuner; none of that may change a
+result.  Bar: relative L2 <= 1e-12 (FP64)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from _parity import announce, rel_l2
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1910_06476_amd as P
+    P.lib()
+
+
+def _case(kx, ky, orders, seed=0, mode=W.HARD, form=W.ADVECTIVE, nsteps=3):
+    w = W.c4(kx=kx, ky=ky, nsteps=nsteps, seed=seed, orders=orders)
+    w.mode, w.form = mode, form
+    return w
+
+
+def _gpu(w, nsteps=None, profiling=False, precision=0):
+    import paper_1910_06476_amd as P
+    m = P.from_mixed_workload(w, precision=precision)
+    try:
+        if profiling:
+            P.sl_set_profiling(m.h, True)
+        m.step(w.dt, w.nsteps if nsteps is None else nsteps, rk=w.rk, constraints=W.BOUNDARY, mode=w.mode)
+        rc, out, st = m.read()
+    finally:
+        m.close()
+    return out, st, rc
+
+
+def _oracle(w, nsteps=None):
+    p = oracle.Params(dim=2, kx=w.kx, ky=w.ky, n=int(w.orders[0]), family=w.family, bc=W.PERIODIC, form=w.form,
+                      rk=w.rk, cmask=W.BOUNDARY, mode=w.mode, energy_maxit=0, vel_kind=0, x0=w.x0, x1=w.x1,
+                      y0=w.y0, y1=w.y1, energy_tol=0.0)
+    return oracle.step_mixed(p, w.orders, w.initial(), a=w.velocity(), dt=w.dt,
+                             nsteps=w.nsteps if nsteps is None else nsteps)
+
+
+@pytest.mark.parametrize("mode", [W.HARD, W.SOFT])
+@pytest.mark.parametrize("form", [W.ADVECTIVE, W.CONSERVATIVE])
+def test_c4_orders_parity(mode, form):
+    w = _case(6, 5, (4, 6, 8, 12), seed=1, mode=mode, form=form)
+    announce(f"mixed c4 orders mode={mode} form={form}")
+    g, st, rc = _gpu(w)
+    o, ost = _oracle(w)
+    assert rc == 0 and (st.flags & ~2) == 0, (rc, st.flags)
+    assert rel_l2(g, o) <= TOL, rel_l2(g, o)
+
+
+@pytest.mark.parametrize("seed", [2, 3])
+def test_all_orders_parity(seed):
+    """Every order 1..12 present: thirteen... twelve buckets, all pairs of
+    interpolation matrices."""
+    w = _case(7, 6, tuple(range(1, 13)), seed=seed, nsteps=2)
+    announce(f"mixed all orders seed={seed}")
+    g, st, rc = _gpu(w)
+    o, ost = _oracle(w)
+    assert rc == 0
+    assert rel_l2(g, o) <= TOL, rel_l2(g, o)
+
+
+@pytest.mark.parametrize("nsteps", [1, 2, 5])
+def test_graph_replay_equals_eager(nsteps):
+    """Profiling forces the eager path; the graph path must give the same
+    bits, also over several replays and an odd final step."""
+    w = _case(5, 5, (4, 6, 8, 12), seed=4, nsteps=nsteps)
+    announce(f"mixed graph vs eager nsteps={nsteps}")
+    g1, _, _ = _gpu(w, profiling=True)
+    g2, _, _ = _gpu(w)
+    assert np.array_equal(g1, g2)
+
+
+def test_uniform_orders_match_the_uniform_mesh():
+    """All elements of one order through the mixed path equal the uniform
+    mesh bit for bit (same arithmetic, other launches)."""
+    import paper_1910_06476_amd as P
+    w = _case(5, 4, (8,), seed=5)
+    announce("mixed uniform vs uniform mesh")
+    g, _, _ = _gpu(w)
+    n = int(w.orders[0])
+    m = P.Mesh(2, w.kx, w.ky, n - 1, w.initial(), nodes=w.family, bc=P.SL_BC_PERIODIC, form=w.form)
+    try:
+        m.set_velocity(w.velocity())
+        m.step(w.dt, w.nsteps, rk=w.rk, constraints=W.BOUNDARY, mode=w.mode)
+        rc, u, st = m.read()
+    finally:
+        m.close()
+    assert np.array_equal(g, u)
+
+
+def test_c4_submesh_accuracy_and_parity():
+    """A 32x32 piece of the C4 recipe (orders {4,6,8,12}, swirl, eight
+    Fourier modes), five steps: oracle parity of the whole field."""
+    w = _case(32, 32, (4, 6, 8, 12), seed=0, nsteps=5)
+    announce("mixed c4 32x32")
+    g, st, rc = _gpu(w)
+    o, ost = _oracle(w)
+    assert rc == 0
+    assert rel_l2(g, o) <= TOL, rel_l2(g, o)
+
+
+def test_mixed_statistics_and_validation():
+    import paper_1910_06476_amd as P
+    w = _case(4, 4, (4, 6), seed=6, nsteps=2)
+    announce("mixed validation")
+    m = P.from_mixed_workload(w)
+    try:
+        with pytest.raises(P.SLError) as e:  # mass rows are not offered on mixed meshes
+            m.step(w.dt, 1, constraints=W.BOUNDARY | W.MASS)
+        assert e.value.status == P.SL_E_INVALID
+        m.step(w.dt, 2)
+        rc, out, st = m.read()
+        assert rc == 0 and st.steps == 2 and out.size == w.dofs
+        assert st.remap_sweeps_max >= 1
+    finally:
+        m.close()
+    with pytest.raises(P.SLError):  # ghost boundaries are not offered on mixed meshes
+        P.Mesh(2, 2, 2, 3, np.zeros(4 * 16), bc=P.SL_BC_GHOST, orders=[3, 3, 3, 3])
+    with pytest.raises(P.SLError):  # order 13 is beyond the 2D limit
+        P.Mesh(2, 2, 2, 3, np.zeros(3 * 16 + 14 * 14), orders=[3, 3, 3, 13])
