@@ -43,6 +43,21 @@ __device__ __forceinline__ double clenshaw_n(const double (&c)[N], double x)
     return fma(x, b1, c[0] - b2);
 }
 
+// the same over coefficients in LDS (read as the recurrence needs them)
+template <int N>
+__device__ __forceinline__ double clenshaw_p(const double* __restrict__ c, double x)
+{
+    double b1 = 0.0, b2 = 0.0;
+    const double x2 = 2.0 * x;
+#pragma unroll
+    for (int k = N - 1; k >= 1; --k) {
+        double b0 = fma(x2, b1, c[k] - b2);
+        b2 = b1;
+        b1 = b0;
+    }
+    return fma(x, b1, c[0] - b2);
+}
+
 template <int N>
 __device__ __forceinline__ double clenshaw(const double (&c)[N], double x)
 {
@@ -258,8 +273,15 @@ __global__ void k_prep1d(int K, int periodic, int has_div, const double* __restr
 // instruction stream as the node lanes' backtraces from the nodes, and the
 // edge traces of the remapped polynomial while the node lanes remap.
 // ---------------------------------------------------------------------------
+// occupancy the advect kernel asks the register allocator for: five waves
+// per SIMD (at most 96 VGPRs) where that needs no spills (advective form,
+// velocity series of up to four terms), the default elsewhere
+template <bool CONS, int NA> struct AdvOcc {
+    static constexpr int W = (!CONS && NA <= 4) ? 5 : 1;
+};
+
 template <int N, bool CONS, int NA, int RKS>
-__global__ __launch_bounds__(kBlock) void k_advect1d(Step1DArgs A)
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(AdvOcc<CONS, NA>::W))) void k_advect1d(Step1DArgs A)
 {
     const Tab<RKS> RK{A.rk};
     constexpr int L = N + 1;
@@ -314,13 +336,13 @@ __global__ __launch_bounds__(kBlock) void k_advect1d(Step1DArgs A)
     }
     __syncthreads();
 
-    double ca[N], cd[N], cp[N];
+    double ca[N], cd[N];
 #pragma unroll
     for (int k = 0; k < N; ++k) {
         ca[k] = s_a[sl][k];
         cd[k] = CONS ? s_d[sl][k] : 0.0;
-        cp[k] = s_q[sl][k];
     }
+    const double* cp = s_q[sl];  // phi^n coefficients, read from LDS where used
     bool out = false;
     // forward motion of particle i (section 4.2)
     double s = xi_i, q = phi_i;
@@ -350,11 +372,11 @@ __global__ __launch_bounds__(kBlock) void k_advect1d(Step1DArgs A)
                 const double cq = RK.cu(qd);
                 double val;
                 if (cq == 0.0) {
-                    val = node ? phi_i : clenshaw<N>(cp, 2.0 * x0 - 1.0);
+                    val = node ? phi_i : clenshaw_p<N>(cp, 2.0 * x0 - 1.0);
                 } else {
                     double sb = x0, hq = 1.0;
                     rk_move<N, CONS, NA, RKS>(A.rk, ca, cd, -1.0, cq * A.dt, invdx, sb, hq, out, node, a_i, dv_i);
-                    val = hq * clenshaw<N>(cp, 2.0 * sb - 1.0);
+                    val = hq * clenshaw_p<N>(cp, 2.0 * sb - 1.0);
                 }
                 const double bq = RK.bu(qd);
                 if (node) {
@@ -379,9 +401,7 @@ __global__ __launch_bounds__(kBlock) void k_advect1d(Step1DArgs A)
     // same polynomial at 0 and 1 (eq. remap_bnd)
     if (inblk && node) s_x[slot][i] = s;
     __syncthreads();
-    double xs[N];
-#pragma unroll
-    for (int m = 0; m < N; ++m) xs[m] = s_x[sl][m];
+    const double* xs = s_x[sl];  // moved positions, read from LDS where used
     if (node) {
         double pr = 1.0;
 #pragma unroll
@@ -390,9 +410,7 @@ __global__ __launch_bounds__(kBlock) void k_advect1d(Step1DArgs A)
         if (inblk) s_c[slot][i] = q / pr;
     }
     __syncthreads();
-    double cw[N];
-#pragma unroll
-    for (int m = 0; m < N; ++m) cw[m] = s_c[sl][m];
+    const double* cw = s_c[sl];
     const double xe = node ? xi_i : 0.0;
     double S = 0.0, P = 1.0;
 #pragma unroll
@@ -496,22 +514,26 @@ __global__ __launch_bounds__(kConBlock) void k_constrain1d(Step1DArgs A)
     const int ee = live ? e : K - 1;
     const double* __restrict__ tab = A.tab;
 
-    // coalesced staging of the block's phihat
+    // every global load the element needs is issued before the first wait:
+    // the block's phihat (coalesced staging), this lane's table entries, the
+    // face speeds and the own and neighbouring records
+    constexpr int kStage = (kConElems * N + kConBlock - 1) / kConBlock;
     const int cnt = (K - e0 < kConElems ? K - e0 : kConElems) * N;
-    for (int k = t; k < cnt; k += kConBlock) s_buf[k] = A.phihat[(size_t)e0 * N + k];
-    __syncthreads();
-    // this lane's nodes and their table entries (absent nodes are zero rows)
-    double ph[NP], l0[NP], l1[NP], Wn[NP];
+    double v[kStage];
+#pragma unroll
+    for (int r2 = 0; r2 < kStage; ++r2) {
+        const int k = t + r2 * kConBlock;
+        v[r2] = k < cnt ? A.phihat[(size_t)e0 * N + k] : 0.0;
+    }
+    double l0[NP], l1[NP], Wn[NP];
 #pragma unroll
     for (int k = 0; k < NP; ++k) {
         const int j = r + kConQ * k;
         const bool on = j < N;
-        ph[k] = (live && on) ? s_buf[le * N + j] : 0.0;
         l0[k] = on ? tab[O::L0 + j] : 0.0;
         l1[k] = on ? tab[O::L1 + j] : 0.0;
         Wn[k] = on ? A.dx * tab[O::W + j] : 0.0;
     }
-    __syncthreads();
 
     const bool bnd = (A.cmask & SL_C_BOUNDARY) != 0;
     const bool mass = (A.cmask & SL_C_MASS) != 0;
@@ -536,6 +558,7 @@ __global__ __launch_bounds__(kConBlock) void k_constrain1d(Step1DArgs A)
     const double T0p = ep >= 0 ? R[(size_t)ep * 8 + 0] : A.gnext[1];
     const double dB0 = upwind(vL, T1m, Re[0]);
     const double dB1 = upwind(vR, Re[1], T0p);
+
     double Mt = 0.0, Et = 0.0;
     if (A.targets) {
         double gM0 = 0.0, gE0 = 0.0, gM1 = 0.0, gE1 = 0.0;
@@ -558,6 +581,20 @@ __global__ __launch_bounds__(kConBlock) void k_constrain1d(Step1DArgs A)
         Et = Re[7] + A.dt * (vL * FEl - vR * FEr);
     }
 
+#pragma unroll
+    for (int r2 = 0; r2 < kStage; ++r2) {
+        const int k = t + r2 * kConBlock;
+        if (k < kConElems * N) s_buf[k] = v[r2];
+    }
+    __syncthreads();
+    // this lane's nodes (absent nodes are zero rows)
+    double ph[NP];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        const int j = r + kConQ * k;
+        ph[k] = (live && j < N) ? s_buf[le * N + j] : 0.0;
+    }
+    __syncthreads();
     // rows l(0), l(1), W (mass), W*psi (energy); inactive rows are zero
     double Cph[3] = {0.0, 0.0, 0.0};
 #pragma unroll
@@ -719,7 +756,11 @@ __global__ __launch_bounds__(kConBlock) void k_constrain1d(Step1DArgs A)
         }
     }
     __syncthreads();
-    for (int k = t; k < cnt; k += kConBlock) A.phi_out[(size_t)e0 * N + k] = s_buf[k];
+#pragma unroll
+    for (int r2 = 0; r2 < kStage; ++r2) {
+        const int k = t + r2 * kConBlock;
+        if (k < cnt) A.phi_out[(size_t)e0 * N + k] = s_buf[k];
+    }
     if (t == 0) {
         if (fl) A.flag_part[A.nblk + blockIdx.x] |= fl;
         double* sp = A.stat_part + (size_t)blockIdx.x * kStatSlots;
