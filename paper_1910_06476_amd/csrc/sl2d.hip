@@ -353,9 +353,11 @@ __global__ __launch_bounds__((Shape2<N, BSEL>::BS)) void k_advect2d(Step2DArgs A
             if (need_div) dv_p = A.divN[g];
         }
         if (inblk) {
-            s_cu[slot][q] = live ? A.aM[g] : 0.0;
-            s_cv[slot][q] = live ? A.aM[(size_t)K * ND + g] : 0.0;
-            if (A.cons) s_cd[slot][q] = live ? A.divM[g] : 0.0;
+            // only the coefficients within the effective degree are read
+            const bool used = live && ii <= A.vdeg && jj <= A.vdeg;
+            s_cu[slot][q] = used ? A.aM[g] : 0.0;
+            s_cv[slot][q] = used ? A.aM[(size_t)K * ND + g] : 0.0;
+            if (A.cons) s_cd[slot][q] = used ? A.divM[g] : 0.0;
             if (TGT) s_x[slot][q] = phi_p;  // phi^n for the backtraces
         }
     }
@@ -428,6 +430,23 @@ __global__ __launch_bounds__((Shape2<N, BSEL>::BS)) void k_advect2d(Step2DArgs A
     const int d = A.vdeg;
     const double h = A.dt;
     double sx, sy, sq;
+    // A series of degree <= 1 (constant, shear, rotation) is evaluated from
+    // registers: the same operations as the Clenshaw sum at that degree.
+    const bool low = d <= 1;
+    double lu[4] = {0.0, 0.0, 0.0, 0.0}, lv[4] = {0.0, 0.0, 0.0, 0.0}, ld[4] = {0.0, 0.0, 0.0, 0.0};
+    if (low) {
+        const int at[4] = {0, 1, N, N + 1};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            lu[k] = s_cu[sl][at[k]];
+            lv[k] = s_cv[sl][at[k]];
+            if (A.cons) ld[k] = s_cd[sl][at[k]];
+        }
+    }
+    auto vel = [&](const double* C, const double (&c)[4], double x, double y) {
+        if (low) return d == 0 ? c[0] : fma(y, fma(x, c[3], c[2]), fma(x, c[1], c[0]));
+        return cheb2<N>(C, x, y, d);
+    };
     {
         const double s = tab[O::XI + ii], rr0 = tab[O::XI + jj], qv = phi_p;
         double ks[4], kr[4], kq[4];
@@ -448,9 +467,9 @@ __global__ __launch_bounds__((Shape2<N, BSEL>::BS)) void k_advect2d(Step2DArgs A
                     dd = dv_p;
                 } else {
                     const double x = 2.0 * ss - 1.0, y = 2.0 * rr - 1.0;
-                    uu = cheb2<N>(s_cu[sl], x, y, d);
-                    vv = cheb2<N>(s_cv[sl], x, y, d);
-                    if (A.cons) dd = cheb2<N>(s_cd[sl], x, y, d);
+                    uu = vel(s_cu[sl], lu, x, y);
+                    vv = vel(s_cv[sl], lv, x, y);
+                    if (A.cons) dd = vel(s_cd[sl], ld, x, y);
                     out |= inblk && (outside2(ss) || outside2(rr));
                 }
                 ks[st] = uu * A.invdx;
