@@ -177,6 +177,97 @@ __device__ __forceinline__ void rk_move(const RKTab& TT, const double (&ca)[N], 
     out |= outside(s);
 }
 
+// The first NA (<= 4) Chebyshev terms on x = 2s - 1 rewritten as a
+// polynomial in s and multiplied by `scale`: T1 = 2s - 1, T2 = 8s^2 - 8s + 1,
+// T3 = 32s^3 - 48s^2 + 18s - 1.  Horner's rule on it costs NA - 1 FMAs per
+// evaluation against Clenshaw's 2(NA - 1) + 2 operations.  The absolute
+// coefficient sums of T1..T3 in s are 3, 17 and 99, which bounds how much the
+// rewriting can magnify the rounding of each term.
+template <int NA, int N>
+__device__ __forceinline__ void cheb_to_mono(const double (&c)[N], double scale, double (&m)[NA])
+{
+    static_assert(NA >= 1 && NA <= 4 && NA <= N, "term count");
+    const double c0 = c[0];
+    const double c1 = NA > 1 ? c[NA > 1 ? 1 : 0] : 0.0;
+    const double c2 = NA > 2 ? c[NA > 2 ? 2 : 0] : 0.0;
+    const double c3 = NA > 3 ? c[NA > 3 ? 3 : 0] : 0.0;
+    const double mm[4] = {c0 - c1 + c2 - c3, 2.0 * c1 - 8.0 * c2 + 18.0 * c3, 8.0 * c2 - 48.0 * c3, 32.0 * c3};
+#pragma unroll
+    for (int k = 0; k < NA; ++k) m[k] = scale * mm[k];
+}
+
+template <int NA>
+__device__ __forceinline__ double horner(const double (&m)[NA], double s)
+{
+    double u = m[NA - 1];
+#pragma unroll
+    for (int k = NA - 2; k >= 0; --k) u = fma(u, s, m[k]);
+    return u;
+}
+
+// rk_move with the velocity (and divergence) as polynomials in s from
+// cheb_to_mono: mu is the velocity over dx, hs = dir * h the signed step of
+// the position, h the step of q; k_first = the first stage's mu value
+template <bool CONS, int NA, int RKS>
+__device__ __forceinline__ void rk_move_mono(const RKTab& TT, const double (&mu)[NA], const double (&md)[NA],
+                                             double hs, double h, double& s, double& q, bool& out,
+                                             bool have_first, double k_first, double dv_first)
+{
+    const Tab<RKS> T{TT};
+    double ks[4], kq[4];
+    const double s0 = s, q0 = q;
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+        ks[st] = 0.0;
+        kq[st] = 0.0;
+        if (st < T.s()) {
+            double ss = s0, qq = q0;
+#pragma unroll
+            for (int j = 0; j < st; ++j) {
+                if (T.a(st, j) == 0.0) continue;
+                ss += hs * T.a(st, j) * ks[j];
+                if (CONS) qq += h * T.a(st, j) * kq[j];
+            }
+            double u, dv = 0.0;
+            if (st == 0 && have_first) {
+                u = k_first;
+                dv = dv_first;
+            } else {
+                u = horner<NA>(mu, ss);
+                if (CONS) dv = horner<NA>(md, ss);
+                out |= outside(ss);
+            }
+            ks[st] = u;
+            if (CONS) kq[st] = -dv * qq;
+        }
+    }
+    double ds = 0.0, dq = 0.0;
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+        if (st < T.s()) {
+            ds += T.b(st) * ks[st];
+            if (CONS) dq += T.b(st) * kq[st];
+        }
+    }
+    s = s0 + hs * ds;
+    if (CONS) q = q0 + h * dq;
+    out |= outside(s);
+}
+
+// value of a Chebyshev series at x = 1 (edge 1) or x = -1 (edge 0), where
+// T_k is 1 or (-1)^k
+template <int N>
+__device__ __forceinline__ double cheb_end(const double* __restrict__ c, int edge)
+{
+    double ev = c[0], od = N > 1 ? c[1] : 0.0;
+#pragma unroll
+    for (int k = 2; k < N; ++k) {
+        if (k & 1) od += c[k];
+        else ev += c[k];
+    }
+    return edge ? ev + od : ev - od;
+}
+
 __device__ __forceinline__ double upwind(double vn, double lo, double hi)
 {
     if (vn > 0.0) return lo;
@@ -270,18 +361,16 @@ __global__ void k_prep1d(int K, int periodic, int has_div, const double* __restr
 //
 // n + 1 lanes per element: n node lanes and one edge lane.  The edge lane
 // runs the backtraces from the element's upwind edge(s) in the same
-// instruction stream as the node lanes' backtraces from the nodes, and the
-// edge traces of the remapped polynomial while the node lanes remap.
+// instruction stream as the node lanes' backtraces from the nodes, evaluates
+// the remapped polynomial at 0 while the node lanes evaluate it at the nodes,
+// and sums l(1) . phihat while node lanes 0 and 1 sum the mass and energy
+// targets.
 // ---------------------------------------------------------------------------
-// occupancy the advect kernel asks the register allocator for: five waves
-// per SIMD (at most 96 VGPRs) where that needs no spills (advective form,
-// velocity series of up to four terms), the default elsewhere
-template <bool CONS, int NA> struct AdvOcc {
-    static constexpr int W = (!CONS && NA <= 4) ? 5 : 1;
-};
-
+// (Register budget: the compiler's default gives 4 waves per SIMD at order 16
+// with a short velocity series; asking for 5 spills inside the backtraces
+// and measured slower.)
 template <int N, bool CONS, int NA, int RKS>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(AdvOcc<CONS, NA>::W))) void k_advect1d(Step1DArgs A)
+__global__ __launch_bounds__(kBlock) void k_advect1d(Step1DArgs A)
 {
     const Tab<RKS> RK{A.rk};
     constexpr int L = N + 1;
@@ -293,7 +382,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(AdvOcc<C
     __shared__ double s_q[E][N];
     __shared__ double s_x[E][N];
     __shared__ double s_c[E][N];
-    __shared__ double s_r[4][E][N];
+    __shared__ double s_r[2][E][N];
     __shared__ int s_flag;
 
     const int t = threadIdx.x;
@@ -309,7 +398,6 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(AdvOcc<C
     if (t == 0) s_flag = 0;
 
     const double xi_i = tab[O::XI + in];
-    const double W_i = A.dx * tab[O::W + in];
     const double invdx = A.invdx;
     double phi_i = 0.0, a_i = 0.0, dv_i = 0.0;
     if (live && node) {
@@ -336,23 +424,37 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(AdvOcc<C
     }
     __syncthreads();
 
+    // a velocity series of at most four terms is evaluated as a polynomial
+    // in the element coordinate (cheb_to_mono), longer ones by Clenshaw
+    constexpr bool MONO = NA <= 4;
     double ca[N], cd[N];
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-        ca[k] = s_a[sl][k];
-        cd[k] = CONS ? s_d[sl][k] : 0.0;
+        ca[k] = (!MONO || k < NA) ? s_a[sl][k] : 0.0;
+        cd[k] = (CONS && (!MONO || k < NA)) ? s_d[sl][k] : 0.0;
     }
+    constexpr int NM = MONO ? NA : 1;
+    double mu[NM], md[NM];
+    if constexpr (MONO) {
+        cheb_to_mono<NA, N>(ca, invdx, mu);
+        cheb_to_mono<NA, N>(cd, 1.0, md);
+    }
+    const double k_i = a_i * invdx;
     const double* cp = s_q[sl];  // phi^n coefficients, read from LDS where used
     bool out = false;
     // forward motion of particle i (section 4.2)
     double s = xi_i, q = phi_i;
-    if (node) rk_move<N, CONS, NA, RKS>(A.rk, ca, cd, 1.0, A.dt, invdx, s, q, out, true, a_i, dv_i);
+    if (node) {
+        if constexpr (MONO) rk_move_mono<CONS, NA, RKS>(A.rk, mu, md, A.dt, A.dt, s, q, out, true, k_i, dv_i);
+        else rk_move<N, CONS, NA, RKS>(A.rk, ca, cd, 1.0, A.dt, invdx, s, q, out, true, a_i, dv_i);
+    }
 
     // element-local target parts: M^n, E^n, volume term at the RK abscissae
     // (node lanes), edge values at the RK abscissae on the upwind edges (edge
     // lane); backtracking as in eq. 4.11
     double vM = 0.0, vE = 0.0, FM[2] = {0.0, 0.0}, FE[2] = {0.0, 0.0};
     if (A.targets) {
+        const double W_i = A.dx * tab[O::W + in];
         int first = -1, second = -1;
         if (!node && live) {
             const double vL = A.vface[e];
@@ -372,10 +474,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(AdvOcc<C
                 const double cq = RK.cu(qd);
                 double val;
                 if (cq == 0.0) {
-                    val = node ? phi_i : clenshaw_p<N>(cp, 2.0 * x0 - 1.0);
+                    val = node ? phi_i : cheb_end<N>(cp, edge);
                 } else {
                     double sb = x0, hq = 1.0;
-                    rk_move<N, CONS, NA, RKS>(A.rk, ca, cd, -1.0, cq * A.dt, invdx, sb, hq, out, node, a_i, dv_i);
+                    const double h = cq * A.dt;
+                    if constexpr (MONO) rk_move_mono<CONS, NA, RKS>(A.rk, mu, md, -h, h, sb, hq, out, node, k_i, dv_i);
+                    else rk_move<N, CONS, NA, RKS>(A.rk, ca, cd, -1.0, h, invdx, sb, hq, out, node, a_i, dv_i);
                     val = hq * clenshaw_p<N>(cp, 2.0 * sb - 1.0);
                 }
                 const double bq = RK.bu(qd);
@@ -388,26 +492,36 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(AdvOcc<C
                 }
             }
         }
+        // per-node parts of the mass and energy targets with their volume
+        // terms: M^n (+ dt V_M) and E^n +- dt V_E
         if (inblk && node) {
-            s_r[0][slot][i] = W_i * phi_i;
-            s_r[1][slot][i] = W_i * phi_i * phi_i;
-            s_r[2][slot][i] = vM;
-            s_r[3][slot][i] = vE;
+            s_r[0][slot][i] = CONS ? W_i * phi_i : fma(A.dt, vM, W_i * phi_i);
+            s_r[1][slot][i] = fma(CONS ? -A.dt : A.dt, vE, W_i * phi_i * phi_i);
         }
     }
 
     // remap (eq. 4.9): phihat_i = sum_j c_j prod_{m != j} (xi_i - s_m),
     // c_j = phi*_j / prod_{m != j} (s_j - s_m); the edge lane evaluates the
-    // same polynomial at 0 and 1 (eq. remap_bnd)
+    // same polynomial at 0, and its value at 1 is l(1) . phihat (eq.
+    // remap_bnd; the polynomial has degree n - 1, so its nodal interpolant is
+    // itself)
     if (inblk && node) s_x[slot][i] = s;
     __syncthreads();
     const double* xs = s_x[sl];  // moved positions, read from LDS where used
     if (node) {
-        double pr = 1.0;
+        // pr = prod_{m != i} (s_i - s_m) = l'(s_i) for l(x) = prod_m (x - s_m),
+        // by the product rule over the partial products P: the factor
+        // s_i - s_i is exactly zero, after which D carries P_i times the
+        // remaining factors, rounded as the direct product.  No test of m
+        // against i, so every read of s_m is unconditional.
+        double P = 1.0, D = 0.0;
 #pragma unroll
-        for (int m = 0; m < N; ++m)
-            if (m != i) pr *= (s - xs[m]);
-        if (inblk) s_c[slot][i] = q / pr;
+        for (int m = 0; m < N; ++m) {
+            const double d = s - xs[m];
+            D = fma(D, d, P);
+            P *= d;
+        }
+        if (inblk) s_c[slot][i] = q / D;
     }
     __syncthreads();
     const double* cw = s_c[sl];
@@ -419,18 +533,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(AdvOcc<C
         S = fma(S, d, cw[j] * P);
         P *= d;
     }
-    double T1 = 0.0;
-    if (!node) {
-        double S2 = 0.0, P2 = 1.0;
-#pragma unroll
-        for (int j = 0; j < N; ++j) {
-            const double d = 1.0 - xs[j];
-            S2 = fma(S2, d, cw[j] * P2);
-            P2 *= d;
-        }
-        T1 = S2;
-    }
-
+    // s_p (phi^n, read before the second barrier) takes l(1)_i phihat_i
+    // store what is final before the last barrier
     int fl = 0;
     if (live) {
         if (out) fl |= FLAG_CONTAIN;
@@ -440,25 +544,24 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(AdvOcc<C
         } else {
             double* r = A.rec + (size_t)e * 8;
             r[0] = S;
-            r[1] = T1;
             r[2] = FM[0];
             r[3] = FM[1];
             r[4] = FE[0];
             r[5] = FE[1];
         }
-        // local mass (node lane 0) and energy (node lane 1) with their
-        // volume terms, summed in node order
-        if (A.targets && i < 2) {
-            double M = 0.0, V = 0.0;
+    }
+    // s_p (phi^n, read before the second barrier) takes l(1)_i phihat_i
+    if (inblk && node) s_p[slot][i] = tab[O::L1 + i] * S;
+    __syncthreads();
+    // one sum over the element's nodes in three lanes at once: the trace at 1
+    // (edge lane, record slot 1), the mass target (node lane 0, slot 6) and
+    // the energy target (node lane 1, slot 7), each summed in node order
+    if (live && (!node || (A.targets && i < 2))) {
+        const double* src = node ? s_r[i][sl] : s_p[sl];
+        double sum = 0.0;
 #pragma unroll
-            for (int j = 0; j < N; ++j) {
-                M += s_r[i][slot][j];
-                V += s_r[2 + i][slot][j];
-            }
-            double* r = A.rec + (size_t)e * 8;
-            if (i == 0) r[6] = CONS ? M : M + A.dt * V;
-            else r[7] = CONS ? M - A.dt * V : M + A.dt * V;
-        }
+        for (int j = 0; j < N; ++j) sum += src[j];
+        A.rec[(size_t)e * 8 + (node ? 6 + i : 1)] = sum;
     }
     if (fl) atomicOr(&s_flag, fl);
     __syncthreads();

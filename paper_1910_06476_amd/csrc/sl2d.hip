@@ -522,15 +522,21 @@ __global__ __launch_bounds__((Shape2<N, BSEL>::BS)) void k_advect2d(Step2DArgs A
         const int l = ii, c = jj;
         const double xl = tab[O::XI + l];
         const double sc = tab[O::XI + c] + s_mx[slot][c], tc = tab[O::XI + c] + s_my[slot][c];
-        double na = 1.0, da = 1.0, nb = 1.0, db = 1.0;
+        // The denominators by the product rule (the factor at k = c is
+        // exactly zero; see the 1D remap weights), the numerators with a
+        // select: no branch on k == c, so every read is unconditional.
+        double na = 1.0, nb = 1.0, pa = 1.0, da = 0.0, pb = 1.0, db = 0.0;
+#pragma unroll
         for (int k = 0; k < N; ++k) {
-            if (k == c) continue;
             const double sk = tab[O::XI + k] + s_mx[slot][k];
             const double tk = tab[O::XI + k] + s_my[slot][k];
-            na *= (xl - sk);
-            da *= (sc - sk);
-            nb *= (xl - tk);
-            db *= (tc - tk);
+            const double fa = sc - sk, fb = tc - tk;
+            da = fma(da, fa, pa);
+            pa *= fa;
+            db = fma(db, fb, pb);
+            pb *= fb;
+            na *= (k == c) ? 1.0 : xl - sk;
+            nb *= (k == c) ? 1.0 : xl - tk;
         }
         s_ai[slot][q] = (PT)(na / da);
         s_bi[slot][q] = (PT)(nb / db);
