@@ -36,19 +36,22 @@ HBM_PEAK = 8.0e12
 
 def advect_flops_per_element(n: int, s: int, nq: int, targets: bool, vel_terms: int) -> float:
     """Algorithmic FP64 flops of the 1D advect kernel for one element (FMA = 2):
-    Clenshaw evaluation 3 flops per term (vel_terms terms for the velocity
-    series, n for phi^n); RK stage update ~4 flops per stage."""
+    velocity series of at most 4 terms by Horner's rule on its polynomial in
+    the element coordinate (2 flops per term after the first), longer ones
+    and phi^n by Clenshaw (3 flops per term); RK stage update ~4 flops per
+    stage; remap in product form (5 flops per node and point)."""
     clen = 3.0 * n
-    clen_v = 3.0 * vel_terms
+    clen_v = 2.0 * (vel_terms - 1) if vel_terms <= 4 else 3.0 * vel_terms
     rk_move = (s - 1) * clen_v + 4.0 * s
     f = n * rk_move                      # forward motion of the n particles
     f += n * (2.0 * n)                   # moved-point weights lambda*: n-1 (sub, mul) + div
-    f += n * (5.0 * n) + 2 * 5.0 * n     # remap at n nodes + 2 edge traces (product form)
+    f += n * (5.0 * n) + 5.0 * n         # remap at n nodes and at 0 (product form)
+    f += 3.0 * n                         # trace at 1: l(1) . phihat
     if targets:
         f += 2.0 * n * n                 # Chebyshev coefficients of phi^n
         back = rk_move + clen            # one backtrace + evaluation of phi^n at its foot
         f += n * (nq - 1) * (back + 6)   # node backtraces (volume term)
-        f += 2 * ((nq - 1) * (back + 4) + clen)  # edge values at the RK abscissae
+        f += 2 * ((nq - 1) * (back + 4) + n)  # edge values at the RK abscissae (at t^n: end-point sum)
         f += 8.0 * n                     # mass/energy sums
     return f
 

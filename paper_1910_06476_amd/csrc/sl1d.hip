@@ -366,9 +366,10 @@ __global__ void k_prep1d(int K, int periodic, int has_div, const double* __restr
 // and sums l(1) . phihat while node lanes 0 and 1 sum the mass and energy
 // targets.
 // ---------------------------------------------------------------------------
-// (Register budget: the compiler's default gives 4 waves per SIMD at order 16
-// with a short velocity series; asking for 5 spills inside the backtraces
-// and measured slower.)
+// (No occupancy attribute: the edge lane stores its stage sums as soon as
+// they are complete, which keeps the per-lane state small enough for the
+// default allocation to hold five waves per SIMD at order 16 with a short
+// velocity series.)
 template <int N, bool CONS, int NA, int RKS>
 __global__ __launch_bounds__(kBlock) void k_advect1d(Step1DArgs A)
 {
@@ -452,7 +453,7 @@ __global__ __launch_bounds__(kBlock) void k_advect1d(Step1DArgs A)
     // element-local target parts: M^n, E^n, volume term at the RK abscissae
     // (node lanes), edge values at the RK abscissae on the upwind edges (edge
     // lane); backtracking as in eq. 4.11
-    double vM = 0.0, vE = 0.0, FM[2] = {0.0, 0.0}, FE[2] = {0.0, 0.0};
+    double vM = 0.0, vE = 0.0;
     if (A.targets) {
         const double W_i = A.dx * tab[O::W + in];
         int first = -1, second = -1;
@@ -462,12 +463,17 @@ __global__ __launch_bounds__(kBlock) void k_advect1d(Step1DArgs A)
             const bool needL = !(vL > A.vzero), needR = !(vR < -A.vzero);
             first = needL ? 0 : (needR ? 1 : -1);
             second = (needL && needR) ? 1 : -1;
+            // an edge without backtraces has zero stage sums
+            double* rc = A.rec + (size_t)e * 8;
+            if (first != 0 && second != 0) rc[2] = rc[4] = 0.0;
+            if (first != 1 && second != 1) rc[3] = rc[5] = 0.0;
         }
         for (int r = 0; r < 2; ++r) {
             const int edge = (r == 0) ? first : second;
             const bool act = node ? (r == 0 && A.vol && live) : (edge >= 0);
             if (!act) continue;
             const double x0 = node ? xi_i : (double)edge;
+            double am = 0.0, ae = 0.0;  // sum_q bu_q v_q and sum_q bu_q v_q^2
 #pragma unroll
             for (int qd = 0; qd < 4; ++qd) {
                 if (qd >= RK.nq()) break;
@@ -483,13 +489,17 @@ __global__ __launch_bounds__(kBlock) void k_advect1d(Step1DArgs A)
                     val = hq * clenshaw_p<N>(cp, 2.0 * sb - 1.0);
                 }
                 const double bq = RK.bu(qd);
-                if (node) {
-                    vM += bq * (W_i * dv_i * val);
-                    vE += bq * (W_i * dv_i * val * val);
-                } else {
-                    FM[edge] += bq * val;
-                    FE[edge] += bq * val * val;
-                }
+                am += bq * val;
+                ae += bq * val * val;
+            }
+            // node: volume terms; edge lane: the edge's stage sums, stored now
+            if (node) {
+                vM = W_i * dv_i * am;
+                vE = W_i * dv_i * ae;
+            } else {
+                double* rc = A.rec + (size_t)e * 8;
+                rc[2 + edge] = am;
+                rc[4 + edge] = ae;
             }
         }
         // per-node parts of the mass and energy targets with their volume
@@ -542,12 +552,7 @@ __global__ __launch_bounds__(kBlock) void k_advect1d(Step1DArgs A)
             if (!isfinite(S)) fl |= FLAG_SINGULAR;
             A.phihat[g] = S;
         } else {
-            double* r = A.rec + (size_t)e * 8;
-            r[0] = S;
-            r[2] = FM[0];
-            r[3] = FM[1];
-            r[4] = FE[0];
-            r[5] = FE[1];
+            A.rec[(size_t)e * 8] = S;
         }
     }
     // s_p (phi^n, read before the second barrier) takes l(1)_i phihat_i
@@ -607,7 +612,15 @@ __global__ __launch_bounds__(kConBlock) void k_constrain1d(Step1DArgs A)
 {
     using O = Off<N>;
     constexpr int NP = (N + kConQ - 1) / kConQ;
+    constexpr int NR = (kConElems + 2) * 8;  // records of elements e0 - 1 .. e0 + kConElems
+    constexpr int NF = kConElems + 1;        // faces e0 .. e0 + kConElems
+    static_assert(3 * kConQ * NP <= kConBlock && NF <= kConBlock, "one table entry / face per lane");
     __shared__ double s_buf[kConElems * N];
+    __shared__ double s_rec[NR];
+    __shared__ double s_vf[NF];
+    __shared__ double s_tab[3][kConQ][NP];  // l(0), l(1), w at node r + 4k of lane r ([row][r][k])
+    __shared__ double s_st[kConElems][4];  // per-element statistics, reduced by four lanes
+    __shared__ int s_fq[kConElems];
     const int t = threadIdx.x;
     const int le = t / kConQ, r = t % kConQ;
     const int e0 = blockIdx.x * kConElems;
@@ -617,32 +630,84 @@ __global__ __launch_bounds__(kConBlock) void k_constrain1d(Step1DArgs A)
     const int ee = live ? e : K - 1;
     const double* __restrict__ tab = A.tab;
 
-    // every global load the element needs is issued before the first wait:
-    // the block's phihat (coalesced staging), this lane's table entries, the
-    // face speeds and the own and neighbouring records
+    // every global load is a coalesced block load issued before the first
+    // wait: phihat, the records of the block's elements and of one neighbour
+    // on each side, the face speeds, and the table rows; the element's values
+    // are then read from LDS
     constexpr int kStage = (kConElems * N + kConBlock - 1) / kConBlock;
+    constexpr int kRStage = (NR + kConBlock - 1) / kConBlock;
     const int cnt = (K - e0 < kConElems ? K - e0 : kConElems) * N;
-    double v[kStage];
+    double v[kStage], rv[kRStage];
 #pragma unroll
     for (int r2 = 0; r2 < kStage; ++r2) {
         const int k = t + r2 * kConBlock;
         v[r2] = k < cnt ? A.phihat[(size_t)e0 * N + k] : 0.0;
     }
-    double l0[NP], l1[NP], Wn[NP];
+    // periodic wrap of an element or face index within [e0 - 1, e0 + kConElems]
+    // (a division only on meshes smaller than the staged window)
+    const bool small = K < kConElems + 2;
+    auto wrap = [&](int i) { return small ? ((i % K) + K) % K : (i < 0 ? i + K : (i >= K ? i - K : i)); };
 #pragma unroll
-    for (int k = 0; k < NP; ++k) {
-        const int j = r + kConQ * k;
-        const bool on = j < N;
-        l0[k] = on ? tab[O::L0 + j] : 0.0;
-        l1[k] = on ? tab[O::L1 + j] : 0.0;
-        Wn[k] = on ? A.dx * tab[O::W + j] : 0.0;
+    for (int r3 = 0; r3 < kRStage; ++r3) {
+        const int j = t + r3 * kConBlock;
+        int ge = e0 + (j >> 3) - 1;  // element of this record entry
+        if (A.periodic) ge = wrap(ge);
+        rv[r3] = (j < NR && ge >= 0 && ge < K) ? A.rec[(size_t)ge * 8 + (j & 7)] : 0.0;
+    }
+    double fv = 0.0;
+    if (t < NF) {
+        // face e0 + t; on a periodic mesh face K is face 0, elsewhere the
+        // K + 1 faces end at K
+        const int f = e0 + t;
+        fv = A.vface[A.periodic ? wrap(f) : (f < K ? f : K)];
+    }
+    double tv = 0.0;
+    if (t < 3 * kConQ * NP) {
+        // one load per lane, no branch on the row
+        static_assert(O::L1 == O::L0 + N, "table layout");
+        const int row = t / (kConQ * NP), j = (t / NP) % kConQ + kConQ * (t % NP);
+        const int at = row == 2 ? O::W + j : O::L0 + row * N + j;
+        if (j < N) tv = tab[at];
+    }
+    // ghost values at t^n and t^{n+1} (a bounded mesh only; scalar loads)
+    double gw0 = 0.0, gw1 = 0.0, gn0 = 0.0, gn1 = 0.0;
+    if (!A.periodic) {
+        gn0 = A.gnext[0];
+        gn1 = A.gnext[1];
+        if (A.targets) {
+            gw0 = A.gnow[0];
+            gw1 = A.gnow[1];
+        }
     }
 
     const bool bnd = (A.cmask & SL_C_BOUNDARY) != 0;
     const bool mass = (A.cmask & SL_C_MASS) != 0;
     const bool energy = (A.cmask & SL_C_ENERGY) != 0;
 
-    // neighbours and face values at t^{n+1} (eq. 4.12a)
+#pragma unroll
+    for (int r2 = 0; r2 < kStage; ++r2) {
+        const int k = t + r2 * kConBlock;
+        if (k < kConElems * N) s_buf[k] = v[r2];
+    }
+#pragma unroll
+    for (int r3 = 0; r3 < kRStage; ++r3) {
+        const int j = t + r3 * kConBlock;
+        if (j < NR) s_rec[j] = rv[r3];
+    }
+    if (t < NF) s_vf[t] = fv;
+    if (t < 3 * kConQ * NP) (&s_tab[0][0][0])[t] = tv;
+    __syncthreads();
+
+    double l0[NP], l1[NP], Wn[NP];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        l0[k] = s_tab[0][r][k];
+        l1[k] = s_tab[1][r][k];
+        Wn[k] = A.dx * s_tab[2][r][k];
+    }
+
+    // neighbours and face values at t^{n+1} (eq. 4.12a); the records of
+    // element le - 1, le, le + 1 of the block sit at rows le, le + 1, le + 2
     int em = ee - 1, ep = ee + 1;
     if (A.periodic) {
         if (em < 0) em = K - 1;
@@ -651,14 +716,15 @@ __global__ __launch_bounds__(kConBlock) void k_constrain1d(Step1DArgs A)
         if (em < 0) em = -1;
         if (ep >= K) ep = -1;
     }
-    double vL = A.vface[ee];
-    double vR = A.vface[(A.periodic && ee == K - 1) ? 0 : ee + 1];
+    double vL = s_vf[le];
+    double vR = s_vf[le + 1];
     if (fabs(vL) <= A.vzero) vL = 0.0;
     if (fabs(vR) <= A.vzero) vR = 0.0;
-    const double* R = A.rec;
-    const double* Re = R + (size_t)ee * 8;
-    const double T1m = em >= 0 ? R[(size_t)em * 8 + 1] : A.gnext[0];
-    const double T0p = ep >= 0 ? R[(size_t)ep * 8 + 0] : A.gnext[1];
+    const double* Rm = s_rec + le * 8;
+    const double* Re = Rm + 8;
+    const double* Rp = Re + 8;
+    const double T1m = em >= 0 ? Rm[1] : gn0;
+    const double T0p = ep >= 0 ? Rp[0] : gn1;
     const double dB0 = upwind(vL, T1m, Re[0]);
     const double dB1 = upwind(vR, Re[1], T0p);
 
@@ -668,28 +734,22 @@ __global__ __launch_bounds__(kConBlock) void k_constrain1d(Step1DArgs A)
         if (!A.periodic) {
             for (int qd = 0; qd < A.rk.nq; ++qd) {
                 const double cq = A.rk.cu[qd];
-                const double v0 = (1.0 - cq) * A.gnow[0] + cq * A.gnext[0];
-                const double v1 = (1.0 - cq) * A.gnow[1] + cq * A.gnext[1];
+                const double v0 = (1.0 - cq) * gw0 + cq * gn0;
+                const double v1 = (1.0 - cq) * gw1 + cq * gn1;
                 gM0 += A.rk.bu[qd] * v0;
                 gE0 += A.rk.bu[qd] * v0 * v0;
                 gM1 += A.rk.bu[qd] * v1;
                 gE1 += A.rk.bu[qd] * v1 * v1;
             }
         }
-        const double FMl = upwind(vL, em >= 0 ? R[(size_t)em * 8 + 3] : gM0, Re[2]);
-        const double FEl = upwind(vL, em >= 0 ? R[(size_t)em * 8 + 5] : gE0, Re[4]);
-        const double FMr = upwind(vR, Re[3], ep >= 0 ? R[(size_t)ep * 8 + 2] : gM1);
-        const double FEr = upwind(vR, Re[5], ep >= 0 ? R[(size_t)ep * 8 + 4] : gE1);
+        const double FMl = upwind(vL, em >= 0 ? Rm[3] : gM0, Re[2]);
+        const double FEl = upwind(vL, em >= 0 ? Rm[5] : gE0, Re[4]);
+        const double FMr = upwind(vR, Re[3], ep >= 0 ? Rp[2] : gM1);
+        const double FEr = upwind(vR, Re[5], ep >= 0 ? Rp[4] : gE1);
         Mt = Re[6] + A.dt * (vL * FMl - vR * FMr);
         Et = Re[7] + A.dt * (vL * FEl - vR * FEr);
     }
 
-#pragma unroll
-    for (int r2 = 0; r2 < kStage; ++r2) {
-        const int k = t + r2 * kConBlock;
-        if (k < kConElems * N) s_buf[k] = v[r2];
-    }
-    __syncthreads();
     // this lane's nodes (absent nodes are zero rows)
     double ph[NP];
 #pragma unroll
@@ -840,14 +900,14 @@ __global__ __launch_bounds__(kConBlock) void k_constrain1d(Step1DArgs A)
         if (singular) fl |= FLAG_SINGULAR;
         if (!finite) fl |= FLAG_NONFINITE;
     }
-    // wave reductions (the block is one wave)
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        rb = fmax(rb, __shfl_xor(rb, off));
-        rm = fmax(rm, __shfl_xor(rm, off));
-        re = fmax(re, __shfl_xor(re, off));
-        pic = fmax(pic, __shfl_xor(pic, off));
-        fl |= __shfl_xor(fl, off);
+    // per-element statistics (the same in the quad's four lanes), reduced
+    // over the block after the next barrier
+    if (r == 0) {
+        s_st[le][0] = rb;
+        s_st[le][1] = rm;
+        s_st[le][2] = re;
+        s_st[le][3] = pic;
+        s_fq[le] = fl;
     }
 
     // coalesced store of phi^{n+1}
@@ -864,13 +924,17 @@ __global__ __launch_bounds__(kConBlock) void k_constrain1d(Step1DArgs A)
         const int k = t + r2 * kConBlock;
         if (k < cnt) A.phi_out[(size_t)e0 * N + k] = s_buf[k];
     }
-    if (t == 0) {
-        if (fl) A.flag_part[A.nblk + blockIdx.x] |= fl;
+    if (t < 4) {  // lane a: statistic a
+        double m = 0.0;
+#pragma unroll
+        for (int q = 0; q < kConElems; ++q) m = fmax(m, s_st[q][t]);
         double* sp = A.stat_part + (size_t)blockIdx.x * kStatSlots;
-        sp[0] = fmax(sp[0], rb);
-        sp[1] = fmax(sp[1], rm);
-        sp[2] = fmax(sp[2], re);
-        sp[3] = fmax(sp[3], pic);
+        sp[t] = fmax(sp[t], m);
+    } else if (t == 4) {
+        int f = 0;
+#pragma unroll
+        for (int q = 0; q < kConElems; ++q) f |= s_fq[q];
+        if (f) A.flag_part[A.nblk + blockIdx.x] |= f;
     }
 }
 
