@@ -384,6 +384,7 @@ __global__ __launch_bounds__(kBlock) void k_advect1d(Step1DArgs A)
     __shared__ double s_x[E][N];
     __shared__ double s_c[E][N];
     __shared__ double s_r[2][E][N];
+    __shared__ double s_ti[N * N];  // nodal-to-Chebyshev matrix (row k: coefficient k)
     __shared__ int s_flag;
 
     const int t = threadIdx.x;
@@ -398,6 +399,10 @@ __global__ __launch_bounds__(kBlock) void k_advect1d(Step1DArgs A)
     const size_t g = (size_t)(live ? e : 0) * N + in;
     if (t == 0) s_flag = 0;
 
+    // a velocity series of at most four terms is evaluated as a polynomial
+    // in the element coordinate (cheb_to_mono), longer ones by Clenshaw;
+    // only the coefficients that are evaluated are read
+    constexpr bool MONO = NA <= 4;
     const double xi_i = tab[O::XI + in];
     const double invdx = A.invdx;
     double phi_i = 0.0, a_i = 0.0, dv_i = 0.0;
@@ -407,10 +412,13 @@ __global__ __launch_bounds__(kBlock) void k_advect1d(Step1DArgs A)
         if (A.targets || CONS) dv_i = A.divN[g];
     }
     if (inblk && node) {
-        s_a[slot][i] = live ? A.aM[g] : 0.0;
-        if (CONS) s_d[slot][i] = live ? A.divM[g] : 0.0;
+        const bool used = live && i < NA;
+        s_a[slot][i] = used ? A.aM[g] : 0.0;
+        if (CONS) s_d[slot][i] = used ? A.divM[g] : 0.0;
         s_p[slot][i] = phi_i;
     }
+    if (A.targets)
+        for (int k = t; k < N * N; k += kBlock) s_ti[k] = tab[O::TINV + k];
     __syncthreads();
     // Chebyshev coefficients of phi^n (for its values at backtraced feet);
     // zero without targets, so that the unconditional register copy below
@@ -419,20 +427,16 @@ __global__ __launch_bounds__(kBlock) void k_advect1d(Step1DArgs A)
         double c = 0.0;
         if (A.targets) {
 #pragma unroll
-            for (int j = 0; j < N; ++j) c = fma(tab[O::TINV + i * N + j], s_p[slot][j], c);
+            for (int j = 0; j < N; ++j) c = fma(s_ti[i * N + j], s_p[slot][j], c);
         }
         s_q[slot][i] = c;
     }
-    __syncthreads();
 
-    // a velocity series of at most four terms is evaluated as a polynomial
-    // in the element coordinate (cheb_to_mono), longer ones by Clenshaw
-    constexpr bool MONO = NA <= 4;
     double ca[N], cd[N];
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-        ca[k] = (!MONO || k < NA) ? s_a[sl][k] : 0.0;
-        cd[k] = (CONS && (!MONO || k < NA)) ? s_d[sl][k] : 0.0;
+        ca[k] = (k < NA) ? s_a[sl][k] : 0.0;
+        cd[k] = (CONS && k < NA) ? s_d[sl][k] : 0.0;
     }
     constexpr int NM = MONO ? NA : 1;
     double mu[NM], md[NM];
@@ -441,7 +445,6 @@ __global__ __launch_bounds__(kBlock) void k_advect1d(Step1DArgs A)
         cheb_to_mono<NA, N>(cd, 1.0, md);
     }
     const double k_i = a_i * invdx;
-    const double* cp = s_q[sl];  // phi^n coefficients, read from LDS where used
     bool out = false;
     // forward motion of particle i (section 4.2)
     double s = xi_i, q = phi_i;
@@ -449,6 +452,8 @@ __global__ __launch_bounds__(kBlock) void k_advect1d(Step1DArgs A)
         if constexpr (MONO) rk_move_mono<CONS, NA, RKS>(A.rk, mu, md, A.dt, A.dt, s, q, out, true, k_i, dv_i);
         else rk_move<N, CONS, NA, RKS>(A.rk, ca, cd, 1.0, A.dt, invdx, s, q, out, true, a_i, dv_i);
     }
+    __syncthreads();  // s_q complete
+    const double* cp = s_q[sl];  // phi^n coefficients, read from LDS where used
 
     // element-local target parts: M^n, E^n, volume term at the RK abscissae
     // (node lanes), edge values at the RK abscissae on the upwind edges (edge
