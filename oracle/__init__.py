@@ -43,7 +43,7 @@ class Params(ctypes.Structure):
         ("mode", ctypes.c_int32), ("energy_maxit", ctypes.c_int32), ("vel_kind", ctypes.c_int32),
         ("x0", ctypes.c_double), ("x1", ctypes.c_double), ("y0", ctypes.c_double),
         ("y1", ctypes.c_double), ("energy_tol", ctypes.c_double),
-        ("vel_param", ctypes.c_double * 4),
+        ("vel_param", ctypes.c_double * 4), ("iface", ctypes.c_int32),
     ]
 
 

@@ -47,6 +47,8 @@ typedef struct {
     double x0, x1, y0, y1;
     double energy_tol;    /* Picard stop: max |phi^(k) - phi^(k-1)| < tol */
     double vel_param[4];
+    int32_t iface;        /* interface values: 0 interpolation (eq. remap_bnd),
+                             1 backtracking (eq. 4.11) */
 } ora_params;
 
 typedef struct {
@@ -630,6 +632,9 @@ static double vel_normal(const ctx* c, int e, int t)
 /* with V*_{p,q} = H_q(moved point p) -- identical in exact arithmetic to  */
 /* evaluating the moved-point Lagrange interpolant at the fixed nodes.     */
 /* ------------------------------------------------------------------------ */
+static double face_velocity(const ctx* c, int e, int t);
+static void face_partner(const ctx* c, int e, int t, int* nbe, int* nbt, int* gidx, int* e_is_high);
+
 static int advect_remap(const ctx* c, int e, const double* phin, work* W)
 {
     int n = c->n, nd = c->nd, d2 = (c->p->dim == 2);
@@ -660,6 +665,25 @@ static int advect_remap(const ctx* c, int e, const double* phin, work* W)
         double s, r;
         trace_point(c, t, &s, &r);
         tr[t] = field_eval(c, ph, s, r);
+    }
+    /* Backtracking interface values (eq. 4.11): the characteristic through
+     * the trace point is traced back over dt with the particles' RK tableau,
+     * and phi^n of this element is evaluated at its foot (times the source
+     * factor in the conservative form).  Computed where this element is the
+     * upwind side of the face (both sides where the face velocity vanishes);
+     * elsewhere the upwind rule (eq. 4.12a) never selects this element's value,
+     * and the interpolated one stays. */
+    if (c->p->iface == 1) {
+        for (int t = 0; t < ntr(c); ++t) {
+            int nbe, nbt, gidx, high;
+            face_partner(c, e, t, &nbe, &nbt, &gidx, &high);
+            double vn = face_velocity(c, e, t);
+            int up = high ? (vn <= 0) : (vn >= 0);
+            if (!up) continue;
+            double s, r;
+            trace_point(c, t, &s, &r);
+            tr[t] = backtrace_value(c, e, phin, c->dt, s, r, &flags);
+        }
     }
     free(V); free(rhs);
     return flags;
@@ -1266,7 +1290,9 @@ static double view_normal(const elem_view* v, int side, double s, double r)
 int ora_step_mixed(const ora_params* p, const int32_t* orders, const double* a, double dt, int nsteps,
                    double* phi, ora_stats* st)
 {
-    if (p->dim != 2 || p->bc != 0 || (p->cmask & ~C_BOUND) || p->kx < 1 || p->ky < 1) return 1;
+    /* interpolated interface values only (the backtracking variant is
+     * defined here for meshes of one order) */
+    if (p->dim != 2 || p->bc != 0 || (p->cmask & ~C_BOUND) || p->kx < 1 || p->ky < 1 || p->iface != 0) return 1;
     int K = p->kx * p->ky;
     size_t* off = malloc(sizeof(size_t) * (K + 1));
     off[0] = 0;

@@ -47,6 +47,8 @@ def run_oracle(w, phi0=None, nsteps=None, ghost=None, want=None, **over):
         kw["cmask"] = over.pop("constraints")
     if "mode" in over:
         kw["mode"] = over.pop("mode")
+    if "iface" in over:
+        kw["iface"] = over.pop("iface")
     over.pop("refine_steps", None)
     p = oracle.params_from(w, **kw)
     a, _ = w.velocity()
