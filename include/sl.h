@@ -56,6 +56,7 @@ enum { SL_FORM_ADVECTIVE = 0, SL_FORM_CONSERVATIVE = 1 };
 enum { SL_PREC_FP64 = 0, SL_PREC_FP32_REFINED = 1 };
 enum { SL_C_BOUNDARY = 1, SL_C_MASS = 2, SL_C_ENERGY = 4 };
 enum { SL_MODE_HARD = 0, SL_MODE_SOFT = 1 };
+enum { SL_IFACE_INTERP = 0, SL_IFACE_BACKTRACK = 1 };
 
 /* Mesh descriptor (sl_create_mesh).
  *   dim        1 or 2
@@ -100,10 +101,19 @@ typedef struct {
  *   energy_maxit  Picard iterations cap for the energy row (default 50)
  *   refine_steps  reserved (the remap refinement runs to its own stop test);
  *                 must be >= 0
+ *   iface         interface values at t^{n+1} (section 4.3): SL_IFACE_INTERP
+ *                 (default), the remapped polynomial at the element edge (eq.
+ *                 remap_bnd); or SL_IFACE_BACKTRACK, phi^n at the foot of the
+ *                 characteristic traced back over dt from the edge point with
+ *                 the particles' RK tableau (eq. 4.11; times the source
+ *                 factor in the conservative form).  Either is computed on
+ *                 the side of each face where the flow leaves (both sides
+ *                 where the face speed vanishes) and selected by upwinding
+ *                 (eq. 4.12a).  Mixed-order meshes take SL_IFACE_INTERP only.
  *   energy_tol    Picard stop |phi^(k) - phi^(k-1)|_max < tol (default 1e-8, the
  *                 paper's; 0 = always run energy_maxit iterations) */
 typedef struct {
-    int32_t rk, constraints, mode, energy_maxit, refine_steps;
+    int32_t rk, constraints, mode, energy_maxit, refine_steps, iface;
     double energy_tol;
 } sl_step_opts;
 

@@ -26,6 +26,7 @@ SL_FORM_ADVECTIVE, SL_FORM_CONSERVATIVE = 0, 1
 SL_PREC_FP64, SL_PREC_FP32_REFINED = 0, 1
 SL_C_BOUNDARY, SL_C_MASS, SL_C_ENERGY = 1, 2, 4
 SL_MODE_HARD, SL_MODE_SOFT = 0, 1
+SL_IFACE_INTERP, SL_IFACE_BACKTRACK = 0, 1
 KER_ADV1D, KER_CON1D, KER_ADV2D, KER_CON2D = 0, 1, 2, 3
 
 EXPORTS = ["sl_create_mesh", "sl_set_velocity", "sl_set_ghost", "sl_ghost_count", "sl_step", "sl_read",
@@ -47,7 +48,7 @@ class MeshDesc(ctypes.Structure):
 class StepOpts(ctypes.Structure):
     _fields_ = [("rk", ctypes.c_int32), ("constraints", ctypes.c_int32), ("mode", ctypes.c_int32),
                 ("energy_maxit", ctypes.c_int32), ("refine_steps", ctypes.c_int32),
-                ("energy_tol", ctypes.c_double)]
+                ("iface", ctypes.c_int32), ("energy_tol", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -183,8 +184,9 @@ def sl_ghost_count(m) -> int:
     return int(lib().sl_ghost_count(m))
 
 
-def step_opts(rk=4, constraints=SL_C_BOUNDARY, mode=SL_MODE_HARD, energy_maxit=50, refine_steps=3, energy_tol=1e-8):
-    return StepOpts(rk, constraints, mode, energy_maxit, refine_steps, energy_tol)
+def step_opts(rk=4, constraints=SL_C_BOUNDARY, mode=SL_MODE_HARD, energy_maxit=50, refine_steps=3, energy_tol=1e-8,
+              iface=0):
+    return StepOpts(rk, constraints, mode, energy_maxit, refine_steps, iface, energy_tol)
 
 
 def sl_step(m, dt, nsteps=1, opts=None):

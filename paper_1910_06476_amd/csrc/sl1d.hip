@@ -417,15 +417,16 @@ __global__ __launch_bounds__(kBlock) void k_advect1d(Step1DArgs A)
         if (CONS) s_d[slot][i] = used ? A.divM[g] : 0.0;
         s_p[slot][i] = phi_i;
     }
-    if (A.targets)
+    const bool bt = A.iface == SL_IFACE_BACKTRACK;  // edge values by backtracking (eq. 4.11)
+    const bool need_cp = A.targets || bt;           // phi^n off the nodes is evaluated
+    if (need_cp)
         for (int k = t; k < N * N; k += kBlock) s_ti[k] = tab[O::TINV + k];
     __syncthreads();
     // Chebyshev coefficients of phi^n (for its values at backtraced feet);
-    // zero without targets, so that the unconditional register copy below
-    // reads defined values
+    // zero when no foot is evaluated, so that LDS holds defined values
     if (inblk && node) {
         double c = 0.0;
-        if (A.targets) {
+        if (need_cp) {
 #pragma unroll
             for (int j = 0; j < N; ++j) c = fma(s_ti[i * N + j], s_p[slot][j], c);
         }
@@ -458,16 +459,20 @@ __global__ __launch_bounds__(kBlock) void k_advect1d(Step1DArgs A)
     // element-local target parts: M^n, E^n, volume term at the RK abscissae
     // (node lanes), edge values at the RK abscissae on the upwind edges (edge
     // lane); backtracking as in eq. 4.11
+    // upwind edges of the element (edge lane): where the flow leaves it, or
+    // the face speed vanishes
+    int first = -1, second = -1;
+    if (need_cp && !node && live) {
+        const double vL = A.vface[e];
+        const double vR = A.vface[(A.periodic && e == A.K - 1) ? 0 : e + 1];
+        const bool needL = !(vL > A.vzero), needR = !(vR < -A.vzero);
+        first = needL ? 0 : (needR ? 1 : -1);
+        second = (needL && needR) ? 1 : -1;
+    }
     double vM = 0.0, vE = 0.0;
     if (A.targets) {
         const double W_i = A.dx * tab[O::W + in];
-        int first = -1, second = -1;
         if (!node && live) {
-            const double vL = A.vface[e];
-            const double vR = A.vface[(A.periodic && e == A.K - 1) ? 0 : e + 1];
-            const bool needL = !(vL > A.vzero), needR = !(vR < -A.vzero);
-            first = needL ? 0 : (needR ? 1 : -1);
-            second = (needL && needR) ? 1 : -1;
             // an edge without backtraces has zero stage sums
             double* rc = A.rec + (size_t)e * 8;
             if (first != 0 && second != 0) rc[2] = rc[4] = 0.0;
@@ -515,6 +520,21 @@ __global__ __launch_bounds__(kBlock) void k_advect1d(Step1DArgs A)
         }
     }
 
+    // backtracking interface values (eq. 4.11): phi^n at the foot of the
+    // characteristic through each upwind edge over the whole step, stored as
+    // that edge's trace (the remap below leaves those slots alone)
+    if (bt && !node && live) {
+        for (int r = 0; r < 2; ++r) {
+            const int edge = (r == 0) ? first : second;
+            if (edge < 0) continue;
+            double sb = (double)edge, hq = 1.0;
+            if constexpr (MONO) rk_move_mono<CONS, NA, RKS>(A.rk, mu, md, -A.dt, A.dt, sb, hq, out, false, k_i, dv_i);
+            else rk_move<N, CONS, NA, RKS>(A.rk, ca, cd, -1.0, A.dt, invdx, sb, hq, out, false, a_i, dv_i);
+            A.rec[(size_t)e * 8 + edge] = hq * clenshaw_p<N>(cp, 2.0 * sb - 1.0);
+        }
+    }
+    const bool bt0 = bt && (first == 0 || second == 0), bt1 = bt && (first == 1 || second == 1);
+
     // remap (eq. 4.9): phihat_i = sum_j c_j prod_{m != j} (xi_i - s_m),
     // c_j = phi*_j / prod_{m != j} (s_j - s_m); the edge lane evaluates the
     // same polynomial at 0, and its value at 1 is l(1) . phihat (eq.
@@ -556,7 +576,7 @@ __global__ __launch_bounds__(kBlock) void k_advect1d(Step1DArgs A)
         if (node) {
             if (!isfinite(S)) fl |= FLAG_SINGULAR;
             A.phihat[g] = S;
-        } else {
+        } else if (!bt0) {
             A.rec[(size_t)e * 8] = S;
         }
     }
@@ -566,7 +586,7 @@ __global__ __launch_bounds__(kBlock) void k_advect1d(Step1DArgs A)
     // one sum over the element's nodes in three lanes at once: the trace at 1
     // (edge lane, record slot 1), the mass target (node lane 0, slot 6) and
     // the energy target (node lane 1, slot 7), each summed in node order
-    if (live && (!node || (A.targets && i < 2))) {
+    if (live && ((!node && !bt1) || (A.targets && i < 2))) {
         const double* src = node ? s_r[i][sl] : s_p[sl];
         double sum = 0.0;
 #pragma unroll

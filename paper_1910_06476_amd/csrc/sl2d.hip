@@ -298,7 +298,8 @@ __device__ double backtrace2(const Step2DArgs& A, const double* cu, const double
 // with TGT also, per edge point where e is upwind, sum_q bu_q v_q and
 // sum_q bu_q v_q^2 of the backtraced stage values v_q (4n each), and
 // M^n + dt sum_q bu_q V_q, E^n + dt sum_q bu_q V'_q with the volume terms
-// V of the balance laws (eq. 4.14 generalised to the RK quadrature).
+// V of the balance laws (eq. 4.14 generalised to the RK quadrature); with
+// backtracking interface values, last, the 4n face values it offers.
 // ---------------------------------------------------------------------------
 // block shapes of the advect kernel: 0 = 256 lanes, 1 = the fewest whole
 // waves that hold one element, 2 = 512 lanes
@@ -665,7 +666,7 @@ __global__ __launch_bounds__((Shape2<N, BSEL>::BS)) void k_advect2d(Step2DArgs A
 // over chunks of E elements
 constexpr int kConGrid = 2048;
 
-template <int N>
+template <int N, bool BT>
 __global__ __launch_bounds__(kBlock2) void k_constrain2d(Step2DArgs A)
 {
     using O = Off2<N>;
@@ -708,13 +709,17 @@ __global__ __launch_bounds__(kBlock2) void k_constrain2d(Step2DArgs A)
             int nbe, nbt, gidx;
             bool high;
             face_partner2<N>(ee, tt, kx, ky, A.periodic, nbe, nbt, gidx, high);
-            const double mine = A.rec[(size_t)ee * A.rstride + tt];
-            const double other = nbe >= 0 ? A.rec[(size_t)nbe * A.rstride + nbt] : A.gnext[gidx];
+            // offered face values: the traces, or with backtracking (BT) the
+            // record's last 4n slots; the residual takes the own trace
+            const int fo = BT ? A.rstride - 4 * N : 0;
+            const double trace = A.rec[(size_t)ee * A.rstride + tt];
+            const double mine = BT ? A.rec[(size_t)ee * A.rstride + fo + tt] : trace;
+            const double other = nbe >= 0 ? A.rec[(size_t)nbe * A.rstride + fo + nbt] : A.gnext[gidx];
             const double vn = A.vface[(size_t)ee * 4 * N + tt];
             const double lo = high ? other : mine, hi = high ? mine : other;
             const double dv = upwind2(vn, lo, hi);
             s_fv[slot][tt] = dv;
-            s_rb[slot][tt] = dv - mine;
+            s_rb[slot][tt] = dv - trace;
         }
         __syncthreads();
 
@@ -824,8 +829,11 @@ __global__ __launch_bounds__(kBlock2) void k_constrain2d_me(Step2DArgs A)
         bool high;
         face_partner2<N>(ee, tt, A.kx, A.ky, A.periodic, nbe, nbt, gidx, high);
         const double vn = A.vface[(size_t)ee * NB + tt];
-        const double mine = rec[tt];
-        const double other = nbe >= 0 ? A.rec[(size_t)nbe * A.rstride + nbt] : A.gnext[gidx];
+        // offered face values: the traces, or with backtracking the record's
+        // last NB slots
+        const int fo = A.iface == SL_IFACE_BACKTRACK ? A.rstride - NB : 0;
+        const double mine = rec[fo + tt];
+        const double other = nbe >= 0 ? A.rec[(size_t)nbe * A.rstride + fo + nbt] : A.gnext[gidx];
         s_fv[slot][tt] = upwind2(vn, high ? other : mine, high ? mine : other);
         double fm = 0.0, fe = 0.0;
         if (vn != 0.0) {
@@ -1264,10 +1272,72 @@ int con_n(const Step2DArgs& A, hipStream_t s)
 {
     constexpr int E = kBlock2 / (N * N);
     const int nchunk = (A.K + E - 1) / E;
+    const dim3 grid(nchunk < kConGrid ? nchunk : kConGrid);
     if (A.cmask & (SL_C_MASS | SL_C_ENERGY))
         hipLaunchKernelGGL(k_constrain2d_me<N>, dim3(nchunk), dim3(kBlock2), 0, s, A);
+    else if (A.iface == SL_IFACE_BACKTRACK)
+        hipLaunchKernelGGL((k_constrain2d<N, true>), grid, dim3(kBlock2), 0, s, A);
     else
-        hipLaunchKernelGGL(k_constrain2d<N>, dim3(nchunk < kConGrid ? nchunk : kConGrid), dim3(kBlock2), 0, s, A);
+        hipLaunchKernelGGL((k_constrain2d<N, false>), grid, dim3(kBlock2), 0, s, A);
+    return hipGetLastError() == hipSuccess ? 0 : 1;
+}
+
+// backtracking interface values (eq. 4.11), a launch of their own before
+// the advect kernel: one lane per edge point (4n per element, floor(256/4n)
+// elements per block).  phi^n and the velocity (and divergence) series of
+// each element are staged in LDS; a lane whose point lies on a face where
+// the flow leaves the element (or the face speed vanishes) traces the
+// characteristic back over dt and stores phi^n at the foot, times the
+// source factor in the conservative form, in the record's last 4n slots.
+// The other points store zero: the upwind rule never selects them.
+template <int N>
+__global__ __launch_bounds__(kBlock2) void k_backtrace2d(Step2DArgs A)
+{
+    using O = Off2<N>;
+    constexpr int ND = N * N, NB = 4 * N, EB = kBlock2 / NB;
+    __shared__ double s_f[EB][ND], s_cu[EB][ND], s_cv[EB][ND], s_cd[EB][ND];
+    __shared__ int s_flag;
+    const int t = threadIdx.x;
+    const int e0 = blockIdx.x * EB;
+    if (t == 0) s_flag = 0;
+    const size_t KND = (size_t)A.K * ND;
+    for (int k = t; k < EB * ND; k += kBlock2) {
+        const int le = k / ND, q = k - le * ND, e = e0 + le;
+        const bool live = e < A.K;
+        const size_t g = (size_t)(live ? e : 0) * ND + q;
+        const int ii = q % N, jj = q / N;
+        const bool used = live && ii <= A.vdeg && jj <= A.vdeg;
+        s_f[le][q] = live ? A.phi[g] : 0.0;
+        s_cu[le][q] = used ? A.aM[g] : 0.0;
+        s_cv[le][q] = used ? A.aM[KND + g] : 0.0;
+        s_cd[le][q] = (used && A.cons) ? A.divM[g] : 0.0;
+    }
+    __syncthreads();
+    const int le = t / NB, tt = t - le * NB, e = e0 + le;
+    bool out = false;
+    if (le < EB && e < A.K) {
+        const int side = tt / N, k = tt % N;
+        const double vn = A.vface[(size_t)e * NB + tt];
+        const bool up = (side == 0 || side == 2) ? vn <= 0.0 : vn >= 0.0;
+        double v = 0.0;
+        if (up) {
+            const double s = side == 0 ? 0.0 : side == 1 ? 1.0 : A.tab[O::XI + k];
+            const double r = side == 2 ? 0.0 : side == 3 ? 1.0 : A.tab[O::XI + k];
+            v = backtrace2<N>(A, s_cu[le], s_cv[le], s_cd[le], s_f[le], A.dt, s, r, out);
+        }
+        A.rec[(size_t)e * A.rstride + (A.rstride - NB) + tt] = v;
+    }
+    if (out) atomicOr(&s_flag, FLAG_CONTAIN);
+    __syncthreads();
+    // the advect kernel's flag slots; several blocks may share one
+    if (t == 0 && s_flag) atomicOr(&A.flag_part[blockIdx.x % A.nblk], s_flag);
+}
+
+template <int N>
+int bt_n(const Step2DArgs& A, hipStream_t s)
+{
+    constexpr int EB = kBlock2 / (4 * N);
+    hipLaunchKernelGGL(k_backtrace2d<N>, dim3((A.K + EB - 1) / EB), dim3(kBlock2), 0, s, A);
     return hipGetLastError() == hipSuccess ? 0 : 1;
 }
 
@@ -1362,6 +1432,13 @@ int launch_constrain2d(int n, const Step2DArgs& A, hipStream_t s)
 #define CON2(N) con_n<N>(A, s)
     SL2D_SWITCH(n, CON2)
 #undef CON2
+}
+
+int launch_backtrace2d(int n, const Step2DArgs& A, hipStream_t s)
+{
+#define BT2(N) bt_n<N>(A, s)
+    SL2D_SWITCH(n, BT2)
+#undef BT2
 }
 
 }  // namespace sl

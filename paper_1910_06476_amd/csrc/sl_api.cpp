@@ -117,7 +117,8 @@ BufSizes buffer_sizes(int dim, int kx, int ky, int n)
     const size_t K = (size_t)kx * ky;
     z.nf = K * (dim == 1 ? n : n * n);
     z.nblocks = dim == 1 ? blocks1d(n, (int)K) : blocks2d(n, (int)K);
-    z.nrec = dim == 1 ? K * 8 : K * (12 * n + 2);
+    // 2D: traces (4n), stage sums (8n), targets (2), backtraced face values (4n)
+    z.nrec = dim == 1 ? K * 8 : K * (16 * n + 2);
     z.nvf = dim == 1 ? K + 1 : K * 4 * n;
     z.ntab = (size_t)tab_offsets(dim, n).total;
     z.nstat = (size_t)z.nblocks * kStatSlots;
@@ -811,12 +812,14 @@ static void ev_end(sl_mesh* m, int k)
 sl_status sl_step(sl_mesh* m, double dt, int32_t nsteps, const sl_step_opts* o)
 {
     if (!m) return SL_E_INVALID;
-    sl_step_opts opt = {4, SL_C_BOUNDARY, SL_MODE_HARD, 50, 3, 1e-8};
+    sl_step_opts opt = {4, SL_C_BOUNDARY, SL_MODE_HARD, 50, 3, SL_IFACE_INTERP, 1e-8};
     if (o) opt = *o;
     if (!(dt > 0) || !std::isfinite(dt) || nsteps < 0) return SL_E_INVALID;
     if (opt.rk < 1 || opt.rk > 4 || (opt.constraints & ~7) || (opt.mode != SL_MODE_HARD && opt.mode != SL_MODE_SOFT) ||
-        opt.energy_maxit < 0 || !(opt.energy_tol >= 0) || opt.refine_steps < 0)
+        opt.energy_maxit < 0 || !(opt.energy_tol >= 0) || opt.refine_steps < 0 ||
+        (opt.iface != SL_IFACE_INTERP && opt.iface != SL_IFACE_BACKTRACK))
         return SL_E_INVALID;
+    if (m->mixed && opt.iface != SL_IFACE_INTERP) return SL_E_INVALID;
     if (!m->has_velocity) return SL_E_STATE;
     if (m->bc == SL_BC_GHOST && m->ghost_rows < 1) return SL_E_STATE;
     // time-step restriction: particles may not cross the element-edge gap
@@ -852,8 +855,9 @@ sl_status sl_step(sl_mesh* m, double dt, int32_t nsteps, const sl_step_opts* o)
         // volume terms of the balance laws: advective form for mass and
         // energy, conservative form for energy only
         B.vol = B.targets && (B.cons ? (opt.constraints & SL_C_ENERGY) != 0 : 1);
-        B.rstride = B.targets ? 12 * m->n + 2 : 4 * m->n;
+        B.rstride = (B.targets ? 12 * m->n + 2 : 4 * m->n) + (opt.iface == SL_IFACE_BACKTRACK ? 4 * m->n : 0);
         B.emaxit = opt.energy_maxit; B.etol = opt.energy_tol;
+        B.iface = opt.iface;
         B.dx = m->dx; B.dy = m->dy;
         B.invdx = 1.0 / m->dx; B.invdy = 1.0 / m->dy; B.dt = dt;
         B.vzero = 1e-12 * std::max(m->amax[0], m->amax[1]);
@@ -868,6 +872,7 @@ sl_status sl_step(sl_mesh* m, double dt, int32_t nsteps, const sl_step_opts* o)
             }
             B.phi = m->phi;
             B.phi_out = m->phi2;
+            if (opt.iface == SL_IFACE_BACKTRACK && launch_backtrace2d(m->n, B, m->stream)) return SL_E_DEVICE;
             ev_begin(m, KER_ADV2D);
             if (launch_advect2d(m->n, B, m->stream)) return SL_E_DEVICE;
             ev_end(m, KER_ADV2D);
@@ -890,6 +895,7 @@ sl_status sl_step(sl_mesh* m, double dt, int32_t nsteps, const sl_step_opts* o)
     A.flag_part = m->flag_part; A.stat_part = m->stat_part; A.nblk = m->nblocks; A.vdeg = m->vdeg;
     A.K = m->K; A.periodic = m->bc == SL_BC_PERIODIC; A.cons = m->form == SL_FORM_CONSERVATIVE;
     A.cmask = opt.constraints; A.mode = opt.mode; A.emaxit = opt.energy_maxit; A.etol = opt.energy_tol;
+    A.iface = opt.iface;
     A.targets = (opt.constraints & (SL_C_MASS | SL_C_ENERGY)) != 0;
     A.vol = A.targets;
     A.dx = m->dx; A.invdx = 1.0 / m->dx; A.dt = dt;

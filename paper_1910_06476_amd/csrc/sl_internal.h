@@ -71,6 +71,7 @@ struct Step1DArgs {
     int nblk;
     int vdeg;              // mesh-wide effective degree of the velocity series
     int K, periodic, cons, cmask, mode, emaxit, vol, targets;
+    int iface;             // SL_IFACE_*: edge values by interpolation or backtracking
     double dx, invdx, dt, etol, vzero;
     double g00, g01, g11, g02, g12, g22;  // constant Gram entries of rows l(0), l(1), W
     double g3i[9];  // inverse of the constant 3x3 block of the launch's system (rows l(0), l(1), W;
@@ -91,7 +92,8 @@ struct Step2DArgs {
     const double* phi;     // [K][n^2] phi^n
     double* phihat;        // [K][n^2] remapped
     double* rec;           // [K][rstride] edge traces of phihat (4n); with targets also the
-                           // upwind stage sums (2 x 4n) and the local mass and energy parts (2)
+                           // upwind stage sums (2 x 4n) and the local mass and energy parts (2);
+                           // with backtracking, last, the offered face values (4n)
     double* phi_out;       // [K][n^2] phi^{n+1}
     const double* aN;      // [2][K][n^2] nodal velocity
     const double* aM;      // [2][K][n^2] tensor Chebyshev coefficients
@@ -105,6 +107,7 @@ struct Step2DArgs {
     double* stat_part;     // [nblk][kStatSlots]
     int nblk, vdeg, rstride;
     int kx, ky, K, periodic, cons, cmask, mode, refine, precision, targets, vol, emaxit;
+    int iface;             // SL_IFACE_*: edge values by interpolation or backtracking
     double dx, dy, invdx, invdy, dt, vzero, etol;
     RKTab rk;
     int bs;                // advect block shape: 0 = 256 lanes, 1 = fewest whole waves, 2 = 512 lanes
@@ -149,6 +152,8 @@ int launch_facevel2d(int n, int kx, int ky, int periodic, const double* aN, cons
                      double* vface, hipStream_t s);
 int launch_advect2d(int n, const Step2DArgs& A, hipStream_t s);
 int launch_constrain2d(int n, const Step2DArgs& A, hipStream_t s);
+// backtracking interface values into the record's last 4n slots (A.phi is phi^n)
+int launch_backtrace2d(int n, const Step2DArgs& A, hipStream_t s);
 int blocks2d(int n, int K);
 
 // 2D boundary tables (4n x 4n, row-major): Qhard = (C_B C_B^T)^+,
