@@ -142,7 +142,7 @@ def step_latency(torch, m, dt, opts, samples=200):
 def bench_c3(args, torch, P, W, stream):
     """2D rotation workload (256x256, order 8, RK4, ghost inflow, boundary HARD)."""
     w = W.c3(nsteps=args.warmup + args.steps)
-    prec = P.SL_PREC_FP32_REFINED if args.precision == "fp32r" else P.SL_PREC_FP64
+    prec = {"fp64": P.SL_PREC_FP64, "fp32r": P.SL_PREC_FP32_REFINED, "bf16r": P.SL_PREC_BF16_REFINED}[args.precision]
     m = P.from_workload(w, stream=stream.cuda_stream, precision=prec)
     m.set_ghost(w.ghost_rows(0.0, args.warmup + 2 * args.steps + 20))
     opts = dict(rk=w.rk, constraints=w.cmask, mode=w.mode)
@@ -344,8 +344,9 @@ def main():
     ap.add_argument("--requests", type=int, default=48, help="serve: number of requests")
     ap.add_argument("--slots", type=int, default=8, help="serve: requests on the device at once")
     ap.add_argument("--budget-gib", type=float, default=32.0, help="serve: device memory budget")
-    ap.add_argument("--precision", choices=["fp64", "fp32r"], default="fp64",
-                    help="c3 only: fp32r stores and applies the remap preconditioner in FP32 (FP64 residuals)")
+    ap.add_argument("--precision", choices=["fp64", "fp32r", "bf16r"], default="fp64",
+                    help="c3 only: fp32r stores and applies the remap preconditioner in FP32, bf16r with BF16 "
+                         "entries and operands and FP32 sums (FP64 residuals in both)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (calibrates HBM counters)")
     args = ap.parse_args()

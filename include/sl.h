@@ -53,7 +53,7 @@ enum {
 enum { SL_NODES_GL = 0, SL_NODES_CG = 1 };          /* Gauss-Legendre / Chebyshev-Gauss */
 enum { SL_BC_PERIODIC = 0, SL_BC_GHOST = 1 };
 enum { SL_FORM_ADVECTIVE = 0, SL_FORM_CONSERVATIVE = 1 };
-enum { SL_PREC_FP64 = 0, SL_PREC_FP32_REFINED = 1 };
+enum { SL_PREC_FP64 = 0, SL_PREC_FP32_REFINED = 1, SL_PREC_BF16_REFINED = 2 };
 enum { SL_C_BOUNDARY = 1, SL_C_MASS = 2, SL_C_ENERGY = 4 };
 enum { SL_MODE_HARD = 0, SL_MODE_SOFT = 1 };
 enum { SL_IFACE_INTERP = 0, SL_IFACE_BACKTRACK = 1 };
@@ -66,10 +66,12 @@ enum { SL_IFACE_INTERP = 0, SL_IFACE_BACKTRACK = 1 };
  *   nodes      SL_NODES_GL (default) or SL_NODES_CG (paper, eq. gaussquad)
  *   bc         SL_BC_PERIODIC, or SL_BC_GHOST (inflow values from sl_set_ghost)
  *   form       SL_FORM_ADVECTIVE or SL_FORM_CONSERVATIVE
- *   precision  SL_PREC_FP64, or SL_PREC_FP32_REFINED (2D only: the
- *              preconditioner of the remap solve is stored and applied in
- *              FP32 while residuals and iterates stay FP64, so the solve
- *              still converges to the FP64 solution; 1D rejects it)
+ *   precision  SL_PREC_FP64, SL_PREC_FP32_REFINED or SL_PREC_BF16_REFINED
+ *              (2D only: the preconditioner of the remap solve is stored
+ *              and applied in FP32, or with BF16 entries and operands and
+ *              FP32 accumulation, while residuals and iterates stay FP64, so
+ *              the solve still converges to the FP64 solution, in more
+ *              sweeps; 1D rejects both)
  *   x0,x1,y0,y1 box (y ignored in 1D), x1 > x0, y1 > y0
  *   u0         host, K * n^dim initial values (layout above)
  *   stream     hipStream_t to run on, or NULL for a stream the mesh creates

@@ -23,7 +23,7 @@ SL_OK, SL_E_INVALID, SL_E_NOMEM, SL_E_DEVICE, SL_E_STATE, SL_E_CFL, SL_E_NONFINI
 SL_NODES_GL, SL_NODES_CG = 0, 1
 SL_BC_PERIODIC, SL_BC_GHOST = 0, 1
 SL_FORM_ADVECTIVE, SL_FORM_CONSERVATIVE = 0, 1
-SL_PREC_FP64, SL_PREC_FP32_REFINED = 0, 1
+SL_PREC_FP64, SL_PREC_FP32_REFINED, SL_PREC_BF16_REFINED = 0, 1, 2
 SL_C_BOUNDARY, SL_C_MASS, SL_C_ENERGY = 1, 2, 4
 SL_MODE_HARD, SL_MODE_SOFT = 0, 1
 SL_IFACE_INTERP, SL_IFACE_BACKTRACK = 0, 1

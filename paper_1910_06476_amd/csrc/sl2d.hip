@@ -291,8 +291,10 @@ __device__ double backtrace2(const Step2DArgs& A, const double* cu, const double
 // the local parts of the mass and energy targets
 //
 // One lane per particle (n^2 lanes per element, floor(256/n^2) elements per
-// block).  With P32 the separable preconditioner is stored and applied in
-// FP32 while the residual and the iterate stay FP64 (iterative refinement).
+// block).  With PR = 1 the separable preconditioner is stored and applied in
+// FP32, with PR = 2 its entries and operands are BF16 with FP32
+// accumulation; the residual and the iterate stay FP64 (iterative
+// refinement).  PR = 0 is FP64 throughout.
 //
 // Record of element e (stride A.rstride): its 4n edge traces of phi-hat;
 // with TGT also, per edge point where e is upwind, sum_q bu_q v_q and
@@ -309,11 +311,42 @@ template <int N, int BSEL> struct Shape2 {
     static constexpr int E = BS / ND;
 };
 
-template <int N, bool P32, bool TGT, int BSEL = 0>
+// Preconditioner storage and arithmetic of precision PR: FP64, FP32, or BF16
+// (the upper half of an FP32, rounded to nearest even) with FP32 products
+// and sums.  The BF16 operands multiply exactly in FP32.
+template <int PR> struct Prec;
+template <> struct Prec<0> {
+    using S = double;  // storage
+    using A = double;  // arithmetic
+    __device__ static S put(double v) { return v; }
+    __device__ static A get(S v) { return v; }
+};
+template <> struct Prec<1> {
+    using S = float;
+    using A = float;
+    __device__ static S put(double v) { return (float)v; }
+    __device__ static A get(S v) { return v; }
+};
+template <> struct Prec<2> {
+    using S = unsigned short;
+    using A = float;
+    __device__ static S put(double v)
+    {
+        const unsigned int b = __float_as_uint((float)v);
+        if ((b & 0x7f800000u) == 0x7f800000u) return (S)(b >> 16);  // inf / nan: truncate
+        return (S)((b + 0x7fffu + ((b >> 16) & 1u)) >> 16);          // round to nearest even
+    }
+    __device__ static A get(S v) { return __uint_as_float((unsigned int)v << 16); }
+};
+
+template <int N, int PR, bool TGT, int BSEL = 0>
 __global__ __launch_bounds__((Shape2<N, BSEL>::BS)) void k_advect2d(Step2DArgs A)
 {
     using O = Off2<N>;
-    using PT = typename std::conditional<P32, float, double>::type;
+    using PP = Prec<PR>;
+    using PT = typename PP::S;
+    using AT = typename PP::A;
+    constexpr bool P32 = PR != 0;  // reduced-precision preconditioner, operands scaled
     constexpr int ND = N * N, E = Shape2<N, BSEL>::E, NB = 4 * N;
     __shared__ double s_cu[E][ND], s_cv[E][ND], s_cd[E][ND];
     __shared__ double s_x[E][ND], s_r[E][ND], s_f[E][ND];
@@ -539,32 +572,33 @@ __global__ __launch_bounds__((Shape2<N, BSEL>::BS)) void k_advect2d(Step2DArgs A
             na *= (k == c) ? 1.0 : xl - sk;
             nb *= (k == c) ? 1.0 : xl - tk;
         }
-        s_ai[slot][q] = (PT)(na / da);
-        s_bi[slot][q] = (PT)(nb / db);
+        s_ai[slot][q] = PP::put(na / da);
+        s_bi[slot][q] = PP::put(nb / db);
     }
     __syncthreads();
 
     // y = M^{-1} f (f in s_f or s_r, node c + N jj):
     //   stage 1: z[jj][l] = sum_c Ai[l][c] f[jj][c]
     //   stage 2: y[m][l] = sum_jj Bi[m][jj] z[jj][l]
-    // In FP32 the operand is first scaled by 2^-e, e = exponent of a
+    // In FP32 or BF16 the operand is first scaled by 2^-e, e = exponent of a
     // reference magnitude of it (max |phi*| of the element, then the last
-    // correction), so that it sits near 1 and never in the FP32 subnormal
-    // range; M^{-1} is linear, so the result is scaled back exactly.
+    // correction), so that it sits near 1 and never in the subnormal range;
+    // M^{-1} is linear, so the result is scaled back exactly.  In BF16 the
+    // operand and the stage-1 result are rounded to BF16 before each product.
     auto precond = [&](double (*src)[ND], int e2) -> double {
         const double sc = P32 ? ldexp(1.0, -e2) : 1.0;
         if (inblk) {
-            PT zz = 0;
+            AT zz = 0;
             for (int c = 0; c < N; ++c) {
                 const double v = src[slot][c + N * jj];
-                zz = fma(s_ai[slot][ii + N * c], (PT)(P32 ? v * sc : v), zz);
+                zz = fma(PP::get(s_ai[slot][ii + N * c]), PP::get(PP::put(P32 ? v * sc : v)), zz);
             }
-            s_z[slot][q] = zz;
+            s_z[slot][q] = PP::put(zz);
         }
         __syncthreads();
-        PT acc = 0;
+        AT acc = 0;
         if (inblk)
-            for (int j = 0; j < N; ++j) acc = fma(s_bi[slot][jj + N * j], s_z[slot][ii + N * j], acc);
+            for (int j = 0; j < N; ++j) acc = fma(PP::get(s_bi[slot][jj + N * j]), PP::get(s_z[slot][ii + N * j]), acc);
         return P32 ? ldexp((double)acc, e2) : (double)acc;
     };
     // exponent of a reference magnitude, clamped so 2^-e stays finite
@@ -1237,33 +1271,34 @@ int facevel_n(int kx, int ky, int periodic, const double* aN, const double* tab,
     return hipGetLastError() == hipSuccess ? 0 : 1;
 }
 
-template <int N, bool P32>
+template <int N, int PR>
 void adv_launch(const Step2DArgs& A, dim3 grid, hipStream_t s)
 {
-    if (A.targets) hipLaunchKernelGGL((k_advect2d<N, P32, true>), grid, dim3(kBlock2), 0, s, A);
-    else hipLaunchKernelGGL((k_advect2d<N, P32, false>), grid, dim3(kBlock2), 0, s, A);
+    if (A.targets) hipLaunchKernelGGL((k_advect2d<N, PR, true>), grid, dim3(kBlock2), 0, s, A);
+    else hipLaunchKernelGGL((k_advect2d<N, PR, false>), grid, dim3(kBlock2), 0, s, A);
 }
 
 template <int N, int BSEL>
 void adv_shape(const Step2DArgs& A, hipStream_t s)
 {
     using S = Shape2<N, BSEL>;
-    hipLaunchKernelGGL((k_advect2d<N, false, false, BSEL>), dim3((A.K + S::E - 1) / S::E), dim3(S::BS), 0, s, A);
+    hipLaunchKernelGGL((k_advect2d<N, 0, false, BSEL>), dim3((A.K + S::E - 1) / S::E), dim3(S::BS), 0, s, A);
 }
 
 template <int N>
 int adv_n(const Step2DArgs& A, hipStream_t s)
 {
     // the alternative block shapes exist for the FP64 boundary-rows kernel
-    if (A.bs != 0 && A.precision != SL_PREC_FP32_REFINED && !A.targets) {
+    if (A.bs != 0 && A.precision == SL_PREC_FP64 && !A.targets) {
         if (A.bs == 1) adv_shape<N, 1>(A, s);
         else adv_shape<N, 2>(A, s);
         return hipGetLastError() == hipSuccess ? 0 : 1;
     }
     constexpr int E = kBlock2 / (N * N);
     const dim3 grid((A.K + E - 1) / E);
-    if (A.precision == SL_PREC_FP32_REFINED) adv_launch<N, true>(A, grid, s);
-    else adv_launch<N, false>(A, grid, s);
+    if (A.precision == SL_PREC_FP32_REFINED) adv_launch<N, 1>(A, grid, s);
+    else if (A.precision == SL_PREC_BF16_REFINED) adv_launch<N, 2>(A, grid, s);
+    else adv_launch<N, 0>(A, grid, s);
     return hipGetLastError() == hipSuccess ? 0 : 1;
 }
 

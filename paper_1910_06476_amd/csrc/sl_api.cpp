@@ -386,7 +386,8 @@ static sl_status create_mixed(const sl_mesh_desc* d, sl_mesh** out)
     if (!mixed_plan(d, &P)) return SL_E_INVALID;
     if (d->nodes != SL_NODES_GL && d->nodes != SL_NODES_CG) return SL_E_INVALID;
     if (d->form != SL_FORM_ADVECTIVE && d->form != SL_FORM_CONSERVATIVE) return SL_E_INVALID;
-    if (d->precision != SL_PREC_FP64 && d->precision != SL_PREC_FP32_REFINED) return SL_E_INVALID;
+    if (d->precision != SL_PREC_FP64 && d->precision != SL_PREC_FP32_REFINED && d->precision != SL_PREC_BF16_REFINED)
+        return SL_E_INVALID;
     if (!(d->x1 > d->x0) || !(d->y1 > d->y0) || !std::isfinite(d->x0) || !std::isfinite(d->x1) ||
         !std::isfinite(d->y0) || !std::isfinite(d->y1))
         return SL_E_INVALID;
@@ -633,7 +634,9 @@ sl_status sl_create_mesh(const sl_mesh_desc* d, sl_mesh** out)
     if (d->nodes != SL_NODES_GL && d->nodes != SL_NODES_CG) return SL_E_INVALID;
     if (d->bc != SL_BC_PERIODIC && d->bc != SL_BC_GHOST) return SL_E_INVALID;
     if (d->form != SL_FORM_ADVECTIVE && d->form != SL_FORM_CONSERVATIVE) return SL_E_INVALID;
-    if (d->precision != SL_PREC_FP64 && !(d->precision == SL_PREC_FP32_REFINED && d->dim == 2)) return SL_E_INVALID;
+    if (d->precision != SL_PREC_FP64 &&
+        !((d->precision == SL_PREC_FP32_REFINED || d->precision == SL_PREC_BF16_REFINED) && d->dim == 2))
+        return SL_E_INVALID;
     if (!(d->x1 > d->x0) || (d->dim == 2 && !(d->y1 > d->y0))) return SL_E_INVALID;
     if (!std::isfinite(d->x0) || !std::isfinite(d->x1)) return SL_E_INVALID;
 

@@ -70,6 +70,37 @@ def test_fp32_refined_tiny_values():
     assert rel_l2(g, o) <= TOL, rel_l2(g, o)
 
 
+@pytest.mark.parametrize("n", [3, 6, 9, 11])
+@pytest.mark.parametrize("mode", [W.HARD, W.SOFT])
+def test_bf16_refined_remap_parity(n, mode):
+    """SL_PREC_BF16_REFINED: BF16 preconditioner entries and operands, FP32
+    sums, FP64 residual and iterate.  Each sweep contracts the error only to
+    about the BF16 rounding (2^-9) times the preconditioner's size, so more
+    sweeps are needed, but the limit is the same FP64 solution of eq. 5.4."""
+    w = _swirl_case(4, 5, n, mode=mode, form=W.CONSERVATIVE, nsteps=4)
+    announce(f"2d bf16-refined n={n} mode={mode}")
+    g, st, rc = run_gpu(w, precision=2)
+    o, ost = run_oracle(w)
+    assert rc == 0 and (st.flags & ~2) == 0, st.flags
+    assert rel_l2(g, o) <= TOL, rel_l2(g, o)
+
+
+def test_bf16_refined_tiny_values_and_sweeps():
+    """The hill's tail (1e-33) with BF16 operands: the power-of-two scaling
+    keeps them in the normal range; every element converges within the cap,
+    in more sweeps than the FP32 and FP64 preconditioners need."""
+    w = W.c3(kx=8, nsteps=5)
+    announce("c3 8x8 bf16-refined")
+    g, st, rc = run_gpu(w, precision=2)
+    _, s32, _ = run_gpu(w, precision=1)
+    _, s64, _ = run_gpu(w)
+    o, ost = run_oracle(w)
+    assert rc == 0 and st.flags == 0, (rc, st.flags)
+    assert st.remap_sweeps_max < 60
+    assert st.remap_sweeps_mean > s32.remap_sweeps_mean >= s64.remap_sweeps_mean
+    assert rel_l2(g, o) <= TOL, rel_l2(g, o)
+
+
 def test_c3_shape_small_parity():
     w = W.c3(kx=8, nsteps=10)
     announce("c3 8x8 10 steps")

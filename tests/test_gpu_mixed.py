@@ -63,6 +63,18 @@ def test_c4_orders_parity(mode, form):
     assert rel_l2(g, o) <= TOL, rel_l2(g, o)
 
 
+@pytest.mark.parametrize("precision", [1, 2])
+def test_c4_orders_reduced_precision_preconditioner_parity(precision):
+    """FP32 and BF16 remap preconditioners on a mixed-order mesh: FP64
+    residuals, so the same FP64 solution."""
+    w = _case(6, 5, (4, 6, 8, 12), seed=4)
+    announce(f"mixed c4 orders precision={precision}")
+    g, st, rc = _gpu(w, precision=precision)
+    o, ost = _oracle(w)
+    assert rc == 0 and (st.flags & ~2) == 0, (rc, st.flags)
+    assert rel_l2(g, o) <= TOL, rel_l2(g, o)
+
+
 @pytest.mark.parametrize("seed", [2, 3])
 def test_all_orders_parity(seed):
     """Every order 1..12 present: thirteen... twelve buckets, all pairs of
