@@ -58,6 +58,32 @@ __device__ __forceinline__ double clenshaw_p(const double* __restrict__ c, doubl
     return fma(x, b1, c[0] - b2);
 }
 
+// clenshaw_p at P points at once: each coefficient is read once for all of
+// them, and the P recurrences are independent (the same operations per
+// point as clenshaw_p)
+template <int N, int P>
+__device__ __forceinline__ void clenshaw_multi(const double* __restrict__ c, const double (&x)[P], double (&v)[P])
+{
+    double b1[P], b2[P], x2[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        b1[p] = b2[p] = 0.0;
+        x2[p] = 2.0 * x[p];
+    }
+#pragma unroll
+    for (int k = N - 1; k >= 1; --k) {
+        const double ck = c[k];
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            const double b0 = fma(x2[p], b1[p], ck - b2[p]);
+            b2[p] = b1[p];
+            b1[p] = b0;
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < P; ++p) v[p] = fma(x[p], b1[p], c[0] - b2[p]);
+}
+
 template <int N>
 __device__ __forceinline__ double clenshaw(const double (&c)[N], double x)
 {
@@ -484,6 +510,24 @@ __global__ __launch_bounds__(kBlock) void k_advect1d(Step1DArgs A)
             if (!act) continue;
             const double x0 = node ? xi_i : (double)edge;
             double am = 0.0, ae = 0.0;  // sum_q bu_q v_q and sum_q bu_q v_q^2
+            if constexpr (RKS == 4 && MONO) {
+                // abscissae 0, 1/2, 1: both backtraces first, then phi^n at
+                // the two feet in one pass over its coefficients
+                double sb[2] = {x0, x0}, hq[2] = {1.0, 1.0}, xf[2], vf[2];
+#pragma unroll
+                for (int z = 0; z < 2; ++z) {
+                    const double h = RK.cu(z + 1) * A.dt;
+                    rk_move_mono<CONS, NA, RKS>(A.rk, mu, md, -h, h, sb[z], hq[z], out, node, k_i, dv_i);
+                    xf[z] = 2.0 * sb[z] - 1.0;
+                }
+                clenshaw_multi<N, 2>(cp, xf, vf);
+                const double val[3] = {node ? phi_i : cheb_end<N>(cp, edge), hq[0] * vf[0], hq[1] * vf[1]};
+#pragma unroll
+                for (int qd = 0; qd < 3; ++qd) {
+                    am += RK.bu(qd) * val[qd];
+                    ae += RK.bu(qd) * val[qd] * val[qd];
+                }
+            } else {
 #pragma unroll
             for (int qd = 0; qd < 4; ++qd) {
                 if (qd >= RK.nq()) break;
@@ -501,6 +545,7 @@ __global__ __launch_bounds__(kBlock) void k_advect1d(Step1DArgs A)
                 const double bq = RK.bu(qd);
                 am += bq * val;
                 ae += bq * val * val;
+            }
             }
             // node: volume terms; edge lane: the edge's stage sums, stored now
             if (node) {
