@@ -647,36 +647,30 @@ __global__ __launch_bounds__(kBlock) void k_advect1d(Step1DArgs A)
 // constrained least squares: one lane per element, values in registers
 // ---------------------------------------------------------------------------
 constexpr int kConBlock = 64;  // one wave
-constexpr int kConQ = 4;       // lanes per element (a quad)
+constexpr int kConQ = 2;       // lanes per element (a pair)
 constexpr int kConElems = kConBlock / kConQ;
 
 // value of the lane whose index differs in bit 0 (CTRL 0xB1, quad_perm
-// [1,0,3,2]) or bit 1 (CTRL 0x4E, quad_perm [2,3,0,1]): a DPP move within
-// the quad, no LDS traffic
+// [1,0,3,2]): a DPP move within the pair, no LDS traffic
 template <int CTRL>
-__device__ __forceinline__ double quad_swap(double v)
+__device__ __forceinline__ double lane_swap(double v)
 {
     const long long b = __double_as_longlong(v);
     const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
     const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
-// sum over the element's quad (lanes 4k .. 4k+3), the same in every lane:
-// (v0 + v1) + (v2 + v3) in each
-__device__ __forceinline__ double quad_sum(double v)
-{
-    v += quad_swap<0xB1>(v);
-    return v + quad_swap<0x4E>(v);
-}
-__device__ __forceinline__ double quad_max(double v)
-{
-    v = fmax(v, quad_swap<0xB1>(v));
-    return fmax(v, quad_swap<0x4E>(v));
-}
+// sum over the element's pair of lanes (2k, 2k+1), the same in both
+// (v0 + v1 = v1 + v0 exactly)
+__device__ __forceinline__ double pair_sum(double v) { return v + lane_swap<0xB1>(v); }
+__device__ __forceinline__ double pair_max(double v) { return fmax(v, lane_swap<0xB1>(v)); }
 
-// Four lanes per element: lane r of the quad holds nodes r, r+4, r+8, ...
-// (NP of them); row products are quad sums, and the small KKT / least-squares
-// solve is repeated in the four lanes.
+// Two lanes per element: lane r of the pair holds nodes r, r+2, r+4, ...
+// (NP of them); row products are pair sums, and the small KKT / least-squares
+// solve is repeated in both lanes.  32 elements per wave: at order 16 the
+// kernel takes about 250 VGPRs (two waves per SIMD), and a 65536-element
+// launch (2048 waves) is resident at once; with four lanes per element its
+// 4096 waves at three per SIMD needed a second, mostly idle round.
 template <int N>
 __global__ __launch_bounds__(kConBlock) void k_constrain1d(Step1DArgs A)
 {
@@ -688,7 +682,7 @@ __global__ __launch_bounds__(kConBlock) void k_constrain1d(Step1DArgs A)
     __shared__ double s_buf[kConElems * N];
     __shared__ double s_rec[NR];
     __shared__ double s_vf[NF];
-    __shared__ double s_tab[3][kConQ][NP];  // l(0), l(1), w at node r + 4k of lane r ([row][r][k])
+    __shared__ double s_tab[3][kConQ][NP];  // l(0), l(1), w at node r + 2k of lane r ([row][r][k])
     __shared__ double s_st[kConElems][4];  // per-element statistics, reduced by four lanes
     __shared__ int s_fq[kConElems];
     const int t = threadIdx.x;
@@ -837,7 +831,7 @@ __global__ __launch_bounds__(kConBlock) void k_constrain1d(Step1DArgs A)
         Cph[2] = fma(Wn[k], ph[k], Cph[2]);
     }
 #pragma unroll
-    for (int a = 0; a < 3; ++a) Cph[a] = quad_sum(Cph[a]);
+    for (int a = 0; a < 3; ++a) Cph[a] = pair_sum(Cph[a]);
     const double dd0 = bnd ? dB0 : 0.0, dd1 = bnd ? dB1 : 0.0, dd2 = mass ? Mt : 0.0;
     const double s0 = bnd ? 1.0 : 0.0, s1 = bnd ? 1.0 : 0.0, s2 = mass ? 1.0 : 0.0;
     bool singular = false;
@@ -909,7 +903,7 @@ __global__ __launch_bounds__(kConBlock) void k_constrain1d(Step1DArgs A)
                 double gw = 0.0;
 #pragma unroll
                 for (int k = 0; k < NP; ++k) gw += (Wn[k] * phi[k]) * Wn[k];
-                mu = quad_sum(gw) / A.g22;
+                mu = pair_sum(gw) / A.g22;
             }
             double red[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -922,7 +916,7 @@ __global__ __launch_bounds__(kConBlock) void k_constrain1d(Step1DArgs A)
                 red[4] += c3 * ph[k];
             }
 #pragma unroll
-            for (int a = 0; a < 5; ++a) red[a] = quad_sum(red[a]);
+            for (int a = 0; a < 5; ++a) red[a] = pair_sum(red[a]);
             solve(true, red, Et - mu * Mt, y);
             double diff = 0.0, back = 0.0;
 #pragma unroll
@@ -934,8 +928,8 @@ __global__ __launch_bounds__(kConBlock) void k_constrain1d(Step1DArgs A)
                 older[k] = phi[k];
                 phi[k] = nv;
             }
-            diff = quad_max(diff);
-            back = quad_max(back);
+            diff = pair_max(diff);
+            back = pair_max(back);
             iters = it;
             if (diff < A.etol) {
                 conv = true;
@@ -956,10 +950,10 @@ __global__ __launch_bounds__(kConBlock) void k_constrain1d(Step1DArgs A)
         r3 = fma(Wn[k] * phi[k], phi[k], r3);
         finite = finite && isfinite(phi[k]);
     }
-    r0 = quad_sum(r0);
-    r1 = quad_sum(r1);
-    r2 = quad_sum(r2);
-    r3 = quad_sum(r3);
+    r0 = pair_sum(r0);
+    r1 = pair_sum(r1);
+    r2 = pair_sum(r2);
+    r3 = pair_sum(r3);
     double rb = (live && bnd) ? fmax(fabs(r0 - dB0), fabs(r1 - dB1)) : 0.0;
     double rm = (live && mass) ? fabs(r2 - Mt) : 0.0;
     double re = (live && energy) ? fabs(r3 - Et) : 0.0;
@@ -970,7 +964,7 @@ __global__ __launch_bounds__(kConBlock) void k_constrain1d(Step1DArgs A)
         if (singular) fl |= FLAG_SINGULAR;
         if (!finite) fl |= FLAG_NONFINITE;
     }
-    // per-element statistics (the same in the quad's four lanes), reduced
+    // per-element statistics (the same in the pair's two lanes), reduced
     // over the block after the next barrier
     if (r == 0) {
         s_st[le][0] = rb;
