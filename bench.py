@@ -435,6 +435,9 @@ def main():
                    "K": w.K, "n": w.n, "dofs": w.dofs, "dt": w.dt, "rk": w.rk, "constraints": "B+M+E",
                    "energy_tol": w.energy_tol},
         "l2_error": l2, "l2_time": T, "status": P.status_string(rc), "max_picard": st.max_picard,
+        "status_note": "HARD energy row: where the energy correction exceeds the tolerance (the Gaussian's "
+                       "peak elements) the Picard map is 2-periodic; the 2-cycle rule stops and flags it, "
+                       "as the oracle does",
         "step_latency": lat,
         "roofline": roof,
     }
