@@ -106,15 +106,17 @@ def cpu_baseline(w, budget_s: float = 12.0):
 
 def advect2d_flops_per_element(n: int, s: int, sweeps: float, vel_terms: int) -> float:
     """Algorithmic FP64 flops of the 2D advect+solve kernel per element:
-    motion (tensor Clenshaw, 2 components, (s-1) evaluations per particle,
-    3 flops per term), the V rows (product form, ~6n per particle), the
-    separable preconditioner (2 n^2 (n-1) products to build, 4 n^3 per
-    application), and per defect-correction sweep the matrix-free V x
-    (2 n^4 + 2 n^2) plus one preconditioner application."""
+    motion (the tensor Chebyshev series summed directly over T_k(x) T_l(y),
+    one FMA per coefficient: 2 m^2 flops per component, 2 components, plus
+    the T recurrences, 8 (m - 2) for m > 2; (s-1) evaluations per particle),
+    the V rows (product form, ~6n per particle), the separable preconditioner
+    (2 n^2 (n-1) products to build, 4 n^3 per application), and per
+    defect-correction sweep the matrix-free V x (2 n^4 + 2 n^2) plus one
+    preconditioner application."""
     nd = n * n
     m = vel_terms
-    clen2 = 3.0 * (m * m + m)
-    f = nd * ((s - 1) * 2 * clen2 + 8.0 * s)
+    ev = 2 * 2.0 * m * m + 8.0 * max(m - 2, 0)
+    f = nd * ((s - 1) * ev + 8.0 * s)
     f += nd * 6.0 * n
     f += 2 * nd * 4.0 * (n - 1)
     apply = 4.0 * n ** 3
@@ -181,7 +183,7 @@ def bench_c3(args, torch, P, W, stream):
         "vel_terms": st.vel_terms,
         "roofline": {"kernel": "sl2d_advect", "bound": "alu", "achieved": ach / 1e12,
                      "peak": FP64_VALU_PEAK / 1e12, "unit": "TFLOP/s", "frac": ach / FP64_VALU_PEAK,
-                     "traffic": measured_traffic("k_advect2d", "sl2d.hip", "sl2d_c3_256x256_n9.md")
+                     "traffic": measured_traffic("k_advect2d", "sl2d_kernels.h", "sl2d_c3_256x256_n9.md")
                      if args.precision == "fp64" else None,
                      "avg_launch_us": adv_avg * 1e6, "algorithmic_flops_per_launch": fl,
                      "kernels_us": {"sl2d_advect": adv_avg * 1e6, "sl2d_constrain": con_avg * 1e6}},

@@ -1,0 +1,1475 @@
+// Kernels and per-order launchers of the 2D step, included by the
+// sl2d_p*.hip units; each unit instantiates them for a few orders, so the
+// orders compile in parallel.  See sl2d.hip for the method's outline.
+#pragma once
+#include <type_traits>
+
+#include "sl2d_ops.h"
+
+namespace sl {
+namespace {
+
+constexpr int kBlock2 = 256;
+
+__device__ __forceinline__ bool outside2(double s) { return s < -1e-10 || s > 1.0 + 1e-10; }
+
+// table layout of a 2D mesh
+template <int N> struct Off2 {
+    static constexpr int ND = N * N;
+    static constexpr int XI = 0, W = N, L0 = 2 * N, L1 = 3 * N, TINV = 4 * N, DM = 4 * N + ND, LAM = 4 * N + 2 * ND,
+                         QH = 5 * N + 2 * ND, QS = QH + 16 * ND, ZMH = QS + 16 * ND, ZMS = ZMH + ND;
+};
+
+__device__ __forceinline__ double upwind2(double vn, double lo, double hi)
+{
+    if (vn > 0.0) return lo;
+    if (vn < 0.0) return hi;
+    return 0.5 * (lo + hi);
+}
+
+// sum_{k,l <= d} C[k + N l] T_k(x) T_l(y): Clenshaw in x inside Clenshaw in y
+template <int N>
+__device__ __forceinline__ double cheb2(const double* __restrict__ C, double x, double y, int d)
+{
+    const double x2 = 2.0 * x, y2 = 2.0 * y;
+    double c1 = 0.0, c2 = 0.0;
+    for (int l = d; l >= 0; --l) {
+        const double* row = C + N * l;
+        double b1 = 0.0, b2 = 0.0;
+        for (int k = d; k >= 1; --k) {
+            const double b0 = fma(x2, b1, row[k] - b2);
+            b2 = b1;
+            b1 = b0;
+        }
+        const double inner = fma(x, b1, row[0] - b2);
+        if (l >= 1) {
+            const double c0 = fma(y2, c1, inner - c2);
+            c2 = c1;
+            c1 = c0;
+        } else {
+            return fma(y, c1, inner - c2);
+        }
+    }
+    return 0.0;
+}
+
+// NC tensor Chebyshev series C[c][N*l + k] (k: degree in x, l: degree in y,
+// both <= D) at (x, y), summed directly over T_k(x) T_l(y).  The three-term
+// recurrence gives T_k(x), T_l(y) (bounded by 1 on [-1, 1], as the sums are
+// for particles inside their element); then (D+1)^2 FMAs per series against
+// Clenshaw's 2(D+1)^2, and the D+1 row sums of every series are independent
+// of each other.
+template <int N, int D, int NC>
+__device__ __forceinline__ void cheb2_direct(const double* const (&C)[NC], double x, double y, double (&out)[NC])
+{
+    static_assert(D < N, "degree");
+    double tx[D + 1], ty[D + 1];
+    tx[0] = ty[0] = 1.0;
+    if constexpr (D >= 1) {
+        tx[1] = x;
+        ty[1] = y;
+    }
+    const double x2 = 2.0 * x, y2 = 2.0 * y;
+#pragma unroll
+    for (int k = 2; k <= D; ++k) {
+        tx[k] = fma(x2, tx[k - 1], -tx[k - 2]);
+        ty[k] = fma(y2, ty[k - 1], -ty[k - 2]);
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        double acc = 0.0;
+#pragma unroll
+        for (int l = 0; l <= D; ++l) {
+            double row = 0.0;
+#pragma unroll
+            for (int k = 0; k <= D; ++k) row = fma(C[c][N * l + k], tx[k], row);
+            acc = fma(ty[l], row, acc);
+        }
+        out[c] = acc;
+    }
+}
+
+// the same at a run-time degree d: compile-time degrees up to 7 (the
+// effective degree of a resolved velocity), Clenshaw beyond
+template <int N, int NC>
+__device__ __forceinline__ void cheb2_eval(const double* const (&C)[NC], double x, double y, int d, double (&out)[NC])
+{
+#define SL_CHEB2_CASE(DD)                                         \
+    if constexpr (N > DD)                                        \
+        if (d == DD) {                                           \
+            cheb2_direct<N, DD, NC>(C, x, y, out);               \
+            return;                                              \
+        }
+    SL_CHEB2_CASE(0) SL_CHEB2_CASE(1) SL_CHEB2_CASE(2) SL_CHEB2_CASE(3)
+    SL_CHEB2_CASE(4) SL_CHEB2_CASE(5) SL_CHEB2_CASE(6) SL_CHEB2_CASE(7)
+#undef SL_CHEB2_CASE
+#pragma unroll
+    for (int c = 0; c < NC; ++c) out[c] = cheb2<N>(C[c], x, y, d);
+}
+
+// ---------------------------------------------------------------------------
+// velocity preparation: tensor Chebyshev coefficients, divergence, own edge
+// normal speeds, effective degree
+// ---------------------------------------------------------------------------
+template <int N>
+__global__ void k_prep2d(int K, int has_div, int cons, const double* __restrict__ aN, double* __restrict__ aM,
+                         double* __restrict__ divN, double* __restrict__ divM, const double* __restrict__ tab, double invdx, double invdy, double vscale,
+                         int* __restrict__ vdeg)
+{
+    using O = Off2<N>;
+    constexpr int ND = N * N;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= K) return;
+    const double* U = aN + (size_t)e * ND;
+    const double* V = aN + (size_t)K * ND + (size_t)e * ND;
+    double* CU = aM + (size_t)e * ND;
+    double* CV = aM + (size_t)K * ND + (size_t)e * ND;
+    // C[l][k] = sum_j sum_i Tinv[l][j] Tinv[k][i] F[j][i]  (F[j][i] = node i + N j)
+    auto modal = [&](const double* F, double* C) {
+        double tmp[ND];  // tmp[j][k] = sum_i Tinv[k][i] F[j][i]
+        for (int j = 0; j < N; ++j)
+            for (int k = 0; k < N; ++k) {
+                double s = 0.0;
+                for (int i = 0; i < N; ++i) s = fma(tab[O::TINV + k * N + i], F[i + N * j], s);
+                tmp[k + N * j] = s;
+            }
+        for (int l = 0; l < N; ++l)
+            for (int k = 0; k < N; ++k) {
+                double s = 0.0;
+                for (int j = 0; j < N; ++j) s = fma(tab[O::TINV + l * N + j], tmp[k + N * j], s);
+                C[k + N * l] = s;
+            }
+    };
+    modal(U, CU);
+    modal(V, CV);
+    double* dvn = divN + (size_t)e * ND;
+    if (!has_div) {
+        for (int j = 0; j < N; ++j)
+            for (int i = 0; i < N; ++i) {
+                double sx = 0.0, sy = 0.0;
+                for (int l = 0; l < N; ++l) sx = fma(tab[O::DM + i * N + l], U[l + N * j], sx);
+                for (int m = 0; m < N; ++m) sy = fma(tab[O::DM + j * N + m], V[i + N * m], sy);
+                dvn[i + N * j] = sx * invdx + sy * invdy;
+            }
+    }
+    modal(dvn, divM + (size_t)e * ND);
+    // effective degree: the 1D rule applied to the row and column sums of
+    // |C|, with the noise threshold taken against max(sum |C|, scale)
+    auto degree = [&](const double* C, double scale) {
+        double tot = 0.0;
+        for (int q = 0; q < ND; ++q) tot += fabs(C[q]);
+        const double thr = fmax(tot, scale) * 0x1p-46;
+        int d = 0;
+        double tx = 0.0, ty = 0.0;
+        for (int k = N - 1; k >= 1; --k) {
+            for (int l = 0; l < N; ++l) {
+                tx += fabs(C[k + N * l]);
+                ty += fabs(C[l + N * k]);
+            }
+            if (d == 0 && (tx > thr || ty > thr)) d = k;
+        }
+        return d;
+    };
+    int d = max(degree(CU, vscale), degree(CV, vscale));
+    if (cons) d = max(d, degree(divM + (size_t)e * ND, 0.0));
+    atomicMax(vdeg, d);
+}
+
+// ---------------------------------------------------------------------------
+// For edge point tt of element e (layout: left j, right j, bottom i, top i):
+// the neighbour across that face (-1 outside the domain), the matching edge
+// point in the neighbour, the ghost index, and whether e is the high side of
+// the face (its left or bottom face)
+// ---------------------------------------------------------------------------
+template <int N>
+__device__ __forceinline__ void face_partner2(int e, int tt, int kx, int ky, int periodic, int& nbe, int& nbt,
+                                              int& gidx, bool& high)
+{
+    const int side = tt / N, k = tt % N;
+    const int ex = e % kx, ey = e / kx;
+    const int KL = ky * N, KB = kx * N;
+    switch (side) {
+    case 0:
+        nbe = ex > 0 ? e - 1 : (periodic ? ey * kx + kx - 1 : -1);
+        nbt = N + k; gidx = ey * N + k; high = true;
+        break;
+    case 1:
+        nbe = ex < kx - 1 ? e + 1 : (periodic ? ey * kx : -1);
+        nbt = k; gidx = KL + ey * N + k; high = false;
+        break;
+    case 2:
+        nbe = ey > 0 ? e - kx : (periodic ? (ky - 1) * kx + ex : -1);
+        nbt = 3 * N + k; gidx = 2 * KL + ex * N + k; high = true;
+        break;
+    default:
+        nbe = ey < ky - 1 ? e + kx : (periodic ? ex : -1);
+        nbt = 2 * N + k; gidx = 2 * KL + KB + ex * N + k; high = false;
+        break;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// face normal velocity at every element's own edge points: the mean of the
+// two sides' interpolated normal components (the interior side alone at a
+// ghost boundary); a speed at or below vzero has no upwind side and is
+// stored as zero.  Built once per velocity.
+// ---------------------------------------------------------------------------
+template <int N>
+__global__ void k_facevel2d(int kx, int ky, int periodic, const double* __restrict__ aN,
+                            const double* __restrict__ tab, double vzero, double* __restrict__ vface)
+{
+    using O = Off2<N>;
+    constexpr int ND = N * N, NB = 4 * N;
+    const int K = kx * ky;
+    const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= (long)K * NB) return;
+    const int e = (int)(gid / NB), tt = (int)(gid % NB);
+    auto normal = [&](int el, int t2) {
+        const int side = t2 / N, k = t2 % N;
+        const double* lv = tab + ((side & 1) ? O::L1 : O::L0);
+        double s = 0.0;
+        if (side < 2) {
+            const double* U = aN + (size_t)el * ND;
+            for (int c = 0; c < N; ++c) s = fma(lv[c], U[c + N * k], s);
+        } else {
+            const double* V = aN + (size_t)K * ND + (size_t)el * ND;
+            for (int c = 0; c < N; ++c) s = fma(lv[c], V[k + N * c], s);
+        }
+        return s;
+    };
+    int nbe, nbt, gidx;
+    bool high;
+    face_partner2<N>(e, tt, kx, ky, periodic, nbe, nbt, gidx, high);
+    double vn = normal(e, tt);
+    if (nbe >= 0) vn = 0.5 * (vn + normal(nbe, nbt));
+    if (fabs(vn) <= vzero) vn = 0.0;
+    vface[gid] = vn;
+}
+
+// ---------------------------------------------------------------------------
+// Lagrange basis row l_k(x), k < N, in product form:
+// l_k(x) = lambda_k prod_{j != k} (x - xi_j), from prefix and suffix products
+// (no division, exact at the nodes)
+// ---------------------------------------------------------------------------
+template <int N>
+__device__ __forceinline__ void lag_row(const double* __restrict__ tab, double x, double (&l)[N])
+{
+    using O = Off2<N>;
+    double pre[N];
+    double acc = 1.0;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        pre[k] = acc;
+        acc *= (x - tab[O::XI + k]);
+    }
+    acc = 1.0;
+#pragma unroll
+    for (int k = N - 1; k >= 0; --k) {
+        l[k] = tab[O::LAM + k] * pre[k] * acc;
+        acc *= (x - tab[O::XI + k]);
+    }
+}
+
+// phi^n (nodal values f of one element, in LDS) carried back along the
+// characteristic through reference point (s, r) over time h: the value of
+// phi^n at the foot, times the source factor of the conservative form.  The
+// trace uses the same explicit RK tableau as the particles (eq. 4.11 in 2D);
+// `out` is set when a stage position leaves the element.
+template <int N>
+__device__ double backtrace2(const Step2DArgs& A, const double* cu, const double* cv, const double* cd,
+                             const double* f, double h, double s, double r, bool& out)
+{
+    const RKTab& T = A.rk;
+    double qf = 1.0;
+    if (h > 0.0) {
+        double ks[4], kr[4], kq[4];
+#pragma unroll
+        for (int st = 0; st < 4; ++st) {
+            ks[st] = kr[st] = kq[st] = 0.0;
+            if (st < T.s) {
+                double ss = s, rr = r, qq = qf;
+                for (int m = 0; m < st; ++m) {
+                    ss += h * T.a[st][m] * ks[m];
+                    rr += h * T.a[st][m] * kr[m];
+                    qq += h * T.a[st][m] * kq[m];
+                }
+                out |= outside2(ss) || outside2(rr);
+                const double x = 2.0 * ss - 1.0, y = 2.0 * rr - 1.0;
+                if (A.cons) {
+                    const double* C3[3] = {cu, cv, cd};
+                    double o[3];
+                    cheb2_eval<N, 3>(C3, x, y, A.vdeg, o);
+                    ks[st] = -o[0] * A.invdx;
+                    kr[st] = -o[1] * A.invdy;
+                    kq[st] = -o[2] * qq;
+                } else {
+                    const double* C2[2] = {cu, cv};
+                    double o[2];
+                    cheb2_eval<N, 2>(C2, x, y, A.vdeg, o);
+                    ks[st] = -o[0] * A.invdx;
+                    kr[st] = -o[1] * A.invdy;
+                    kq[st] = 0.0;
+                }
+            }
+        }
+#pragma unroll
+        for (int st = 0; st < 4; ++st)
+            if (st < T.s) {
+                s += h * T.b[st] * ks[st];
+                r += h * T.b[st] * kr[st];
+                qf += h * T.b[st] * kq[st];
+            }
+        out |= outside2(s) || outside2(r);
+    }
+    double ls[N], lr[N];
+    lag_row<N>(A.tab, s, ls);
+    lag_row<N>(A.tab, r, lr);
+    double acc = 0.0;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        double in = 0.0;
+#pragma unroll
+        for (int i = 0; i < N; ++i) in = fma(ls[i], f[i + N * j], in);
+        acc = fma(lr[j], in, acc);
+    }
+    return qf * acc;
+}
+
+// ---------------------------------------------------------------------------
+// advect + remap (eq. 5.4 by defect correction) + edge traces, and with TGT
+// the local parts of the mass and energy targets
+//
+// One lane per particle (n^2 lanes per element, floor(256/n^2) elements per
+// block).  With PR = 1 the separable preconditioner is stored and applied in
+// FP32, with PR = 2 its entries and operands are BF16 with FP32
+// accumulation; the residual and the iterate stay FP64 (iterative
+// refinement).  PR = 0 is FP64 throughout.
+//
+// Record of element e (stride A.rstride): its 4n edge traces of phi-hat;
+// with TGT also, per edge point where e is upwind, sum_q bu_q v_q and
+// sum_q bu_q v_q^2 of the backtraced stage values v_q (4n each), and
+// M^n + dt sum_q bu_q V_q, E^n + dt sum_q bu_q V'_q with the volume terms
+// V of the balance laws (eq. 4.14 generalised to the RK quadrature); with
+// backtracking interface values, last, the 4n face values it offers.
+// ---------------------------------------------------------------------------
+// block shapes of the advect kernel: 0 = 256 lanes, 1 = the fewest whole
+// waves that hold one element, 2 = 512 lanes
+template <int N, int BSEL> struct Shape2 {
+    static constexpr int ND = N * N;
+    static constexpr int BS = BSEL == 0 ? kBlock2 : BSEL == 1 ? ((ND + 63) / 64) * 64 : 2 * kBlock2;
+    static constexpr int E = BS / ND;
+};
+
+// Preconditioner storage and arithmetic of precision PR: FP64, FP32, or BF16
+// (the upper half of an FP32, rounded to nearest even) with FP32 products
+// and sums.  The BF16 operands multiply exactly in FP32.
+template <int PR> struct Prec;
+template <> struct Prec<0> {
+    using S = double;  // storage
+    using A = double;  // arithmetic
+    __device__ static S put(double v) { return v; }
+    __device__ static A get(S v) { return v; }
+};
+template <> struct Prec<1> {
+    using S = float;
+    using A = float;
+    __device__ static S put(double v) { return (float)v; }
+    __device__ static A get(S v) { return v; }
+};
+template <> struct Prec<2> {
+    using S = unsigned short;
+    using A = float;
+    __device__ static S put(double v)
+    {
+        const unsigned int b = __float_as_uint((float)v);
+        if ((b & 0x7f800000u) == 0x7f800000u) return (S)(b >> 16);  // inf / nan: truncate
+        return (S)((b + 0x7fffu + ((b >> 16) & 1u)) >> 16);          // round to nearest even
+    }
+    __device__ static A get(S v) { return __uint_as_float((unsigned int)v << 16); }
+};
+
+template <int N, int PR, bool TGT, int BSEL = 0>
+__global__ __launch_bounds__((Shape2<N, BSEL>::BS)) void k_advect2d(Step2DArgs A)
+{
+    using O = Off2<N>;
+    using PP = Prec<PR>;
+    using PT = typename PP::S;
+    using AT = typename PP::A;
+    constexpr bool P32 = PR != 0;  // reduced-precision preconditioner, operands scaled
+    constexpr int ND = N * N, E = Shape2<N, BSEL>::E, NB = 4 * N;
+    __shared__ double s_cu[E][ND], s_cv[E][ND], s_cd[E][ND];
+    __shared__ double s_x[E][ND], s_r[E][ND], s_f[E][ND];
+    __shared__ PT s_z[E][ND];
+    __shared__ PT s_ai[E][ND], s_bi[E][ND];
+    __shared__ double s_mx[E][N], s_my[E][N];
+    __shared__ unsigned long long s_nrm[2][E];  // max |y| per element, double-buffered by sweep parity
+    __shared__ int s_flag, s_sw_sum, s_sw_max;
+    __shared__ unsigned long long s_res;
+    __shared__ unsigned long long s_ref[E];  // max |phi*| per element
+
+    const int t = threadIdx.x;
+    const int slot = t / ND, q = t - slot * ND;
+    const bool inblk = slot < E;
+    const int sl = inblk ? slot : 0;
+    const int e = blockIdx.x * E + slot;
+    const bool live = inblk && e < A.K;
+    const double* __restrict__ tab = A.tab;
+    const int K = A.K;
+    const int ii = q % N, jj = q / N;
+    if (t == 0) {
+        s_flag = 0;
+        s_sw_sum = 0;
+        s_sw_max = 0;
+        s_res = 0ull;
+    }
+    if (t < E * 2) s_nrm[t / E][t % E] = 0ull;
+    if (t < E) s_ref[t] = 0ull;
+
+    const bool need_div = A.cons || (TGT && A.vol);
+    double phi_p = 0.0, u_p = 0.0, v_p = 0.0, dv_p = 0.0;
+    {
+        const size_t g = (size_t)(live ? e : 0) * ND + (inblk ? q : 0);
+        if (live) {
+            phi_p = A.phi[g];
+            u_p = A.aN[g];
+            v_p = A.aN[(size_t)K * ND + g];
+            if (need_div) dv_p = A.divN[g];
+        }
+        if (inblk) {
+            // only the coefficients within the effective degree are read
+            const bool used = live && ii <= A.vdeg && jj <= A.vdeg;
+            s_cu[slot][q] = used ? A.aM[g] : 0.0;
+            s_cv[slot][q] = used ? A.aM[(size_t)K * ND + g] : 0.0;
+            if (A.cons) s_cd[slot][q] = used ? A.divM[g] : 0.0;
+            if (TGT) s_x[slot][q] = phi_p;  // phi^n for the backtraces
+        }
+    }
+    __syncthreads();
+
+    const RKTab& T = A.rk;
+    bool out = false;
+
+    if constexpr (TGT) {
+        double* rec = A.rec + (size_t)(live ? e : 0) * A.rstride;
+        // upwind edge points: stage sums of the backtraced values
+        for (int tt = q; live && tt < NB; tt += ND) {
+            const int side = tt / N, k = tt % N;
+            const double vn = A.vface[(size_t)e * NB + tt];
+            // e is upwind where the flow leaves it: left/bottom faces for
+            // vn < 0, right/top faces for vn > 0
+            const bool up = (side == 0 || side == 2) ? vn < 0.0 : vn > 0.0;
+            double fm = 0.0, fe = 0.0;
+            if (up) {
+                const double s = side == 0 ? 0.0 : side == 1 ? 1.0 : tab[O::XI + k];
+                const double r = side == 2 ? 0.0 : side == 3 ? 1.0 : tab[O::XI + k];
+                for (int c = 0; c < T.nq; ++c) {
+                    const double v =
+                        backtrace2<N>(A, s_cu[slot], s_cv[slot], s_cd[slot], s_x[slot], T.cu[c] * A.dt, s, r, out);
+                    fm = fma(T.bu[c], v, fm);
+                    fe = fma(T.bu[c], v * v, fe);
+                }
+            }
+            rec[NB + tt] = fm;
+            rec[2 * NB + tt] = fe;
+        }
+        // local mass and energy with the volume terms of the balance laws:
+        // advective form +div phi (mass) and +div phi^2 (energy),
+        // conservative form -div phi^2 (energy)
+        double cm = 0.0, ce = 0.0;
+        if (live) {
+            const double Wp = A.dx * A.dy * tab[O::W + ii] * tab[O::W + jj];
+            cm = Wp * phi_p;
+            ce = Wp * phi_p * phi_p;
+            if (A.vol && dv_p != 0.0) {
+                double vm = 0.0, ve = 0.0;
+                for (int c = 0; c < T.nq; ++c) {
+                    const double v = backtrace2<N>(A, s_cu[slot], s_cv[slot], s_cd[slot], s_x[slot],
+                                                   T.cu[c] * A.dt, tab[O::XI + ii], tab[O::XI + jj], out);
+                    vm = fma(T.bu[c], v, vm);
+                    ve = fma(T.bu[c], v * v, ve);
+                }
+                if (!A.cons) cm += A.dt * Wp * dv_p * vm;
+                ce += A.dt * Wp * dv_p * (A.cons ? -ve : ve);
+            }
+        }
+        if (inblk) {
+            s_r[slot][q] = cm;
+            s_f[slot][q] = ce;
+        }
+        __syncthreads();
+        if (live && q == 0) {
+            double M = 0.0, En = 0.0;
+            for (int p = 0; p < ND; ++p) {
+                M += s_r[slot][p];
+                En += s_f[slot][p];
+            }
+            rec[3 * NB] = M;
+            rec[3 * NB + 1] = En;
+        }
+        __syncthreads();  // s_x, s_r, s_f are reused below
+    }
+
+    // forward motion of the particle (eq. 5.1 tensor interpolant of the velocity)
+    const int d = A.vdeg;
+    const double h = A.dt;
+    double sx, sy, sq;
+    // A series of degree <= 1 (constant, shear, rotation) is evaluated from
+    // registers: the same operations as the Clenshaw sum at that degree.
+    const bool low = d <= 1;
+    double lu[4] = {0.0, 0.0, 0.0, 0.0}, lv[4] = {0.0, 0.0, 0.0, 0.0}, ld[4] = {0.0, 0.0, 0.0, 0.0};
+    if (low) {
+        const int at[4] = {0, 1, N, N + 1};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            lu[k] = s_cu[sl][at[k]];
+            lv[k] = s_cv[sl][at[k]];
+            if (A.cons) ld[k] = s_cd[sl][at[k]];
+        }
+    }
+    auto vel = [&](const double (&c)[4], double x, double y) {
+        return d == 0 ? c[0] : fma(y, fma(x, c[3], c[2]), fma(x, c[1], c[0]));
+    };
+    {
+        const double s = tab[O::XI + ii], rr0 = tab[O::XI + jj], qv = phi_p;
+        double ks[4], kr[4], kq[4];
+#pragma unroll
+        for (int st = 0; st < 4; ++st) {
+            ks[st] = kr[st] = kq[st] = 0.0;
+            if (st < T.s) {
+                double ss = s, rr = rr0, qq = qv;
+                for (int m = 0; m < st; ++m) {
+                    ss += h * T.a[st][m] * ks[m];
+                    rr += h * T.a[st][m] * kr[m];
+                    qq += h * T.a[st][m] * kq[m];
+                }
+                double uu, vv, dd = 0.0;
+                if (st == 0) {
+                    uu = u_p;
+                    vv = v_p;
+                    dd = dv_p;
+                } else {
+                    const double x = 2.0 * ss - 1.0, y = 2.0 * rr - 1.0;
+                    if (low) {
+                        uu = vel(lu, x, y);
+                        vv = vel(lv, x, y);
+                        if (A.cons) dd = vel(ld, x, y);
+                    } else if (A.cons) {
+                        const double* C3[3] = {s_cu[sl], s_cv[sl], s_cd[sl]};
+                        double o[3];
+                        cheb2_eval<N, 3>(C3, x, y, d, o);
+                        uu = o[0];
+                        vv = o[1];
+                        dd = o[2];
+                    } else {
+                        const double* C2[2] = {s_cu[sl], s_cv[sl]};
+                        double o[2];
+                        cheb2_eval<N, 2>(C2, x, y, d, o);
+                        uu = o[0];
+                        vv = o[1];
+                    }
+                    out |= inblk && (outside2(ss) || outside2(rr));
+                }
+                ks[st] = uu * A.invdx;
+                kr[st] = vv * A.invdy;
+                kq[st] = A.cons ? -dd * qq : 0.0;
+            }
+        }
+        double ds = 0.0, dr = 0.0, dq = 0.0;
+#pragma unroll
+        for (int st = 0; st < 4; ++st)
+            if (st < T.s) {
+                ds += T.b[st] * ks[st];
+                dr += T.b[st] * kr[st];
+                dq += T.b[st] * kq[st];
+            }
+        sx = s + h * ds;
+        sy = rr0 + h * dr;
+        sq = qv + h * dq;
+        out |= inblk && (outside2(sx) || outside2(sy));
+    }
+
+    // row of V for this particle: a_l = l_l(xi*), b_m = l_m(eta*) (eq. 5.4)
+    double a[N], b[N];
+    lag_row<N>(tab, sx, a);
+    lag_row<N>(tab, sy, b);
+
+    // separable preconditioner: mean displacement of each x-column i and of
+    // each y-row j of particles
+    if (inblk) {
+        s_r[slot][q] = sx - tab[O::XI + ii];
+        s_x[slot][q] = sy - tab[O::XI + jj];
+        s_f[slot][q] = sq;  // phi*
+        atomicMax(&s_ref[slot], (unsigned long long)__double_as_longlong(fabs(sq)));
+    }
+    __syncthreads();
+    for (int c = q; inblk && c < 2 * N; c += ND) {
+        double m = 0.0;
+        if (c < N) {
+            for (int j = 0; j < N; ++j) m += s_r[slot][c + N * j];
+            s_mx[slot][c] = m / N;
+        } else {
+            for (int i = 0; i < N; ++i) m += s_x[slot][i + N * (c - N)];
+            s_my[slot][c - N] = m / N;
+        }
+    }
+    __syncthreads();
+    // A0^{-1}[l][c]: interpolation from the shifted nodes xi_k + mx_k back to
+    // node xi_l, prod_{k != c} (xi_l - s_k) / prod_{k != c} (s_c - s_k)
+    if (inblk) {
+        const int l = ii, c = jj;
+        const double xl = tab[O::XI + l];
+        const double sc = tab[O::XI + c] + s_mx[slot][c], tc = tab[O::XI + c] + s_my[slot][c];
+        // The denominators by the product rule (the factor at k = c is
+        // exactly zero; see the 1D remap weights), the numerators with a
+        // select: no branch on k == c, so every read is unconditional.
+        double na = 1.0, nb = 1.0, pa = 1.0, da = 0.0, pb = 1.0, db = 0.0;
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            const double sk = tab[O::XI + k] + s_mx[slot][k];
+            const double tk = tab[O::XI + k] + s_my[slot][k];
+            const double fa = sc - sk, fb = tc - tk;
+            da = fma(da, fa, pa);
+            pa *= fa;
+            db = fma(db, fb, pb);
+            pb *= fb;
+            na *= (k == c) ? 1.0 : xl - sk;
+            nb *= (k == c) ? 1.0 : xl - tk;
+        }
+        s_ai[slot][q] = PP::put(na / da);
+        s_bi[slot][q] = PP::put(nb / db);
+    }
+    __syncthreads();
+
+    // y = M^{-1} f (f in s_f or s_r, node c + N jj):
+    //   stage 1: z[jj][l] = sum_c Ai[l][c] f[jj][c]
+    //   stage 2: y[m][l] = sum_jj Bi[m][jj] z[jj][l]
+    // In FP32 or BF16 the operand is first scaled by 2^-e, e = exponent of a
+    // reference magnitude of it (max |phi*| of the element, then the last
+    // correction), so that it sits near 1 and never in the subnormal range;
+    // M^{-1} is linear, so the result is scaled back exactly.  In BF16 the
+    // operand and the stage-1 result are rounded to BF16 before each product.
+    auto precond = [&](double (*src)[ND], int e2) -> double {
+        const double sc = P32 ? ldexp(1.0, -e2) : 1.0;
+        if (inblk) {
+            AT zz = 0;
+            for (int c = 0; c < N; ++c) {
+                const double v = src[slot][c + N * jj];
+                zz = fma(PP::get(s_ai[slot][ii + N * c]), PP::get(PP::put(P32 ? v * sc : v)), zz);
+            }
+            s_z[slot][q] = PP::put(zz);
+        }
+        __syncthreads();
+        AT acc = 0;
+        if (inblk)
+            for (int j = 0; j < N; ++j) acc = fma(PP::get(s_bi[slot][jj + N * j]), PP::get(s_z[slot][ii + N * j]), acc);
+        return P32 ? ldexp((double)acc, e2) : (double)acc;
+    };
+    // exponent of a reference magnitude, clamped so 2^-e stays finite
+    auto ref_exp = [](double ref) { return ref > 0.0 ? max(ilogb(ref), -1000) : 0; };
+
+    const double ref = __longlong_as_double((long long)s_ref[sl]);  // max |phi*| of the element
+    int e2 = P32 ? ref_exp(ref) : 0;
+    double x = precond(s_f, e2);
+    if (inblk) s_x[slot][q] = x;
+    __syncthreads();
+    bool conv = !live;
+    int sweeps = A.refine;   // sweeps this element needed
+    double lastrel = 0.0;    // its estimated error left, relative to max |phi*|
+    double prev = 0.0;       // max |y| of the previous sweep
+    for (int it = 0; it < A.refine; ++it) {
+        // residual r_p = phi*_p - (V x)_p, (V x)_p = sum_m b_m sum_l a_l x[m][l]
+        double vx = 0.0;
+#pragma unroll
+        for (int m = 0; m < N; ++m) {
+            double inner = 0.0;
+#pragma unroll
+            for (int l = 0; l < N; ++l) inner = fma(a[l], s_x[sl][l + N * m], inner);
+            vx = fma(b[m], inner, vx);
+        }
+        if (inblk) s_r[slot][q] = sq - vx;
+        __syncthreads();  // s_x is no longer read in this sweep
+        // clear the other parity's slot, last read before this sweep's first barrier
+        if (t < E) s_nrm[(it + 1) & 1][t] = 0ull;
+        const double y = precond(s_r, e2);
+        if (inblk) {
+            if (!conv) x += y;
+            s_x[slot][q] = x;
+            atomicMax(&s_nrm[it & 1][slot], (unsigned long long)__double_as_longlong(fabs(y)));
+        }
+        __syncthreads();
+        if (inblk) {
+            const double eny = __longlong_as_double((long long)s_nrm[it & 1][slot]);
+            if (P32 && eny > 0.0) e2 = ref_exp(eny);
+            if (!conv) {
+                // estimated error left: the correction times the observed contraction
+                const double left = (it > 0 && prev > 0.0) ? fmin(eny, eny * eny / prev) : eny;
+                lastrel = ref > 0.0 ? left / ref : 0.0;
+                // Stop when the correction is below 2^-44 of max |phi*|, or
+                // when the observed contraction q = |y_k| / |y_{k-1}| <= 1/2
+                // puts the remaining error (about q |y_k|) below 2^-50 of it.
+                // Both sit above the rounding floor of the residual (about
+                // n^2 eps) and far below the FP64 parity bar.
+                const bool small = eny <= 0x1p-44 * ref;
+                const bool contracted = it > 0 && eny <= 0.5 * prev && eny * eny <= 0x1p-50 * ref * prev;
+                if (small || contracted) {
+                    conv = true;
+                    sweeps = it + 1;
+                }
+            }
+            prev = eny;
+        }
+        if (__syncthreads_and(conv)) break;
+    }
+
+    // edge traces of the remapped polynomial (eq. 2dx/2dy_bnd_interpolate):
+    // t < N left (xi=0, eta_t), < 2N right, < 3N bottom (xi_k, eta=0), top
+    int fl = 0;
+    if (live) {
+        if (out) fl |= FLAG_CONTAIN;
+        if (!conv || !isfinite(x)) fl |= FLAG_SINGULAR;
+        if (q == 0) {
+            atomicAdd(&s_sw_sum, sweeps);
+            atomicMax(&s_sw_max, sweeps);
+            atomicMax(&s_res, (unsigned long long)__double_as_longlong(lastrel));
+        }
+        A.phihat[(size_t)e * ND + q] = x;
+        for (int tt = q; tt < NB; tt += ND) {
+            const int side = tt / N, k = tt % N;
+            const double* lv = tab + ((side & 1) ? O::L1 : O::L0);
+            double tr = 0.0;
+            if (side < 2)
+                for (int c = 0; c < N; ++c) tr = fma(lv[c], s_x[slot][c + N * k], tr);
+            else
+                for (int c = 0; c < N; ++c) tr = fma(lv[c], s_x[slot][k + N * c], tr);
+            A.rec[(size_t)e * A.rstride + tt] = tr;
+        }
+    }
+    if (fl) atomicOr(&s_flag, fl);
+    __syncthreads();
+    if (t == 0) {
+        if (s_flag) A.flag_part[blockIdx.x] |= s_flag;
+        // one block owns each slot row; launches on the stream are ordered
+        double* sp = A.stat_part + (size_t)blockIdx.x * kStatSlots;
+        sp[4] += (double)s_sw_sum;
+        sp[5] = fmax(sp[5], (double)s_sw_max);
+        sp[6] = fmax(sp[6], __longlong_as_double((long long)s_res));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// boundary-constrained least squares (2D)
+// ---------------------------------------------------------------------------
+// persistent blocks: each loads the 4n x 4n table Q into LDS once and loops
+// over chunks of E elements
+constexpr int kConGrid = 2048;
+
+template <int N, bool BT>
+__global__ __launch_bounds__(kBlock2) void k_constrain2d(Step2DArgs A)
+{
+    using O = Off2<N>;
+    constexpr int ND = N * N;
+    constexpr int E = kBlock2 / ND;
+    constexpr int NQ = 16 * N * N;
+    __shared__ double s_q[NQ];
+    // per element: z, d_B - C_B phihat, d_B, phi
+    __shared__ double s_d[E][4 * N], s_rb[E][4 * N], s_fv[E][4 * N], s_y[E][ND];
+    __shared__ int s_flag;
+    __shared__ unsigned long long s_stat;
+
+    const int t = threadIdx.x;
+    const int slot = t / ND, p = t - slot * ND;
+    const bool inblk = slot < E;
+    const double* __restrict__ tab = A.tab;
+    const int kx = A.kx, ky = A.ky, K = A.K;
+    const bool bnd = (A.cmask & SL_C_BOUNDARY) != 0;
+    const double* Qg = tab + (A.mode == SL_MODE_HARD ? O::QH : O::QS);
+    for (int k = t; k < NQ; k += kBlock2) s_q[k] = Qg[k];
+    if (t == 0) {
+        s_flag = 0;
+        s_stat = 0ull;
+    }
+    const int i = p % N, j = p / N;
+    const double l0i = tab[O::L0 + i], l1i = tab[O::L1 + i], l0j = tab[O::L0 + j], l1j = tab[O::L1 + j];
+    const int nchunk = (K + E - 1) / E;
+
+    for (int chunk = blockIdx.x; chunk < nchunk; chunk += gridDim.x) {
+        const int e = chunk * E + slot;
+        const bool live = inblk && e < K;
+        const int ee = live ? e : 0;
+        const size_t g = (size_t)ee * ND + p;
+        const double ph = live ? A.phihat[g] : 0.0;
+
+        // face value at the element's edge point tt: upwind of its own trace
+        // and the neighbour's matching trace (eq. 4.12a); ghost values at the
+        // domain boundary
+        for (int tt = p; inblk && tt < 4 * N; tt += ND) {
+            int nbe, nbt, gidx;
+            bool high;
+            face_partner2<N>(ee, tt, kx, ky, A.periodic, nbe, nbt, gidx, high);
+            // offered face values: the traces, or with backtracking (BT) the
+            // record's last 4n slots; the residual takes the own trace
+            const int fo = BT ? A.rstride - 4 * N : 0;
+            const double trace = A.rec[(size_t)ee * A.rstride + tt];
+            const double mine = BT ? A.rec[(size_t)ee * A.rstride + fo + tt] : trace;
+            const double other = nbe >= 0 ? A.rec[(size_t)nbe * A.rstride + fo + nbt] : A.gnext[gidx];
+            const double vn = A.vface[(size_t)ee * 4 * N + tt];
+            const double lo = high ? other : mine, hi = high ? mine : other;
+            const double dv = upwind2(vn, lo, hi);
+            s_fv[slot][tt] = dv;
+            s_rb[slot][tt] = dv - trace;
+        }
+        __syncthreads();
+
+        // phi = phihat + C_B^T z, z = Q (d_B - C_B phihat), Q = (C_B C_B^T)^+
+        // (HARD) or (I + C_B C_B^T)^{-1} (SOFT); lanes t < 4n form z, then
+        // every node applies C_B^T (four products)
+        double phi = ph;
+        if (bnd) {
+            for (int tt = p; inblk && tt < 4 * N; tt += ND) {
+                double z = 0.0;
+                for (int q = 0; q < 4 * N; ++q) z = fma(s_q[tt * 4 * N + q], s_rb[slot][q], z);
+                s_d[slot][tt] = z;
+            }
+            __syncthreads();
+            if (inblk)
+                phi = ph + l0i * s_d[slot][j] + l1i * s_d[slot][N + j] + l0j * s_d[slot][2 * N + i] +
+                      l1j * s_d[slot][3 * N + i];
+        }
+        if (inblk) s_y[slot][p] = phi;
+        __syncthreads();
+        int fl = 0;
+        if (live) {
+            if (!isfinite(phi)) fl |= FLAG_NONFINITE;
+            A.phi_out[g] = phi;
+            for (int tt = p; bnd && tt < 4 * N; tt += ND) {
+                const int side = tt / N, k = tt % N;
+                const double* lv = tab + ((side & 1) ? O::L1 : O::L0);
+                double tr = 0.0;
+                if (side < 2)
+                    for (int c = 0; c < N; ++c) tr = fma(lv[c], s_y[slot][c + N * k], tr);
+                else
+                    for (int c = 0; c < N; ++c) tr = fma(lv[c], s_y[slot][k + N * c], tr);
+                atomicMax(&s_stat, (unsigned long long)__double_as_longlong(fabs(tr - s_fv[slot][tt])));
+            }
+        }
+        if (fl) atomicOr(&s_flag, fl);
+        __syncthreads();  // s_fv, s_rb, s_d, s_y are rewritten by the next chunk
+    }
+    if (t == 0) {
+        if (s_flag) A.flag_part[A.nblk + blockIdx.x] |= s_flag;
+        double* sp = A.stat_part + (size_t)blockIdx.x * kStatSlots;
+        sp[0] = fmax(sp[0], __longlong_as_double((long long)s_stat));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// boundary-constrained least squares with mass and energy rows (2D)
+//
+// With the boundary rows' solution `base` (as in k_constrain2d) and the
+// extra rows G (mass W, energy W o phi linearised at the previous Picard
+// iterate), both modes take the form
+//   phi = base + Z S^{-1} (d_G - G base),  Z = P G^T,  S = G Z (+ I in SOFT),
+// with P = I - C_B^T Q C_B: the projector onto null(C_B) for HARD (Q =
+// (C_B C_B^T)^+, the prioritised reading), and (I + C_B^T C_B)^{-1} by
+// Woodbury for SOFT (Q = (I + C_B C_B^T)^{-1}), i.e. the paper's stacked
+// least squares.  Without boundary rows P = I and base = phi-hat.  HARD with
+// a mass row replaces the energy row by its part orthogonal to the mass row
+// (the same constraint set, better conditioned).  P W is a per-mesh table.
+// One block handles floor(256/n^2) elements, one lane per node.
+// ---------------------------------------------------------------------------
+template <int N>
+__global__ __launch_bounds__(kBlock2) void k_constrain2d_me(Step2DArgs A)
+{
+    using O = Off2<N>;
+    constexpr int ND = N * N, E = kBlock2 / ND, NB = 4 * N, NQ = 16 * ND, NDOT = 5;
+    __shared__ double s_q[NQ];
+    __shared__ double s_fv[E][NB], s_tr[E][NB], s_w[E][NB];
+    __shared__ double s_v[E][ND];
+    __shared__ double s_red[E][NDOT][ND];
+    __shared__ double s_dot[E][NDOT];
+    __shared__ double s_tgt[E][2];
+    __shared__ unsigned long long s_mx[E][2];
+    __shared__ int s_flag, s_pic;
+    __shared__ unsigned long long s_stat[3];
+
+    const int t = threadIdx.x;
+    const int slot = t / ND, p = t - slot * ND;
+    const bool inblk = slot < E;
+    const int sl = inblk ? slot : 0;
+    const int e = blockIdx.x * E + slot;
+    const bool live = inblk && e < A.K;
+    const int ee = live ? e : 0;
+    const double* __restrict__ tab = A.tab;
+    const bool bnd = (A.cmask & SL_C_BOUNDARY) != 0;
+    const bool mass = (A.cmask & SL_C_MASS) != 0;
+    const bool energy = (A.cmask & SL_C_ENERGY) != 0;
+    const bool soft = A.mode == SL_MODE_SOFT;
+    const double* Qg = tab + (soft ? O::QS : O::QH);
+    for (int k = t; k < NQ; k += kBlock2) s_q[k] = Qg[k];
+    if (t == 0) {
+        s_flag = 0;
+        s_pic = 0;
+        s_stat[0] = s_stat[1] = s_stat[2] = 0ull;
+    }
+    if (t < 2 * E) s_mx[t / 2][t % 2] = 0ull;
+    const int i = p % N, j = p / N;
+    const double l0i = tab[O::L0 + i], l1i = tab[O::L1 + i], l0j = tab[O::L0 + j], l1j = tab[O::L1 + j];
+    const double Wp = A.dx * A.dy * tab[O::W + i] * tab[O::W + j];
+    const double* rec = A.rec + (size_t)ee * A.rstride;
+    const double ph = live ? A.phihat[(size_t)ee * ND + p] : 0.0;
+
+    // face values (eq. 4.12a) and the face terms of the targets: inflow
+    // positive, the upwind side's stage sums (own, neighbour's or ghost)
+    const RKTab& T = A.rk;
+    for (int tt = p; inblk && tt < NB; tt += ND) {
+        int nbe, nbt, gidx;
+        bool high;
+        face_partner2<N>(ee, tt, A.kx, A.ky, A.periodic, nbe, nbt, gidx, high);
+        const double vn = A.vface[(size_t)ee * NB + tt];
+        // offered face values: the traces, or with backtracking the record's
+        // last NB slots
+        const int fo = A.iface == SL_IFACE_BACKTRACK ? A.rstride - NB : 0;
+        const double mine = rec[fo + tt];
+        const double other = nbe >= 0 ? A.rec[(size_t)nbe * A.rstride + fo + nbt] : A.gnext[gidx];
+        s_fv[slot][tt] = upwind2(vn, high ? other : mine, high ? mine : other);
+        double fm = 0.0, fe = 0.0;
+        if (vn != 0.0) {
+            const bool up = high ? vn < 0.0 : vn > 0.0;
+            double sm, se;
+            if (up) {
+                sm = rec[NB + tt];
+                se = rec[2 * NB + tt];
+            } else if (nbe >= 0) {
+                sm = A.rec[(size_t)nbe * A.rstride + NB + nbt];
+                se = A.rec[(size_t)nbe * A.rstride + 2 * NB + nbt];
+            } else {
+                // inflow from outside: ghost values, linear in time
+                sm = se = 0.0;
+                for (int c = 0; c < T.nq; ++c) {
+                    const double g = (1.0 - T.cu[c]) * A.gnow[gidx] + T.cu[c] * A.gnext[gidx];
+                    sm = fma(T.bu[c], g, sm);
+                    se = fma(T.bu[c], g * g, se);
+                }
+            }
+            const int side = tt / N, k = tt % N;
+            const double fw = (side < 2 ? A.dy : A.dx) * tab[O::W + k];
+            const double sg = high ? vn : -vn;
+            fm = sg * fw * sm;
+            fe = sg * fw * se;
+        }
+        s_tr[slot][tt] = fm;
+        s_w[slot][tt] = fe;
+    }
+    __syncthreads();
+    if (live && p == 0) {
+        double fm = 0.0, fe = 0.0;
+        for (int tt = 0; tt < NB; ++tt) {
+            fm += s_tr[slot][tt];
+            fe += s_w[slot][tt];
+        }
+        s_tgt[slot][0] = rec[3 * NB] + A.dt * fm;
+        s_tgt[slot][1] = rec[3 * NB + 1] + A.dt * fe;
+    }
+    __syncthreads();
+    const double Mt = s_tgt[sl][0], Et = s_tgt[sl][1];
+
+    // element-wise sums of up to NDOT per-node values, in a fixed order
+    auto dots = [&](int k, const double* vals) {
+        if (inblk)
+            for (int c = 0; c < k; ++c) s_red[slot][c][p] = vals[c];
+        __syncthreads();
+        for (int c = p; inblk && c < k; c += ND) {
+            double s = 0.0;
+            for (int r = 0; r < ND; ++r) s += s_red[slot][c][r];
+            s_dot[slot][c] = s;
+        }
+        __syncthreads();
+    };
+    // C_B^T Q (h - C_B v) at this node, v in s_v; h = d_B (face values) or 0
+    auto cbt_q = [&](bool with_data) -> double {
+        for (int tt = p; inblk && tt < NB; tt += ND) {
+            const int side = tt / N, k = tt % N;
+            const double* lv = tab + ((side & 1) ? O::L1 : O::L0);
+            double tr = 0.0;
+            if (side < 2)
+                for (int c = 0; c < N; ++c) tr = fma(lv[c], s_v[slot][c + N * k], tr);
+            else
+                for (int c = 0; c < N; ++c) tr = fma(lv[c], s_v[slot][k + N * c], tr);
+            s_tr[slot][tt] = (with_data ? s_fv[slot][tt] : 0.0) - tr;
+        }
+        __syncthreads();
+        for (int tt = p; inblk && tt < NB; tt += ND) {
+            double z = 0.0;
+            for (int c = 0; c < NB; ++c) z = fma(s_q[tt * NB + c], s_tr[slot][c], z);
+            s_w[slot][tt] = z;
+        }
+        __syncthreads();
+        const double r = l0i * s_w[sl][j] + l1i * s_w[sl][N + j] + l0j * s_w[sl][2 * N + i] +
+                         l1j * s_w[sl][3 * N + i];
+        __syncthreads();  // s_v, s_tr, s_w are rewritten by the next call
+        return r;
+    };
+
+    // boundary rows: base = phihat + C_B^T Q (d_B - C_B phihat)
+    double base = ph;
+    if (bnd) {
+        if (inblk) s_v[slot][p] = ph;
+        __syncthreads();
+        base = ph + cbt_q(true);
+    }
+    // mass row: Z_M = P W from the table (P W is W without boundary rows)
+    const double zm = bnd ? A.dx * A.dy * tab[(soft ? O::ZMS : O::ZMH) + p] : Wp;
+    const double shift = soft ? 1.0 : 0.0;
+    int fl = 0;
+    double gb = 0.0, gz = 0.0;
+    double cur = base;
+    if (mass) {
+        const double v[2] = {Wp * base, Wp * zm};
+        dots(2, v);
+        gb = s_dot[sl][0];
+        gz = s_dot[sl][1];
+        const double S = gz + shift;
+        if (!(S != 0.0) || !isfinite(S)) fl |= FLAG_SINGULAR;
+        cur = base + zm * ((Mt - gb) / S);
+    }
+    double prev = cur;
+    int picard = 0;
+    if (energy) {
+        // Picard on the energy row linearised at the previous iterate; stop
+        // when the change is below tol (strict), or, unconverged, when the
+        // iterate returns to within tol of the one two sweeps earlier
+        double older = prev;
+        bool done = !live, conv = false;
+        for (int k = 1; k <= A.emaxit; ++k) {
+            double gE = Wp * prev;
+            if (inblk) s_v[slot][p] = gE;
+            __syncthreads();
+            double zE = bnd ? gE + cbt_q(false) : gE;
+            double dE = Et;
+            if (!soft && mass) {
+                const double v[2] = {gE * Wp, Wp * Wp};
+                dots(2, v);
+                const double mu = s_dot[sl][0] / s_dot[sl][1];
+                gE -= mu * Wp;
+                zE -= mu * zm;
+                dE -= mu * Mt;
+            }
+            double sig_m = 0.0, sig_e = 0.0;
+            bool bad = false;
+            if (mass) {
+                const double v[4] = {Wp * zE, gE * zm, gE * zE, gE * base};
+                dots(4, v);
+                const double a11 = gz + shift, a12 = s_dot[sl][0], a21 = s_dot[sl][1], a22 = s_dot[sl][2] + shift;
+                const double r1 = Mt - gb, r2 = dE - s_dot[sl][3];
+                const double det = a11 * a22 - a12 * a21;
+                bad = !(det != 0.0) || !isfinite(det);
+                sig_m = (r1 * a22 - a12 * r2) / det;
+                sig_e = (a11 * r2 - a21 * r1) / det;
+            } else {
+                const double v[2] = {gE * zE, gE * base};
+                dots(2, v);
+                const double S = s_dot[sl][0] + shift;
+                bad = !(S != 0.0) || !isfinite(S);
+                sig_e = (dE - s_dot[sl][1]) / S;
+            }
+            const double nxt = base + zm * sig_m + zE * sig_e;
+            if (inblk && !done) {
+                if (bad) fl |= FLAG_SINGULAR;
+                atomicMax(&s_mx[slot][0], (unsigned long long)__double_as_longlong(fabs(nxt - prev)));
+                atomicMax(&s_mx[slot][1], (unsigned long long)__double_as_longlong(fabs(nxt - older)));
+            }
+            __syncthreads();
+            if (inblk && !done) {
+                const double diff = __longlong_as_double((long long)s_mx[slot][0]);
+                const double back = __longlong_as_double((long long)s_mx[slot][1]);
+                older = prev;
+                prev = nxt;
+                picard = k;
+                if (diff < A.etol) {
+                    conv = true;
+                    done = true;
+                } else if (k >= 2 && back < A.etol) {
+                    done = true;
+                }
+            }
+            const bool all = __syncthreads_and(done);
+            if (t < 2 * E) s_mx[t / 2][t % 2] = 0ull;
+            __syncthreads();
+            if (all) break;
+        }
+        if (live && !conv && A.etol > 0.0) fl |= FLAG_NOCONV;
+    }
+
+    // store, residuals: boundary (traces of phi vs the face values), mass,
+    // energy
+    const double phi = prev;
+    if (live) {
+        if (!isfinite(phi)) fl |= FLAG_NONFINITE;
+        A.phi_out[(size_t)e * ND + p] = phi;
+    }
+    if (inblk) s_v[slot][p] = phi;
+    {
+        const double v[2] = {Wp * phi, Wp * phi * phi};
+        dots(2, v);  // its first barrier also publishes s_v
+    }
+    if (live) {
+        for (int tt = p; bnd && tt < NB; tt += ND) {
+            const int side = tt / N, k = tt % N;
+            const double* lv = tab + ((side & 1) ? O::L1 : O::L0);
+            double tr = 0.0;
+            if (side < 2)
+                for (int c = 0; c < N; ++c) tr = fma(lv[c], s_v[slot][c + N * k], tr);
+            else
+                for (int c = 0; c < N; ++c) tr = fma(lv[c], s_v[slot][k + N * c], tr);
+            atomicMax(&s_stat[0], (unsigned long long)__double_as_longlong(fabs(tr - s_fv[slot][tt])));
+        }
+        if (p == 0) {
+            if (mass) atomicMax(&s_stat[1], (unsigned long long)__double_as_longlong(fabs(s_dot[slot][0] - Mt)));
+            if (energy) atomicMax(&s_stat[2], (unsigned long long)__double_as_longlong(fabs(s_dot[slot][1] - Et)));
+            atomicMax(&s_pic, picard);
+        }
+    }
+    if (fl) atomicOr(&s_flag, fl);
+    __syncthreads();
+    if (t == 0) {
+        if (s_flag) A.flag_part[A.nblk + blockIdx.x] |= s_flag;
+        double* sp = A.stat_part + (size_t)blockIdx.x * kStatSlots;
+        sp[0] = fmax(sp[0], __longlong_as_double((long long)s_stat[0]));
+        sp[1] = fmax(sp[1], __longlong_as_double((long long)s_stat[1]));
+        sp[2] = fmax(sp[2], __longlong_as_double((long long)s_stat[2]));
+        sp[3] = fmax(sp[3], (double)s_pic);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// mixed-order meshes (periodic, boundary rows): elements are grouped in
+// buckets of one order; each launch covers one bucket.  The face value at an
+// element's own edge point comes from the upwind side; when the neighbour
+// has another order its edge polynomial (its n' traces along the shared
+// edge) is interpolated to this element's edge nodes by a precomputed
+// n x n' Lagrange matrix, which is exact for that polynomial.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void periodic_partner(int e, int side, int kx, int ky, int& nbe, bool& high)
+{
+    const int ex = e % kx, ey = e / kx;
+    switch (side) {
+    case 0: nbe = ey * kx + (ex + kx - 1) % kx; high = true; break;
+    case 1: nbe = ey * kx + (ex + 1) % kx; high = false; break;
+    case 2: nbe = ((ey + ky - 1) % ky) * kx + ex; high = true; break;
+    default: nbe = ((ey + 1) % ky) * kx + ex; high = false; break;
+    }
+}
+
+// normal velocity of element j of bucket b (order n) at its own edge point
+// q of side sd: the u (x-faces) or v (y-faces) interpolant on that edge
+__device__ double edge_speed_mixed(const int* meta, const double* __restrict__ aN_all,
+                                   const double* __restrict__ tab_all, int b, int j, int sd, int q)
+{
+    const int n = meta[MixMeta::kN + b], nd = n * n;
+    const double* lv = tab_all + meta[MixMeta::kTab + b] + ((sd & 1) ? 3 * n : 2 * n);  // l(1) or l(0)
+    const double* base = aN_all + meta[MixMeta::kVel + b];
+    double s = 0.0;
+    if (sd < 2) {
+        const double* U = base + (size_t)j * nd;
+        for (int c = 0; c < n; ++c) s = fma(lv[c], U[c + n * q], s);
+    } else {
+        const double* V = base + ((size_t)meta[MixMeta::kK + b] + j) * nd;
+        for (int c = 0; c < n; ++c) s = fma(lv[c], V[q + n * c], s);
+    }
+    return s;
+}
+
+// face normal velocity at the own edge points of one bucket's elements: the
+// mean of this element's normal velocity interpolant and the neighbour's,
+// both at this element's edge node (the neighbour's edge values
+// interpolated when its order differs); at or below vzero it is zero
+template <int N>
+__global__ void k_facevel2d_mixed(int K_b, int bucket, int kx, int ky, const int32_t* __restrict__ elems,
+                                  const int32_t* __restrict__ mix, const double* __restrict__ aN_all,
+                                  const double* __restrict__ tab_all, const double* __restrict__ interp,
+                                  double vzero, double* __restrict__ vface)
+{
+    constexpr int NB = 4 * N;
+    const int K = kx * ky;
+    const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= (long)K_b * NB) return;
+    const int i = (int)(gid / NB), tt = (int)(gid % NB);
+    const int side = tt / N, k = tt % N;
+    const int e = elems[i];
+    const int* meta = mix + 2 * K;
+    double vn = edge_speed_mixed(meta, aN_all, tab_all, bucket, i, side, k);
+    int nbe;
+    bool high;
+    periodic_partner(e, side, kx, ky, nbe, high);
+    const int b2 = mix[nbe], j2 = mix[K + nbe];
+    const int n2 = meta[MixMeta::kN + b2];
+    const int s2 = side ^ 1;  // the neighbour's side on the shared face
+    double other = 0.0;
+    if (n2 == N) {
+        other = edge_speed_mixed(meta, aN_all, tab_all, b2, j2, s2, k);
+    } else {
+        const double* M = interp + meta[MixMeta::kInterp + kMaxBuckets * bucket + b2];
+        for (int q = 0; q < n2; ++q) other = fma(M[k * n2 + q], edge_speed_mixed(meta, aN_all, tab_all, b2, j2, s2, q), other);
+    }
+    vn = 0.5 * (vn + other);
+    if (fabs(vn) <= vzero) vn = 0.0;
+    vface[(size_t)i * NB + tt] = vn;
+}
+
+// boundary least squares of one bucket's elements (as k_constrain2d), with
+// the neighbour's trace taken from its bucket and interpolated to this
+// element's edge nodes when the orders differ
+template <int N>
+__global__ __launch_bounds__(kBlock2) void k_constrain2d_mixed(Step2DArgs A)
+{
+    using O = Off2<N>;
+    constexpr int ND = N * N, E = kBlock2 / ND, NB = 4 * N, NQ = 16 * ND;
+    __shared__ double s_q[NQ];
+    __shared__ double s_d[E][NB], s_rb[E][NB], s_fv[E][NB], s_y[E][ND];
+    __shared__ int s_flag;
+    __shared__ unsigned long long s_stat;
+
+    const int t = threadIdx.x;
+    const int slot = t / ND, p = t - slot * ND;
+    const bool inblk = slot < E;
+    const double* __restrict__ tab = A.tab;
+    const int K_b = A.K, Kall = A.kx * A.ky;
+    const int* meta = A.mix + 2 * Kall;
+    const double* Qg = tab + (A.mode == SL_MODE_HARD ? O::QH : O::QS);
+    for (int k = t; k < NQ; k += kBlock2) s_q[k] = Qg[k];
+    if (t == 0) {
+        s_flag = 0;
+        s_stat = 0ull;
+    }
+    const int i = p % N, j = p / N;
+    const double l0i = tab[O::L0 + i], l1i = tab[O::L1 + i], l0j = tab[O::L0 + j], l1j = tab[O::L1 + j];
+    const int nchunk = (K_b + E - 1) / E;
+
+    for (int chunk = blockIdx.x; chunk < nchunk; chunk += gridDim.x) {
+        const int li = chunk * E + slot;  // index within the bucket
+        const bool live = inblk && li < K_b;
+        const int ll = live ? li : 0;
+        const size_t g = (size_t)ll * ND + p;
+        const double ph = live ? A.phihat[g] : 0.0;
+        const double* myrec = A.rec + (size_t)ll * NB;
+
+        for (int tt = p; inblk && tt < NB; tt += ND) {
+            const int side = tt / N, k = tt % N;
+            int nbe;
+            bool high;
+            periodic_partner(A.elems[ll], side, A.kx, A.ky, nbe, high);
+            const int b2 = A.mix[nbe], j2 = A.mix[Kall + nbe];
+            const int n2 = meta[MixMeta::kN + b2];
+            const double* tr2 = A.rec_all + meta[MixMeta::kRec + b2] + (size_t)j2 * 4 * n2 + (side ^ 1) * n2;
+            double other = 0.0;
+            if (n2 == N) {
+                other = tr2[k];
+            } else {
+                const double* M = A.interp + meta[MixMeta::kInterp + kMaxBuckets * A.bucket + b2];
+                for (int q = 0; q < n2; ++q) other = fma(M[k * n2 + q], tr2[q], other);
+            }
+            const double mine = myrec[tt];
+            const double vn = A.vface[(size_t)ll * NB + tt];
+            const double dv = upwind2(vn, high ? other : mine, high ? mine : other);
+            s_fv[slot][tt] = dv;
+            s_rb[slot][tt] = dv - mine;
+        }
+        __syncthreads();
+
+        double phi = ph;
+        for (int tt = p; inblk && tt < NB; tt += ND) {
+            double z = 0.0;
+            for (int q = 0; q < NB; ++q) z = fma(s_q[tt * NB + q], s_rb[slot][q], z);
+            s_d[slot][tt] = z;
+        }
+        __syncthreads();
+        if (inblk)
+            phi = ph + l0i * s_d[slot][j] + l1i * s_d[slot][N + j] + l0j * s_d[slot][2 * N + i] +
+                  l1j * s_d[slot][3 * N + i];
+        if (inblk) s_y[slot][p] = phi;
+        __syncthreads();
+        int fl = 0;
+        if (live) {
+            if (!isfinite(phi)) fl |= FLAG_NONFINITE;
+            A.phi_out[g] = phi;
+            for (int tt = p; tt < NB; tt += ND) {
+                const int side = tt / N, k = tt % N;
+                const double* lv = tab + ((side & 1) ? O::L1 : O::L0);
+                double tr = 0.0;
+                if (side < 2)
+                    for (int c = 0; c < N; ++c) tr = fma(lv[c], s_y[slot][c + N * k], tr);
+                else
+                    for (int c = 0; c < N; ++c) tr = fma(lv[c], s_y[slot][k + N * c], tr);
+                atomicMax(&s_stat, (unsigned long long)__double_as_longlong(fabs(tr - s_fv[slot][tt])));
+            }
+        }
+        if (fl) atomicOr(&s_flag, fl);
+        __syncthreads();  // s_fv, s_rb, s_d, s_y are rewritten by the next chunk
+    }
+    if (t == 0) {
+        if (s_flag) A.flag_part[A.nblk + blockIdx.x] |= s_flag;
+        double* sp = A.stat_part + (size_t)blockIdx.x * kStatSlots;
+        sp[0] = fmax(sp[0], __longlong_as_double((long long)s_stat));
+    }
+}
+
+template <int N>
+int prep_n(int K, int has_div, int cons, const double* aN, double* aM, double* divN, double* divM,
+           const double* tab, double dx, double dy, double vscale, int* vdeg, hipStream_t s)
+{
+    const int bs = 64;
+    hipLaunchKernelGGL(k_prep2d<N>, dim3((K + bs - 1) / bs), dim3(bs), 0, s, K, has_div, cons, aN, aM, divN, divM,
+                       tab, 1.0 / dx, 1.0 / dy, vscale, vdeg);
+    return hipGetLastError() == hipSuccess ? 0 : 1;
+}
+
+template <int N>
+int facevel_n(int kx, int ky, int periodic, const double* aN, const double* tab, double vzero, double* vface,
+              hipStream_t s)
+{
+    const int bs = 256;
+    const long tot = (long)kx * ky * 4 * N;
+    hipLaunchKernelGGL(k_facevel2d<N>, dim3((unsigned)((tot + bs - 1) / bs)), dim3(bs), 0, s, kx, ky, periodic, aN,
+                       tab, vzero, vface);
+    return hipGetLastError() == hipSuccess ? 0 : 1;
+}
+
+template <int N, int PR>
+void adv_launch(const Step2DArgs& A, dim3 grid, hipStream_t s)
+{
+    if (A.targets) hipLaunchKernelGGL((k_advect2d<N, PR, true>), grid, dim3(kBlock2), 0, s, A);
+    else hipLaunchKernelGGL((k_advect2d<N, PR, false>), grid, dim3(kBlock2), 0, s, A);
+}
+
+template <int N, int BSEL>
+void adv_shape(const Step2DArgs& A, hipStream_t s)
+{
+    using S = Shape2<N, BSEL>;
+    hipLaunchKernelGGL((k_advect2d<N, 0, false, BSEL>), dim3((A.K + S::E - 1) / S::E), dim3(S::BS), 0, s, A);
+}
+
+template <int N>
+int adv_n(const Step2DArgs& A, hipStream_t s)
+{
+    // the alternative block shapes exist for the FP64 boundary-rows kernel
+    if (A.bs != 0 && A.precision == SL_PREC_FP64 && !A.targets) {
+        if (A.bs == 1) adv_shape<N, 1>(A, s);
+        else adv_shape<N, 2>(A, s);
+        return hipGetLastError() == hipSuccess ? 0 : 1;
+    }
+    constexpr int E = kBlock2 / (N * N);
+    const dim3 grid((A.K + E - 1) / E);
+    if (A.precision == SL_PREC_FP32_REFINED) adv_launch<N, 1>(A, grid, s);
+    else if (A.precision == SL_PREC_BF16_REFINED) adv_launch<N, 2>(A, grid, s);
+    else adv_launch<N, 0>(A, grid, s);
+    return hipGetLastError() == hipSuccess ? 0 : 1;
+}
+
+template <int N>
+int con_n(const Step2DArgs& A, hipStream_t s)
+{
+    constexpr int E = kBlock2 / (N * N);
+    const int nchunk = (A.K + E - 1) / E;
+    const dim3 grid(nchunk < kConGrid ? nchunk : kConGrid);
+    if (A.cmask & (SL_C_MASS | SL_C_ENERGY))
+        hipLaunchKernelGGL(k_constrain2d_me<N>, dim3(nchunk), dim3(kBlock2), 0, s, A);
+    else if (A.iface == SL_IFACE_BACKTRACK)
+        hipLaunchKernelGGL((k_constrain2d<N, true>), grid, dim3(kBlock2), 0, s, A);
+    else
+        hipLaunchKernelGGL((k_constrain2d<N, false>), grid, dim3(kBlock2), 0, s, A);
+    return hipGetLastError() == hipSuccess ? 0 : 1;
+}
+
+// backtracking interface values (eq. 4.11), a launch of their own before
+// the advect kernel: one lane per edge point (4n per element, floor(256/4n)
+// elements per block).  phi^n and the velocity (and divergence) series of
+// each element are staged in LDS; a lane whose point lies on a face where
+// the flow leaves the element (or the face speed vanishes) traces the
+// characteristic back over dt and stores phi^n at the foot, times the
+// source factor in the conservative form, in the record's last 4n slots.
+// The other points store zero: the upwind rule never selects them.
+template <int N>
+__global__ __launch_bounds__(kBlock2) void k_backtrace2d(Step2DArgs A)
+{
+    using O = Off2<N>;
+    constexpr int ND = N * N, NB = 4 * N, EB = kBlock2 / NB;
+    __shared__ double s_f[EB][ND], s_cu[EB][ND], s_cv[EB][ND], s_cd[EB][ND];
+    __shared__ int s_flag;
+    const int t = threadIdx.x;
+    const int e0 = blockIdx.x * EB;
+    if (t == 0) s_flag = 0;
+    const size_t KND = (size_t)A.K * ND;
+    for (int k = t; k < EB * ND; k += kBlock2) {
+        const int le = k / ND, q = k - le * ND, e = e0 + le;
+        const bool live = e < A.K;
+        const size_t g = (size_t)(live ? e : 0) * ND + q;
+        const int ii = q % N, jj = q / N;
+        const bool used = live && ii <= A.vdeg && jj <= A.vdeg;
+        s_f[le][q] = live ? A.phi[g] : 0.0;
+        s_cu[le][q] = used ? A.aM[g] : 0.0;
+        s_cv[le][q] = used ? A.aM[KND + g] : 0.0;
+        s_cd[le][q] = (used && A.cons) ? A.divM[g] : 0.0;
+    }
+    __syncthreads();
+    const int le = t / NB, tt = t - le * NB, e = e0 + le;
+    bool out = false;
+    if (le < EB && e < A.K) {
+        const int side = tt / N, k = tt % N;
+        const double vn = A.vface[(size_t)e * NB + tt];
+        const bool up = (side == 0 || side == 2) ? vn <= 0.0 : vn >= 0.0;
+        double v = 0.0;
+        if (up) {
+            const double s = side == 0 ? 0.0 : side == 1 ? 1.0 : A.tab[O::XI + k];
+            const double r = side == 2 ? 0.0 : side == 3 ? 1.0 : A.tab[O::XI + k];
+            v = backtrace2<N>(A, s_cu[le], s_cv[le], s_cd[le], s_f[le], A.dt, s, r, out);
+        }
+        A.rec[(size_t)e * A.rstride + (A.rstride - NB) + tt] = v;
+    }
+    if (out) atomicOr(&s_flag, FLAG_CONTAIN);
+    __syncthreads();
+    // the advect kernel's flag slots; several blocks may share one
+    if (t == 0 && s_flag) atomicOr(&A.flag_part[blockIdx.x % A.nblk], s_flag);
+}
+
+template <int N>
+int bt_n(const Step2DArgs& A, hipStream_t s)
+{
+    constexpr int EB = kBlock2 / (4 * N);
+    hipLaunchKernelGGL(k_backtrace2d<N>, dim3((A.K + EB - 1) / EB), dim3(kBlock2), 0, s, A);
+    return hipGetLastError() == hipSuccess ? 0 : 1;
+}
+
+template <int N>
+int facevel_mixed_n(int K_b, int bucket, int kx, int ky, const int32_t* elems, const int32_t* mix,
+                    const double* aN_all, const double* tab_all, const double* interp, double vzero, double* vface,
+                    hipStream_t s)
+{
+    const int bs = 256;
+    const long tot = (long)K_b * 4 * N;
+    hipLaunchKernelGGL(k_facevel2d_mixed<N>, dim3((unsigned)((tot + bs - 1) / bs)), dim3(bs), 0, s, K_b, bucket, kx, ky,
+                       elems, mix, aN_all, tab_all, interp, vzero, vface);
+    return hipGetLastError() == hipSuccess ? 0 : 1;
+}
+
+template <int N>
+int con_mixed_n(const Step2DArgs& A, hipStream_t s)
+{
+    constexpr int E = kBlock2 / (N * N);
+    const int nchunk = (A.K + E - 1) / E;
+    hipLaunchKernelGGL(k_constrain2d_mixed<N>, dim3(nchunk < kConGrid ? nchunk : kConGrid), dim3(kBlock2), 0, s, A);
+    return hipGetLastError() == hipSuccess ? 0 : 1;
+}
+
+}  // namespace
+}  // namespace sl
+
+// the per-order launch table of one order N (defined in one sl2d_p*.hip)
+#define SL2D_DEFINE_OPS(N)                                                                                  \
+    namespace sl {                                                                                          \
+    const Ops2D* ops2d_##N()                                                                                \
+    {                                                                                                       \
+        static const Ops2D t = {prep_n<N>, facevel_n<N>, facevel_mixed_n<N>, con_mixed_n<N>,                \
+                                adv_n<N>,  con_n<N>,     bt_n<N>};                                          \
+        return &t;                                                                                          \
+    }                                                                                                       \
+    }
