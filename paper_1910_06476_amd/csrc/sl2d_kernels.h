@@ -554,16 +554,30 @@ __global__ __launch_bounds__((Shape2<N, BSEL>::BS)) void k_advect2d(Step2DArgs A
                         vv = vel(lv, x, y);
                         if (A.cons) dd = vel(ld, x, y);
                     } else if (A.cons) {
-                        const double* C3[3] = {s_cu[sl], s_cv[sl], s_cd[sl]};
                         double o[3];
-                        cheb2_eval<N, 3>(C3, x, y, d, o);
+                        if constexpr (Shape2<N, BSEL>::E == 1) {
+                            // one element per block: its coefficients have a block-uniform
+                            // address and are read through the scalar cache, not LDS
+                            const double* gu = A.aM + (size_t)blockIdx.x * ND;
+                            const double* C3[3] = {gu, gu + (size_t)K * ND, A.divM + (size_t)blockIdx.x * ND};
+                            cheb2_eval<N, 3>(C3, x, y, d, o);
+                        } else {
+                            const double* C3[3] = {s_cu[sl], s_cv[sl], s_cd[sl]};
+                            cheb2_eval<N, 3>(C3, x, y, d, o);
+                        }
                         uu = o[0];
                         vv = o[1];
                         dd = o[2];
                     } else {
-                        const double* C2[2] = {s_cu[sl], s_cv[sl]};
                         double o[2];
-                        cheb2_eval<N, 2>(C2, x, y, d, o);
+                        if constexpr (Shape2<N, BSEL>::E == 1) {
+                            const double* gu = A.aM + (size_t)blockIdx.x * ND;
+                            const double* C2[2] = {gu, gu + (size_t)K * ND};
+                            cheb2_eval<N, 2>(C2, x, y, d, o);
+                        } else {
+                            const double* C2[2] = {s_cu[sl], s_cv[sl]};
+                            cheb2_eval<N, 2>(C2, x, y, d, o);
+                        }
                         uu = o[0];
                         vv = o[1];
                     }
