@@ -777,6 +777,24 @@ __global__ __launch_bounds__((Shape2<N, BSEL>::BS)) void k_advect2d(Step2DArgs A
 // over chunks of E elements
 constexpr int kConGrid = 2048;
 
+// Blocks of a persistent launch: no more than are resident at once (the
+// 4n x 4n table limits them by LDS at large n: 24 KB per block at n = 13),
+// so that no block waits for a whole element loop of another, and at most
+// kConGrid.  Computed once per kernel.
+template <typename Kern>
+int resident_blocks(Kern kernel, int* cache)
+{
+    if (*cache == 0) {
+        int dev = 0, cus = 0, per = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, kBlock2, 0) != hipSuccess || per < 1 || cus < 1)
+            return kConGrid;  // not cached: asked again next time
+        *cache = per * cus < kConGrid ? per * cus : kConGrid;
+    }
+    return *cache;
+}
+
 template <int N, bool BT>
 __global__ __launch_bounds__(kBlock2) void k_constrain2d(Step2DArgs A)
 {
@@ -1384,13 +1402,16 @@ int con_n(const Step2DArgs& A, hipStream_t s)
 {
     constexpr int E = kBlock2 / (N * N);
     const int nchunk = (A.K + E - 1) / E;
-    const dim3 grid(nchunk < kConGrid ? nchunk : kConGrid);
-    if (A.cmask & (SL_C_MASS | SL_C_ENERGY))
+    static int cap_bt = 0, cap = 0;
+    if (A.cmask & (SL_C_MASS | SL_C_ENERGY)) {
         hipLaunchKernelGGL(k_constrain2d_me<N>, dim3(nchunk), dim3(kBlock2), 0, s, A);
-    else if (A.iface == SL_IFACE_BACKTRACK)
-        hipLaunchKernelGGL((k_constrain2d<N, true>), grid, dim3(kBlock2), 0, s, A);
-    else
-        hipLaunchKernelGGL((k_constrain2d<N, false>), grid, dim3(kBlock2), 0, s, A);
+    } else if (A.iface == SL_IFACE_BACKTRACK) {
+        const int r = resident_blocks(k_constrain2d<N, true>, &cap_bt);
+        hipLaunchKernelGGL((k_constrain2d<N, true>), dim3(nchunk < r ? nchunk : r), dim3(kBlock2), 0, s, A);
+    } else {
+        const int r = resident_blocks(k_constrain2d<N, false>, &cap);
+        hipLaunchKernelGGL((k_constrain2d<N, false>), dim3(nchunk < r ? nchunk : r), dim3(kBlock2), 0, s, A);
+    }
     return hipGetLastError() == hipSuccess ? 0 : 1;
 }
 
@@ -1470,7 +1491,9 @@ int con_mixed_n(const Step2DArgs& A, hipStream_t s)
 {
     constexpr int E = kBlock2 / (N * N);
     const int nchunk = (A.K + E - 1) / E;
-    hipLaunchKernelGGL(k_constrain2d_mixed<N>, dim3(nchunk < kConGrid ? nchunk : kConGrid), dim3(kBlock2), 0, s, A);
+    static int cap = 0;
+    const int r = resident_blocks(k_constrain2d_mixed<N>, &cap);
+    hipLaunchKernelGGL(k_constrain2d_mixed<N>, dim3(nchunk < r ? nchunk : r), dim3(kBlock2), 0, s, A);
     return hipGetLastError() == hipSuccess ? 0 : 1;
 }
 
