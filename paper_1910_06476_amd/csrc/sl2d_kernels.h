@@ -1287,17 +1287,17 @@ __global__ __launch_bounds__(kBlock2) void k_constrain2d_mixed(Step2DArgs A)
 
         for (int tt = p; inblk && tt < NB; tt += ND) {
             const int side = tt / N, k = tt % N;
-            int nbe;
-            bool high;
-            periodic_partner(A.elems[ll], side, A.kx, A.ky, nbe, high);
-            const int b2 = A.mix[nbe], j2 = A.mix[Kall + nbe];
-            const int n2 = meta[MixMeta::kN + b2];
-            const double* tr2 = A.rec_all + meta[MixMeta::kRec + b2] + (size_t)j2 * 4 * n2 + (side ^ 1) * n2;
+            const bool high = side == 0 || side == 2;  // e is the high side of its left and bottom faces
+            // the neighbour's trace row from the face partner table (one load
+            // where the topology lookup took a chain of four)
+            const int32_t* f = A.nbr + (size_t)ll * MixFace::kPer + side * MixFace::kField;
+            const int n2 = f[MixFace::kOrder];
+            const double* tr2 = A.rec_all + f[MixFace::kRecOff];
             double other = 0.0;
             if (n2 == N) {
                 other = tr2[k];
             } else {
-                const double* M = A.interp + meta[MixMeta::kInterp + kMaxBuckets * A.bucket + b2];
+                const double* M = A.interp + f[MixFace::kInterpOff];
                 for (int q = 0; q < n2; ++q) other = fma(M[k * n2 + q], tr2[q], other);
             }
             const double mine = myrec[tt];

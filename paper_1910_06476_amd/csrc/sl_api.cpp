@@ -7,6 +7,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <limits>
 #include <vector>
 
 #include "sl_internal.h"
@@ -48,6 +49,7 @@ struct sl_mesh {
     std::vector<size_t> uoff;          // caller layout offset of element e (n_e^2 values each)
     std::vector<size_t> doff;          // device (bucket) layout offset of element e
     int32_t *elems_d, *mix_d;
+    int32_t* nbr_d;                    // [K][4 sides][3]: face partner table in bucket order (see MixFace)
     double *interp_d;
     size_t dofs;
     hipGraph_t graph;
@@ -82,7 +84,7 @@ void release(sl_mesh* m)
     dfree(m->phi); dfree(m->phi2); dfree(m->phihat); dfree(m->rec); dfree(m->eloc); dfree(m->aN);
     dfree(m->aM); dfree(m->divN); dfree(m->divM); dfree(m->vface); dfree(m->tab); dfree(m->ghost);
     dfree(m->stat_part); dfree(m->flag_part); dfree(m->vdeg_d);
-    dfree(m->elems_d); dfree(m->mix_d); dfree(m->interp_d);
+    dfree(m->elems_d); dfree(m->mix_d); dfree(m->interp_d); dfree(m->nbr_d);
     if (m->gexec) (void)hipGraphExecDestroy(m->gexec);
     if (m->graph) (void)hipGraphDestroy(m->graph);
     m->gexec = nullptr;
@@ -249,7 +251,7 @@ size_t mixed_bytes(const sl_mesh_desc* d, const MixedPlan& P)
     const size_t K = (size_t)d->kx * d->ky;
     const size_t dbl = 3 * P.dofs + 2 * 2 * P.dofs + 2 * P.dofs + 2 * P.nrec + P.ntab + P.ninterp +
                        (size_t)P.nblocks * kStatSlots;
-    const size_t ints = 2 * (size_t)P.nblocks + 1 + K + (size_t)MixMeta::size((int)K);
+    const size_t ints = 2 * (size_t)P.nblocks + 1 + K + (size_t)MixMeta::size((int)K) + K * MixFace::kPer;
     return dbl * sizeof(double) + ints * sizeof(int32_t);
 }
 
@@ -292,6 +294,7 @@ Step2DArgs bucket_args(const sl_mesh* m, int b, double dt, const sl_step_opts& o
     B.bs = m->bs[b] > 0 ? m->bs[b] : 0;
     B.elems = m->elems_d + m->elemOff[b];
     B.mix = m->mix_d;
+    B.nbr = m->nbr_d + m->elemOff[b] * MixFace::kPer;
     B.rec_all = m->rec;
     B.interp = m->interp_d;
     B.bucket = b;
@@ -424,6 +427,11 @@ static sl_status create_mixed(const sl_mesh_desc* d, sl_mesh** out)
         to += (size_t)tab_offsets(2, n).total;
         eo += (size_t)P.bK[b];
     }
+    // the device meta data and face table hold these offsets as int32
+    if (2 * bo > (size_t)std::numeric_limits<int32_t>::max() || ro > (size_t)std::numeric_limits<int32_t>::max()) {
+        delete m;
+        return SL_E_INVALID;
+    }
     // element placement: caller layout (element order) and bucket layout
     int bucket_of[kMax2D + 1];
     for (int b = 0; b < P.nbk; ++b) bucket_of[P.bn[b]] = b;
@@ -485,6 +493,28 @@ static sl_status create_mixed(const sl_mesh_desc* d, sl_mesh** out)
             io += (size_t)P.bn[a] * P.bn[b];
         }
     if (!ok) { delete m; return SL_E_INVALID; }
+    // face partner table, in bucket order: for each side of each element the
+    // neighbour's matching trace row in the records of all buckets, its
+    // order, and the interpolation matrix from its order (-1: the same)
+    std::vector<int32_t> nbr((size_t)K * MixFace::kPer);
+    for (int e = 0; e < K; ++e) {
+        const int b = meta[e], pos = (int)m->elemOff[b] + meta[(size_t)K + e];
+        const int ex = e % d->kx, ey = e / d->kx;
+        for (int side = 0; side < 4; ++side) {
+            int nbe;
+            switch (side) {
+            case 0: nbe = ey * d->kx + (ex + d->kx - 1) % d->kx; break;
+            case 1: nbe = ey * d->kx + (ex + 1) % d->kx; break;
+            case 2: nbe = ((ey + d->ky - 1) % d->ky) * d->kx + ex; break;
+            default: nbe = ((ey + 1) % d->ky) * d->kx + ex; break;
+            }
+            const int b2 = meta[nbe], j2 = meta[(size_t)K + nbe], n2 = P.bn[b2];
+            int32_t* f = &nbr[(size_t)pos * MixFace::kPer + side * MixFace::kField];
+            f[MixFace::kRecOff] = (int32_t)(m->recOff[b2] + (size_t)j2 * 4 * n2 + (size_t)(side ^ 1) * n2);
+            f[MixFace::kOrder] = n2;
+            f[MixFace::kInterpOff] = b2 == b ? -1 : mm[MixMeta::kInterp + kMaxBuckets * b + b2];
+        }
+    }
     if (d->stream) { m->stream = (hipStream_t)d->stream; m->own_stream = false; }
     else {
         if (hipStreamCreateWithFlags(&m->stream, hipStreamNonBlocking) != hipSuccess) { delete m; return SL_E_DEVICE; }
@@ -496,12 +526,13 @@ static sl_status create_mixed(const sl_mesh_desc* d, sl_mesh** out)
          dalloc(&m->divN, P.dofs) && dalloc(&m->divM, P.dofs) && dalloc(&m->vface, P.nrec) &&
          dalloc(&m->tab, P.ntab) && dalloc(&m->stat_part, (size_t)m->nblocks * kStatSlots) &&
          dalloc(&m->flag_part, (size_t)2 * m->nblocks) && dalloc(&m->vdeg_d, 1) && dalloc(&m->elems_d, (size_t)K) &&
-         dalloc(&m->mix_d, meta.size()) && dalloc(&m->interp_d, interp.size());
+         dalloc(&m->mix_d, meta.size()) && dalloc(&m->interp_d, interp.size()) && dalloc(&m->nbr_d, nbr.size());
     if (!ok) { release(m); delete m; return SL_E_NOMEM; }
     std::vector<double> u((size_t)P.dofs);
     for (int e = 0; e < K; ++e)
         std::memcpy(&u[m->doff[e]], d->u0 + m->uoff[e], sizeof(double) * m->orders[e] * m->orders[e]);
-    hipError_t r[8] = {
+    hipError_t r[9] = {
+        hipMemcpyAsync(m->nbr_d, nbr.data(), nbr.size() * sizeof(int32_t), hipMemcpyHostToDevice, m->stream),
         hipMemcpyAsync(m->tab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice, m->stream),
         hipMemcpyAsync(m->phi, u.data(), u.size() * sizeof(double), hipMemcpyHostToDevice, m->stream),
         hipMemcpyAsync(m->elems_d, elems.data(), elems.size() * sizeof(int32_t), hipMemcpyHostToDevice, m->stream),

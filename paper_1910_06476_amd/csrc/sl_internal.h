@@ -114,6 +114,7 @@ struct Step2DArgs {
     // mixed-order meshes (elements grouped in buckets of one order; this
     // launch covers one bucket, K above is its element count)
     const int32_t* elems;  // [K] global element index of the bucket's elements
+    const int32_t* nbr;    // [K][MixFace::kPer] face partners of the bucket's elements
     const int32_t* mix;    // device meta data, see MixMeta
     const double* rec_all; // records of all buckets
     const double* interp;  // interpolation matrices between the orders
@@ -135,6 +136,16 @@ struct MixMeta {
     static constexpr int kN = 0, kRec = kMaxBuckets, kVel = 2 * kMaxBuckets, kTab = 3 * kMaxBuckets,
                          kK = 4 * kMaxBuckets, kInterp = 5 * kMaxBuckets;
     static constexpr int size(int K) { return 2 * K + 5 * kMaxBuckets + kMaxBuckets * kMaxBuckets; }
+};
+
+// Face partner table of a mixed-order mesh (int32, bucket order): for element
+// position p and side s (left, right, bottom, top), at [p][s][field]: the
+// offset in the records of all buckets of the neighbour's trace row on the
+// shared face, the neighbour's nodes per direction, and the offset in the
+// interpolation matrices of the one from its order to the element's (-1 when
+// the orders agree).  Built on the host with the mesh.
+struct MixFace {
+    static constexpr int kRecOff = 0, kOrder = 1, kInterpOff = 2, kField = 3, kPer = 4 * kField;
 };
 
 // face normal velocity of one bucket's elements (aN_all, tab_all: all
