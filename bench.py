@@ -56,17 +56,22 @@ def advect_flops_per_element(n: int, s: int, nq: int, targets: bool, vel_terms: 
     return f
 
 
-def advect_bytes_per_element(n: int, targets: bool) -> float:
-    """Algorithmic HBM bytes of the 1D advect kernel per element: read phi,
-    nodal and modal velocity (+ nodal divergence with targets), write phihat
-    and the 8-double element record."""
-    return 8.0 * n * (3 + (1 if targets else 0)) + 8.0 * n + 64.0
+def advect_bytes_per_element(n: int, targets: bool, vel_terms: int) -> float:
+    """Algorithmic HBM bytes of the 1D advect kernel per element: read phi^n
+    and the nodal velocity (+ the nodal divergence and the face speed with
+    targets) and the velocity series coefficients that are evaluated; write
+    phihat and the element record (the two traces, + the six target entries
+    with targets)."""
+    rd = 8.0 * n * (3 if targets else 2) + 8.0 * vel_terms + (8.0 if targets else 0.0)
+    wr = 8.0 * n + (64.0 if targets else 16.0)
+    return rd + wr
 
 
-def constrain_bytes_per_element(n: int) -> float:
-    """read phihat, the element record (neighbours' are cache hits), two face
-    velocities; write phi."""
-    return 8.0 * n + 64.0 + 8.0 + 8.0 * n
+def constrain_bytes_per_element(n: int, targets: bool = True) -> float:
+    """read phihat, the element record entries in use (the two traces, + the
+    targets' six; the neighbours' are cache hits) and one face speed; write
+    phi."""
+    return 8.0 * n + (64.0 if targets else 16.0) + 8.0 + 8.0 * n
 
 
 def measured_traffic(kernel: str, source: str = "sl1d.hip", profile: str = "sl1d_c2_K65536_n17.md"):
@@ -333,14 +338,78 @@ def bench_serve(args, torch, P, W):
     print(json.dumps(out))
 
 
+def bench_c2bw(args, torch, P, W, stream):
+    """The HBM side of the 1D step: the C2 problem (order 16, RK4, the same
+    velocity and initial data) with boundary rows only, on K = 2^22 elements
+    (71.3 M DOF, 0.57 GB per nodal array), far beyond the last-level cache.
+    Without targets the advect kernel carries about 2.7 kflop per element
+    against about 0.46 kB, so both kernels are bound by HBM."""
+    w = W.c2(K=1 << 22, cmask=W.BOUNDARY)
+    steps = max(1, min(args.steps, 200))
+    warm = max(1, min(args.warmup, 20))
+    m = P.from_workload(w, stream=stream.cuda_stream)
+    opts = dict(rk=w.rk, constraints=w.cmask, mode=w.mode)
+    m.step(w.dt, warm, **opts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    m.step(w.dt, steps, **opts)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    P.sl_set_profiling(m.h, True)
+    m.step(w.dt, 20, **opts)
+    t_adv, c_adv = P.sl_kernel_time(m.h, P.KER_ADV1D)
+    t_con, c_con = P.sl_kernel_time(m.h, P.KER_CON1D)
+    P.sl_set_profiling(m.h, False)
+    rc, phi, st = m.read()
+    T = (warm + steps + 20) * w.dt
+    l2 = w.l2_error(phi, T)
+    m.close()
+
+    adv_avg = t_adv / max(c_adv, 1) * 1e-3
+    con_avg = t_con / max(c_con, 1) * 1e-3
+    by_a = advect_bytes_per_element(w.n, False, st.vel_terms) * w.K
+    by_c = constrain_bytes_per_element(w.n, False) * w.K
+    fl_a = advect_flops_per_element(w.n, 4, 3, False, st.vel_terms) * w.K
+    kern = {"sl1d_advect": {"avg_launch_us": adv_avg * 1e6, "algorithmic_bytes_per_launch": by_a,
+                            "achieved_GBps": by_a / adv_avg / 1e9, "frac_hbm": by_a / adv_avg / HBM_PEAK,
+                            "algorithmic_flops_per_launch": fl_a,
+                            "achieved_TFLOPs": fl_a / adv_avg / 1e12},
+            "sl1d_constrain": {"avg_launch_us": con_avg * 1e6, "algorithmic_bytes_per_launch": by_c,
+                               "achieved_GBps": by_c / con_avg / 1e9, "frac_hbm": by_c / con_avg / HBM_PEAK}}
+    dom, by, avg = ("sl1d_advect", by_a, adv_avg) if adv_avg >= con_avg else ("sl1d_constrain", by_c, con_avg)
+    roof = {"kernel": dom, "bound": "hbm", "achieved": by / avg / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+            "frac": by / avg / HBM_PEAK,
+            "traffic": measured_traffic("k_advect1d" if dom == "sl1d_advect" else "k_constrain1d",
+                                        profile="sl1d_c2bw_K4194304_n17.md"),
+            "avg_launch_us": avg * 1e6, "algorithmic_bytes_per_launch": by, "kernels": kern}
+    out = {
+        "metric": METRIC, "value": w.dofs * steps / el, "unit": "DOF-updates/s", "n_gpus": 1, "steps": steps,
+        "warmup": warm, "ms_per_step": el / steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "HBM probe: 1D a(x)=1+0.5sin(pi x) on [0,2] periodic, K=2^22, order 16 (17 GL "
+                               "nodes), u0=exp(-40(x-1)^2), RK4, boundary rows only, HARD, dt=0.2*gap*dx/1.5",
+                   "K": w.K, "n": w.n, "dofs": w.dofs, "dt": w.dt, "rk": w.rk, "constraints": "B"},
+        "l2_error": l2, "l2_time": T, "status": P.status_string(rc),
+        "roofline": roof,
+    }
+    if not args.no_cpu:
+        piece = W.c2(cmask=W.BOUNDARY)
+        cb = cpu_baseline(piece)
+        cb["sample"] = "a K=65536 piece of the same problem (the same work per element): " + cb["sample"]
+        out["cpu_baseline"] = cb
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--workload", choices=["c2", "c3", "c4", "serve"], default="c2",
-                    help="c2: the headline 1D configuration (default); c3: the 2D rotation configuration; "
+    ap.add_argument("--workload", choices=["c2", "c2bw", "c3", "c4", "serve"], default="c2",
+                    help="c2: the headline 1D configuration (default); c2bw: the C2 problem with boundary "
+                         "rows only on K=2^22 elements, a probe of the HBM side; "
+                         "c3: the 2D rotation configuration; "
                          "c4: the 2D mixed-order batch; "
                          "serve: a Poisson stream of independent problems through the request loop")
     ap.add_argument("--requests", type=int, default=48, help="serve: number of requests")
@@ -380,6 +449,8 @@ def main():
         return bench_serve(args, torch, P, W)
     if args.workload == "c4":
         return bench_c4(args, torch, P, W, stream)
+    if args.workload == "c2bw":
+        return bench_c2bw(args, torch, P, W, stream)
     w = W.c2()
     m = P.from_workload(w, stream=stream.cuda_stream)
     opts = dict(rk=w.rk, constraints=w.cmask, mode=w.mode, energy_maxit=w.energy_maxit, energy_tol=w.energy_tol)
@@ -409,7 +480,7 @@ def main():
     nq = 3
     targets = True
     fl = advect_flops_per_element(w.n, s_stages, nq, targets, st.vel_terms) * w.K
-    by = advect_bytes_per_element(w.n, targets) * w.K
+    by = advect_bytes_per_element(w.n, targets, st.vel_terms) * w.K
     adv_avg = t_adv / max(c_adv, 1) * 1e-3
     con_avg = t_con / max(c_con, 1) * 1e-3
     if adv_avg >= con_avg:
