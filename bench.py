@@ -92,21 +92,47 @@ def measured_traffic(kernel: str, source: str = "sl1d.hip", profile: str = "sl1d
 
 def cpu_baseline(w, budget_s: float = 12.0):
     import oracle
+    import workloads as W
     oracle.build(force=False)
     p = oracle.params_from(w)
     a, _ = w.velocity()
     phi = w.initial()
+    ghost = w.bc == W.GHOST  # inflow rows from the exact solution, as on the device
     t0 = time.perf_counter()
-    phi, _ = oracle.step(p, phi, a=a, dt=w.dt, nsteps=1)
+    phi, _ = oracle.step(p, phi, a=a, ghost=w.ghost_rows(0.0, 1) if ghost else None, dt=w.dt, nsteps=1)
     one = time.perf_counter() - t0
     steps = max(1, min(50, int(budget_s / max(one, 1e-3))))
+    g = w.ghost_rows(w.dt, steps) if ghost else None
     t0 = time.perf_counter()
-    oracle.step(p, phi, a=a, dt=w.dt, nsteps=steps)
+    oracle.step(p, phi, a=a, ghost=g, dt=w.dt, nsteps=steps)
     el = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": w.dofs * steps / el, "unit": "DOF-updates/s", "cores": cores, "kind": "oracle",
             "sample": f"full mesh (K={w.K}, n={w.n}), {steps} steps after 1 warm-up step, "
                       f"{el:.1f} s, OpenMP threads={cores}"}
+
+
+def cpu_baseline_mixed(w, budget_s: float = 12.0):
+    """The mixed-order oracle on `w` (a piece of the C4 recipe), timed over
+    as many steps as fit in about budget_s."""
+    import oracle
+    import workloads as W
+    oracle.build(force=False)
+    p = oracle.Params(dim=2, kx=w.kx, ky=w.ky, n=int(w.orders[0]), family=w.family, bc=W.PERIODIC, form=w.form,
+                      rk=w.rk, cmask=W.BOUNDARY, mode=w.mode, energy_maxit=0, vel_kind=0, x0=w.x0, x1=w.x1,
+                      y0=w.y0, y1=w.y1, energy_tol=0.0)
+    a = w.velocity()
+    t0 = time.perf_counter()
+    phi, _ = oracle.step_mixed(p, w.orders, w.initial(), a=a, dt=w.dt, nsteps=1)
+    one = time.perf_counter() - t0
+    steps = max(1, min(50, int(budget_s / max(one, 1e-3))))
+    t0 = time.perf_counter()
+    oracle.step_mixed(p, w.orders, phi, a=a, dt=w.dt, nsteps=steps)
+    el = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": w.dofs * steps / el, "unit": "DOF-updates/s", "cores": cores, "kind": "oracle",
+            "sample": f"a {w.kx}x{w.ky} mesh of the same recipe (orders {{4,6,8,12}} by seed, {w.dofs} DOF), "
+                      f"{steps} steps after 1 warm-up step, {el:.1f} s, OpenMP threads={cores}"}
 
 
 def advect2d_flops_per_element(n: int, s: int, sweeps: float, vel_terms: int) -> float:
@@ -193,6 +219,8 @@ def bench_c3(args, torch, P, W, stream):
                      "avg_launch_us": adv_avg * 1e6, "algorithmic_flops_per_launch": fl,
                      "kernels_us": {"sl2d_advect": adv_avg * 1e6, "sl2d_constrain": con_avg * 1e6}},
     }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out))
 
 
@@ -231,6 +259,8 @@ def bench_c4(args, torch, P, W, stream):
         "eager_step_ms": t_eager / max(c_eager, 1),
         "graph_step_ms": el / args.steps * 1e3,
     }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline_mixed(W.c4(kx=16, nsteps=1))
     print(json.dumps(out))
 
 

@@ -148,6 +148,18 @@ def test_c2_full_size_parity(cmask):
     assert rc == 0 and st.flags == 0
 
 
+def test_c2_probe_size_parity():
+    """The HBM probe's size (K=2^22, n=17, RK4, boundary rows) in the launch
+    configuration the benchmark times, one step, compared on the whole field
+    (71.3 M values; the oracle takes a few seconds on the host's cores)."""
+    w = W.c2(K=1 << 22, cmask=W.BOUNDARY)
+    announce("c2 probe size K=2^22 one step")
+    g, st, rc = run_gpu(w, nsteps=1)
+    o, ost = run_oracle(w, nsteps=1)
+    assert_parity(w, g, o)
+    assert rc == 0 and st.flags == 0
+
+
 def test_c2_full_size_invariants_after_steps():
     """At full size over 50 steps with the paper's Picard stop (1e-8): the
     boundary and mass rows hold to round-off; a handful of elements at the
