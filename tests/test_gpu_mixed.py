@@ -127,6 +127,41 @@ def test_c4_submesh_accuracy_and_parity():
     assert rel_l2(g, o) <= TOL, rel_l2(g, o)
 
 
+def test_c4_full_size_sampled_parity():
+    """Full size (316x316, orders {4,6,8,12} by seed, 8.08 M DOF) in the
+    launch configuration the benchmark times: order buckets in one captured
+    graph, block shapes from the autotuner.  Two steps (one graph replay).
+    With boundary rows only, an element's value after two steps depends on
+    the elements within two of it, so 48 seeded elements are each compared
+    with the oracle run on the 5x5 window of elements around it (periodic
+    within the window; the centre's dependencies are all inside)."""
+    w = _case(316, 316, (4, 6, 8, 12), seed=0, nsteps=2)
+    announce("mixed c4 full size, sampled")
+    g, st, rc = _gpu(w)
+    assert rc == 0
+    off = w.offsets
+    phi0 = w.initial()
+    a = w.velocity()
+    u, v = a[:w.dofs], a[w.dofs:]
+    dx, dy = (w.x1 - w.x0) / w.kx, (w.y1 - w.y0) / w.ky
+    rng = np.random.default_rng(11)
+    G, O = [], []
+    for e in rng.choice(w.K, 48, replace=False):
+        ex, ey = int(e) % w.kx, int(e) // w.kx
+        idx = [((ey + j) % w.ky) * w.kx + (ex + i) % w.kx for j in range(-2, 3) for i in range(-2, 3)]
+        orders = w.orders[idx]
+        cut = lambda arr: np.concatenate([arr[off[k]:off[k + 1]] for k in idx])
+        p = oracle.Params(dim=2, kx=5, ky=5, n=int(orders[0]), family=w.family, bc=W.PERIODIC, form=w.form,
+                          rk=w.rk, cmask=W.BOUNDARY, mode=w.mode, energy_maxit=0, vel_kind=0, x0=0.0,
+                          x1=5 * dx, y0=0.0, y1=5 * dy, energy_tol=0.0)
+        o, _ = oracle.step_mixed(p, orders, cut(phi0), a=np.concatenate([cut(u), cut(v)]), dt=w.dt, nsteps=2)
+        sub = np.concatenate([[0], np.cumsum(orders.astype(np.int64) ** 2)])
+        G.append(g[off[e]:off[e + 1]])
+        O.append(o[sub[12]:sub[13]])
+    err = rel_l2(np.concatenate(G), np.concatenate(O))
+    assert err <= TOL, err
+
+
 def test_mixed_statistics_and_validation():
     import paper_1910_06476_amd as P
     w = _case(4, 4, (4, 6), seed=6, nsteps=2)
