@@ -2,6 +2,7 @@
 // sl2d_p*.hip units; each unit instantiates them for a few orders, so the
 // orders compile in parallel.  See sl2d.hip for the method's outline.
 #pragma once
+#include <atomic>
 #include <type_traits>
 
 #include "sl2d_ops.h"
@@ -780,19 +781,24 @@ constexpr int kConGrid = 2048;
 // Blocks of a persistent launch: no more than are resident at once (the
 // 4n x 4n table limits them by LDS at large n: 24 KB per block at n = 13),
 // so that no block waits for a whole element loop of another, and at most
-// kConGrid.  Computed once per kernel.
+// kConGrid.  Computed once per kernel and device, in cache[device] (atomic:
+// meshes may be stepped from several host threads).
+constexpr int kMaxDevices = 64;
 template <typename Kern>
-int resident_blocks(Kern kernel, int* cache)
+int resident_blocks(Kern kernel, std::atomic<int>* cache)
 {
-    if (*cache == 0) {
-        int dev = 0, cus = 0, per = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return kConGrid;
+    int c = cache[dev].load(std::memory_order_relaxed);
+    if (c == 0) {
+        int cus = 0, per = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
             hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, kBlock2, 0) != hipSuccess || per < 1 || cus < 1)
             return kConGrid;  // not cached: asked again next time
-        *cache = per * cus < kConGrid ? per * cus : kConGrid;
+        c = per * cus < kConGrid ? per * cus : kConGrid;
+        cache[dev].store(c, std::memory_order_relaxed);
     }
-    return *cache;
+    return c;
 }
 
 template <int N, bool BT>
@@ -1402,14 +1408,14 @@ int con_n(const Step2DArgs& A, hipStream_t s)
 {
     constexpr int E = kBlock2 / (N * N);
     const int nchunk = (A.K + E - 1) / E;
-    static int cap_bt = 0, cap = 0;
+    static std::atomic<int> cap_bt[kMaxDevices], cap[kMaxDevices];
     if (A.cmask & (SL_C_MASS | SL_C_ENERGY)) {
         hipLaunchKernelGGL(k_constrain2d_me<N>, dim3(nchunk), dim3(kBlock2), 0, s, A);
     } else if (A.iface == SL_IFACE_BACKTRACK) {
-        const int r = resident_blocks(k_constrain2d<N, true>, &cap_bt);
+        const int r = resident_blocks(k_constrain2d<N, true>, cap_bt);
         hipLaunchKernelGGL((k_constrain2d<N, true>), dim3(nchunk < r ? nchunk : r), dim3(kBlock2), 0, s, A);
     } else {
-        const int r = resident_blocks(k_constrain2d<N, false>, &cap);
+        const int r = resident_blocks(k_constrain2d<N, false>, cap);
         hipLaunchKernelGGL((k_constrain2d<N, false>), dim3(nchunk < r ? nchunk : r), dim3(kBlock2), 0, s, A);
     }
     return hipGetLastError() == hipSuccess ? 0 : 1;
@@ -1491,8 +1497,8 @@ int con_mixed_n(const Step2DArgs& A, hipStream_t s)
 {
     constexpr int E = kBlock2 / (N * N);
     const int nchunk = (A.K + E - 1) / E;
-    static int cap = 0;
-    const int r = resident_blocks(k_constrain2d_mixed<N>, &cap);
+    static std::atomic<int> cap[kMaxDevices];
+    const int r = resident_blocks(k_constrain2d_mixed<N>, cap);
     hipLaunchKernelGGL(k_constrain2d_mixed<N>, dim3(nchunk < r ? nchunk : r), dim3(kBlock2), 0, s, A);
     return hipGetLastError() == hipSuccess ? 0 : 1;
 }
