@@ -209,3 +209,19 @@ def test_error_paths_on_device():
         assert rc == 0 and st.steps == 2
     finally:
         m.close()
+
+
+@pytest.mark.parametrize("form", [W.ADVECTIVE, W.CONSERVATIVE])
+@pytest.mark.parametrize("rk", [1, 2, 3, 4])
+def test_linear_velocity_closed_form(rk, form):
+    """The device step against mathematics, not only the oracle: for a = c x
+    (2D: (c x, c y)) and a linear field, one step without constraint rows is
+    u0 / R(c dt) (advective) or R(-d c dt) / R(c dt) u0 (conservative), R the
+    degree-rk Taylor polynomial of e^z (tests/_linear_flow.py); the
+    next-order polynomial would differ by more than 1e-10."""
+    import _linear_flow as LF
+    w, a, div, ghost, expect = LF.case(1, rk, form)
+    announce(f"linear velocity 1D rk={rk} form={form}")
+    g, st, rc = run_gpu(w, nsteps=1, ghost=ghost)
+    assert rc == 0 and st.flags == 0
+    np.testing.assert_allclose(g, expect, rtol=0, atol=1e-14)

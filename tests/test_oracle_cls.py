@@ -51,6 +51,24 @@ def test_hard_equals_lse_bruteforce(ora, seed):
 
 
 @pytest.mark.parametrize("seed", range(4))
+def test_hard_is_a_projection(ora, seed):
+    """HARD returns the nearest point of the affine set {C x = d}: solving
+    again from that point changes nothing, and the correction is orthogonal
+    to the null space of C (it lies in the row space)."""
+    rng = np.random.default_rng(300 + seed)
+    n, m = 17, 4
+    C = rng.normal(size=(m, n))
+    d = rng.normal(size=m)
+    ph = rng.normal(size=n)
+    x1 = ora.cls(C, d, ph, 0)
+    x2 = ora.cls(C, d, x1, 0)
+    np.testing.assert_allclose(x2, x1, rtol=0, atol=1e-13)
+    _, _, Vt = np.linalg.svd(C)
+    Z = Vt[m:].T  # null space basis
+    np.testing.assert_allclose(Z.T @ (x1 - ph), 0.0, atol=1e-13)
+
+
+@pytest.mark.parametrize("seed", range(4))
 def test_hard_equals_lse_svd_larger(ora, seed):
     rng = np.random.default_rng(100 + seed)
     n, m = 17, 4

@@ -10,7 +10,9 @@
 * mirror symmetry x -> L - x, a -> -a;
 * HARD mass rows make the global mass telescope (periodic);
 * the constraint residuals and the Picard fixed point;
-* convergence to the closed-form solutions of the workloads.
+* convergence to the closed-form solutions of the workloads;
+* for a linear velocity, one step is the method's stability polynomial
+  (closed form, every tableau, both forms, 1D and 2D).
 """
 import math
 
@@ -351,3 +353,24 @@ def test_2d_hard_rows_beyond_boundary_null_space_refused(ora, n, cmask, ok):
         else:
             with pytest.raises(ValueError):
                 ora.step(p, w.initial(), a=a, ghost=g, dt=w.dt, nsteps=1)
+
+
+@pytest.mark.parametrize("form", [W.ADVECTIVE, W.CONSERVATIVE])
+@pytest.mark.parametrize("rk", [1, 2, 3, 4])
+@pytest.mark.parametrize("dim", [1, 2])
+def test_linear_velocity_step_is_the_stability_polynomial(ora, dim, rk, form):
+    """a = c x: one step gives u0 / R(c dt) (advective) or R(-d c dt) /
+    R(c dt) u0 (conservative), R the degree-rk Taylor polynomial of e^z
+    (tests/_linear_flow.py).  The same field with the next-order polynomial
+    differs by more than 1e-10 here, so a dropped stage, a wrong weight or a
+    wrong sign in the motion or in the source term fails."""
+    import _linear_flow as LF
+    w, a, div, ghost, expect = LF.case(dim, rk, form)
+    p = ora.params_from(w)
+    out, st = ora.step(p, w.initial(), a=a, div=div, ghost=ghost, dt=w.dt, nsteps=1)
+    assert st.flags == 0
+    np.testing.assert_allclose(out, expect, rtol=0, atol=4e-15)
+    z = 0.9 * w.dt
+    nxt = LF.stability(z, rk + 1)
+    alt = w.initial() / nxt if form == W.ADVECTIVE else LF.stability(-dim * z, rk + 1) / nxt * w.initial()
+    assert np.abs(alt - expect).max() > 1e-10
