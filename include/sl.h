@@ -51,7 +51,11 @@ enum {
 };
 
 enum { SL_NODES_GL = 0, SL_NODES_CG = 1 };          /* Gauss-Legendre / Chebyshev-Gauss */
-enum { SL_BC_PERIODIC = 0, SL_BC_GHOST = 1 };
+/* Boundary conditions.  Periodicity pairs opposite sides, so in 2D it is
+ * chosen per direction: SL_BC_PERIODIC_X wraps the left and right sides
+ * onto each other and takes ghost values on the bottom and top sides;
+ * SL_BC_PERIODIC_Y the other way round. */
+enum { SL_BC_PERIODIC = 0, SL_BC_GHOST = 1, SL_BC_PERIODIC_X = 2, SL_BC_PERIODIC_Y = 3 };
 enum { SL_FORM_ADVECTIVE = 0, SL_FORM_CONSERVATIVE = 1 };
 enum { SL_PREC_FP64 = 0, SL_PREC_FP32_REFINED = 1, SL_PREC_BF16_REFINED = 2 };
 enum { SL_C_BOUNDARY = 1, SL_C_MASS = 2, SL_C_ENERGY = 4 };
@@ -64,7 +68,10 @@ enum { SL_IFACE_INTERP = 0, SL_IFACE_BACKTRACK = 1 };
  *   order      polynomial order N >= 1 (n = N + 1 nodes per direction);
  *              1D: N <= 16, 2D: N <= 12
  *   nodes      SL_NODES_GL (default) or SL_NODES_CG (paper, eq. gaussquad)
- *   bc         SL_BC_PERIODIC, or SL_BC_GHOST (inflow values from sl_set_ghost)
+ *   bc         SL_BC_PERIODIC, or SL_BC_GHOST (inflow values from sl_set_ghost
+ *              on every side), or in 2D SL_BC_PERIODIC_X / SL_BC_PERIODIC_Y
+ *              (periodic in one direction, ghost values on the two sides
+ *              of the other)
  *   form       SL_FORM_ADVECTIVE or SL_FORM_CONSERVATIVE
  *   precision  SL_PREC_FP64, SL_PREC_FP32_REFINED or SL_PREC_BF16_REFINED
  *              (2D only: the preconditioner of the remap solve is stored
@@ -166,13 +173,15 @@ sl_status sl_create_mesh(const sl_mesh_desc* desc, sl_mesh** out);
  * built on the device.  Errors: SL_E_INVALID, SL_E_NONFINITE, SL_E_DEVICE. */
 sl_status sl_set_velocity(sl_mesh* m, const double* a, const double* div_a);
 
-/* Ghost (outside) values at the domain boundary for SL_BC_GHOST meshes.
+/* Ghost (outside) values at the domain boundary for meshes with ghost
+ * sides (SL_BC_GHOST, SL_BC_PERIODIC_X, SL_BC_PERIODIC_Y).
  * g: host, nrows rows of nghost values; row r holds the outside state at
  * time t + r dt where t is the mesh time at this call, so the i-th following
  * step reads rows i and i+1 (clamped to the last row; nrows = 1 is a steady
  * ghost).  Row layout -- 1D: [left, right]; 2D: left edge (ky * n values,
  * by iy then node j), right edge (ky * n), bottom edge (kx * n, by ix then
- * node i), top edge (kx * n).  Errors: SL_E_STATE (periodic mesh),
+ * node i), top edge (kx * n); the values of periodic sides are not read.
+ * Errors: SL_E_STATE (periodic mesh),
  * SL_E_INVALID, SL_E_NOMEM. */
 sl_status sl_set_ghost(sl_mesh* m, const double* g, int32_t nrows);
 

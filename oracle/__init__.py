@@ -205,7 +205,7 @@ def run_workload(w, nsteps=None, analytic=False, ghost_t0=0.0, **over):
             kw["vel_param"] = [float(np.ravel(u)[0]), float(np.ravel(v)[0]) if np.ndim(v) else float(v), 0, 0]
     p = params_from(w, **kw)
     a, _ = w.velocity()
-    ghost = w.ghost_rows(ghost_t0, nsteps) if w.bc == 1 else None
+    ghost = w.ghost_rows(ghost_t0, nsteps) if w.bc != 0 else None
     return step(p, w.initial(), a=a, ghost=ghost, dt=w.dt, nsteps=nsteps)
 
 

@@ -37,7 +37,10 @@ typedef struct {
     int32_t kx, ky;       /* elements per direction (ky = 1 in 1D) */
     int32_t n;            /* nodes per direction (order N = n - 1) */
     int32_t family;       /* 0 Gauss-Legendre, 1 Chebyshev-Gauss (eq. gaussquad) */
-    int32_t bc;           /* 0 periodic, 1 ghost values at the domain boundary */
+    int32_t bc;           /* 0 periodic, 1 ghost values at the domain boundary;  */
+                          /* 2D only: 2 periodic in x, ghost values on the       */
+                          /* bottom and top sides; 3 ghost values on the left    */
+                          /* and right sides, periodic in y                      */
     int32_t form;         /* 0 advective u_t + a.grad u = 0, 1 conservative (eq. 2.3) */
     int32_t rk;           /* tableau id, see rk_tableau() */
     int32_t cmask;        /* bit0 boundary, bit1 mass, bit2 energy */
@@ -546,34 +549,39 @@ typedef struct {
 
 static int ntr(const ctx* c) { return c->p->dim == 1 ? 2 : 4 * c->n; }
 
+/* whether the left/right (x) and bottom/top (y) sides of the domain wrap
+ * around to each other (otherwise their faces take ghost values) */
+static int periodic_x(const ora_params* p) { return p->bc == 0 || p->bc == 2; }
+static int periodic_y(const ora_params* p) { return p->bc == 0 || p->bc == 3; }
+
 /* element neighbours; -1 = outside (ghost) */
 static int nb_left(const ctx* c, int e)
 {
     const ora_params* p = c->p;
     int ex = e % p->kx, ey = e / p->kx;
     if (ex > 0) return e - 1;
-    return p->bc == 0 ? ey * p->kx + p->kx - 1 : -1;
+    return periodic_x(p) ? ey * p->kx + p->kx - 1 : -1;
 }
 static int nb_right(const ctx* c, int e)
 {
     const ora_params* p = c->p;
     int ex = e % p->kx, ey = e / p->kx;
     if (ex < p->kx - 1) return e + 1;
-    return p->bc == 0 ? ey * p->kx : -1;
+    return periodic_x(p) ? ey * p->kx : -1;
 }
 static int nb_down(const ctx* c, int e)
 {
     const ora_params* p = c->p;
     int ex = e % p->kx, ey = e / p->kx;
     if (ey > 0) return e - p->kx;
-    return p->bc == 0 ? (p->ky - 1) * p->kx + ex : -1;
+    return periodic_y(p) ? (p->ky - 1) * p->kx + ex : -1;
 }
 static int nb_up(const ctx* c, int e)
 {
     const ora_params* p = c->p;
     int ex = e % p->kx, ey = e / p->kx;
     if (ey < p->ky - 1) return e + p->kx;
-    return p->bc == 0 ? ex : -1;
+    return periodic_y(p) ? ex : -1;
 }
 
 /* reference coordinates of trace point t (layout of work.tr) */
@@ -1028,6 +1036,7 @@ int ora_step(const ora_params* p, const double* a, const double* div, const doub
     if (p->dim != 1 && p->dim != 2) return 1;
     if (p->n < 1 || p->n > 16 * (p->dim == 1 ? 4 : 1)) return 1;
     if (p->kx < 1 || p->ky < 1 || (p->dim == 1 && p->ky != 1)) return 1;
+    if (p->bc < 0 || p->bc > (p->dim == 1 ? 1 : 3)) return 1;
     if (want && nsteps != 1) return 1;
     /* 2D HARD: the rows after the boundary block are imposed inside
      * null(C_B), of dimension (n-2)^2 since C_B has rank 4n-4; more rows
@@ -1137,7 +1146,7 @@ int ora_step(const ora_params* p, const double* a, const double* div, const doub
         /* ghost rows hold boundary values at t0, t0 + dt, ...; this step runs
          * from row 'step' to row 'step + 1' (both clamped to the last row) */
         const double *g = NULL, *gn = NULL;
-        if (p->bc == 1 && ghost) {
+        if (p->bc != 0 && ghost) {
             g = ghost + (size_t)nghost * (step < ghost_rows ? step : ghost_rows - 1);
             gn = ghost + (size_t)nghost * (step + 1 < ghost_rows ? step + 1 : ghost_rows - 1);
         }

@@ -21,7 +21,7 @@ LIBPATH = os.path.join(_HERE, "libsl.so")
 
 SL_OK, SL_E_INVALID, SL_E_NOMEM, SL_E_DEVICE, SL_E_STATE, SL_E_CFL, SL_E_NONFINITE, SL_E_SINGULAR, SL_E_NOCONV = range(9)
 SL_NODES_GL, SL_NODES_CG = 0, 1
-SL_BC_PERIODIC, SL_BC_GHOST = 0, 1
+SL_BC_PERIODIC, SL_BC_GHOST, SL_BC_PERIODIC_X, SL_BC_PERIODIC_Y = 0, 1, 2, 3
 SL_FORM_ADVECTIVE, SL_FORM_CONSERVATIVE = 0, 1
 SL_PREC_FP64, SL_PREC_FP32_REFINED, SL_PREC_BF16_REFINED = 0, 1, 2
 SL_C_BOUNDARY, SL_C_MASS, SL_C_ENERGY = 1, 2, 4

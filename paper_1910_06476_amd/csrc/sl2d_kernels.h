@@ -180,7 +180,8 @@ __global__ void k_prep2d(int K, int has_div, int cons, const double* __restrict_
 // For edge point tt of element e (layout: left j, right j, bottom i, top i):
 // the neighbour across that face (-1 outside the domain), the matching edge
 // point in the neighbour, the ghost index, and whether e is the high side of
-// the face (its left or bottom face)
+// the face (its left or bottom face).  periodic: bit 0 the left and right
+// sides of the domain wrap onto each other, bit 1 the bottom and top sides.
 // ---------------------------------------------------------------------------
 template <int N>
 __device__ __forceinline__ void face_partner2(int e, int tt, int kx, int ky, int periodic, int& nbe, int& nbt,
@@ -191,19 +192,19 @@ __device__ __forceinline__ void face_partner2(int e, int tt, int kx, int ky, int
     const int KL = ky * N, KB = kx * N;
     switch (side) {
     case 0:
-        nbe = ex > 0 ? e - 1 : (periodic ? ey * kx + kx - 1 : -1);
+        nbe = ex > 0 ? e - 1 : ((periodic & 1) ? ey * kx + kx - 1 : -1);
         nbt = N + k; gidx = ey * N + k; high = true;
         break;
     case 1:
-        nbe = ex < kx - 1 ? e + 1 : (periodic ? ey * kx : -1);
+        nbe = ex < kx - 1 ? e + 1 : ((periodic & 1) ? ey * kx : -1);
         nbt = k; gidx = KL + ey * N + k; high = false;
         break;
     case 2:
-        nbe = ey > 0 ? e - kx : (periodic ? (ky - 1) * kx + ex : -1);
+        nbe = ey > 0 ? e - kx : ((periodic & 2) ? (ky - 1) * kx + ex : -1);
         nbt = 3 * N + k; gidx = 2 * KL + ex * N + k; high = true;
         break;
     default:
-        nbe = ey < ky - 1 ? e + kx : (periodic ? ex : -1);
+        nbe = ey < ky - 1 ? e + kx : ((periodic & 2) ? ex : -1);
         nbt = 2 * N + k; gidx = 2 * KL + KB + ex * N + k; high = false;
         break;
     }

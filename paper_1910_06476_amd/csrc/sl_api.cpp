@@ -279,7 +279,7 @@ Step2DArgs bucket_args(const sl_mesh* m, int b, double dt, const sl_step_opts& o
     B.kx = m->kx;
     B.ky = m->ky;
     B.K = m->bK[b];
-    B.periodic = 1;
+    B.periodic = 3;
     B.cons = m->form == SL_FORM_CONSERVATIVE;
     B.cmask = opt.constraints;
     B.mode = opt.mode;
@@ -663,7 +663,9 @@ sl_status sl_create_mesh(const sl_mesh_desc* d, sl_mesh** out)
     if (d->kx < 1 || d->ky < 1 || (d->dim == 1 && d->ky != 1)) return SL_E_INVALID;
     if ((int64_t)d->kx * d->ky > (1 << 26)) return SL_E_INVALID;
     if (d->nodes != SL_NODES_GL && d->nodes != SL_NODES_CG) return SL_E_INVALID;
-    if (d->bc != SL_BC_PERIODIC && d->bc != SL_BC_GHOST) return SL_E_INVALID;
+    if (d->bc != SL_BC_PERIODIC && d->bc != SL_BC_GHOST &&
+        !(d->dim == 2 && (d->bc == SL_BC_PERIODIC_X || d->bc == SL_BC_PERIODIC_Y)))
+        return SL_E_INVALID;
     if (d->form != SL_FORM_ADVECTIVE && d->form != SL_FORM_CONSERVATIVE) return SL_E_INVALID;
     if (d->precision != SL_PREC_FP64 &&
         !((d->precision == SL_PREC_FP32_REFINED || d->precision == SL_PREC_BF16_REFINED) && d->dim == 2))
@@ -753,7 +755,7 @@ sl_status sl_mesh_bytes(const sl_mesh_desc* d, int32_t ghost_rows, size_t* bytes
     const BufSizes z = buffer_sizes(d->dim, d->kx, d->ky, n);
     const size_t ng = d->dim == 1 ? 2 : (size_t)2 * n * (d->kx + d->ky);
     const size_t dbl = 3 * z.nf + z.nrec + 2 * z.nf * d->dim + 2 * z.nf + z.nvf + z.ntab + z.nstat +
-                       (d->bc == SL_BC_GHOST ? ng * ghost_rows : 0);
+                       (d->bc != SL_BC_PERIODIC ? ng * ghost_rows : 0);
     *bytes = dbl * sizeof(double) + (z.nflag + 1) * sizeof(int32_t);
     return SL_OK;
 }
@@ -780,7 +782,7 @@ sl_status sl_set_velocity(sl_mesh* m, const double* a, const double* div_a)
                  : launch_prep2d(m->n, m->K, div_a != nullptr, cons, m->aN, m->aM, m->divN, m->divM, m->tab, m->dx,
                                  m->dy, std::max(am[0], am[1]), m->vdeg_d, m->stream);
     if (!rc && m->dim == 2)
-        rc = launch_facevel2d(m->n, m->kx, m->ky, m->bc == SL_BC_PERIODIC, m->aN, m->tab,
+        rc = launch_facevel2d(m->n, m->kx, m->ky, periodic_mask(m->bc), m->aN, m->tab,
                               1e-12 * std::max(am[0], am[1]), m->vface, m->stream);
     int32_t vdeg = m->n - 1;
     if (rc || hipMemcpyAsync(&vdeg, m->vdeg_d, sizeof(int32_t), hipMemcpyDeviceToHost, m->stream) ||
@@ -802,7 +804,7 @@ int32_t sl_ghost_count(const sl_mesh* m)
 sl_status sl_set_ghost(sl_mesh* m, const double* g, int32_t nrows)
 {
     if (!m) return SL_E_INVALID;
-    if (m->bc != SL_BC_GHOST) return SL_E_STATE;
+    if (m->bc == SL_BC_PERIODIC) return SL_E_STATE;
     if (!g || nrows < 1) return SL_E_INVALID;
     const size_t cnt = (size_t)sl_ghost_count(m) * nrows;
     if (!all_finite(g, cnt)) return SL_E_NONFINITE;
@@ -855,7 +857,7 @@ sl_status sl_step(sl_mesh* m, double dt, int32_t nsteps, const sl_step_opts* o)
         return SL_E_INVALID;
     if (m->mixed && opt.iface != SL_IFACE_INTERP) return SL_E_INVALID;
     if (!m->has_velocity) return SL_E_STATE;
-    if (m->bc == SL_BC_GHOST && m->ghost_rows < 1) return SL_E_STATE;
+    if (m->bc != SL_BC_PERIODIC && m->ghost_rows < 1) return SL_E_STATE;
     // time-step restriction: particles may not cross the element-edge gap
     // dt <= gap dx / max|a| (the paper's condition admits equality; a relative
     // 1e-12 slack absorbs the rounding of dt computed at the limit)
@@ -881,7 +883,7 @@ sl_status sl_step(sl_mesh* m, double dt, int32_t nsteps, const sl_step_opts* o)
         B.aN = m->aN; B.aM = m->aM; B.divN = m->divN; B.divM = m->divM; B.vface = m->vface; B.tab = m->tab;
         B.rec = m->rec; B.phihat = m->phihat;
         B.flag_part = m->flag_part; B.stat_part = m->stat_part; B.nblk = m->nblocks; B.vdeg = m->vdeg;
-        B.kx = m->kx; B.ky = m->ky; B.K = m->K; B.periodic = m->bc == SL_BC_PERIODIC;
+        B.kx = m->kx; B.ky = m->ky; B.K = m->K; B.periodic = periodic_mask(m->bc);
         B.cons = m->form == SL_FORM_CONSERVATIVE; B.cmask = opt.constraints; B.mode = opt.mode;
         B.refine = 60;  // cap on defect-correction sweeps of the remap solve
         B.precision = m->precision;
@@ -896,7 +898,7 @@ sl_status sl_step(sl_mesh* m, double dt, int32_t nsteps, const sl_step_opts* o)
         B.invdx = 1.0 / m->dx; B.invdy = 1.0 / m->dy; B.dt = dt;
         B.vzero = 1e-12 * std::max(m->amax[0], m->amax[1]);
         for (int s = 0; s < nsteps; ++s) {
-            if (m->bc == SL_BC_GHOST) {
+            if (m->bc != SL_BC_PERIODIC) {
                 const long r0 = std::min<long>(m->ghost_step, m->ghost_rows - 1);
                 const long r1 = std::min<long>(m->ghost_step + 1, m->ghost_rows - 1);
                 B.gnow = m->ghost + r0 * sl_ghost_count(m);
@@ -955,7 +957,7 @@ sl_status sl_step(sl_mesh* m, double dt, int32_t nsteps, const sl_step_opts* o)
     static const double zero2[2] = {0.0, 0.0};
     (void)zero2;
     for (int s = 0; s < nsteps; ++s) {
-        if (m->bc == SL_BC_GHOST) {
+        if (m->bc != SL_BC_PERIODIC) {
             const long r0 = std::min<long>(m->ghost_step, m->ghost_rows - 1);
             const long r1 = std::min<long>(m->ghost_step + 1, m->ghost_rows - 1);
             A.gnow = m->ghost + r0 * sl_ghost_count(m);

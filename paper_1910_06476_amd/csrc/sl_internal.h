@@ -21,6 +21,14 @@ struct Tables {
     double Tinv[kMaxTableN * kMaxTableN];
 };
 
+// Periodicity of a boundary condition as a mask for the kernels: bit 0 the
+// left and right sides wrap, bit 1 the bottom and top sides (1D meshes use
+// bit 0 only).
+inline int periodic_mask(int bc)
+{
+    return bc == SL_BC_PERIODIC ? 3 : bc == SL_BC_PERIODIC_X ? 1 : bc == SL_BC_PERIODIC_Y ? 2 : 0;
+}
+
 bool node_rule(int family, int n, double* xi, double* w);
 bool invert(int n, const double* A, double* Ainv);
 bool build_tables(int family, int n, Tables* T);
@@ -106,6 +114,7 @@ struct Step2DArgs {
     int32_t* flag_part;    // [2][nblk]
     double* stat_part;     // [nblk][kStatSlots]
     int nblk, vdeg, rstride;
+    // periodic: mask of periodic_mask() (bit 0 x, bit 1 y)
     int kx, ky, K, periodic, cons, cmask, mode, refine, precision, targets, vol, emaxit;
     int iface;             // SL_IFACE_*: edge values by interpolation or backtracking
     double dx, dy, invdx, invdy, dt, vzero, etol;

@@ -152,10 +152,10 @@ sl_status sl_server_create(const sl_server_desc* d, sl_server** out)
 sl_status sl_server_submit(sl_server* s, const sl_request* q, int64_t* id)
 {
     if (!s || !q || !id || !q->mesh.u0 || !q->a || q->nsteps < 0 || !(q->dt > 0)) return SL_E_INVALID;
-    if (q->mesh.bc == SL_BC_GHOST && (!q->ghost || q->ghost_rows < 1)) return SL_E_INVALID;
+    if (q->mesh.bc != SL_BC_PERIODIC && (!q->ghost || q->ghost_rows < 1)) return SL_E_INVALID;
     std::unique_ptr<Request> r(new (std::nothrow) Request());
     if (!r) return SL_E_NOMEM;
-    sl_status rc = sl_mesh_bytes(&q->mesh, q->mesh.bc == SL_BC_GHOST ? q->ghost_rows : 0, &r->bytes);
+    sl_status rc = sl_mesh_bytes(&q->mesh, q->mesh.bc != SL_BC_PERIODIC ? q->ghost_rows : 0, &r->bytes);
     if (rc != SL_OK) return rc;
     if (r->bytes > s->budget) return SL_E_NOMEM;  // could never be admitted
     const int n = q->mesh.order + 1;
@@ -165,7 +165,7 @@ sl_status sl_server_submit(sl_server* s, const sl_request* q, int64_t* id)
         r->u0.assign(q->mesh.u0, q->mesh.u0 + nf);
         r->a.assign(q->a, q->a + nf * q->mesh.dim);
         if (q->div_a) r->div.assign(q->div_a, q->div_a + nf);
-        if (q->mesh.bc == SL_BC_GHOST) {
+        if (q->mesh.bc != SL_BC_PERIODIC) {
             const size_t ng = q->mesh.dim == 1 ? 2 : (size_t)2 * n * (q->mesh.kx + q->mesh.ky);
             r->ghost.assign(q->ghost, q->ghost + ng * (size_t)q->ghost_rows);
             r->ghost_rows = q->ghost_rows;

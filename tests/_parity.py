@@ -24,7 +24,7 @@ def run_gpu(w, phi0=None, nsteps=None, precision=0, ghost=None, **over):
     try:
         a, _ = w.velocity()
         m.set_velocity(a)
-        if w.bc == W.GHOST:
+        if w.bc != W.PERIODIC:
             m.set_ghost(w.ghost_rows(0.0, nsteps) if ghost is None else ghost)
         m.step(w.dt, nsteps, **opts_dict(w, **over))
         rc, out, st = m.read()
@@ -53,7 +53,7 @@ def run_oracle(w, phi0=None, nsteps=None, ghost=None, want=None, **over):
     p = oracle.params_from(w, **kw)
     a, _ = w.velocity()
     g = None
-    if w.bc == W.GHOST:
+    if w.bc != W.PERIODIC:
         g = w.ghost_rows(0.0, nsteps) if ghost is None else ghost
     return oracle.step(p, u0, a=a, ghost=g, dt=w.dt, nsteps=nsteps, want=want)
 

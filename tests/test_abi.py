@@ -67,7 +67,8 @@ def test_status_strings(sl):
 
 
 @pytest.mark.parametrize("bad", [
-    dict(dim=3), dict(order=0), dict(order=17), dict(kx=0), dict(ky=2), dict(nodes=5), dict(bc=3),
+    dict(dim=3), dict(order=0), dict(order=17), dict(kx=0), dict(ky=2), dict(nodes=5), dict(bc=2), dict(bc=3),
+    dict(bc=4),
     dict(form=2), dict(precision=1), dict(precision=2), dict(precision=3), dict(x1=0.0),
 ])
 def test_create_mesh_validates_before_touching_the_device(sl, bad):

@@ -37,7 +37,7 @@ def _case(**kw):
 @pytest.mark.parametrize("cmask", [B | M, B | E, B | M | E])
 @pytest.mark.parametrize("mode", [W.HARD, W.SOFT])
 @pytest.mark.parametrize("form", [W.ADVECTIVE, W.CONSERVATIVE])
-@pytest.mark.parametrize("bc", [W.PERIODIC, W.GHOST])
+@pytest.mark.parametrize("bc", [W.PERIODIC, W.GHOST, W.PERIODIC_X, W.PERIODIC_Y])
 def test_mass_energy_matrix_parity(cmask, mode, form, bc):
     w = _case(cmask=cmask, mode=mode, form=form, bc=bc)
     announce(f"2d me cmask={cmask} mode={mode} form={form} bc={bc}")

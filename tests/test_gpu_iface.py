@@ -78,7 +78,7 @@ def test_backtrack_1d_orders_and_sizes(n, K):
     assert_parity(w, g, o)
 
 
-@pytest.mark.parametrize("bc", [W.PERIODIC, W.GHOST])
+@pytest.mark.parametrize("bc", [W.PERIODIC, W.GHOST, W.PERIODIC_X, W.PERIODIC_Y])
 @pytest.mark.parametrize("form", [W.ADVECTIVE, W.CONSERVATIVE])
 @pytest.mark.parametrize("cmask", [W.BOUNDARY, W.BOUNDARY | W.MASS])
 @pytest.mark.parametrize("n", [3, 5, 9])

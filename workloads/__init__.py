@@ -30,6 +30,9 @@ import numpy as np
 
 GL, CG = 0, 1
 PERIODIC, GHOST = 0, 1
+# 2D: periodic in x with ghost values on the bottom and top sides, or the
+# other way round
+PERIODIC_X, PERIODIC_Y = 2, 3
 ADVECTIVE, CONSERVATIVE = 0, 1
 HARD, SOFT = 0, 1
 BOUNDARY, MASS, ENERGY = 1, 2, 4
