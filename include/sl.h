@@ -180,7 +180,8 @@ sl_status sl_set_velocity(sl_mesh* m, const double* a, const double* div_a);
  * step reads rows i and i+1 (clamped to the last row; nrows = 1 is a steady
  * ghost).  Row layout -- 1D: [left, right]; 2D: left edge (ky * n values,
  * by iy then node j), right edge (ky * n), bottom edge (kx * n, by ix then
- * node i), top edge (kx * n); the values of periodic sides are not read.
+ * node i), top edge (kx * n); the values of periodic sides are neither
+ * read nor checked.
  * Errors: SL_E_STATE (periodic mesh),
  * SL_E_INVALID, SL_E_NOMEM. */
 sl_status sl_set_ghost(sl_mesh* m, const double* g, int32_t nrows);

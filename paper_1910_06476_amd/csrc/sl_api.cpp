@@ -806,8 +806,14 @@ sl_status sl_set_ghost(sl_mesh* m, const double* g, int32_t nrows)
     if (!m) return SL_E_INVALID;
     if (m->bc == SL_BC_PERIODIC) return SL_E_STATE;
     if (!g || nrows < 1) return SL_E_INVALID;
-    const size_t cnt = (size_t)sl_ghost_count(m) * nrows;
-    if (!all_finite(g, cnt)) return SL_E_NONFINITE;
+    const size_t per = (size_t)sl_ghost_count(m), cnt = per * nrows;
+    // the values that are read must be finite: every side of a GHOST mesh,
+    // the bottom and top sides of SL_BC_PERIODIC_X, the left and right
+    // sides of SL_BC_PERIODIC_Y (row layout: left, right, bottom, top)
+    const size_t lr = m->dim == 2 ? (size_t)2 * m->ky * m->n : per;
+    const size_t lo = m->bc == SL_BC_PERIODIC_X ? lr : 0, hi = m->bc == SL_BC_PERIODIC_Y ? lr : per;
+    for (int32_t r = 0; r < nrows; ++r)
+        if (!all_finite(g + r * per + lo, hi - lo)) return SL_E_NONFINITE;
     if (hipStreamSynchronize(m->stream)) return SL_E_DEVICE;
     dfree(m->ghost);
     if (!dalloc(&m->ghost, cnt)) { m->ghost_rows = 0; return SL_E_NOMEM; }
