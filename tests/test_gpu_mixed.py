@@ -181,3 +181,53 @@ def test_mixed_statistics_and_validation():
         P.Mesh(2, 2, 2, 3, np.zeros(4 * 16), bc=P.SL_BC_GHOST, orders=[3, 3, 3, 3])
     with pytest.raises(P.SLError):  # order 13 is beyond the 2D limit
         P.Mesh(2, 2, 2, 3, np.zeros(3 * 16 + 14 * 14), orders=[3, 3, 3, 13])
+
+
+def test_distinct_meshes_step_concurrently():
+    """Distinct meshes may be stepped from several host threads at once (the
+    C-ABI's thread-safety rule): a mixed-order mesh (graph capture per
+    thread), a uniform 2D mesh and a 1D mesh, each stepped in its own thread,
+    give bit for bit the results of the same meshes stepped one after
+    another."""
+    import threading
+    import paper_1910_06476_amd as P
+    from _parity import run_gpu
+    wm = _case(8, 6, (4, 6, 8, 12), seed=4, nsteps=6)
+    w2 = W.c3(kx=12, n=7, nsteps=6)
+    w1 = W.c2(K=300, nsteps=6)
+    announce("concurrent meshes")
+
+    def mixed():
+        g, st, rc = _gpu(wm)
+        return g
+
+    def uni2():
+        return run_gpu(w2)[0]
+
+    def uni1():
+        return run_gpu(w1)[0]
+
+    jobs = [mixed, uni2, uni1]
+    ref = [f() for f in jobs]
+    out = [None] * len(jobs)
+    errs = []
+
+    def runner(i):
+        try:
+            for _ in range(3):
+                r = jobs[i]()
+                if out[i] is None:
+                    out[i] = r
+                elif not np.array_equal(out[i], r):
+                    errs.append(i)
+        except Exception as e:  # reported below
+            errs.append(repr(e))
+
+    th = [threading.Thread(target=runner, args=(i,)) for i in range(len(jobs))]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    assert not errs, errs
+    for r, o in zip(ref, out):
+        assert np.array_equal(r, o)
