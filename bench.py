@@ -368,6 +368,45 @@ def bench_serve(args, torch, P, W):
     print(json.dumps(out))
 
 
+def bench_c1(args, torch, P, W, stream):
+    """The small 1D configuration: u_t + u_x = 0 on [0,2] periodic, K=16,
+    order 8 (144 DOF), RK4, boundary rows, dt = 1.6516e-3.  Far too small to
+    load the GPU: what it measures is the cost of a step's launches, as a
+    stream of steps (one sl_step of `steps` steps) and as the served latency
+    of single steps.  No roofline claim is made for it."""
+    w = W.c1()
+    m = P.from_workload(w, stream=stream.cuda_stream)
+    opts = dict(rk=w.rk, constraints=w.cmask, mode=w.mode)
+    m.step(w.dt, args.warmup, **opts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    m.step(w.dt, args.steps, **opts)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    rc, phi, st = m.read()
+    T = (args.warmup + args.steps) * w.dt
+    l2 = w.l2_error(phi, T)
+    lat = step_latency(torch, m, w.dt, opts, samples=min(200, max(10, args.steps)))
+    P.sl_set_profiling(m.h, True)
+    m.step(w.dt, 50, **opts)
+    t_adv, c_adv = P.sl_kernel_time(m.h, P.KER_ADV1D)
+    t_con, c_con = P.sl_kernel_time(m.h, P.KER_CON1D)
+    P.sl_set_profiling(m.h, False)
+    m.close()
+    out = {
+        "metric": METRIC, "value": w.dofs * args.steps / el, "unit": "DOF-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": el / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "1D u_t+u_x=0 on [0,2] periodic, K=16, order 8 (9 GL nodes), u0=sin(pi x), RK4, "
+                               "boundary HARD, dt=0.2*gap*dx", "K": w.K, "n": w.n, "dofs": w.dofs, "dt": w.dt},
+        "l2_error": l2, "l2_time": T, "status": P.status_string(rc),
+        "step_latency": lat,
+        "kernels_us": {"sl1d_advect": t_adv / max(c_adv, 1) * 1e3, "sl1d_constrain": t_con / max(c_con, 1) * 1e3},
+        "roofline": None,
+    }
+    print(json.dumps(out))
+
+
 def bench_c2bw(args, torch, P, W, stream):
     """The HBM side of the 1D step: the C2 problem (order 16, RK4, the same
     velocity and initial data) with boundary rows only, on K = 2^22 elements
@@ -436,8 +475,9 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--workload", choices=["c2", "c2bw", "c3", "c4", "serve"], default="c2",
-                    help="c2: the headline 1D configuration (default); c2bw: the C2 problem with boundary "
+    ap.add_argument("--workload", choices=["c1", "c2", "c2bw", "c3", "c4", "serve"], default="c2",
+                    help="c1: the small 1D configuration (144 DOF), a launch-latency probe; "
+                         "c2: the headline 1D configuration (default); c2bw: the C2 problem with boundary "
                          "rows only on K=2^22 elements, a probe of the HBM side; "
                          "c3: the 2D rotation configuration; "
                          "c4: the 2D mixed-order batch; "
@@ -481,6 +521,8 @@ def main():
         return bench_c4(args, torch, P, W, stream)
     if args.workload == "c2bw":
         return bench_c2bw(args, torch, P, W, stream)
+    if args.workload == "c1":
+        return bench_c1(args, torch, P, W, stream)
     w = W.c2()
     m = P.from_workload(w, stream=stream.cuda_stream)
     opts = dict(rk=w.rk, constraints=w.cmask, mode=w.mode, energy_maxit=w.energy_maxit, energy_tol=w.energy_tol)

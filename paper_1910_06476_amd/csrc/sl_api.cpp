@@ -960,8 +960,6 @@ sl_status sl_step(sl_mesh* m, double dt, int32_t nsteps, const sl_step_opts* o)
         }
         if (!invert(3, G3, A.g3i)) return SL_E_INVALID;
     }
-    static const double zero2[2] = {0.0, 0.0};
-    (void)zero2;
     for (int s = 0; s < nsteps; ++s) {
         if (m->bc != SL_BC_PERIODIC) {
             const long r0 = std::min<long>(m->ghost_step, m->ghost_rows - 1);

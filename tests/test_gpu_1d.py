@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from _parity import announce, assert_parity, rel_l2, run_gpu, run_oracle
+from _parity import announce, assert_parity, opts_dict, rel_l2, run_gpu, run_oracle
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-12
@@ -225,3 +225,30 @@ def test_linear_velocity_closed_form(rk, form):
     g, st, rc = run_gpu(w, nsteps=1, ghost=ghost)
     assert rc == 0 and st.flags == 0
     np.testing.assert_allclose(g, expect, rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("nsteps", [2, 5, 6])
+def test_multistep_call_equals_single_steps(nsteps):
+    """Several steps in one sl_step call (counts odd and even, so a call can
+    start from either ping-pong buffer) equal one sl_step per step: the
+    field and the statistics, bit for bit."""
+    import paper_1910_06476_amd as P
+    w = W.c2(K=301, nsteps=nsteps)
+    announce(f"1d multistep vs single steps nsteps={nsteps}")
+    opts = opts_dict(w)
+    calls = [nsteps, 3, 4, 2]
+    mg = P.from_workload(w)
+    me = P.from_workload(w)
+    try:
+        for c in calls:
+            mg.step(w.dt, c, **opts)
+            for _ in range(c):
+                me.step(w.dt, 1, **opts)
+        rg, g, sg = mg.read()
+        re_, e, se = me.read()
+    finally:
+        mg.close()
+        me.close()
+    assert np.array_equal(g, e)
+    assert (rg, sg.steps, sg.flags, sg.max_picard) == (re_, se.steps, se.flags, se.max_picard)
+    assert sg.steps == sum(calls)

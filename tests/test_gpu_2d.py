@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from _parity import announce, assert_parity, rel_l2, run_gpu, run_oracle
+from _parity import announce, assert_parity, opts_dict, rel_l2, run_gpu, run_oracle
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-12
@@ -251,3 +251,28 @@ def test_periodic_in_one_direction(bc, deg, cmask, mode):
     assert_parity(w, gp, o, solves=w.nsteps * 6)
     ex = w.exact_at(w.nsteps * w.dt)
     np.testing.assert_allclose(gp, ex, rtol=0, atol=1e-11 * max(1.0, np.abs(ex).max()))
+
+
+@pytest.mark.parametrize("nsteps", [2, 5])
+def test_multistep_call_equals_single_steps(nsteps):
+    """2D periodic mesh with mass and energy rows: several steps in one
+    sl_step call equal one sl_step per step, bit for bit."""
+    import paper_1910_06476_amd as P
+    w = _swirl_case(5, 4, 6, nsteps=nsteps, cmask=W.BOUNDARY | W.MASS | W.ENERGY, energy_tol=0.0, energy_maxit=3)
+    announce(f"2d multistep vs single steps nsteps={nsteps}")
+    opts = opts_dict(w)
+    calls = [nsteps, 3, 2]
+    mg = P.from_workload(w)
+    me = P.from_workload(w)
+    try:
+        for c in calls:
+            mg.step(w.dt, c, **opts)
+            for _ in range(c):
+                me.step(w.dt, 1, **opts)
+        rg, g, sg = mg.read()
+        re_, e, se = me.read()
+    finally:
+        mg.close()
+        me.close()
+    assert np.array_equal(g, e)
+    assert (rg, sg.steps, sg.flags, sg.max_picard) == (re_, se.steps, se.flags, se.max_picard)
