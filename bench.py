@@ -90,6 +90,21 @@ def measured_traffic(kernel: str, source: str = "sl1d.hip", profile: str = "sl1d
     return None
 
 
+def host_cpu():
+    """The host's CPU model and logical CPU count, printed with the oracle
+    baseline."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count()}
+
+
 def cpu_baseline(w, budget_s: float = 12.0):
     import oracle
     import workloads as W
@@ -109,7 +124,7 @@ def cpu_baseline(w, budget_s: float = 12.0):
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": w.dofs * steps / el, "unit": "DOF-updates/s", "cores": cores, "kind": "oracle",
             "sample": f"full mesh (K={w.K}, n={w.n}), {steps} steps after 1 warm-up step, "
-                      f"{el:.1f} s, OpenMP threads={cores}"}
+                      f"{el:.1f} s, OpenMP threads={cores}", **host_cpu()}
 
 
 def cpu_baseline_mixed(w, budget_s: float = 12.0):
@@ -132,7 +147,7 @@ def cpu_baseline_mixed(w, budget_s: float = 12.0):
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": w.dofs * steps / el, "unit": "DOF-updates/s", "cores": cores, "kind": "oracle",
             "sample": f"a {w.kx}x{w.ky} mesh of the same recipe (orders {{4,6,8,12}} by seed, {w.dofs} DOF), "
-                      f"{steps} steps after 1 warm-up step, {el:.1f} s, OpenMP threads={cores}"}
+                      f"{steps} steps after 1 warm-up step, {el:.1f} s, OpenMP threads={cores}", **host_cpu()}
 
 
 def advect2d_flops_per_element(n: int, s: int, sweeps: float, vel_terms: int) -> float:
