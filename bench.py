@@ -105,6 +105,28 @@ def host_cpu():
     return {"cpu_model": model, "nproc": os.cpu_count()}
 
 
+def single_thread_rate(run, dofs: int, est_s: float, limit_s: float = 15.0):
+    """DOF-updates/s of one oracle step on one OpenMP thread (the OpenMP
+    runtime's thread count is set to 1 and restored); None when that step
+    would take longer than limit_s (est_s: the all-core step time times the
+    thread count) or the runtime cannot be reached."""
+    import ctypes
+    if est_s > limit_s:
+        return None
+    try:
+        gomp = ctypes.CDLL("libgomp.so.1")
+    except OSError:
+        return None
+    prev = gomp.omp_get_max_threads()
+    gomp.omp_set_num_threads(1)
+    try:
+        t0 = time.perf_counter()
+        run()
+        return dofs / (time.perf_counter() - t0)
+    finally:
+        gomp.omp_set_num_threads(prev)
+
+
 def cpu_baseline(w, budget_s: float = 12.0):
     import oracle
     import workloads as W
@@ -122,7 +144,11 @@ def cpu_baseline(w, budget_s: float = 12.0):
     oracle.step(p, phi, a=a, ghost=g, dt=w.dt, nsteps=steps)
     el = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    g1 = w.ghost_rows(0.0, 1) if ghost else None
+    one_thread = single_thread_rate(lambda: oracle.step(p, phi, a=a, ghost=g1, dt=w.dt, nsteps=1), w.dofs,
+                                    el / steps * cores)
     return {"value": w.dofs * steps / el, "unit": "DOF-updates/s", "cores": cores, "kind": "oracle",
+            "single_thread_value": one_thread,
             "sample": f"full mesh (K={w.K}, n={w.n}), {steps} steps after 1 warm-up step, "
                       f"{el:.1f} s, OpenMP threads={cores}", **host_cpu()}
 
@@ -145,7 +171,10 @@ def cpu_baseline_mixed(w, budget_s: float = 12.0):
     oracle.step_mixed(p, w.orders, phi, a=a, dt=w.dt, nsteps=steps)
     el = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    one_thread = single_thread_rate(lambda: oracle.step_mixed(p, w.orders, phi, a=a, dt=w.dt, nsteps=1), w.dofs,
+                                    el / steps * cores)
     return {"value": w.dofs * steps / el, "unit": "DOF-updates/s", "cores": cores, "kind": "oracle",
+            "single_thread_value": one_thread,
             "sample": f"a {w.kx}x{w.ky} mesh of the same recipe (orders {{4,6,8,12}} by seed, {w.dofs} DOF), "
                       f"{steps} steps after 1 warm-up step, {el:.1f} s, OpenMP threads={cores}", **host_cpu()}
 
