@@ -866,6 +866,9 @@ __global__ __launch_bounds__(kBlock2) void k_constrain2d(Step2DArgs A)
         if (bnd) {
             for (int tt = p; inblk && tt < 4 * N; tt += ND) {
                 double z = 0.0;
+                // a partial unroll: the loads of a full one held 126 VGPRs
+                // (four waves per SIMD), this 68 (seven)
+#pragma unroll 8
                 for (int q = 0; q < 4 * N; ++q) z = fma(s_q[tt * 4 * N + q], s_rb[slot][q], z);
                 s_d[slot][tt] = z;
             }
@@ -1039,6 +1042,7 @@ __global__ __launch_bounds__(kBlock2) void k_constrain2d_me(Step2DArgs A)
         __syncthreads();
         for (int tt = p; inblk && tt < NB; tt += ND) {
             double z = 0.0;
+#pragma unroll 8
             for (int c = 0; c < NB; ++c) z = fma(s_q[tt * NB + c], s_tr[slot][c], z);
             s_w[slot][tt] = z;
         }
@@ -1318,6 +1322,7 @@ __global__ __launch_bounds__(kBlock2) void k_constrain2d_mixed(Step2DArgs A)
         double phi = ph;
         for (int tt = p; inblk && tt < NB; tt += ND) {
             double z = 0.0;
+#pragma unroll 8
             for (int q = 0; q < NB; ++q) z = fma(s_q[tt * NB + q], s_rb[slot][q], z);
             s_d[slot][tt] = z;
         }
