@@ -311,9 +311,9 @@ template <int N> struct Off {
 // ---------------------------------------------------------------------------
 template <int N>
 __global__ void k_prep1d(int K, int periodic, int has_div, const double* __restrict__ aN, double* __restrict__ aM,
-                         double* __restrict__ divN, double* __restrict__ divM, double* __restrict__ vface,
-                         const double* __restrict__ tab, double invdx, int cons, double vscale,
-                         int* __restrict__ vdeg)
+                         double* __restrict__ divN, double* __restrict__ divM, double* __restrict__ aM4,
+                         double* __restrict__ divM4, double* __restrict__ vface, const double* __restrict__ tab,
+                         double invdx, int cons, double vscale, int* __restrict__ vdeg)
 {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= K) return;
@@ -327,7 +327,9 @@ __global__ void k_prep1d(int K, int periodic, int has_div, const double* __restr
 #pragma unroll
         for (int j = 0; j < N; ++j) c = fma(tab[O::TINV + k * N + j], a[j], c);
         aM[(size_t)e * N + k] = c;
+        if (k < 4) aM4[(size_t)e * 4 + k] = c;
     }
+    for (int k = N; k < 4; ++k) aM4[(size_t)e * 4 + k] = 0.0;
 #pragma unroll
     for (int i = 0; i < N; ++i) {
         if (!has_div) {
@@ -346,7 +348,9 @@ __global__ void k_prep1d(int K, int periodic, int has_div, const double* __restr
 #pragma unroll
         for (int j = 0; j < N; ++j) c = fma(tab[O::TINV + k * N + j], dv[j], c);
         divM[(size_t)e * N + k] = c;
+        if (k < 4) divM4[(size_t)e * 4 + k] = c;
     }
+    for (int k = N; k < 4; ++k) divM4[(size_t)e * 4 + k] = 0.0;
     // effective degree of the velocity (and divergence) series
     {
         double c[N], cdv[N];
@@ -438,9 +442,12 @@ __global__ __launch_bounds__(kBlock) void k_advect1d(Step1DArgs A)
         if (A.targets || CONS) dv_i = A.divN[g];
     }
     if (inblk && node) {
+        // a series of at most four terms reads the contiguous [K][4] copies:
+        // whole lines of used coefficients instead of a few from each row
         const bool used = live && i < NA;
-        s_a[slot][i] = used ? A.aM[g] : 0.0;
-        if (CONS) s_d[slot][i] = used ? A.divM[g] : 0.0;
+        const size_t g4 = (size_t)(live ? e : 0) * 4 + (i < 4 ? i : 0);
+        s_a[slot][i] = used ? (MONO ? A.aM4[g4] : A.aM[g]) : 0.0;
+        if (CONS) s_d[slot][i] = used ? (MONO ? A.divM4[g4] : A.divM[g]) : 0.0;
         s_p[slot][i] = phi_i;
     }
     const bool bt = A.iface == SL_IFACE_BACKTRACK;  // edge values by backtracking (eq. 4.11)
@@ -1004,11 +1011,12 @@ __global__ __launch_bounds__(kConBlock) void k_constrain1d(Step1DArgs A)
 
 template <int N>
 int launch_prep_n(int K, int periodic, int has_div, const double* aN, double* aM, double* divN, double* divM,
-                  double* vface, const double* tab, double dx, int cons, double vscale, int* vdeg, hipStream_t s)
+                  double* aM4, double* divM4, double* vface, const double* tab, double dx, int cons, double vscale,
+                  int* vdeg, hipStream_t s)
 {
     const int bs = 128;
     hipLaunchKernelGGL(k_prep1d<N>, dim3((K + bs - 1) / bs), dim3(bs), 0, s, K, periodic, has_div, aN, aM, divN,
-                       divM, vface, tab, 1.0 / dx, cons, vscale, vdeg);
+                       divM, aM4, divM4, vface, tab, 1.0 / dx, cons, vscale, vdeg);
     return hipGetLastError() == hipSuccess ? 0 : 1;
 }
 
@@ -1057,10 +1065,11 @@ int blocks1d(int n, int K)
     return a > c ? a : c;
 }
 
-#define PREP_CALL(N) launch_prep_n<N>(K, periodic, has_div, aN, aM, divN, divM, vface, tab, dx, cons, vscale, vdeg, s)
+#define PREP_CALL(N) \
+    launch_prep_n<N>(K, periodic, has_div, aN, aM, divN, divM, aM4, divM4, vface, tab, dx, cons, vscale, vdeg, s)
 int launch_prep1d(int n, int K, int periodic, int has_div, const double* aN, double* aM, double* divN,
-                  double* divM, double* vface, const double* tab, double dx, int cons, double vscale, int* vdeg,
-                  hipStream_t s)
+                  double* divM, double* aM4, double* divM4, double* vface, const double* tab, double dx, int cons,
+                  double vscale, int* vdeg, hipStream_t s)
 {
     switch (n) {
     case 2: return PREP_CALL(2); case 3: return PREP_CALL(3); case 4: return PREP_CALL(4);

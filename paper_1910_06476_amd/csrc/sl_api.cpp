@@ -111,6 +111,7 @@ bool dalloc(T** p, size_t count)
 // element counts of a mesh's device buffers (the single place that sizes them)
 struct BufSizes {
     size_t nf, nrec, nvf, ntab, nstat, nflag;
+    size_t ncoef;  // velocity coefficients: dim * nf, and in 1D the [K][4] copies of aM and divM after them
     int nblocks;
 };
 BufSizes buffer_sizes(int dim, int kx, int ky, int n)
@@ -125,6 +126,7 @@ BufSizes buffer_sizes(int dim, int kx, int ky, int n)
     z.ntab = (size_t)tab_offsets(dim, n).total;
     z.nstat = (size_t)z.nblocks * kStatSlots;
     z.nflag = (size_t)2 * z.nblocks;
+    z.ncoef = z.nf * dim + (dim == 1 ? 8 * K : 0);
     return z;
 }
 
@@ -695,7 +697,7 @@ sl_status sl_create_mesh(const sl_mesh_desc* d, sl_mesh** out)
     const BufSizes z = buffer_sizes(m->dim, m->kx, m->ky, n);
     m->nblocks = z.nblocks;
     bool ok = dalloc(&m->phi, z.nf) && dalloc(&m->phi2, z.nf) && dalloc(&m->phihat, z.nf) &&
-              dalloc(&m->rec, z.nrec) && dalloc(&m->aN, z.nf * m->dim) && dalloc(&m->aM, z.nf * m->dim) &&
+              dalloc(&m->rec, z.nrec) && dalloc(&m->aN, z.nf * m->dim) && dalloc(&m->aM, z.ncoef) &&
               dalloc(&m->divN, z.nf) && dalloc(&m->divM, z.nf) && dalloc(&m->vface, z.nvf) &&
               dalloc(&m->tab, z.ntab) && dalloc(&m->stat_part, z.nstat) && dalloc(&m->flag_part, z.nflag) &&
               dalloc(&m->vdeg_d, 1);
@@ -754,7 +756,7 @@ sl_status sl_mesh_bytes(const sl_mesh_desc* d, int32_t ghost_rows, size_t* bytes
     if ((int64_t)d->kx * d->ky > (1 << 26)) return SL_E_INVALID;
     const BufSizes z = buffer_sizes(d->dim, d->kx, d->ky, n);
     const size_t ng = d->dim == 1 ? 2 : (size_t)2 * n * (d->kx + d->ky);
-    const size_t dbl = 3 * z.nf + z.nrec + 2 * z.nf * d->dim + 2 * z.nf + z.nvf + z.ntab + z.nstat +
+    const size_t dbl = 3 * z.nf + z.nrec + z.nf * d->dim + z.ncoef + 2 * z.nf + z.nvf + z.ntab + z.nstat +
                        (d->bc != SL_BC_PERIODIC ? ng * ghost_rows : 0);
     *bytes = dbl * sizeof(double) + (z.nflag + 1) * sizeof(int32_t);
     return SL_OK;
@@ -777,8 +779,8 @@ sl_status sl_set_velocity(sl_mesh* m, const double* a, const double* div_a)
     const int cons = m->form == SL_FORM_CONSERVATIVE;
     int rc = m->dim == 1
                  ? launch_prep1d(m->n, m->K, m->bc == SL_BC_PERIODIC, div_a != nullptr, m->aN, m->aM, m->divN,
-                                 m->divM, m->vface, m->tab, m->dx, cons, std::max(am[0], am[1]), m->vdeg_d,
-                                 m->stream)
+                                 m->divM, m->aM + (size_t)m->K * m->n, m->aM + (size_t)m->K * (m->n + 4), m->vface,
+                                 m->tab, m->dx, cons, std::max(am[0], am[1]), m->vdeg_d, m->stream)
                  : launch_prep2d(m->n, m->K, div_a != nullptr, cons, m->aN, m->aM, m->divN, m->divM, m->tab, m->dx,
                                  m->dy, std::max(am[0], am[1]), m->vdeg_d, m->stream);
     if (!rc && m->dim == 2)
@@ -933,6 +935,8 @@ sl_status sl_step(sl_mesh* m, double dt, int32_t nsteps, const sl_step_opts* o)
     std::memset(&A, 0, sizeof(A));
     rk_tableau(opt.rk, &A.rk);
     A.aN = m->aN; A.aM = m->aM; A.divN = m->divN; A.divM = m->divM; A.vface = m->vface; A.tab = m->tab;
+    A.aM4 = m->aM + (size_t)m->K * m->n;
+    A.divM4 = m->aM + (size_t)m->K * (m->n + 4);
     A.rec = m->rec; A.phihat = m->phihat;
     A.flag_part = m->flag_part; A.stat_part = m->stat_part; A.nblk = m->nblocks; A.vdeg = m->vdeg;
     A.K = m->K; A.periodic = m->bc == SL_BC_PERIODIC; A.cons = m->form == SL_FORM_CONSERVATIVE;

@@ -70,6 +70,8 @@ struct Step1DArgs {
     const double* aM;      // Chebyshev coefficients of the velocity
     const double* divN;    // nodal divergence
     const double* divM;    // Chebyshev coefficients of the divergence
+    const double* aM4;     // [K][4] the first four of aM, contiguous (a short series reads only these)
+    const double* divM4;   // [K][4] the first four of divM
     const double* vface;   // [K+1] face velocity
     const double* tab;
     const double* gnow;    // ghost row at t^n (2 values) or null
@@ -90,8 +92,8 @@ struct Step1DArgs {
 // vscale: mesh-wide max |a|, the floor of the noise threshold of the
 // velocity series' effective degree
 int launch_prep1d(int n, int K, int periodic, int has_div, const double* aN, double* aM, double* divN,
-                  double* divM, double* vface, const double* tab, double dx, int cons, double vscale, int* vdeg,
-                  hipStream_t s);
+                  double* divM, double* aM4, double* divM4, double* vface, const double* tab, double dx, int cons,
+                  double vscale, int* vdeg, hipStream_t s);
 int launch_advect1d(int n, const Step1DArgs& A, hipStream_t s);
 int launch_constrain1d(int n, const Step1DArgs& A, hipStream_t s);
 int blocks1d(int n, int K);
