@@ -91,7 +91,9 @@ def test_orders_parity(n):
 @pytest.mark.parametrize("K", [1, 2, 3, 14, 15, 16, 31, 47, 301])
 @pytest.mark.parametrize("bc", [W.PERIODIC, W.GHOST])
 def test_ragged_sizes_parity(K, bc):
-    """K around multiples of the 15 elements a 256-lane block holds at n=17."""
+    """K around the 14 elements a 256-lane advect block holds at n=17 (18
+    lanes each) and the 32 a constrain wave holds, and a few larger ragged
+    counts."""
     w = _case(n=17, K=K, bc=bc, cmask=W.BOUNDARY | W.MASS | W.ENERGY)
     announce(f"ragged K={K} bc={bc}")
     g, st, rc = run_gpu(w)
@@ -252,3 +254,26 @@ def test_multistep_call_equals_single_steps(nsteps):
     assert np.array_equal(g, e)
     assert (rg, sg.steps, sg.flags, sg.max_picard) == (re_, se.steps, se.flags, se.max_picard)
     assert sg.steps == sum(calls)
+
+
+@pytest.mark.parametrize("dim", [1, 2])
+def test_zero_steps_leave_the_field(dim):
+    """sl_step with nsteps = 0 launches nothing: the field reads back as
+    given, bit for bit, with no steps counted and no flags; a negative count
+    is rejected."""
+    import paper_1910_06476_amd as P
+    w = W.c2(K=40) if dim == 1 else W.c3(kx=5, n=6)
+    announce(f"zero steps {dim}D")
+    m = P.from_workload(w)
+    try:
+        if w.bc != W.PERIODIC:
+            m.set_ghost(w.ghost_rows(0.0, 2))
+        m.step(w.dt, 0, **opts_dict(w))
+        rc, out, st = m.read()
+        assert rc == 0 and st.steps == 0 and st.flags == 0
+        assert np.array_equal(out, w.initial())
+        with pytest.raises(P.SLError) as e:
+            m.step(w.dt, -1, **opts_dict(w))
+        assert e.value.status == P.SL_E_INVALID
+    finally:
+        m.close()
