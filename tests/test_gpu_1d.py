@@ -277,3 +277,22 @@ def test_zero_steps_leave_the_field(dim):
         assert e.value.status == P.SL_E_INVALID
     finally:
         m.close()
+
+
+@pytest.mark.parametrize("mode", [W.HARD, W.SOFT])
+@pytest.mark.parametrize("cmask", [W.BOUNDARY, W.BOUNDARY | W.MASS | W.ENERGY])
+def test_zero_velocity(cmask, mode):
+    """a = 0, every face on the zero-speed tie rule (tests/_zerovel.py): a
+    global polynomial comes back unchanged on the device; a periodic field
+    whose element traces differ matches the oracle."""
+    import _zerovel
+    w = _zerovel.polynomial_case(1, cmask, mode)
+    announce(f"zero velocity 1D cmask={cmask} mode={mode}")
+    g, st, rc = run_gpu(w)
+    assert rc == 0 and st.flags == 0
+    np.testing.assert_allclose(g, w.initial(), rtol=0, atol=1e-13)
+    w = _zerovel.periodic_case(1, cmask, mode)
+    g, st, rc = run_gpu(w)
+    o, ost = run_oracle(w)
+    assert rc == 0
+    assert_parity(w, g, o, solves=w.nsteps * w.energy_maxit)

@@ -276,3 +276,22 @@ def test_multistep_call_equals_single_steps(nsteps):
         me.close()
     assert np.array_equal(g, e)
     assert (rg, sg.steps, sg.flags, sg.max_picard) == (re_, se.steps, se.flags, se.max_picard)
+
+
+@pytest.mark.parametrize("mode", [W.HARD, W.SOFT])
+@pytest.mark.parametrize("cmask", [W.BOUNDARY, W.BOUNDARY | W.MASS | W.ENERGY])
+def test_zero_velocity(cmask, mode):
+    """a = 0, every face on the zero-speed tie rule (tests/_zerovel.py): a
+    global polynomial comes back unchanged on the device; a periodic field
+    whose element traces differ matches the oracle."""
+    import _zerovel
+    w = _zerovel.polynomial_case(2, cmask, mode)
+    announce(f"zero velocity 2D cmask={cmask} mode={mode}")
+    g, st, rc = run_gpu(w)
+    assert rc == 0 and st.flags == 0
+    np.testing.assert_allclose(g, w.initial(), rtol=0, atol=1e-13)
+    w = _zerovel.periodic_case(2, cmask, mode)
+    g, st, rc = run_gpu(w)
+    o, ost = run_oracle(w)
+    assert rc == 0
+    assert_parity(w, g, o, solves=w.nsteps * w.energy_maxit)

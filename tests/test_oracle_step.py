@@ -15,7 +15,9 @@
   (closed form, every tableau, both forms, 1D and 2D);
 * meshes periodic in one direction with ghost values on the sides of the
   other reproduce polynomials across the ghost sides and never read the
-  ghost values of the periodic sides.
+  ghost values of the periodic sides;
+* zero velocity (every face on the tie rule) leaves a global polynomial
+  unchanged.
 """
 import math
 
@@ -398,3 +400,18 @@ def test_periodic_in_one_direction(ora, bc, deg, cmask, mode):
     ex = w.exact_at(w.nsteps * w.dt)
     assert np.all(np.isfinite(phi)) and st.flags == 0
     np.testing.assert_allclose(phi, ex, rtol=0, atol=1e-12 * max(1.0, np.abs(ex).max()))
+
+
+@pytest.mark.parametrize("mode", [W.HARD, W.SOFT])
+@pytest.mark.parametrize("cmask", [W.BOUNDARY, W.BOUNDARY | W.MASS | W.ENERGY])
+@pytest.mark.parametrize("dim", [1, 2])
+def test_zero_velocity_leaves_polynomials(ora, dim, cmask, mode):
+    """a = 0 (tests/_zerovel.py): no particle moves and every face speed is
+    zero, so each face takes the mean of its two traces.  A global polynomial
+    of degree <= N has equal traces on both sides of every face (the ghost
+    rows hold its own values), so three steps return it unchanged."""
+    import _zerovel
+    w = _zerovel.polynomial_case(dim, cmask, mode)
+    phi, st = ora.run_workload(w)
+    assert st.flags == 0
+    np.testing.assert_allclose(phi, w.initial(), rtol=0, atol=1e-13)
