@@ -209,6 +209,11 @@ def test_error_paths_on_device():
         m.step(m.max_dt(0.5), 2)
         rc, out, st = m.read()
         assert rc == 0 and st.steps == 2
+        # the paper's restriction admits equality: the particle next to the
+        # edge lands on it, inside the containment tolerance
+        m.step(m.max_dt(1.0), 1)
+        rc, out, st = m.read()
+        assert rc == 0 and st.flags == 0 and np.all(np.isfinite(out))
     finally:
         m.close()
 
