@@ -390,6 +390,35 @@ template <> struct Prec<2> {
     __device__ static A get(S v) { return __uint_as_float((unsigned int)v << 16); }
 };
 
+// Maximum of the bit patterns `bits` (non-negative doubles, and NaN above
+// them, order as their bits) over the lanes of each element slot present in
+// one 64-lane wave, published to dst[slot] with one LDS atomic per slot
+// instead of one per lane: same-address LDS atomics serialise.  Valid when a
+// wave spans at most two slots (n^2 >= 64), or with every lane in slot 0
+// (the constrain kernels' block-wide residual).  Every lane of the wave calls
+// it; lanes without a value pass 0.
+template <int E>
+__device__ __forceinline__ void slot_max(unsigned long long* dst, int slot, unsigned long long bits)
+{
+    const int first = __shfl(slot, 0);
+    unsigned long long a = slot == first ? bits : 0ull, b = slot == first + 1 ? bits : 0ull;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const unsigned long long ao = __shfl_xor(a, off), bo = __shfl_xor(b, off);
+        a = ao > a ? ao : a;
+        b = bo > b ? bo : b;
+    }
+    if ((threadIdx.x & 63) == 0) {
+        if (first < E && a) atomicMax(&dst[first], a);
+        if (first + 1 < E && b) atomicMax(&dst[first + 1], b);
+    }
+}
+
+__device__ __forceinline__ unsigned long long abs_bits(double v)
+{
+    return (unsigned long long)__double_as_longlong(fabs(v));
+}
+
 template <int N, int PR, bool TGT, int BSEL = 0>
 __global__ __launch_bounds__((Shape2<N, BSEL>::BS)) void k_advect2d(Step2DArgs A)
 {
@@ -615,8 +644,10 @@ __global__ __launch_bounds__((Shape2<N, BSEL>::BS)) void k_advect2d(Step2DArgs A
         s_r[slot][q] = sx - tab[O::XI + ii];
         s_x[slot][q] = sy - tab[O::XI + jj];
         s_f[slot][q] = sq;  // phi*
-        atomicMax(&s_ref[slot], (unsigned long long)__double_as_longlong(fabs(sq)));
     }
+    // per-lane atomics here: a wave reduction's shuffles go through the LDS
+    // unit too, and the sweeps are bound by it (measured slower on C3)
+    if (inblk) atomicMax(&s_ref[slot], abs_bits(sq));
     __syncthreads();
     for (int c = q; inblk && c < 2 * N; c += ND) {
         double m = 0.0;
@@ -710,8 +741,8 @@ __global__ __launch_bounds__((Shape2<N, BSEL>::BS)) void k_advect2d(Step2DArgs A
         if (inblk) {
             if (!conv) x += y;
             s_x[slot][q] = x;
-            atomicMax(&s_nrm[it & 1][slot], (unsigned long long)__double_as_longlong(fabs(y)));
         }
+        if (inblk) atomicMax(&s_nrm[it & 1][slot], abs_bits(y));
         __syncthreads();
         if (inblk) {
             const double eny = __longlong_as_double((long long)s_nrm[it & 1][slot]);
@@ -880,6 +911,7 @@ __global__ __launch_bounds__(kBlock2) void k_constrain2d(Step2DArgs A)
         if (inblk) s_y[slot][p] = phi;
         __syncthreads();
         int fl = 0;
+        unsigned long long rmax = 0ull;  // this lane's largest boundary-row residual
         if (live) {
             if (!isfinite(phi)) fl |= FLAG_NONFINITE;
             A.phi_out[g] = phi;
@@ -891,9 +923,11 @@ __global__ __launch_bounds__(kBlock2) void k_constrain2d(Step2DArgs A)
                     for (int c = 0; c < N; ++c) tr = fma(lv[c], s_y[slot][c + N * k], tr);
                 else
                     for (int c = 0; c < N; ++c) tr = fma(lv[c], s_y[slot][k + N * c], tr);
-                atomicMax(&s_stat, (unsigned long long)__double_as_longlong(fabs(tr - s_fv[slot][tt])));
+                const unsigned long long r = abs_bits(tr - s_fv[slot][tt]);
+                rmax = r > rmax ? r : rmax;
             }
         }
+        slot_max<1>(&s_stat, 0, rmax);  // one block-wide slot: one atomic per wave
         if (fl) atomicOr(&s_flag, fl);
         __syncthreads();  // s_fv, s_rb, s_d, s_y are rewritten by the next chunk
     }
@@ -1333,6 +1367,7 @@ __global__ __launch_bounds__(kBlock2) void k_constrain2d_mixed(Step2DArgs A)
         if (inblk) s_y[slot][p] = phi;
         __syncthreads();
         int fl = 0;
+        unsigned long long rmax = 0ull;  // this lane's largest boundary-row residual
         if (live) {
             if (!isfinite(phi)) fl |= FLAG_NONFINITE;
             A.phi_out[g] = phi;
@@ -1344,9 +1379,11 @@ __global__ __launch_bounds__(kBlock2) void k_constrain2d_mixed(Step2DArgs A)
                     for (int c = 0; c < N; ++c) tr = fma(lv[c], s_y[slot][c + N * k], tr);
                 else
                     for (int c = 0; c < N; ++c) tr = fma(lv[c], s_y[slot][k + N * c], tr);
-                atomicMax(&s_stat, (unsigned long long)__double_as_longlong(fabs(tr - s_fv[slot][tt])));
+                const unsigned long long r = abs_bits(tr - s_fv[slot][tt]);
+                rmax = r > rmax ? r : rmax;
             }
         }
+        slot_max<1>(&s_stat, 0, rmax);  // one block-wide slot: one atomic per wave
         if (fl) atomicOr(&s_flag, fl);
         __syncthreads();  // s_fv, s_rb, s_d, s_y are rewritten by the next chunk
     }
