@@ -397,18 +397,40 @@ template <> struct Prec<2> {
 // wave spans at most two slots (n^2 >= 64), or with every lane in slot 0
 // (the constrain kernels' block-wide residual).  Every lane of the wave calls
 // it; lanes without a value pass 0.
+// max with the value DPP control CTRL brings to this lane (rows outside
+// ROWMASK keep their own value), on both 32-bit halves of a 64-bit word
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ unsigned long long dpp_max_u64(unsigned long long v)
+{
+    const int lo = (int)(unsigned)v, hi = (int)(v >> 32);
+    const int l2 = __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROWMASK, 0xF, false);
+    const int h2 = __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROWMASK, 0xF, false);
+    const unsigned long long o = ((unsigned long long)(unsigned)h2 << 32) | (unsigned)l2;
+    return o > v ? o : v;
+}
+
+// Maximum over the 64 lanes of a wave, left in lane 63: butterflies within
+// quads (quad_perm [1,0,3,2], [2,3,0,1]), then half-rows and rows (mirror),
+// then across rows (broadcast of lane 15 into rows 1 and 3, of lane 31 into
+// rows 2 and 3).  VALU data movement only, none through the LDS unit.
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
+{
+    v = dpp_max_u64<0xB1, 0xF>(v);
+    v = dpp_max_u64<0x4E, 0xF>(v);
+    v = dpp_max_u64<0x141, 0xF>(v);
+    v = dpp_max_u64<0x140, 0xF>(v);
+    v = dpp_max_u64<0x142, 0xA>(v);
+    v = dpp_max_u64<0x143, 0xC>(v);
+    return v;
+}
+
 template <int E>
 __device__ __forceinline__ void slot_max(unsigned long long* dst, int slot, unsigned long long bits)
 {
-    const int first = __shfl(slot, 0);
-    unsigned long long a = slot == first ? bits : 0ull, b = slot == first + 1 ? bits : 0ull;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        const unsigned long long ao = __shfl_xor(a, off), bo = __shfl_xor(b, off);
-        a = ao > a ? ao : a;
-        b = bo > b ? bo : b;
-    }
-    if ((threadIdx.x & 63) == 0) {
+    const int first = __builtin_amdgcn_readfirstlane(slot);  // every lane is active here: lane 0's slot
+    const unsigned long long a = wave_max_u64(slot == first ? bits : 0ull);
+    const unsigned long long b = wave_max_u64(slot == first + 1 ? bits : 0ull);
+    if ((threadIdx.x & 63) == 63) {
         if (first < E && a) atomicMax(&dst[first], a);
         if (first + 1 < E && b) atomicMax(&dst[first + 1], b);
     }
@@ -645,9 +667,8 @@ __global__ __launch_bounds__((Shape2<N, BSEL>::BS)) void k_advect2d(Step2DArgs A
         s_x[slot][q] = sy - tab[O::XI + jj];
         s_f[slot][q] = sq;  // phi*
     }
-    // per-lane atomics here: a wave reduction's shuffles go through the LDS
-    // unit too, and the sweeps are bound by it (measured slower on C3)
-    if (inblk) atomicMax(&s_ref[slot], abs_bits(sq));
+    if constexpr (ND >= 64) slot_max<E>(s_ref, slot, inblk ? abs_bits(sq) : 0ull);
+    else if (inblk) atomicMax(&s_ref[slot], abs_bits(sq));
     __syncthreads();
     for (int c = q; inblk && c < 2 * N; c += ND) {
         double m = 0.0;
@@ -742,7 +763,8 @@ __global__ __launch_bounds__((Shape2<N, BSEL>::BS)) void k_advect2d(Step2DArgs A
             if (!conv) x += y;
             s_x[slot][q] = x;
         }
-        if (inblk) atomicMax(&s_nrm[it & 1][slot], abs_bits(y));
+        if constexpr (ND >= 64) slot_max<E>(s_nrm[it & 1], slot, inblk ? abs_bits(y) : 0ull);
+        else if (inblk) atomicMax(&s_nrm[it & 1][slot], abs_bits(y));
         __syncthreads();
         if (inblk) {
             const double eny = __longlong_as_double((long long)s_nrm[it & 1][slot]);
