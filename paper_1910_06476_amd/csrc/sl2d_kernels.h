@@ -424,15 +424,16 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
     return v;
 }
 
-template <int E>
+// (the slots sit S words apart in dst)
+template <int E, int S = 1>
 __device__ __forceinline__ void slot_max(unsigned long long* dst, int slot, unsigned long long bits)
 {
     const int first = __builtin_amdgcn_readfirstlane(slot);  // every lane is active here: lane 0's slot
     const unsigned long long a = wave_max_u64(slot == first ? bits : 0ull);
     const unsigned long long b = wave_max_u64(slot == first + 1 ? bits : 0ull);
     if ((threadIdx.x & 63) == 63) {
-        if (first < E && a) atomicMax(&dst[first], a);
-        if (first + 1 < E && b) atomicMax(&dst[first + 1], b);
+        if (first < E && a) atomicMax(&dst[first * S], a);
+        if (first + 1 < E && b) atomicMax(&dst[(first + 1) * S], b);
     }
 }
 
@@ -1172,10 +1173,14 @@ __global__ __launch_bounds__(kBlock2) void k_constrain2d_me(Step2DArgs A)
                 sig_e = (dE - s_dot[sl][1]) / S;
             }
             const double nxt = base + zm * sig_m + zE * sig_e;
-            if (inblk && !done) {
-                if (bad) fl |= FLAG_SINGULAR;
-                atomicMax(&s_mx[slot][0], (unsigned long long)__double_as_longlong(fabs(nxt - prev)));
-                atomicMax(&s_mx[slot][1], (unsigned long long)__double_as_longlong(fabs(nxt - older)));
+            const bool act = inblk && !done;
+            if (act && bad) fl |= FLAG_SINGULAR;
+            if constexpr (ND >= 64) {
+                slot_max<E, 2>(&s_mx[0][0], slot, act ? abs_bits(nxt - prev) : 0ull);
+                slot_max<E, 2>(&s_mx[0][1], slot, act ? abs_bits(nxt - older) : 0ull);
+            } else if (act) {
+                atomicMax(&s_mx[slot][0], abs_bits(nxt - prev));
+                atomicMax(&s_mx[slot][1], abs_bits(nxt - older));
             }
             __syncthreads();
             if (inblk && !done) {
@@ -1211,6 +1216,7 @@ __global__ __launch_bounds__(kBlock2) void k_constrain2d_me(Step2DArgs A)
         const double v[2] = {Wp * phi, Wp * phi * phi};
         dots(2, v);  // its first barrier also publishes s_v
     }
+    unsigned long long rmax = 0ull;  // this lane's largest boundary-row residual
     if (live) {
         for (int tt = p; bnd && tt < NB; tt += ND) {
             const int side = tt / N, k = tt % N;
@@ -1220,8 +1226,12 @@ __global__ __launch_bounds__(kBlock2) void k_constrain2d_me(Step2DArgs A)
                 for (int c = 0; c < N; ++c) tr = fma(lv[c], s_v[slot][c + N * k], tr);
             else
                 for (int c = 0; c < N; ++c) tr = fma(lv[c], s_v[slot][k + N * c], tr);
-            atomicMax(&s_stat[0], (unsigned long long)__double_as_longlong(fabs(tr - s_fv[slot][tt])));
+            const unsigned long long r = abs_bits(tr - s_fv[slot][tt]);
+            rmax = r > rmax ? r : rmax;
         }
+    }
+    slot_max<1>(&s_stat[0], 0, rmax);  // one block-wide slot: one atomic per wave
+    if (live) {
         if (p == 0) {
             if (mass) atomicMax(&s_stat[1], (unsigned long long)__double_as_longlong(fabs(s_dot[slot][0] - Mt)));
             if (energy) atomicMax(&s_stat[2], (unsigned long long)__double_as_longlong(fabs(s_dot[slot][1] - Et)));
