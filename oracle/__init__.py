@@ -80,6 +80,8 @@ def lib():
         L.ora_rk_tableau.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_int), dp, dp, dp]
         L.ora_cls.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, dp, ctypes.c_int, dp]
         L.ora_boundary_pinv.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp]
+        L.ora_energy_hard.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, dp, ctypes.c_double, ctypes.c_double,
+                                      dp, ctypes.c_double, ctypes.c_int, dp, ctypes.POINTER(ctypes.c_int)]
         _lib = L
     return _lib
 
@@ -128,6 +130,24 @@ def cls(C, d, phihat, mode: int):
     if bad:
         raise np.linalg.LinAlgError("singular constrained system")
     return out
+
+
+def energy_hard(C, d, Wq, s, T, phihat, tol=0.0, maxit=20):
+    """HARD constrained least squares with the energy row as the step imposes
+    it (section "Local energy conservation", eq. remap_energy, with the
+    reading of its fixed-point iteration documented in sl_oracle.c):
+    min ||phi - phihat|| s.t. C phi = d and sum Wq (phi - s)^2 = T.
+    Returns (phi, sweeps, flags)."""
+    C = np.ascontiguousarray(np.atleast_2d(C), dtype=np.float64)
+    d = np.ascontiguousarray(d, dtype=np.float64)
+    Wq = np.ascontiguousarray(Wq, dtype=np.float64)
+    ph = np.ascontiguousarray(phihat, dtype=np.float64)
+    out = np.zeros(len(ph))
+    fl = ctypes.c_int()
+    m = C.shape[0] if C.size else 0
+    k = lib().ora_energy_hard(len(ph), m, _p(C), _p(d), _p(Wq), float(s), float(T), _p(ph), float(tol),
+                              int(maxit), _p(out), ctypes.byref(fl))
+    return out, k, fl.value
 
 
 def boundary_pinv(family: int, n: int):

@@ -543,8 +543,10 @@ typedef struct {
     double* tr;      /* [K][4n] own traces of phihat: left j, right j, bottom i, top i (1D: 2) */
     double* fv;      /* face value at t^{n+1} seen by element: same layout as tr */
     double* vn;      /* face velocity at the element's face points, same layout */
-    double* Mt;      /* mass target */
-    double* Et;      /* energy target */
+    double* Mt;      /* mass target M^{n+1} */
+    double* Et;      /* energy target E^{n+1} (sum W phi^2) */
+    double* Ec;      /* energy target of the deviation from cref: sum W (phi - cref)^2 */
+    double* cref;    /* the element's mean at t^n, M^n / sum W */
 } work;
 
 static int ntr(const ctx* c) { return c->p->dim == 1 ? 2 : 4 * c->n; }
@@ -756,6 +758,20 @@ static void face_values(const ctx* c, int e, const double* ghost, work* W)
 /* at time t^n + c dt come from backtracking over c dt (eq. 4.11) in the    */
 /* upwind element; with c = 0 and Euler this is the paper's first-order     */
 /* update exactly.                                                          */
+/*                                                                          */
+/* Reading (energy): the balance law is taken for the deviation psi =       */
+/* phi - c from the element's mean c = M^n / sum W, held fixed over the     */
+/* step.  In the advective form psi obeys the same transport equation as    */
+/* phi, so d/dt int psi^2 = inflow - outflow of psi^2 + int (div a) psi^2;  */
+/* in the conservative form psi_t + div(a psi) = -c div a, which gives the  */
+/* volume term -int (div a)(psi^2 + 2 c psi).  For the PDE this is the same */
+/* law as the one for phi^2.  Discretely the two differ by c^2 dt times the */
+/* element's divergence defect (net face inflow speed + int div a, zero by  */
+/* the divergence theorem), a rounding-level quantity for a resolved        */
+/* velocity that the phi^2 form would multiply by the field's square and    */
+/* that a near-constant element's energy row amplifies without bound.  The  */
+/* energy target is E^{n+1} = Ec + 2 c M^{n+1} - c^2 sum W, where Ec is the  */
+/* deviation target; Ec itself is what HARD imposes next to a mass row.     */
 /* ------------------------------------------------------------------------ */
 static int targets(const ctx* c, int e, const double* phin, const double* ghost, const double* ghost_next,
                    work* W)
@@ -765,13 +781,21 @@ static int targets(const ctx* c, int e, const double* phin, const double* ghost,
     double cu[4], bu[4];
     int nq = rk_nodes(&c->T, cu, bu);
     const double* ph = phin + (size_t)e * nd;
-    double M = 0, E = 0;
+    double M = 0, SW = 0;
     for (int jj = 0; jj < (d2 ? n : 1); ++jj)
         for (int ii = 0; ii < n; ++ii) {
             int pidx = ii + n * jj;
             double Wp = c->dx * c->w[ii] * (d2 ? c->dy * c->w[jj] : 1.0);
             M += Wp * ph[pidx];
-            E += Wp * ph[pidx] * ph[pidx];
+            SW += Wp;
+        }
+    const double cr = M / SW;
+    double Ed = 0;
+    for (int jj = 0; jj < (d2 ? n : 1); ++jj)
+        for (int ii = 0; ii < n; ++ii) {
+            int pidx = ii + n * jj;
+            double Wp = c->dx * c->w[ii] * (d2 ? c->dy * c->w[jj] : 1.0);
+            Ed += Wp * (ph[pidx] - cr) * (ph[pidx] - cr);
         }
     double dM = 0, dE = 0;
     for (int q = 0; q < nq; ++q) {
@@ -798,7 +822,7 @@ static int targets(const ctx* c, int e, const double* phin, const double* ghost,
             double sign = high ? 1.0 : -1.0; /* inflow positive */
             double fw = face_weight(c, t);
             fM += sign * vn * val * fw;
-            fE += sign * vn * val * val * fw;
+            fE += sign * vn * (val - cr) * (val - cr) * fw;
         }
         double vM = 0, vE = 0;
         for (int jj = 0; jj < (d2 ? n : 1); ++jj)
@@ -810,16 +834,20 @@ static int targets(const ctx* c, int e, const double* phin, const double* ghost,
                 else vel_eval(c, e, s, r, &u, &v, &dv);
                 if (dv == 0.0) continue;
                 double val = backtrace_value(c, e, phin, h, s, r, &flags);
+                double dev = val - cr;
                 vM += Wp * dv * val;
-                vE += Wp * dv * val * val;
+                /* advective: + int (div a) psi^2; conservative: - int (div a)(psi^2 + 2 c psi) */
+                vE += Wp * dv * (p->form == 0 ? dev * dev : -(dev * dev + 2.0 * cr * dev));
             }
         double RM = fM + (p->form == 0 ? vM : 0.0);
-        double RE = fE + (p->form == 0 ? vE : -vE);
+        double RE = fE + vE;
         dM += bu[q] * RM;
         dE += bu[q] * RE;
     }
     W->Mt[e] = M + c->dt * dM;
-    W->Et[e] = E + c->dt * dE;
+    W->Ec[e] = Ed + c->dt * dE;
+    W->cref[e] = cr;
+    W->Et[e] = W->Ec[e] + 2.0 * cr * W->Mt[e] - cr * cr * SW;
     return flags;
 }
 
@@ -849,27 +877,14 @@ static int assemble_rows(const ctx* c, int e, const work* W, const double* prev,
         ++m;
     }
     if (with_energy) {
+        /* the paper's linearised energy row sum W phi^(k-1) phi = E^{n+1}
+         * (used by SOFT; HARD imposes the energy row in constrain()) */
         for (int jj = 0; jj < (d2 ? n : 1); ++jj)
             for (int ii = 0; ii < n; ++ii) {
                 int pidx = ii + n * jj;
                 C[m * nd + pidx] = c->dx * c->w[ii] * (d2 ? c->dy * c->w[jj] : 1.0) * prev[pidx];
             }
         d[m] = W->Et[e];
-        /* HARD with a mass row: represent the energy row by its part
-         * orthogonal to the mass row (same constraint set: subtract mu times
-         * the mass equation).  For smooth phi the two rows are nearly
-         * parallel, and this keeps the KKT system well conditioned. */
-        if (p->mode == 0 && (p->cmask & C_MASS)) {
-            int mr = m - 1;
-            double gw = 0, ww = 0;
-            for (int i = 0; i < nd; ++i) {
-                gw += C[m * nd + i] * C[mr * nd + i];
-                ww += C[mr * nd + i] * C[mr * nd + i];
-            }
-            double mu = gw / ww;
-            for (int i = 0; i < nd; ++i) C[m * nd + i] -= mu * C[mr * nd + i];
-            d[m] -= mu * d[mr];
-        }
         ++m;
     }
     return m;
@@ -954,6 +969,132 @@ static int solve_once(const ctx* c, int e, const work* W, const double* CB, cons
     return bad;
 }
 
+/* Orthonormal basis of the span of the rows of R (m x nd) by modified
+ * Gram-Schmidt, applied twice per row; a row whose remainder falls below
+ * 1e-10 of its own norm depends on the earlier ones and is dropped.  Returns
+ * the number of basis vectors written to Q (rank x nd). */
+static int row_basis(int m, int nd, const double* R, double* Q)
+{
+    int k = 0;
+    for (int r = 0; r < m; ++r) {
+        double* q = Q + (size_t)k * nd;
+        double n0 = 0, n1 = 0;
+        for (int i = 0; i < nd; ++i) { q[i] = R[(size_t)r * nd + i]; n0 += q[i] * q[i]; }
+        for (int pass = 0; pass < 2; ++pass)
+            for (int b = 0; b < k; ++b) {
+                const double* qb = Q + (size_t)b * nd;
+                double s = 0;
+                for (int i = 0; i < nd; ++i) s += qb[i] * q[i];
+                for (int i = 0; i < nd; ++i) q[i] -= s * qb[i];
+            }
+        for (int i = 0; i < nd; ++i) n1 += q[i] * q[i];
+        if (n1 <= 1e-20 * n0 || n1 == 0.0) continue;
+        n1 = sqrt(n1);
+        for (int i = 0; i < nd; ++i) q[i] /= n1;
+        ++k;
+    }
+    return k;
+}
+
+/* HARD energy row (section "Local energy conservation", eq. remap_energy).
+ * Reading: the paper's fixed-point iteration sum W phi^(k-1) phi^(k) = E
+ * is kept as the definition of the result -- its fixed point is the point
+ * of the constraint set {linear rows, sum W phi^2 = E} nearest phihat (the
+ * KKT point of the quadratic row) -- but under HARD that map is 2-periodic
+ * (it sends the no-energy solution phi1 to a point phi2 and phi2 back to
+ * phi1, because sum W phi2 phi1 = E holds by construction).  The fixed point
+ * is reached instead by Newton's linearisation of the same row,
+ *   2 sum W y^(k-1) y = T + sum W (y^(k-1))^2,
+ * i.e. the paper's row with its target replaced by the mean of T and the
+ * current energy; each sweep is the nearest point to phihat (equivalently
+ * to phi1, the solution without the energy row) that satisfies the linear
+ * rows and the linearised one.  A fixed point of the sweep satisfies the
+ * energy row exactly and is stationary for the distance, so it is the
+ * paper's fixed point.  y = phi - s: with a mass row the row is written for
+ * the deviation from the element's mean (s = cref, T = Ec), the same
+ * constraint set on the mass row's level set, and computed from differences
+ * of like size; without a mass row s = 0 and T = E^{n+1}.  Stop when
+ * max |y^(k) - y^(k-1)| < tol (strict, as printed), y^(0) = y1.
+ *   linear rows: 1D l(0), l(1) (boundary), W (mass); 2D C_B, W.
+ * Returns the number of sweeps; *conv set when the stop rule was met;
+ * *sing set when the linearised row lies in the span of the linear rows
+ * (no correction possible) while the energy is not met. */
+static int energy_newton_core(int nd, int m, const double* R, const double* Wq, double s, double T,
+                              const double* phi1, double tol, int maxit, double* out, int* conv, int* sing)
+{
+    double* Q = malloc(sizeof(double) * (size_t)(m > 0 ? m : 1) * nd);
+    double* y1 = malloc(sizeof(double) * nd);
+    double* y = malloc(sizeof(double) * nd);
+    double* g = malloc(sizeof(double) * nd);
+    int rank = row_basis(m, nd, R, Q);
+    for (int i = 0; i < nd; ++i) { y1[i] = phi1[i] - s; y[i] = y1[i]; }
+    int k = 0;
+    *conv = 0;
+    *sing = 0;
+    for (k = 1; k <= maxit; ++k) {
+        /* gradient direction w = W y (half the gradient of sum W y^2),
+         * projected onto the null space of the linear rows (twice) */
+        double en = 0;
+        for (int i = 0; i < nd; ++i) { g[i] = Wq[i] * y[i]; en += Wq[i] * y[i] * y[i]; }
+        double wy1 = 0;
+        for (int i = 0; i < nd; ++i) wy1 += g[i] * y1[i];
+        for (int pass = 0; pass < 2; ++pass)
+            for (int b = 0; b < rank; ++b) {
+                const double* qb = Q + (size_t)b * nd;
+                double t = 0;
+                for (int i = 0; i < nd; ++i) t += qb[i] * g[i];
+                for (int i = 0; i < nd; ++i) g[i] -= t * qb[i];
+            }
+        double gg = 0;
+        for (int i = 0; i < nd; ++i) gg += g[i] * g[i];
+        const double rhs = 0.5 * (T + en) - wy1; /* w.(y - y1) required */
+        double diff = 0;
+        if (gg > 0.0) {
+            const double a = rhs / gg;
+            for (int i = 0; i < nd; ++i) {
+                double nv = y1[i] + a * g[i];
+                diff = fmax(diff, fabs(nv - y[i]));
+                y[i] = nv;
+            }
+        } else if (rhs != 0.0) {
+            *sing = 1;
+        }
+        if (diff < tol) { *conv = 1; break; }
+    }
+    if (k > maxit) k = maxit;
+    for (int i = 0; i < nd; ++i) out[i] = y[i] + s;
+    free(Q); free(y1); free(y); free(g);
+    return k;
+}
+
+/* the element's linear rows and weights for energy_newton_core */
+static int energy_newton(const ctx* c, int e, const work* W, const double* CB, const double* phi1, double* out,
+                         int* conv, int* sing)
+{
+    const ora_params* p = c->p;
+    int n = c->n, nd = c->nd, d2 = (p->dim == 2);
+    int bound = (p->cmask & C_BOUND) != 0, mass = (p->cmask & C_MASS) != 0;
+    int mr = (bound ? (d2 ? 4 * n : 2) : 0) + (mass ? 1 : 0);
+    double* R = malloc(sizeof(double) * (size_t)(mr > 0 ? mr : 1) * nd);
+    double* Wq = malloc(sizeof(double) * nd);
+    for (int jj = 0; jj < (d2 ? n : 1); ++jj)
+        for (int ii = 0; ii < n; ++ii) Wq[ii + n * jj] = c->dx * c->w[ii] * (d2 ? c->dy * c->w[jj] : 1.0);
+    int m = 0;
+    if (bound) {
+        if (d2) { memcpy(R, CB, sizeof(double) * 4 * n * nd); m = 4 * n; }
+        else {
+            for (int i = 0; i < nd; ++i) { R[i] = c->l0[i]; R[nd + i] = c->l1[i]; }
+            m = 2;
+        }
+    }
+    if (mass) { memcpy(R + (size_t)m * nd, Wq, sizeof(double) * nd); ++m; }
+    const double s = mass ? W->cref[e] : 0.0;
+    const double T = mass ? W->Ec[e] : W->Et[e];
+    int k = energy_newton_core(nd, m, R, Wq, s, T, phi1, p->energy_tol, p->energy_maxit, out, conv, sing);
+    free(R); free(Wq);
+    return k;
+}
+
 static cls_out constrain(const ctx* c, int e, const work* W, const double* CB, const double* CBp,
                          const double* PB, double* out)
 {
@@ -963,28 +1104,25 @@ static cls_out constrain(const ctx* c, int e, const work* W, const double* CB, c
     double* prev = malloc(sizeof(double) * nd);
     double* cur = malloc(sizeof(double) * nd);
     if (solve_once(c, e, W, CB, CBp, PB, NULL, 0, prev)) o.flags |= F_SINGULAR;
-    if (p->cmask & C_ENERGY) {
-        /* Picard on the energy row (section "Local energy conservation").
-         * Stop when the change is below tol (strict, as printed).  Reading:
-         * also stop, unconverged, when the iterate comes back to within tol
-         * of the one two iterations earlier -- the linearised energy row
-         * makes the map (close to) 2-periodic, so further sweeps repeat. */
+    if ((p->cmask & C_ENERGY) && p->mode == 0) {
+        int conv, sing;
+        o.picard = energy_newton(c, e, W, CB, prev, cur, &conv, &sing);
+        memcpy(prev, cur, sizeof(double) * nd);
+        if (sing) o.flags |= F_SINGULAR;
+        if (!conv && p->energy_tol > 0) o.flags |= F_NOCONV;
+    } else if (p->cmask & C_ENERGY) {
+        /* SOFT: Picard on the paper's linearised energy row (section "Local
+         * energy conservation"), stacked with the other rows; stop when the
+         * change is below tol (strict, as printed) */
         int conv = 0;
-        double* older = malloc(sizeof(double) * nd);
         for (int k = 1; k <= p->energy_maxit; ++k) {
             if (solve_once(c, e, W, CB, CBp, PB, prev, 1, cur)) o.flags |= F_SINGULAR;
-            double diff = 0, back = 0;
-            for (int i = 0; i < nd; ++i) {
-                diff = fmax(diff, fabs(cur[i] - prev[i]));
-                if (k >= 2) back = fmax(back, fabs(cur[i] - older[i]));
-            }
-            memcpy(older, prev, sizeof(double) * nd);
+            double diff = 0;
+            for (int i = 0; i < nd; ++i) diff = fmax(diff, fabs(cur[i] - prev[i]));
             memcpy(prev, cur, sizeof(double) * nd);
             o.picard = k;
             if (diff < p->energy_tol) { conv = 1; break; }
-            if (k >= 2 && back < p->energy_tol) break;
         }
-        free(older);
         if (!conv && p->energy_tol > 0) o.flags |= F_NOCONV;
     }
     memcpy(out, prev, sizeof(double) * nd);
@@ -998,15 +1136,20 @@ static cls_out constrain(const ctx* c, int e, const work* W, const double* CB, c
             o.rb = fmax(o.rb, fabs(v - W->fv[(size_t)e * nt + t]));
         }
     }
+    /* energy residual of the row as imposed: HARD with a mass row in the
+     * deviation form, otherwise sum W phi^2 against E^{n+1} */
+    const int dev = (p->mode == 0) && (p->cmask & C_MASS);
+    const double s0 = dev ? W->cref[e] : 0.0;
     double M = 0, E = 0;
     for (int jj = 0; jj < (d2 ? n : 1); ++jj)
         for (int ii = 0; ii < n; ++ii) {
             double Wp = c->dx * c->w[ii] * (d2 ? c->dy * c->w[jj] : 1.0);
-            M += Wp * out[ii + n * jj];
-            E += Wp * out[ii + n * jj] * out[ii + n * jj];
+            double v = out[ii + n * jj];
+            M += Wp * v;
+            E += Wp * (v - s0) * (v - s0);
         }
     if (p->cmask & C_MASS) o.rm = fabs(M - W->Mt[e]);
-    if (p->cmask & C_ENERGY) o.re = fabs(E - W->Et[e]);
+    if (p->cmask & C_ENERGY) o.re = fabs(E - (dev ? W->Ec[e] : W->Et[e]));
     free(prev); free(cur);
     return o;
 }
@@ -1123,6 +1266,8 @@ int ora_step(const ora_params* p, const double* a, const double* div, const doub
     W.vn = malloc(sizeof(double) * (size_t)K * nt);
     W.Mt = calloc((size_t)K, sizeof(double));
     W.Et = calloc((size_t)K, sizeof(double));
+    W.Ec = calloc((size_t)K, sizeof(double));
+    W.cref = calloc((size_t)K, sizeof(double));
     double* out = malloc(sizeof(double) * (size_t)K * nd);
     uint8_t* need = NULL;
     if (want) {
@@ -1188,7 +1333,7 @@ int ora_step(const ora_params* p, const double* a, const double* div, const doub
     }
     if (st) *st = S;
     free(c.div); free(CB); free(CBp); free(PB);
-    free(W.phihat); free(W.tr); free(W.fv); free(W.vn); free(W.Mt); free(W.Et);
+    free(W.phihat); free(W.tr); free(W.fv); free(W.vn); free(W.Mt); free(W.Et); free(W.Ec); free(W.cref);
     free(out); free(need);
     return 0;
 }
@@ -1411,6 +1556,29 @@ int ora_rk_tableau(int id, int* s, double* a16, double* b4, double* c4)
 int ora_cls(int nd, int m, const double* C, const double* d, const double* phihat, int mode, double* phi)
 {
     return cls_solve(nd, m, C, d, phihat, mode, phi);
+}
+
+/* HARD least squares with one quadratic row (the energy row as imposed by
+ * constrain()): min ||phi - phihat|| s.t. C phi = d (m x nd, full row rank)
+ * and sum_i Wq_i (phi_i - s)^2 = T, by the LSE solution of the linear rows
+ * followed by energy_newton_core.  Returns the sweep count; flags get
+ * F_NOCONV (tol > 0, not met) and F_SINGULAR. */
+int ora_energy_hard(int nd, int m, const double* C, const double* d, const double* Wq, double s, double T,
+                    const double* phihat, double tol, int maxit, double* phi, int* flags)
+{
+    double* phi1 = malloc(sizeof(double) * nd);
+    int conv, sing;
+    *flags = 0;
+    if (m > 0) {
+        if (cls_solve(nd, m, C, d, phihat, 0, phi1)) *flags |= F_SINGULAR;
+    } else {
+        memcpy(phi1, phihat, sizeof(double) * nd);
+    }
+    int k = energy_newton_core(nd, m, C, Wq, s, T, phi1, tol, maxit, phi, &conv, &sing);
+    if (sing) *flags |= F_SINGULAR;
+    if (!conv && tol > 0) *flags |= F_NOCONV;
+    free(phi1);
+    return k;
 }
 
 int ora_boundary_pinv(int family, int n, double* CB, double* CBp)
