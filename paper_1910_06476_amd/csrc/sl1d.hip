@@ -502,21 +502,37 @@ __global__ __launch_bounds__(kBlock) void k_advect1d(Step1DArgs A)
         first = needL ? 0 : (needR ? 1 : -1);
         second = (needL && needR) ? 1 : -1;
     }
+    // the element's mean at t^n, c = M^n / sum W: the energy balance is
+    // taken for the deviation phi - c (same law as for phi^2 in the PDE,
+    // computed from differences of like size)
+    double cmean = 0.0;
+    if (A.targets) {
+        double sw = 0.0;
+        const double* pn = s_p[sl];
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            cmean = fma(tab[O::W + j], pn[j], cmean);
+            sw += tab[O::W + j];
+        }
+        cmean /= sw;
+    }
     double vM = 0.0, vE = 0.0;
     if (A.targets) {
         const double W_i = A.dx * tab[O::W + in];
         if (!node && live) {
             // an edge without backtraces has zero stage sums
-            double* rc = A.rec + (size_t)e * 8;
+            double* rc = A.rec + (size_t)e * kRec1;
             if (first != 0 && second != 0) rc[2] = rc[4] = 0.0;
             if (first != 1 && second != 1) rc[3] = rc[5] = 0.0;
+            rc[8] = cmean;
         }
         for (int r = 0; r < 2; ++r) {
             const int edge = (r == 0) ? first : second;
             const bool act = node ? (r == 0 && A.vol && live) : (edge >= 0);
             if (!act) continue;
             const double x0 = node ? xi_i : (double)edge;
-            double am = 0.0, ae = 0.0;  // sum_q bu_q v_q and sum_q bu_q v_q^2
+            // sum_q bu_q v_q, sum_q bu_q (v_q - c) and sum_q bu_q (v_q - c)^2
+            double am = 0.0, ad = 0.0, ae = 0.0;
             if constexpr (RKS == 4 && MONO) {
                 // abscissae 0, 1/2, 1: both backtraces first, then phi^n at
                 // the two feet in one pass over its coefficients
@@ -531,8 +547,10 @@ __global__ __launch_bounds__(kBlock) void k_advect1d(Step1DArgs A)
                 const double val[3] = {node ? phi_i : cheb_end<N>(cp, edge), hq[0] * vf[0], hq[1] * vf[1]};
 #pragma unroll
                 for (int qd = 0; qd < 3; ++qd) {
+                    const double dq = val[qd] - cmean;
                     am += RK.bu(qd) * val[qd];
-                    ae += RK.bu(qd) * val[qd] * val[qd];
+                    ad += RK.bu(qd) * dq;
+                    ae += RK.bu(qd) * dq * dq;
                 }
             } else {
 #pragma unroll
@@ -550,25 +568,31 @@ __global__ __launch_bounds__(kBlock) void k_advect1d(Step1DArgs A)
                     val = hq * clenshaw_p<N>(cp, 2.0 * sb - 1.0);
                 }
                 const double bq = RK.bu(qd);
+                const double dq = val - cmean;
                 am += bq * val;
-                ae += bq * val * val;
+                ad += bq * dq;
+                ae += bq * dq * dq;
             }
             }
-            // node: volume terms; edge lane: the edge's stage sums, stored now
+            // node: volume terms (mass: + int (div a) phi in the advective
+            // form; deviation energy: + int (div a) psi^2 advective,
+            // - int (div a)(psi^2 + 2 c psi) conservative); edge lane: the
+            // edge's stage sums, stored now
             if (node) {
                 vM = W_i * dv_i * am;
-                vE = W_i * dv_i * ae;
+                vE = W_i * dv_i * (CONS ? -fma(2.0 * cmean, ad, ae) : ae);
             } else {
-                double* rc = A.rec + (size_t)e * 8;
-                rc[2 + edge] = am;
+                double* rc = A.rec + (size_t)e * kRec1;
+                rc[2 + edge] = ad;
                 rc[4 + edge] = ae;
             }
         }
-        // per-node parts of the mass and energy targets with their volume
-        // terms: M^n (+ dt V_M) and E^n +- dt V_E
+        // per-node parts of the mass and deviation energy targets with their
+        // volume terms: M^n (+ dt V_M) and sum W (phi^n - c)^2 + dt V_E
         if (inblk && node) {
+            const double dn = phi_i - cmean;
             s_r[0][slot][i] = CONS ? W_i * phi_i : fma(A.dt, vM, W_i * phi_i);
-            s_r[1][slot][i] = fma(CONS ? -A.dt : A.dt, vE, W_i * phi_i * phi_i);
+            s_r[1][slot][i] = fma(A.dt, vE, W_i * dn * dn);
         }
     }
 
@@ -582,7 +606,7 @@ __global__ __launch_bounds__(kBlock) void k_advect1d(Step1DArgs A)
             double sb = (double)edge, hq = 1.0;
             if constexpr (MONO) rk_move_mono<CONS, NA, RKS>(A.rk, mu, md, -A.dt, A.dt, sb, hq, out, false, k_i, dv_i);
             else rk_move<N, CONS, NA, RKS>(A.rk, ca, cd, -1.0, A.dt, invdx, sb, hq, out, false, a_i, dv_i);
-            A.rec[(size_t)e * 8 + edge] = hq * clenshaw_p<N>(cp, 2.0 * sb - 1.0);
+            A.rec[(size_t)e * kRec1 + edge] = hq * clenshaw_p<N>(cp, 2.0 * sb - 1.0);
         }
     }
     const bool bt0 = bt && (first == 0 || second == 0), bt1 = bt && (first == 1 || second == 1);
@@ -629,7 +653,7 @@ __global__ __launch_bounds__(kBlock) void k_advect1d(Step1DArgs A)
             if (!isfinite(S)) fl |= FLAG_SINGULAR;
             A.phihat[g] = S;
         } else if (!bt0) {
-            A.rec[(size_t)e * 8] = S;
+            A.rec[(size_t)e * kRec1] = S;
         }
     }
     // s_p (phi^n, read before the second barrier) takes l(1)_i phihat_i
@@ -643,7 +667,7 @@ __global__ __launch_bounds__(kBlock) void k_advect1d(Step1DArgs A)
         double sum = 0.0;
 #pragma unroll
         for (int j = 0; j < N; ++j) sum += src[j];
-        A.rec[(size_t)e * 8 + (node ? 6 + i : 1)] = sum;
+        A.rec[(size_t)e * kRec1 + (node ? 6 + i : 1)] = sum;
     }
     if (fl) atomicOr(&s_flag, fl);
     __syncthreads();
@@ -683,7 +707,7 @@ __global__ __launch_bounds__(kConBlock) void k_constrain1d(Step1DArgs A)
 {
     using O = Off<N>;
     constexpr int NP = (N + kConQ - 1) / kConQ;
-    constexpr int NR = (kConElems + 2) * 8;  // records of elements e0 - 1 .. e0 + kConElems
+    constexpr int NR = (kConElems + 2) * kRec1;  // records of elements e0 - 1 .. e0 + kConElems
     constexpr int NF = kConElems + 1;        // faces e0 .. e0 + kConElems
     static_assert(3 * kConQ * NP <= kConBlock && NF <= kConBlock, "one table entry / face per lane");
     __shared__ double s_buf[kConElems * N];
@@ -721,9 +745,10 @@ __global__ __launch_bounds__(kConBlock) void k_constrain1d(Step1DArgs A)
 #pragma unroll
     for (int r3 = 0; r3 < kRStage; ++r3) {
         const int j = t + r3 * kConBlock;
-        int ge = e0 + (j >> 3) - 1;  // element of this record entry
+        const int jr = j / kRec1;
+        int ge = e0 + jr - 1;  // element of this record entry
         if (A.periodic) ge = wrap(ge);
-        rv[r3] = (j < NR && ge >= 0 && ge < K) ? A.rec[(size_t)ge * 8 + (j & 7)] : 0.0;
+        rv[r3] = (j < NR && ge >= 0 && ge < K) ? A.rec[(size_t)ge * kRec1 + (j - jr * kRec1)] : 0.0;
     }
     double fv = 0.0;
     if (t < NF) {
@@ -791,15 +816,22 @@ __global__ __launch_bounds__(kConBlock) void k_constrain1d(Step1DArgs A)
     double vR = s_vf[le + 1];
     if (fabs(vL) <= A.vzero) vL = 0.0;
     if (fabs(vR) <= A.vzero) vR = 0.0;
-    const double* Rm = s_rec + le * 8;
-    const double* Re = Rm + 8;
-    const double* Rp = Re + 8;
+    const double* Rm = s_rec + le * kRec1;
+    const double* Re = Rm + kRec1;
+    const double* Rp = Re + kRec1;
     const double T1m = em >= 0 ? Rm[1] : gn0;
     const double T0p = ep >= 0 ? Rp[0] : gn1;
     const double dB0 = upwind(vL, T1m, Re[0]);
     const double dB1 = upwind(vR, Re[1], T0p);
 
-    double Mt = 0.0, Et = 0.0;
+    // targets: M^{n+1} and the deviation energy Ed^{n+1} = sum W (phi - c)^2
+    // about the element's mean c at t^n, from the own record's volume parts
+    // and the upwind edge sums.  A neighbour's sums are about its own mean
+    // c'; with delta = c' - c, sum_q b_q (v_q - c)^2 = S2 + delta (2 S1 +
+    // delta) and sum_q b_q v_q = S1 + c' (the weights b_q sum to one).
+    // E^{n+1} = Ed + 2 c M - c^2 sum W is the energy target of phi^2.
+    double Mt = 0.0, Edt = 0.0, Et = 0.0;
+    const double cr = Re[8];
     if (A.targets) {
         double gM0 = 0.0, gE0 = 0.0, gM1 = 0.0, gE1 = 0.0;
         if (!A.periodic) {
@@ -808,17 +840,19 @@ __global__ __launch_bounds__(kConBlock) void k_constrain1d(Step1DArgs A)
                 const double v0 = (1.0 - cq) * gw0 + cq * gn0;
                 const double v1 = (1.0 - cq) * gw1 + cq * gn1;
                 gM0 += A.rk.bu[qd] * v0;
-                gE0 += A.rk.bu[qd] * v0 * v0;
+                gE0 += A.rk.bu[qd] * (v0 - cr) * (v0 - cr);
                 gM1 += A.rk.bu[qd] * v1;
-                gE1 += A.rk.bu[qd] * v1 * v1;
+                gE1 += A.rk.bu[qd] * (v1 - cr) * (v1 - cr);
             }
         }
-        const double FMl = upwind(vL, em >= 0 ? Rm[3] : gM0, Re[2]);
-        const double FEl = upwind(vL, em >= 0 ? Rm[5] : gE0, Re[4]);
-        const double FMr = upwind(vR, Re[3], ep >= 0 ? Rp[2] : gM1);
-        const double FEr = upwind(vR, Re[5], ep >= 0 ? Rp[4] : gE1);
+        const double dm = Rm[8] - cr, dp = Rp[8] - cr;
+        const double FMl = upwind(vL, em >= 0 ? Rm[3] + Rm[8] : gM0, Re[2] + cr);
+        const double FEl = upwind(vL, em >= 0 ? fma(dm, fma(2.0, Rm[3], dm), Rm[5]) : gE0, Re[4]);
+        const double FMr = upwind(vR, Re[3] + cr, ep >= 0 ? Rp[2] + Rp[8] : gM1);
+        const double FEr = upwind(vR, Re[5], ep >= 0 ? fma(dp, fma(2.0, Rp[2], dp), Rp[4]) : gE1);
         Mt = Re[6] + A.dt * (vL * FMl - vR * FMr);
-        Et = Re[7] + A.dt * (vL * FEl - vR * FEr);
+        Edt = Re[7] + A.dt * (vL * FEl - vR * FEr);
+        Et = Edt + cr * (2.0 * Mt - cr * A.sumW);
     }
 
     // this lane's nodes (absent nodes are zero rows)
@@ -848,8 +882,10 @@ __global__ __launch_bounds__(kConBlock) void k_constrain1d(Step1DArgs A)
     // energy row borders it with its Gram entries red[0..3] (against l0,
     // l1, W, itself), its product with phihat red[4] and target d3, and is
     // eliminated through the Schur complement.  HARD: G y = C phihat - d;
-    // SOFT: (I + G) z = C phihat + G d, y = z - d.
-    auto solve = [&](bool use_e, const double (&red)[5], double d3, double (&y)[4]) {
+    // SOFT: (I + G) z = C phihat + G d, y = z - d.  Returns false when the
+    // energy row's Schur complement vanishes (the row lies in the span of the
+    // others): then y4 = 0 and num holds the energy row's residual.
+    auto solve = [&](bool use_e, const double (&red)[5], double d3, double (&y)[4], double& num) {
         const double ge[3] = {use_e ? red[0] * s0 : 0.0, use_e ? red[1] * s1 : 0.0, use_e ? red[2] * s2 : 0.0};
         const double gam = use_e ? red[3] : 0.0;
         const double dd[4] = {dd0, dd1, dd2, use_e ? d3 : 0.0};
@@ -875,10 +911,13 @@ __global__ __launch_bounds__(kConBlock) void k_constrain1d(Step1DArgs A)
             w[a] = A.g3i[3 * a] * ge[0] + A.g3i[3 * a + 1] * ge[1] + A.g3i[3 * a + 2] * ge[2];
         }
         double y4 = 0.0;
+        bool ok = true;
+        num = 0.0;
         if (use_e) {
             const double sch = (soft ? gam + 1.0 : gam) - (ge[0] * w[0] + ge[1] * w[1] + ge[2] * w[2]);
-            singular |= !(sch > 0.0);
-            y4 = (r4 - (ge[0] * z[0] + ge[1] * z[1] + ge[2] * z[2])) / sch;
+            num = r4 - (ge[0] * z[0] + ge[1] * z[1] + ge[2] * z[2]);
+            ok = sch > 0.0;
+            y4 = ok ? num / sch : 0.0;
         }
 #pragma unroll
         for (int a = 0; a < 3; ++a) y[a] = z[a] - w[a] * y4;
@@ -886,67 +925,71 @@ __global__ __launch_bounds__(kConBlock) void k_constrain1d(Step1DArgs A)
         if (soft)
 #pragma unroll
             for (int a = 0; a < 4; ++a) y[a] -= dd[a];
+        return ok;
     };
 
-    double phi[NP], y[4];
+    double phi[NP], y[4], num;
     const double zero5[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    solve(false, zero5, 0.0, y);
+    solve(false, zero5, 0.0, y, num);
 #pragma unroll
     for (int k = 0; k < NP; ++k) phi[k] = ph[k] - (l0[k] * s0 * y[0] + l1[k] * s1 * y[1] + Wn[k] * s2 * y[2]);
 
+    // the energy row (section "Local energy conservation").  SOFT: the
+    // paper's linearisation sum W phi^(k-1) phi = E^{n+1}, stacked with the
+    // other rows.  HARD: its fixed point, reached by Newton's linearisation
+    // of the same row, written for y = phi - sh with the target T:
+    //   sum W y^(k-1) y = (T + sum W (y^(k-1))^2) / 2,
+    // with a mass row as the deviation from the element's mean (sh = c,
+    // T = Ed^{n+1}: the same constraint on the mass row's level set),
+    // otherwise sh = 0, T = E^{n+1}.  Each sweep solves from phihat; stop
+    // when max |phi^(k) - phi^(k-1)| < tol (strict, as printed).
+    const bool hard = A.mode == SL_MODE_HARD;
+    const bool devf = hard && mass;
+    const double sh = devf ? cr : 0.0;
     int iters = 0;
     bool conv = false;
     if (energy && live) {
-        // Picard on the energy row (section "Local energy conservation");
-        // HARD with a mass row: energy row orthogonalised against the mass
-        // row (same constraint set); stop below tol, or on a 2-cycle
-        const bool center = (A.mode == SL_MODE_HARD) && mass;
-        double older[NP];
-#pragma unroll
-        for (int k = 0; k < NP; ++k) older[k] = phi[k];
+        const double Tt = devf ? Edt : Et;
         for (int it = 1; it <= A.emaxit; ++it) {
-            double mu = 0.0;
-            if (center) {
-                double gw = 0.0;
-#pragma unroll
-                for (int k = 0; k < NP; ++k) gw += (Wn[k] * phi[k]) * Wn[k];
-                mu = pair_sum(gw) / A.g22;
-            }
-            double red[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+            double red[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, en = 0.0;
 #pragma unroll
             for (int k = 0; k < NP; ++k) {
-                const double c3 = Wn[k] * phi[k] - mu * Wn[k];
+                const double yk = phi[k] - sh;
+                const double c3 = Wn[k] * yk;
                 red[0] += c3 * l0[k];
                 red[1] += c3 * l1[k];
                 red[2] += c3 * Wn[k];
                 red[3] += c3 * c3;
-                red[4] += c3 * ph[k];
+                red[4] += c3 * (ph[k] - sh);
+                en += c3 * yk;
             }
 #pragma unroll
             for (int a = 0; a < 5; ++a) red[a] = pair_sum(red[a]);
-            solve(true, red, Et - mu * Mt, y);
-            double diff = 0.0, back = 0.0;
+            en = pair_sum(en);
+            const bool ok = solve(true, red, hard ? 0.5 * (Tt + en) : Et, y, num);
+            double diff = 0.0;
+            if (ok) {
 #pragma unroll
-            for (int k = 0; k < NP; ++k) {
-                const double c3 = Wn[k] * phi[k] - mu * Wn[k];
-                const double nv = ph[k] - (l0[k] * s0 * y[0] + l1[k] * s1 * y[1] + Wn[k] * s2 * y[2] + c3 * y[3]);
-                diff = fmax(diff, fabs(nv - phi[k]));
-                back = fmax(back, fabs(nv - older[k]));
-                older[k] = phi[k];
-                phi[k] = nv;
+                for (int k = 0; k < NP; ++k) {
+                    const double c3 = Wn[k] * (phi[k] - sh);
+                    const double nv = ph[k] - (l0[k] * s0 * y[0] + l1[k] * s1 * y[1] + Wn[k] * s2 * y[2] + c3 * y[3]);
+                    diff = fmax(diff, fabs(nv - phi[k]));
+                    phi[k] = nv;
+                }
+            } else if (num != 0.0) {
+                singular = true;
             }
             diff = pair_max(diff);
-            back = pair_max(back);
             iters = it;
             if (diff < A.etol) {
                 conv = true;
                 break;
             }
-            if (it >= 2 && back < A.etol) break;  // 2-cycle: further sweeps repeat
         }
     }
 
-    // residuals of the rows actually imposed
+    // residuals of the rows actually imposed (energy: HARD with a mass row
+    // in the deviation form, otherwise sum W phi^2 against E^{n+1})
     double r0 = 0.0, r1 = 0.0, r2 = 0.0, r3 = 0.0;
     bool finite = true;
 #pragma unroll
@@ -954,7 +997,7 @@ __global__ __launch_bounds__(kConBlock) void k_constrain1d(Step1DArgs A)
         r0 = fma(l0[k], phi[k], r0);
         r1 = fma(l1[k], phi[k], r1);
         r2 = fma(Wn[k], phi[k], r2);
-        r3 = fma(Wn[k] * phi[k], phi[k], r3);
+        r3 = fma(Wn[k] * (phi[k] - sh), phi[k] - sh, r3);
         finite = finite && isfinite(phi[k]);
     }
     r0 = pair_sum(r0);
@@ -963,7 +1006,7 @@ __global__ __launch_bounds__(kConBlock) void k_constrain1d(Step1DArgs A)
     r3 = pair_sum(r3);
     double rb = (live && bnd) ? fmax(fabs(r0 - dB0), fabs(r1 - dB1)) : 0.0;
     double rm = (live && mass) ? fabs(r2 - Mt) : 0.0;
-    double re = (live && energy) ? fabs(r3 - Et) : 0.0;
+    double re = (live && energy) ? fabs(r3 - (devf ? Edt : Et)) : 0.0;
     double pic = live ? (double)iters : 0.0;
     int fl = 0;
     if (live) {

@@ -348,11 +348,13 @@ __device__ double backtrace2(const Step2DArgs& A, const double* cu, const double
 // refinement).  PR = 0 is FP64 throughout.
 //
 // Record of element e (stride A.rstride): its 4n edge traces of phi-hat;
-// with TGT also, per edge point where e is upwind, sum_q bu_q v_q and
-// sum_q bu_q v_q^2 of the backtraced stage values v_q (4n each), and
-// M^n + dt sum_q bu_q V_q, E^n + dt sum_q bu_q V'_q with the volume terms
-// V of the balance laws (eq. 4.14 generalised to the RK quadrature); with
-// backtracking interface values, last, the 4n face values it offers.
+// with TGT also, per edge point where e is upwind, sum_q bu_q (v_q - c) and
+// sum_q bu_q (v_q - c)^2 of the backtraced stage values v_q (4n each) about
+// the element's mean c at t^n, then M^n + dt sum_q bu_q V_q,
+// sum W (phi^n - c)^2 + dt sum_q bu_q V'_q with the volume terms V, V' of
+// the mass and deviation energy balance laws (eq. 4.14 generalised to the
+// RK quadrature), and c; with backtracking interface values, last, the 4n
+// face values it offers.
 // ---------------------------------------------------------------------------
 // block shapes of the advect kernel: 0 = 256 lanes, 1 = the fewest whole
 // waves that hold one element, 2 = 512 lanes
@@ -505,7 +507,21 @@ __global__ __launch_bounds__((Shape2<N, BSEL>::BS)) void k_advect2d(Step2DArgs A
 
     if constexpr (TGT) {
         double* rec = A.rec + (size_t)(live ? e : 0) * A.rstride;
-        // upwind edge points: stage sums of the backtraced values
+        // the element's mean at t^n, c = M^n / sum W: the energy balance is
+        // taken for the deviation phi - c (the same law as for phi^2 in the
+        // PDE, computed from differences of like size)
+        double cmean = 0.0;
+        {
+            double sw = 0.0;
+            for (int pp = 0; pp < ND; ++pp) {
+                const double wq = tab[O::W + pp % N] * tab[O::W + pp / N];
+                cmean = fma(wq, s_x[sl][pp], cmean);
+                sw += wq;
+            }
+            cmean /= sw;
+        }
+        if (live && q == 0) rec[3 * NB + 2] = cmean;
+        // upwind edge points: stage sums of the backtraced values about c
         for (int tt = q; live && tt < NB; tt += ND) {
             const int side = tt / N, k = tt % N;
             const double vn = A.vface[(size_t)e * NB + tt];
@@ -519,31 +535,35 @@ __global__ __launch_bounds__((Shape2<N, BSEL>::BS)) void k_advect2d(Step2DArgs A
                 for (int c = 0; c < T.nq; ++c) {
                     const double v =
                         backtrace2<N>(A, s_cu[slot], s_cv[slot], s_cd[slot], s_x[slot], T.cu[c] * A.dt, s, r, out);
-                    fm = fma(T.bu[c], v, fm);
-                    fe = fma(T.bu[c], v * v, fe);
+                    const double dv = v - cmean;
+                    fm = fma(T.bu[c], dv, fm);
+                    fe = fma(T.bu[c], dv * dv, fe);
                 }
             }
             rec[NB + tt] = fm;
             rec[2 * NB + tt] = fe;
         }
-        // local mass and energy with the volume terms of the balance laws:
-        // advective form +div phi (mass) and +div phi^2 (energy),
-        // conservative form -div phi^2 (energy)
+        // local mass and deviation energy with the volume terms of the
+        // balance laws: mass +div phi (advective form); deviation energy
+        // +div psi^2 (advective), -div (psi^2 + 2 c psi) (conservative)
         double cm = 0.0, ce = 0.0;
         if (live) {
             const double Wp = A.dx * A.dy * tab[O::W + ii] * tab[O::W + jj];
+            const double dn = phi_p - cmean;
             cm = Wp * phi_p;
-            ce = Wp * phi_p * phi_p;
+            ce = Wp * dn * dn;
             if (A.vol && dv_p != 0.0) {
-                double vm = 0.0, ve = 0.0;
+                double vm = 0.0, vd = 0.0, ve = 0.0;
                 for (int c = 0; c < T.nq; ++c) {
                     const double v = backtrace2<N>(A, s_cu[slot], s_cv[slot], s_cd[slot], s_x[slot],
                                                    T.cu[c] * A.dt, tab[O::XI + ii], tab[O::XI + jj], out);
+                    const double dv = v - cmean;
                     vm = fma(T.bu[c], v, vm);
-                    ve = fma(T.bu[c], v * v, ve);
+                    vd = fma(T.bu[c], dv, vd);
+                    ve = fma(T.bu[c], dv * dv, ve);
                 }
                 if (!A.cons) cm += A.dt * Wp * dv_p * vm;
-                ce += A.dt * Wp * dv_p * (A.cons ? -ve : ve);
+                ce += A.dt * Wp * dv_p * (A.cons ? -fma(2.0 * cmean, vd, ve) : ve);
             }
         }
         if (inblk) {
@@ -965,15 +985,14 @@ __global__ __launch_bounds__(kBlock2) void k_constrain2d(Step2DArgs A)
 // boundary-constrained least squares with mass and energy rows (2D)
 //
 // With the boundary rows' solution `base` (as in k_constrain2d) and the
-// extra rows G (mass W, energy W o phi linearised at the previous Picard
-// iterate), both modes take the form
+// extra rows G (mass W, energy W o phi linearised at the previous iterate),
+// both modes take the form
 //   phi = base + Z S^{-1} (d_G - G base),  Z = P G^T,  S = G Z (+ I in SOFT),
 // with P = I - C_B^T Q C_B: the projector onto null(C_B) for HARD (Q =
 // (C_B C_B^T)^+, the prioritised reading), and (I + C_B^T C_B)^{-1} by
 // Woodbury for SOFT (Q = (I + C_B C_B^T)^{-1}), i.e. the paper's stacked
-// least squares.  Without boundary rows P = I and base = phi-hat.  HARD with
-// a mass row replaces the energy row by its part orthogonal to the mass row
-// (the same constraint set, better conditioned).  P W is a per-mesh table.
+// least squares.  Without boundary rows P = I and base = phi-hat.  P W is a
+// per-mesh table.
 // One block handles floor(256/n^2) elements, one lane per node.
 // ---------------------------------------------------------------------------
 template <int N>
@@ -986,7 +1005,7 @@ __global__ __launch_bounds__(kBlock2) void k_constrain2d_me(Step2DArgs A)
     __shared__ double s_v[E][ND];
     __shared__ double s_red[E][NDOT][ND];
     __shared__ double s_dot[E][NDOT];
-    __shared__ double s_tgt[E][2];
+    __shared__ double s_tgt[E][3];
     __shared__ unsigned long long s_mx[E][2];
     __shared__ int s_flag, s_pic;
     __shared__ unsigned long long s_stat[3];
@@ -1016,6 +1035,7 @@ __global__ __launch_bounds__(kBlock2) void k_constrain2d_me(Step2DArgs A)
     const double Wp = A.dx * A.dy * tab[O::W + i] * tab[O::W + j];
     const double* rec = A.rec + (size_t)ee * A.rstride;
     const double ph = live ? A.phihat[(size_t)ee * ND + p] : 0.0;
+    const double cme = rec[3 * NB + 2];  // the element's mean at t^n
 
     // face values (eq. 4.12a) and the face terms of the targets: inflow
     // positive, the upwind side's stage sums (own, neighbour's or ghost)
@@ -1034,20 +1054,25 @@ __global__ __launch_bounds__(kBlock2) void k_constrain2d_me(Step2DArgs A)
         double fm = 0.0, fe = 0.0;
         if (vn != 0.0) {
             const bool up = high ? vn < 0.0 : vn > 0.0;
+            // sum_q b_q v_q and sum_q b_q (v_q - c)^2 about this element's
+            // mean c; a neighbour's sums are about its own mean c', so with
+            // delta = c' - c: S2 + delta (2 S1 + delta) and S1 + c'
             double sm, se;
             if (up) {
-                sm = rec[NB + tt];
+                sm = rec[NB + tt] + cme;
                 se = rec[2 * NB + tt];
             } else if (nbe >= 0) {
-                sm = A.rec[(size_t)nbe * A.rstride + NB + nbt];
-                se = A.rec[(size_t)nbe * A.rstride + 2 * NB + nbt];
+                const double* rn = A.rec + (size_t)nbe * A.rstride;
+                const double s1 = rn[NB + nbt], cn = rn[3 * NB + 2], dl = cn - cme;
+                sm = s1 + cn;
+                se = fma(dl, fma(2.0, s1, dl), rn[2 * NB + nbt]);
             } else {
                 // inflow from outside: ghost values, linear in time
                 sm = se = 0.0;
                 for (int c = 0; c < T.nq; ++c) {
                     const double g = (1.0 - T.cu[c]) * A.gnow[gidx] + T.cu[c] * A.gnext[gidx];
                     sm = fma(T.bu[c], g, sm);
-                    se = fma(T.bu[c], g * g, se);
+                    se = fma(T.bu[c], (g - cme) * (g - cme), se);
                 }
             }
             const int side = tt / N, k = tt % N;
@@ -1066,11 +1091,15 @@ __global__ __launch_bounds__(kBlock2) void k_constrain2d_me(Step2DArgs A)
             fm += s_tr[slot][tt];
             fe += s_w[slot][tt];
         }
-        s_tgt[slot][0] = rec[3 * NB] + A.dt * fm;
-        s_tgt[slot][1] = rec[3 * NB + 1] + A.dt * fe;
+        const double Mn = rec[3 * NB] + A.dt * fm, Ed = rec[3 * NB + 1] + A.dt * fe;
+        s_tgt[slot][0] = Mn;
+        s_tgt[slot][1] = Ed;
+        s_tgt[slot][2] = Ed + cme * (2.0 * Mn - cme * A.sumW);
     }
     __syncthreads();
-    const double Mt = s_tgt[sl][0], Et = s_tgt[sl][1];
+    // M^{n+1}, the deviation energy Ed^{n+1} = sum W (phi - c)^2 and the
+    // energy E^{n+1} = Ed + 2 c M - c^2 sum W of phi^2
+    const double Mt = s_tgt[sl][0], Edt = s_tgt[sl][1], Et = s_tgt[sl][2];
 
     // element-wise sums of up to NDOT per-node values, in a fixed order
     auto dots = [&](int k, const double* vals) {
@@ -1134,65 +1163,64 @@ __global__ __launch_bounds__(kBlock2) void k_constrain2d_me(Step2DArgs A)
     }
     double prev = cur;
     int picard = 0;
+    // the energy row (section "Local energy conservation").  SOFT: the
+    // paper's linearisation sum W phi^(k-1) phi = E^{n+1}, stacked.  HARD:
+    // its fixed point, reached by Newton's linearisation of the same row,
+    // written for y = phi - sh with the target Tt:
+    //   sum W y^(k-1) y = (Tt + sum W (y^(k-1))^2) / 2,
+    // with a mass row as the deviation from the element's mean (sh = c,
+    // Tt = Ed^{n+1}: the same constraint on the mass row's level set),
+    // otherwise sh = 0, Tt = E^{n+1}.  Stop when max |phi^(k) - phi^(k-1)|
+    // < tol (strict, as printed).  Where the linearised row lies in the span
+    // of the others the sweep makes no change (singular if the row is not
+    // met).
+    const bool devf = !soft && mass;
+    const double sh = devf ? cme : 0.0;
     if (energy) {
-        // Picard on the energy row linearised at the previous iterate; stop
-        // when the change is below tol (strict), or, unconverged, when the
-        // iterate returns to within tol of the one two sweeps earlier
-        double older = prev;
+        const double Tt = devf ? Edt : Et;
         bool done = !live, conv = false;
         for (int k = 1; k <= A.emaxit; ++k) {
-            double gE = Wp * prev;
+            const double yv = prev - sh;
+            const double gE = Wp * yv;
             if (inblk) s_v[slot][p] = gE;
             __syncthreads();
-            double zE = bnd ? gE + cbt_q(false) : gE;
-            double dE = Et;
-            if (!soft && mass) {
-                const double v[2] = {gE * Wp, Wp * Wp};
-                dots(2, v);
-                const double mu = s_dot[sl][0] / s_dot[sl][1];
-                gE -= mu * Wp;
-                zE -= mu * zm;
-                dE -= mu * Mt;
-            }
-            double sig_m = 0.0, sig_e = 0.0;
-            bool bad = false;
+            const double zE = bnd ? gE + cbt_q(false) : gE;
+            double sig_m = 0.0, sig_e = 0.0, numer;
+            bool ok;
             if (mass) {
-                const double v[4] = {Wp * zE, gE * zm, gE * zE, gE * base};
-                dots(4, v);
+                const double v[5] = {Wp * zE, gE * zm, gE * zE, gE * (base - sh), gE * yv};
+                dots(5, v);
                 const double a11 = gz + shift, a12 = s_dot[sl][0], a21 = s_dot[sl][1], a22 = s_dot[sl][2] + shift;
-                const double r1 = Mt - gb, r2 = dE - s_dot[sl][3];
+                const double r1 = Mt - gb;
+                const double r2 = (soft ? Et : 0.5 * (Tt + s_dot[sl][4])) - s_dot[sl][3];
                 const double det = a11 * a22 - a12 * a21;
-                bad = !(det != 0.0) || !isfinite(det);
-                sig_m = (r1 * a22 - a12 * r2) / det;
-                sig_e = (a11 * r2 - a21 * r1) / det;
+                numer = a11 * r2 - a21 * r1;
+                ok = det != 0.0 && isfinite(det);
+                sig_m = ok ? (r1 * a22 - a12 * r2) / det : 0.0;
+                sig_e = ok ? numer / det : 0.0;
             } else {
-                const double v[2] = {gE * zE, gE * base};
-                dots(2, v);
+                const double v[3] = {gE * zE, gE * (base - sh), gE * yv};
+                dots(3, v);
                 const double S = s_dot[sl][0] + shift;
-                bad = !(S != 0.0) || !isfinite(S);
-                sig_e = (dE - s_dot[sl][1]) / S;
+                numer = (soft ? Et : 0.5 * (Tt + s_dot[sl][2])) - s_dot[sl][1];
+                ok = S != 0.0 && isfinite(S);
+                sig_e = ok ? numer / S : 0.0;
             }
-            const double nxt = base + zm * sig_m + zE * sig_e;
+            const double nxt = ok ? base + zm * sig_m + zE * sig_e : prev;
             const bool act = inblk && !done;
-            if (act && bad) fl |= FLAG_SINGULAR;
+            if (act && !ok && numer != 0.0) fl |= FLAG_SINGULAR;
             if constexpr (ND >= 64) {
                 slot_max<E, 2>(&s_mx[0][0], slot, act ? abs_bits(nxt - prev) : 0ull);
-                slot_max<E, 2>(&s_mx[0][1], slot, act ? abs_bits(nxt - older) : 0ull);
             } else if (act) {
                 atomicMax(&s_mx[slot][0], abs_bits(nxt - prev));
-                atomicMax(&s_mx[slot][1], abs_bits(nxt - older));
             }
             __syncthreads();
             if (inblk && !done) {
                 const double diff = __longlong_as_double((long long)s_mx[slot][0]);
-                const double back = __longlong_as_double((long long)s_mx[slot][1]);
-                older = prev;
                 prev = nxt;
                 picard = k;
                 if (diff < A.etol) {
                     conv = true;
-                    done = true;
-                } else if (k >= 2 && back < A.etol) {
                     done = true;
                 }
             }
@@ -1213,7 +1241,9 @@ __global__ __launch_bounds__(kBlock2) void k_constrain2d_me(Step2DArgs A)
     }
     if (inblk) s_v[slot][p] = phi;
     {
-        const double v[2] = {Wp * phi, Wp * phi * phi};
+        // energy residual of the row as imposed: HARD with a mass row in the
+        // deviation form, otherwise sum W phi^2 against E^{n+1}
+        const double v[2] = {Wp * phi, Wp * (phi - sh) * (phi - sh)};
         dots(2, v);  // its first barrier also publishes s_v
     }
     unsigned long long rmax = 0ull;  // this lane's largest boundary-row residual
@@ -1234,7 +1264,9 @@ __global__ __launch_bounds__(kBlock2) void k_constrain2d_me(Step2DArgs A)
     if (live) {
         if (p == 0) {
             if (mass) atomicMax(&s_stat[1], (unsigned long long)__double_as_longlong(fabs(s_dot[slot][0] - Mt)));
-            if (energy) atomicMax(&s_stat[2], (unsigned long long)__double_as_longlong(fabs(s_dot[slot][1] - Et)));
+            if (energy)
+                atomicMax(&s_stat[2],
+                          (unsigned long long)__double_as_longlong(fabs(s_dot[slot][1] - (devf ? Edt : Et))));
             atomicMax(&s_pic, picard);
         }
     }

@@ -121,7 +121,7 @@ BufSizes buffer_sizes(int dim, int kx, int ky, int n)
     z.nf = K * (dim == 1 ? n : n * n);
     z.nblocks = dim == 1 ? blocks1d(n, (int)K) : blocks2d(n, (int)K);
     // 2D: traces (4n), stage sums (8n), targets (2), backtraced face values (4n)
-    z.nrec = dim == 1 ? K * 8 : K * (16 * n + 2);
+    z.nrec = dim == 1 ? K * kRec1 : K * (16 * n + 3);
     z.nvf = dim == 1 ? K + 1 : K * 4 * n;
     z.ntab = (size_t)tab_offsets(dim, n).total;
     z.nstat = (size_t)z.nblocks * kStatSlots;
@@ -899,7 +899,10 @@ sl_status sl_step(sl_mesh* m, double dt, int32_t nsteps, const sl_step_opts* o)
         // volume terms of the balance laws: advective form for mass and
         // energy, conservative form for energy only
         B.vol = B.targets && (B.cons ? (opt.constraints & SL_C_ENERGY) != 0 : 1);
-        B.rstride = (B.targets ? 12 * m->n + 2 : 4 * m->n) + (opt.iface == SL_IFACE_BACKTRACK ? 4 * m->n : 0);
+        B.rstride = (B.targets ? 12 * m->n + 3 : 4 * m->n) + (opt.iface == SL_IFACE_BACKTRACK ? 4 * m->n : 0);
+        B.sumW = 0.0;
+        for (int j = 0; j < m->n; ++j)
+            for (int i = 0; i < m->n; ++i) B.sumW += m->dx * m->dy * m->T.w[i] * m->T.w[j];
         B.emaxit = opt.energy_maxit; B.etol = opt.energy_tol;
         B.iface = opt.iface;
         B.dx = m->dx; B.dy = m->dy;
@@ -949,6 +952,8 @@ sl_status sl_step(sl_mesh* m, double dt, int32_t nsteps, const sl_step_opts* o)
     double g[6];
     gram1d(m, g);
     A.g00 = g[0]; A.g01 = g[1]; A.g11 = g[2]; A.g02 = g[3]; A.g12 = g[4]; A.g22 = g[5];
+    A.sumW = 0.0;
+    for (int j = 0; j < m->n; ++j) A.sumW += m->dx * m->T.w[j];
     {
         // the block of the constrained system that does not depend on the
         // element: rows l(0), l(1) (boundary) and W (mass); an inactive row

@@ -59,11 +59,25 @@ enum { FLAG_NONFINITE = 1, FLAG_CONTAIN = 2, FLAG_SINGULAR = 4, FLAG_NOCONV = 8 
 // elements, max sweeps, max final relative correction] from the 2D advect
 constexpr int kStatSlots = 7;
 
+// 1D per-element record (doubles), written by the advect kernel and read by
+// the constrain kernel of the element and of its two neighbours:
+//   [0] T0, [1] T1          edge values at t^{n+1} (traces of phihat, or
+//                           backtraced values at upwind edges)
+//   [2] S1_L, [3] S1_R      sum_q b_q (v_q - c) over the RK abscissae of the
+//                           values v_q at the left / right edge (upwind
+//                           edges only, else zero)
+//   [4] S2_L, [5] S2_R      sum_q b_q (v_q - c)^2
+//   [6] M                   M^n + dt * volume term of the mass balance
+//   [7] Ed                  sum W (phi^n - c)^2 + dt * volume term of the
+//                           deviation energy balance
+//   [8] c                   the element's mean at t^n, M^n / sum W
+constexpr int kRec1 = 9;
+
 struct Step1DArgs {
     // fields
     const double* phi;     // [K][n] phi^n
     double* phihat;        // [K][n] remapped
-    double* rec;           // [K][8] per-element record
+    double* rec;           // [K][kRec1] per-element record
     double* phi_out;       // [K][n] phi^{n+1}
     // velocity
     const double* aN;      // nodal velocity
@@ -83,6 +97,7 @@ struct Step1DArgs {
     int K, periodic, cons, cmask, mode, emaxit, vol, targets;
     int iface;             // SL_IFACE_*: edge values by interpolation or backtracking
     double dx, invdx, dt, etol, vzero;
+    double sumW;  // sum of the element's quadrature weights W = dx w
     double g00, g01, g11, g02, g12, g22;  // constant Gram entries of rows l(0), l(1), W
     double g3i[9];  // inverse of the constant 3x3 block of the launch's system (rows l(0), l(1), W;
                     // inactive rows as identity; + I in SOFT), row-major
@@ -102,8 +117,9 @@ struct Step2DArgs {
     const double* phi;     // [K][n^2] phi^n
     double* phihat;        // [K][n^2] remapped
     double* rec;           // [K][rstride] edge traces of phihat (4n); with targets also the
-                           // upwind stage sums (2 x 4n) and the local mass and energy parts (2);
-                           // with backtracking, last, the offered face values (4n)
+                           // upwind stage sums about the element's mean c (2 x 4n), the local
+                           // mass and deviation energy parts (2) and c; with backtracking,
+                           // last, the offered face values (4n)
     double* phi_out;       // [K][n^2] phi^{n+1}
     const double* aN;      // [2][K][n^2] nodal velocity
     const double* aM;      // [2][K][n^2] tensor Chebyshev coefficients
@@ -120,6 +136,7 @@ struct Step2DArgs {
     int kx, ky, K, periodic, cons, cmask, mode, refine, precision, targets, vol, emaxit;
     int iface;             // SL_IFACE_*: edge values by interpolation or backtracking
     double dx, dy, invdx, invdy, dt, vzero, etol;
+    double sumW;           // sum of the element's quadrature weights dx dy w_i w_j
     RKTab rk;
     int bs;                // advect block shape: 0 = 256 lanes, 1 = fewest whole waves, 2 = 512 lanes
     // mixed-order meshes (elements grouped in buckets of one order; this

@@ -69,53 +69,17 @@ def announce(msg):
     sys.stdout.flush()
 
 
-EPS = np.finfo(np.float64).eps
-
-
-def energy_kappa(w, phi):
-    """Per-element amplification of rounding by a HARD energy row: 1/sin of
-    the angle between the energy row W*phi and the mass row W,
-    kappa_e = |W*phi|_2 / |W*phi - mu W|_2 (mu = projection coefficient).
-    A result constrained by both rows is determined in FP64 only to about
-    eps * kappa_e relative to the element's values."""
-    xi, wq = oracle.nodes(w.family, w.n)
-    if w.dim == 1:
-        Wr = wq * w.dx
-    else:
-        Wr = np.outer(wq, wq).ravel() * w.dx * w.dy
-    P = np.asarray(phi).reshape(w.K, w.nd)
-    g = Wr * P
-    mu = (g @ Wr) / (Wr @ Wr)
-    gp = g - mu[:, None] * Wr
-    return np.linalg.norm(g, axis=1) / np.maximum(np.linalg.norm(gp, axis=1), 1e-300)
-
-
-def assert_parity(w, g, o, cmask=None, mode=None, tol=1e-12, elems=None, solves=None):
-    """GPU-vs-oracle parity.  Without a HARD energy row: relative L2 <= tol.
-    With one (and a mass row) each energy-constrained solve is exact only to
-    about eps * kappa_e, and these errors add up over the Picard sweeps and
-    the steps (the sweep map has an eigenvalue near -1, so they are neither
-    damped nor amplified); element-wise bound
-    |g_e - o_e|_max <= max(tol, 64 eps kappa_e * solves) |o_e|_max,
-    solves = steps * sweeps (default from the workload)."""
-    cmask = w.cmask if cmask is None else cmask
-    mode = w.mode if mode is None else mode
+def assert_parity(w, g, o, tol=1e-12, elems=None):
+    """GPU-vs-oracle parity on the whole field (or on the elements `elems`):
+    relative L2 <= tol, and no value off by more than 10 tol of the largest
+    magnitude.  Returns the relative L2."""
     G = np.asarray(g).reshape(w.K, w.nd)
     O = np.asarray(o).reshape(w.K, w.nd)
     if elems is not None:
         G, O = G[elems], O[elems]
-    hard_e = (cmask & W.ENERGY) and (cmask & W.MASS) and mode == W.HARD
-    if not hard_e:
-        err = rel_l2(G, O)
-        assert err <= tol, f"rel L2 {err:.3e} > {tol:.0e}"
-        return err
-    k = energy_kappa(w, o)
-    if elems is not None:
-        k = k[elems]
-    if solves is None:
-        solves = max(1, w.nsteps) * max(1, w.energy_maxit)
-    bound = np.maximum(tol, 64 * EPS * k * solves) * np.maximum(np.abs(O).max(1), 1e-300)
-    e = np.abs(G - O).max(1)
-    bad = np.nonzero(e > bound)[0]
-    assert bad.size == 0, f"{bad.size} elements above the conditioning bound, worst ratio {np.max(e / bound):.2f}"
-    return rel_l2(G, O)
+    err = rel_l2(G, O)
+    assert err <= tol, f"rel L2 {err:.3e} > {tol:.0e}"
+    scale = max(float(np.abs(O).max()), 1e-300)
+    worst = float(np.abs(G - O).max()) / scale
+    assert worst <= 10 * tol, f"max abs error {worst:.3e} of max |o| > {10 * tol:.0e}"
+    return err

@@ -4,7 +4,7 @@ eq. 4.11) against the oracle, through the C-ABI, 1D and 2D.
 The velocity fields change sign inside the domain, so every case has faces
 where the flow leaves through the left and through the right edge, and the
 backtraces start from both edges.  Bar: relative L2 <= 1e-12 (FP64);
-mass+energy HARD cases use the kappa-aware bound of _parity.assert_parity."""
+mass+energy HARD cases are held to the same whole-field bar."""
 import math
 
 import numpy as np
