@@ -265,7 +265,8 @@ typedef struct {
 } sl_server_desc;
 
 typedef struct {
-    sl_mesh_desc mesh;    /* mesh.u0: host initial field; mesh.stream ignored */
+    sl_mesh_desc mesh;    /* mesh.u0: host initial field; mesh.stream ignored;
+                             mesh.orders must be NULL (uniform meshes only) */
     const double* a;      /* host nodal velocity, layout of sl_set_velocity */
     const double* div_a;  /* host nodal divergence or NULL */
     const double* ghost;  /* host ghost rows (GHOST meshes), layout of sl_set_ghost */
@@ -287,8 +288,8 @@ typedef struct {
 sl_status sl_server_create(const sl_server_desc* d, sl_server** out);
 
 /* Queue a request; *id names it in sl_server_result.  Errors: SL_E_INVALID
- * (bad request or descriptor), SL_E_NOMEM (it could never fit the budget,
- * or host memory). */
+ * (bad request or descriptor, or a mixed-order descriptor: mesh.orders is
+ * not NULL), SL_E_NOMEM (it could never fit the budget, or host memory). */
 sl_status sl_server_submit(sl_server* s, const sl_request* r, int64_t* id);
 
 /* Non-blocking: retire finished requests (field and statistics copied to

@@ -8,6 +8,7 @@
 #include <cstring>
 #include <new>
 #include <limits>
+#include <shared_mutex>
 #include <vector>
 
 #include "sl_internal.h"
@@ -131,20 +132,6 @@ BufSizes buffer_sizes(int dim, int kx, int ky, int n)
 }
 
 // 2D Gram constants are not needed; 1D rows l(0), l(1), W
-void gram1d(const sl_mesh* m, double g[6])
-{
-    double g00 = 0, g01 = 0, g11 = 0, g02 = 0, g12 = 0, g22 = 0;
-    for (int j = 0; j < m->n; ++j) {
-        const double W = m->dx * m->T.w[j];
-        g00 += m->T.l0[j] * m->T.l0[j];
-        g01 += m->T.l0[j] * m->T.l1[j];
-        g11 += m->T.l1[j] * m->T.l1[j];
-        g02 += m->T.l0[j] * W;
-        g12 += m->T.l1[j] * W;
-        g22 += W * W;
-    }
-    g[0] = g00; g[1] = g01; g[2] = g11; g[3] = g02; g[4] = g12; g[5] = g22;
-}
 
 }  // namespace
 
@@ -194,6 +181,81 @@ bool rk_tableau(int order, RKTab* T)
         else T->bu[f] += T->b[s];
     }
     return true;
+}
+
+namespace {
+std::shared_mutex g_dev_mu;
+thread_local int tl_hold = 0;  // depth of this thread's ApiHold
+}  // namespace
+
+ApiHold::ApiHold()
+{
+    if (tl_hold++ == 0) g_dev_mu.lock_shared();
+}
+ApiHold::~ApiHold()
+{
+    if (--tl_hold == 0) g_dev_mu.unlock_shared();
+}
+CaptureHold::CaptureHold() : saved(tl_hold)
+{
+    if (saved) g_dev_mu.unlock_shared();
+    tl_hold = 0;
+    g_dev_mu.lock();
+}
+CaptureHold::~CaptureHold()
+{
+    g_dev_mu.unlock();
+    tl_hold = saved;
+    if (saved) g_dev_mu.lock_shared();
+}
+
+bool step_opts_valid(const sl_step_opts& opt)
+{
+    return opt.rk >= 1 && opt.rk <= 4 && !(opt.constraints & ~7) &&
+           (opt.mode == SL_MODE_HARD || opt.mode == SL_MODE_SOFT) && opt.energy_maxit >= 0 &&
+           opt.energy_tol >= 0 && opt.refine_steps >= 0 &&
+           (opt.iface == SL_IFACE_INTERP || opt.iface == SL_IFACE_BACKTRACK);
+}
+
+bool step1d_setup(const Tables& T, int n, double dx, int periodic, int cons, const sl_step_opts& opt, double amax,
+                  Step1DArgs* A)
+{
+    rk_tableau(opt.rk, &A->rk);
+    A->periodic = periodic;
+    A->cons = cons;
+    A->cmask = opt.constraints; A->mode = opt.mode; A->emaxit = opt.energy_maxit; A->etol = opt.energy_tol;
+    A->iface = opt.iface;
+    A->targets = (opt.constraints & (SL_C_MASS | SL_C_ENERGY)) != 0;
+    A->vol = A->targets;
+    A->dx = dx; A->invdx = 1.0 / dx;
+    A->vzero = 1e-12 * amax;
+    // Gram entries of the rows l(0), l(1) (boundary) and W (mass)
+    double g00 = 0, g01 = 0, g11 = 0, g02 = 0, g12 = 0, g22 = 0;
+    A->sumW = 0.0;
+    for (int j = 0; j < n; ++j) {
+        const double W = dx * T.w[j];
+        g00 += T.l0[j] * T.l0[j];
+        g01 += T.l0[j] * T.l1[j];
+        g11 += T.l1[j] * T.l1[j];
+        g02 += T.l0[j] * W;
+        g12 += T.l1[j] * W;
+        g22 += W * W;
+        A->sumW += W;
+    }
+    A->g00 = g00; A->g01 = g01; A->g11 = g11; A->g02 = g02; A->g12 = g12; A->g22 = g22;
+    // the block of the constrained system that does not depend on the
+    // element: rows l(0), l(1) (boundary) and W (mass); an inactive row is an
+    // identity row, SOFT adds I
+    const bool bnd = (opt.constraints & SL_C_BOUNDARY) != 0, mass = (opt.constraints & SL_C_MASS) != 0;
+    const bool ac[3] = {bnd, bnd, mass};
+    double G3[9] = {bnd ? g00 : 0.0, bnd ? g01 : 0.0, (bnd && mass) ? g02 : 0.0,
+                    bnd ? g01 : 0.0, bnd ? g11 : 0.0, (bnd && mass) ? g12 : 0.0,
+                    (bnd && mass) ? g02 : 0.0, (bnd && mass) ? g12 : 0.0, mass ? g22 : 0.0};
+    for (int a = 0; a < 3; ++a) {
+        if (opt.mode == SL_MODE_HARD && !ac[a]) G3[a * 3 + a] = 1.0;
+        if (opt.mode == SL_MODE_SOFT) G3[a * 3 + a] += 1.0;
+    }
+    return invert(3, G3, A->g3i);
 }
 
 }  // namespace sl
@@ -559,6 +621,9 @@ static sl_status set_velocity_mixed(sl_mesh* m, const double* a, const double* d
     double am[2] = {0.0, 0.0};
     for (int c = 0; c < 2; ++c)
         for (size_t i = 0; i < nf; ++i) am[c] = std::max(am[c], std::fabs(a[c * nf + i]));
+    // steps already queued on the mesh's stream read the velocity arrays:
+    // let them finish before the copies below overwrite them
+    if (hipStreamSynchronize(m->stream)) return SL_E_DEVICE;
     std::vector<double> da(2 * nf), dd(div_a ? nf : 0);
     for (int e = 0; e < m->K; ++e) {
         const int n = m->orders[e], nd = n * n;
@@ -622,6 +687,9 @@ static sl_status step_mixed(sl_mesh* m, double dt, int32_t nsteps, const sl_step
             m->gexec = nullptr;
             m->graph = nullptr;
             m->graph_ok = false;
+            // the capture holds out this library's allocating and
+            // synchronising calls in other threads
+            const CaptureHold excl;
             if (hipStreamBeginCapture(m->stream, hipStreamCaptureModeThreadLocal)) return SL_E_DEVICE;
             const int bad = mixed_launch_step(m, B, m->phi, m->phi2) | mixed_launch_step(m, B, m->phi2, m->phi);
             hipGraph_t g = nullptr;
@@ -655,6 +723,7 @@ static sl_status step_mixed(sl_mesh* m, double dt, int32_t nsteps, const sl_step
 
 sl_status sl_create_mesh(const sl_mesh_desc* d, sl_mesh** out)
 {
+    const ApiHold hold;
     if (!out) return SL_E_INVALID;
     *out = nullptr;
     if (!d || !d->u0) return SL_E_INVALID;
@@ -735,6 +804,7 @@ sl_status sl_create_mesh(const sl_mesh_desc* d, sl_mesh** out)
 
 sl_status sl_destroy_mesh(sl_mesh* m)
 {
+    const ApiHold hold;
     if (!m) return SL_E_INVALID;
     (void)hipStreamSynchronize(m->stream);
     release(m);
@@ -764,6 +834,7 @@ sl_status sl_mesh_bytes(const sl_mesh_desc* d, int32_t ghost_rows, size_t* bytes
 
 sl_status sl_set_velocity(sl_mesh* m, const double* a, const double* div_a)
 {
+    const ApiHold hold;
     if (!m || !a) return SL_E_INVALID;
     if (m->mixed) return set_velocity_mixed(m, a, div_a);
     const size_t nf = (size_t)m->K * m->nd;
@@ -805,6 +876,7 @@ int32_t sl_ghost_count(const sl_mesh* m)
 
 sl_status sl_set_ghost(sl_mesh* m, const double* g, int32_t nrows)
 {
+    const ApiHold hold;
     if (!m) return SL_E_INVALID;
     if (m->bc == SL_BC_PERIODIC) return SL_E_STATE;
     if (!g || nrows < 1) return SL_E_INVALID;
@@ -855,14 +927,12 @@ static void ev_end(sl_mesh* m, int k)
 
 sl_status sl_step(sl_mesh* m, double dt, int32_t nsteps, const sl_step_opts* o)
 {
+    const ApiHold hold;
     if (!m) return SL_E_INVALID;
     sl_step_opts opt = {4, SL_C_BOUNDARY, SL_MODE_HARD, 50, 3, SL_IFACE_INTERP, 1e-8};
     if (o) opt = *o;
     if (!(dt > 0) || !std::isfinite(dt) || nsteps < 0) return SL_E_INVALID;
-    if (opt.rk < 1 || opt.rk > 4 || (opt.constraints & ~7) || (opt.mode != SL_MODE_HARD && opt.mode != SL_MODE_SOFT) ||
-        opt.energy_maxit < 0 || !(opt.energy_tol >= 0) || opt.refine_steps < 0 ||
-        (opt.iface != SL_IFACE_INTERP && opt.iface != SL_IFACE_BACKTRACK))
-        return SL_E_INVALID;
+    if (!step_opts_valid(opt)) return SL_E_INVALID;
     if (m->mixed && opt.iface != SL_IFACE_INTERP) return SL_E_INVALID;
     if (!m->has_velocity) return SL_E_STATE;
     if (m->bc != SL_BC_PERIODIC && m->ghost_rows < 1) return SL_E_STATE;
@@ -936,39 +1006,16 @@ sl_status sl_step(sl_mesh* m, double dt, int32_t nsteps, const sl_step_opts* o)
 
     Step1DArgs A;
     std::memset(&A, 0, sizeof(A));
-    rk_tableau(opt.rk, &A.rk);
+    if (!step1d_setup(m->T, m->n, m->dx, m->bc == SL_BC_PERIODIC, m->form == SL_FORM_CONSERVATIVE, opt,
+                      m->amax[0], &A))
+        return SL_E_INVALID;
     A.aN = m->aN; A.aM = m->aM; A.divN = m->divN; A.divM = m->divM; A.vface = m->vface; A.tab = m->tab;
     A.aM4 = m->aM + (size_t)m->K * m->n;
     A.divM4 = m->aM + (size_t)m->K * (m->n + 4);
     A.rec = m->rec; A.phihat = m->phihat;
     A.flag_part = m->flag_part; A.stat_part = m->stat_part; A.nblk = m->nblocks; A.vdeg = m->vdeg;
-    A.K = m->K; A.periodic = m->bc == SL_BC_PERIODIC; A.cons = m->form == SL_FORM_CONSERVATIVE;
-    A.cmask = opt.constraints; A.mode = opt.mode; A.emaxit = opt.energy_maxit; A.etol = opt.energy_tol;
-    A.iface = opt.iface;
-    A.targets = (opt.constraints & (SL_C_MASS | SL_C_ENERGY)) != 0;
-    A.vol = A.targets;
-    A.dx = m->dx; A.invdx = 1.0 / m->dx; A.dt = dt;
-    A.vzero = 1e-12 * m->amax[0];
-    double g[6];
-    gram1d(m, g);
-    A.g00 = g[0]; A.g01 = g[1]; A.g11 = g[2]; A.g02 = g[3]; A.g12 = g[4]; A.g22 = g[5];
-    A.sumW = 0.0;
-    for (int j = 0; j < m->n; ++j) A.sumW += m->dx * m->T.w[j];
-    {
-        // the block of the constrained system that does not depend on the
-        // element: rows l(0), l(1) (boundary) and W (mass); an inactive row
-        // is an identity row, SOFT adds I
-        const bool bnd = (opt.constraints & SL_C_BOUNDARY) != 0, mass = (opt.constraints & SL_C_MASS) != 0;
-        const bool ac[3] = {bnd, bnd, mass};
-        double G3[9] = {bnd ? g[0] : 0.0, bnd ? g[1] : 0.0, (bnd && mass) ? g[3] : 0.0,
-                        bnd ? g[1] : 0.0, bnd ? g[2] : 0.0, (bnd && mass) ? g[4] : 0.0,
-                        (bnd && mass) ? g[3] : 0.0, (bnd && mass) ? g[4] : 0.0, mass ? g[5] : 0.0};
-        for (int a = 0; a < 3; ++a) {
-            if (opt.mode == SL_MODE_HARD && !ac[a]) G3[a * 3 + a] = 1.0;
-            if (opt.mode == SL_MODE_SOFT) G3[a * 3 + a] += 1.0;
-        }
-        if (!invert(3, G3, A.g3i)) return SL_E_INVALID;
-    }
+    A.K = m->K;
+    A.dt = dt;
     for (int s = 0; s < nsteps; ++s) {
         if (m->bc != SL_BC_PERIODIC) {
             const long r0 = std::min<long>(m->ghost_step, m->ghost_rows - 1);
@@ -996,6 +1043,7 @@ sl_status sl_step(sl_mesh* m, double dt, int32_t nsteps, const sl_step_opts* o)
 
 sl_status sl_read(sl_mesh* m, double* u_out, sl_stats* st)
 {
+    const ApiHold hold;
     if (!m) return SL_E_INVALID;
     if (hipStreamSynchronize(m->stream)) return SL_E_DEVICE;
     const size_t nf = m->mixed ? m->dofs : (size_t)m->K * m->nd;
@@ -1087,6 +1135,7 @@ sl_status sl_device_field(sl_mesh* m, double** d_phi, void** stream)
 
 sl_status sl_set_profiling(sl_mesh* m, int32_t enable)
 {
+    const ApiHold hold;
     if (!m) return SL_E_INVALID;
     (void)hipStreamSynchronize(m->stream);
     for (int k = 0; k < KER_COUNT; ++k) {
@@ -1101,6 +1150,7 @@ sl_status sl_set_profiling(sl_mesh* m, int32_t enable)
 
 sl_status sl_kernel_time(sl_mesh* m, int32_t which, double* total_ms, int64_t* launches)
 {
+    const ApiHold hold;
     if (!m || which < 0 || which >= KER_COUNT) return SL_E_INVALID;
     if (hipStreamSynchronize(m->stream)) return SL_E_DEVICE;
     auto& v = m->pending[which];

@@ -104,6 +104,33 @@ struct Step1DArgs {
     RKTab rk;
 };
 
+// Ordering of the library's graph captures against its own calls that may
+// allocate, free or synchronise device memory from other host threads: a
+// capture that such a call disturbs fails (the stream's capture is
+// invalidated, or the call is refused while a capture is active), so
+// distinct meshes used from several threads could see spurious device
+// errors.  ApiHold is taken (shared, nestable within a thread) by the public
+// calls that make such calls; CaptureHold (exclusive) by a capture, which
+// only enqueues launches; it gives up the thread's own shared hold meanwhile.
+struct ApiHold {
+    ApiHold();
+    ~ApiHold();
+};
+struct CaptureHold {
+    CaptureHold();
+    ~CaptureHold();
+    int saved;
+};
+
+// Step options within their documented ranges.
+bool step_opts_valid(const sl_step_opts& opt);
+// Launch constants of a 1D step that do not depend on the buffers: tableau,
+// options, the Gram entries of the rows l(0), l(1), W and the inverse of
+// their constant 3x3 block, sum W, and the stagnation threshold 1e-12 amax
+// (amax = max |a| over the nodes).  False if that block is singular.
+bool step1d_setup(const Tables& T, int n, double dx, int periodic, int cons, const sl_step_opts& opt, double amax,
+                  Step1DArgs* A);
+
 // vscale: mesh-wide max |a|, the floor of the noise threshold of the
 // velocity series' effective degree
 int launch_prep1d(int n, int K, int periodic, int has_div, const double* aN, double* aM, double* divN,

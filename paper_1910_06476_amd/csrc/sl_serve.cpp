@@ -138,6 +138,7 @@ extern "C" {
 
 sl_status sl_server_create(const sl_server_desc* d, sl_server** out)
 {
+    const sl::ApiHold hold;
     if (!out) return SL_E_INVALID;
     *out = nullptr;
     if (!d || d->max_active < 1 || d->max_active > 64 || d->hbm_budget == 0) return SL_E_INVALID;
@@ -151,7 +152,11 @@ sl_status sl_server_create(const sl_server_desc* d, sl_server** out)
 
 sl_status sl_server_submit(sl_server* s, const sl_request* q, int64_t* id)
 {
+    const sl::ApiHold hold;
     if (!s || !q || !id || !q->mesh.u0 || !q->a || q->nsteps < 0 || !(q->dt > 0)) return SL_E_INVALID;
+    // requests are uniform meshes: the field, velocity and result are sized
+    // from kx, ky and order, and the descriptor keeps no caller pointer
+    if (q->mesh.orders) return SL_E_INVALID;
     if (q->mesh.bc != SL_BC_PERIODIC && (!q->ghost || q->ghost_rows < 1)) return SL_E_INVALID;
     std::unique_ptr<Request> r(new (std::nothrow) Request());
     if (!r) return SL_E_NOMEM;
@@ -188,6 +193,7 @@ sl_status sl_server_submit(sl_server* s, const sl_request* q, int64_t* id)
 
 sl_status sl_server_progress(sl_server* s, int32_t* active, int32_t* waiting)
 {
+    const sl::ApiHold hold;
     if (!s) return SL_E_INVALID;
     // retire finished requests (in admission order among those done)
     for (size_t i = 0; i < s->active.size();) {
@@ -221,6 +227,7 @@ sl_status sl_server_progress(sl_server* s, int32_t* active, int32_t* waiting)
 
 sl_status sl_server_drain(sl_server* s)
 {
+    const sl::ApiHold hold;
     if (!s) return SL_E_INVALID;
     int32_t a = 1, w = 1;
     while (a > 0 || w > 0) {
@@ -236,6 +243,7 @@ sl_status sl_server_drain(sl_server* s)
 
 sl_status sl_server_result(sl_server* s, int64_t id, double* u_out, sl_stats* st, sl_request_timing* tm)
 {
+    const sl::ApiHold hold;
     if (!s) return SL_E_INVALID;
     auto it = s->all.find(id);
     if (it == s->all.end()) return SL_E_INVALID;
@@ -257,6 +265,7 @@ sl_status sl_server_result(sl_server* s, int64_t id, double* u_out, sl_stats* st
 
 sl_status sl_server_latency(sl_server* s, double p50_p99[2], int64_t* samples, int64_t* dof_updates)
 {
+    const sl::ApiHold hold;
     if (!s || !p50_p99) return SL_E_INVALID;
     std::vector<float> v = s->step_ms;
     p50_p99[0] = p50_p99[1] = 0.0;
@@ -272,6 +281,7 @@ sl_status sl_server_latency(sl_server* s, double p50_p99[2], int64_t* samples, i
 
 sl_status sl_server_destroy(sl_server* s)
 {
+    const sl::ApiHold hold;
     if (!s) return SL_E_INVALID;
     for (Request* r : s->active) {
         if (r->ev.size()) (void)hipEventSynchronize(r->ev.back());

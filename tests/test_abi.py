@@ -128,5 +128,20 @@ def test_server_host_side_validation(sl):
             s.result(rid + 100)
         with pytest.raises(sl.SLError):  # ghost mesh without ghost rows
             s.submit(1, 16, 1, n - 1, np.zeros(16 * n), np.ones(16 * n), dt=1e-4, nsteps=1, bc=sl.SL_BC_GHOST)
+        # a mixed-order descriptor (mesh.orders set) is refused: requests are
+        # sized as uniform meshes
+        kx = ky = 2
+        orders = np.array([3, 4, 3, 4], dtype=np.int32)
+        dofs = int(((orders + 1) ** 2).sum())
+        u0, av = np.zeros(dofs), np.ones(2 * dofs)
+        q = sl.Request()
+        q.mesh = sl.MeshDesc(dim=2, kx=kx, ky=ky, order=3, nodes=0, bc=0, form=0, precision=0, x0=0.0, x1=1.0,
+                             y0=0.0, y1=1.0, u0=u0.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), stream=None,
+                             orders=orders.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+        q.a = av.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        q.nsteps, q.dt, q.opts = 1, 1e-4, sl.step_opts()
+        rid = ctypes.c_int64(-1)
+        assert sl.lib().sl_server_submit(s.h, ctypes.byref(q), ctypes.byref(rid)) == sl.SL_E_INVALID
     finally:
         s.close()
+

@@ -116,6 +116,33 @@ def test_uniform_orders_match_the_uniform_mesh():
     assert np.array_equal(g, u)
 
 
+def test_velocity_change_right_after_steps():
+    """A new velocity set right after sl_step, with no read in between, must
+    not change the steps already queued: two graph replays (four steps) with
+    the velocity a, then four steps with a / 2, equal the oracle run in the
+    same two legs."""
+    import paper_1910_06476_amd as P
+    w = _case(6, 5, (4, 6, 8, 12), seed=6, nsteps=4)
+    announce("mixed velocity change after steps")
+    a1 = w.velocity()
+    a2 = 0.5 * a1
+    m = P.from_mixed_workload(w)
+    try:
+        m.step(w.dt, 4, rk=w.rk, constraints=W.BOUNDARY, mode=w.mode)
+        m.set_velocity(a2)
+        m.step(w.dt, 4, rk=w.rk, constraints=W.BOUNDARY, mode=w.mode)
+        rc, g, st = m.read()
+    finally:
+        m.close()
+    p = oracle.Params(dim=2, kx=w.kx, ky=w.ky, n=int(w.orders[0]), family=w.family, bc=W.PERIODIC, form=w.form,
+                      rk=w.rk, cmask=W.BOUNDARY, mode=w.mode, energy_maxit=0, vel_kind=0, x0=w.x0, x1=w.x1,
+                      y0=w.y0, y1=w.y1, energy_tol=0.0)
+    o, _ = oracle.step_mixed(p, w.orders, w.initial(), a=a1, dt=w.dt, nsteps=4)
+    o, _ = oracle.step_mixed(p, w.orders, o, a=a2, dt=w.dt, nsteps=4)
+    assert rc == 0
+    assert rel_l2(g, o) <= TOL, rel_l2(g, o)
+
+
 def test_c4_submesh_accuracy_and_parity():
     """A 32x32 piece of the C4 recipe (orders {4,6,8,12}, swirl, eight
     Fourier modes), five steps: oracle parity of the whole field."""
