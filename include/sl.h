@@ -243,6 +243,48 @@ sl_status sl_kernel_time(sl_mesh* m, int32_t which, double* total_ms, int64_t* l
  * memory budget.  d->u0 is not read.  Errors: SL_E_INVALID. */
 sl_status sl_mesh_bytes(const sl_mesh_desc* d, int32_t ghost_rows, size_t* bytes);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): nsteps 1D
+ * steps, the work sl_step does on a 1D mesh, on the caller's device
+ * buffers, with no mesh and no allocation.  Each call prepares the velocity
+ * (its Chebyshev series, divergence and face speeds), then runs the steps on
+ * `stream` (hipStream_t, or NULL for the null stream) and returns without
+ * synchronising.  The kernels' scratch memory is one fixed device array of
+ * the library (about 54 MB, held on each GPU the library runs on until the
+ * process ends); its device address is looked up, and the reference tables
+ * of every order are copied into it, at the first call on a device (a
+ * synchronous copy).  Every call on one GPU shares that array and it keeps
+ * the last call's contents, so calls that overlap on one GPU (other streams
+ * or host threads) race and must be ordered by the caller.
+ *   K, order   elements and order N: 1 <= K <= 65536, 1 <= N <= 16,
+ *              K (N + 1) <= 1114112; larger sizes are rejected with
+ *              SL_E_INVALID before any device call
+ *   nodes, bc, form   as in sl_mesh_desc (bc: SL_BC_PERIODIC or SL_BC_GHOST)
+ *   x0, x1     the interval
+ *   phi_in     device, K (N + 1) values, the field at t (layout of u0)
+ *   phi_out    device, K (N + 1) values, the field after nsteps steps; may
+ *              equal phi_in
+ *   a          device, K (N + 1) nodal velocity values
+ *   div_a      device, K (N + 1) nodal values of div(a), or NULL to take the
+ *              divergence of the interpolant
+ *   amax       host value: the largest |a| over the nodes (the stagnation
+ *              threshold 1e-12 amax and the time-step check, as sl_step)
+ *   ghost      device, SL_BC_GHOST only: nsteps + 1 rows of [left, right]
+ *              outside values, row r at time t + r dt
+ *   dt, nsteps, opts   as sl_step (opts NULL: defaults); nsteps = 0 copies
+ *              phi_in to phi_out
+ *   stats      device, 4 doubles or NULL: the largest boundary, mass and
+ *              energy residuals and energy sweep count over the call's steps
+ *   flags      device, 1 int32 or NULL: the call's flag bits (sl_stats.flags)
+ * Results equal those of sl_create_mesh + sl_set_velocity + sl_step on the
+ * same data to rounding (this call evaluates the whole velocity series,
+ * sl_step only its effective degree).  Errors: SL_E_INVALID, SL_E_CFL,
+ * SL_E_DEVICE. */
+sl_status sl_step1d_static(int32_t K, int32_t order, int32_t nodes, int32_t bc, int32_t form, double x0, double x1,
+                           const double* phi_in, double* phi_out, const double* a, const double* div_a, double amax,
+                           const double* ghost, double dt, int32_t nsteps, const sl_step_opts* opts, double* stats,
+                           int32_t* flags, void* stream);
+
 /* ------------------------------------------------------------------------
  * Request loop (continuous batching of independent problems on one GPU).
  *

@@ -33,7 +33,7 @@ EXPORTS = ["sl_create_mesh", "sl_set_velocity", "sl_set_ghost", "sl_ghost_count"
            "sl_destroy_mesh", "sl_status_string", "sl_max_dt", "sl_node_coords", "sl_device_field",
            "sl_set_profiling", "sl_kernel_time", "sl_mesh_bytes", "sl_server_create", "sl_server_submit",
            "sl_server_progress", "sl_server_drain", "sl_server_result", "sl_server_latency",
-           "sl_server_destroy"]
+           "sl_server_destroy", "sl_step1d_static"]
 
 
 class MeshDesc(ctypes.Structure):
@@ -122,6 +122,9 @@ def lib():
         L.sl_server_result.argtypes = [vp, ctypes.c_int64, dp, ctypes.POINTER(Stats), ctypes.POINTER(RequestTiming)]
         L.sl_server_latency.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
         L.sl_server_destroy.argtypes = [vp]
+        i32, f64 = ctypes.c_int32, ctypes.c_double
+        L.sl_step1d_static.argtypes = [i32, i32, i32, i32, i32, f64, f64, vp, vp, vp, vp, f64, vp, f64, i32,
+                                       ctypes.POINTER(StepOpts), vp, vp, vp]
         for name in EXPORTS:
             if name not in ("sl_status_string", "sl_max_dt", "sl_ghost_count"):
                 getattr(L, name).restype = ctypes.c_int32
@@ -192,6 +195,17 @@ def step_opts(rk=4, constraints=SL_C_BOUNDARY, mode=SL_MODE_HARD, energy_maxit=5
 def sl_step(m, dt, nsteps=1, opts=None):
     o = opts if opts is not None else step_opts()
     _check(lib().sl_step(m, float(dt), int(nsteps), ctypes.byref(o)), "sl_step")
+
+
+def sl_step1d_static(K, order, phi_in, phi_out, a, amax, dt, nsteps=1, opts=None, div_a=0, ghost=0,
+                     nodes=SL_NODES_GL, bc=SL_BC_PERIODIC, form=SL_FORM_ADVECTIVE, x0=0.0, x1=1.0, stats=0,
+                     flags=0, stream=0):
+    """1D steps on caller device buffers, allocating nothing (device
+    addresses as ints: phi_in, phi_out, a, div_a, ghost, stats, flags)."""
+    o = opts if opts is not None else step_opts()
+    _check(lib().sl_step1d_static(K, order, nodes, bc, form, x0, x1, phi_in, phi_out, a, div_a or None, amax,
+                                  ghost or None, dt, nsteps, ctypes.byref(o), stats or None, flags or None,
+                                  stream or None), "sl_step1d_static")
 
 
 def sl_read(m, size: int):

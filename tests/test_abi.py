@@ -145,3 +145,30 @@ def test_server_host_side_validation(sl):
     finally:
         s.close()
 
+
+def test_step1d_static_rejects_before_any_device_call(sl):
+    """The allocation-free 1D entry point refuses sizes beyond its scratch
+    array (65536 elements, order 16) and bad arguments with SL_E_INVALID,
+    before touching the device (this runs without a GPU)."""
+    L = sl.lib()
+    one = ctypes.c_void_p(16)  # never dereferenced: validation fails first
+    o = sl.step_opts()
+    cases = [
+        dict(K=65537, order=16), dict(K=0, order=4), dict(K=100, order=17), dict(K=100, order=0),
+        dict(K=100, order=4, nsteps=-1), dict(K=100, order=4, dt=0.0), dict(K=100, order=4, bc=2),
+        dict(K=100, order=4, nodes=3), dict(K=100, order=4, x1=0.0), dict(K=100, order=4, amax=-1.0),
+    ]
+    for c in cases:
+        K, order = c["K"], c["order"]
+        rc = L.sl_step1d_static(K, order, c.get("nodes", 0), c.get("bc", 0), 0, 0.0, c.get("x1", 1.0), one, one,
+                                one, None, c.get("amax", 1.0), None, c.get("dt", 1e-6), c.get("nsteps", 1),
+                                ctypes.byref(o), None, None, None)
+        assert rc == sl.SL_E_INVALID, c
+    # a NULL field pointer, and a ghost mesh without ghost rows
+    assert L.sl_step1d_static(100, 4, 0, 0, 0, 0.0, 1.0, None, one, one, None, 1.0, None, 1e-6, 1,
+                              ctypes.byref(o), None, None, None) == sl.SL_E_INVALID
+    assert L.sl_step1d_static(100, 4, 0, 1, 0, 0.0, 1.0, one, one, one, None, 1.0, None, 1e-6, 1,
+                              ctypes.byref(o), None, None, None) == sl.SL_E_INVALID
+    # the time-step restriction, as sl_step
+    assert L.sl_step1d_static(100, 4, 0, 0, 0, 0.0, 1.0, one, one, one, None, 1.0, None, 1e-2, 1,
+                              ctypes.byref(o), None, None, None) == sl.SL_E_CFL
