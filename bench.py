@@ -1,19 +1,24 @@
 """Benchmark of the explicit semi-Lagrangian spectral step on one MI355X.
 
-Workload (the headline configuration): 1D variable-velocity advection
-a(x) = 1 + sin(pi x)/2 on [0,2] periodic, K = 65536 elements of order 16
-(17 Gauss-Legendre nodes, 1,114,112 DOF), u0 = exp(-40 (x-1)^2), RK4,
-boundary + mass + energy constraints (HARD), dt = 0.2 * min node gap * dx /
-1.5, FP64.  One "step" is one sl_step over the whole mesh (all stages of the
-method).  Inputs are resident in HBM before the timed region.
+Workload of the headline line (the largest configuration on one GPU): the
+2D mixed-order batch, 316 x 316 quads on [0,1]^2 (8.08 M DOF) with the order
+of each element drawn from {4, 6, 8, 12} by seed, the swirl velocity
+a = (sin^2(pi x) sin(2 pi y), -sin^2(pi y) sin(2 pi x)), eight random Fourier
+modes, periodic, boundary rows (HARD), RK4, FP64.  One "step" is one sl_step
+over the whole mesh (every order bucket, all stages of the method), replayed
+from the mesh's captured graph.  Inputs are resident in HBM before the timed
+region.
 
-Prints one JSON line: DOF-updates/s over K timed steps, the L2 error against
-the closed-form solution at the final time, the served per-step latency
-(p50/p99), the roofline of the dominant kernel (HIP events on the mesh's
-stream, algorithmic flop count per element from the functions below), and
-the CPU oracle timed on a bounded sample.  --workload c3 runs the 2D
-rotation configuration, --workload serve a Poisson stream of independent
-problems through the request loop.
+Prints one JSON line: DOF-updates/s over K timed steps, the stated L2 error
+(here of a forward-and-back round trip under the steady swirl, whose exact
+result is the initial field), the served per-step latency (p50/p99), the
+roofline of the dominant kernel (HIP events on the mesh's stream around
+every launch, algorithmic flop count per element from the functions below),
+and the CPU oracle timed on a bounded sample.  Other workloads: --workload
+c2 (the 1D configuration with boundary, mass and energy rows), c3 (2D
+rotation, --precision fp64 / fp32r / bf16r), c2bw (HBM probe), c1 (launch
+latency), serve (a Poisson stream of independent problems through the
+request loop).
 """
 from __future__ import annotations
 
@@ -127,10 +132,18 @@ def single_thread_rate(run, dofs: int, est_s: float, limit_s: float = 15.0):
         gomp.omp_set_num_threads(prev)
 
 
-def cpu_baseline(w, budget_s: float = 12.0):
+def native_oracle():
+    """The oracle built with -O3 -march=native on this host (once)."""
     import oracle
+    if not getattr(native_oracle, "done", False):
+        oracle.use_native_build()
+        native_oracle.done = True
+    return oracle
+
+
+def cpu_baseline(w, budget_s: float = 12.0):
     import workloads as W
-    oracle.build(force=False)
+    oracle = native_oracle()
     p = oracle.params_from(w)
     a, _ = w.velocity()
     phi = w.initial()
@@ -150,15 +163,14 @@ def cpu_baseline(w, budget_s: float = 12.0):
     return {"value": w.dofs * steps / el, "unit": "DOF-updates/s", "cores": cores, "kind": "oracle",
             "single_thread_value": one_thread,
             "sample": f"full mesh (K={w.K}, n={w.n}), {steps} steps after 1 warm-up step, "
-                      f"{el:.1f} s, OpenMP threads={cores}", **host_cpu()}
+                      f"{el:.1f} s, OpenMP threads={cores}, gcc -O3 -march=native", **host_cpu()}
 
 
 def cpu_baseline_mixed(w, budget_s: float = 12.0):
     """The mixed-order oracle on `w` (a piece of the C4 recipe), timed over
     as many steps as fit in about budget_s."""
-    import oracle
     import workloads as W
-    oracle.build(force=False)
+    oracle = native_oracle()
     p = oracle.Params(dim=2, kx=w.kx, ky=w.ky, n=int(w.orders[0]), family=w.family, bc=W.PERIODIC, form=w.form,
                       rk=w.rk, cmask=W.BOUNDARY, mode=w.mode, energy_maxit=0, vel_kind=0, x0=w.x0, x1=w.x1,
                       y0=w.y0, y1=w.y1, energy_tol=0.0)
@@ -176,7 +188,8 @@ def cpu_baseline_mixed(w, budget_s: float = 12.0):
     return {"value": w.dofs * steps / el, "unit": "DOF-updates/s", "cores": cores, "kind": "oracle",
             "single_thread_value": one_thread,
             "sample": f"a {w.kx}x{w.ky} mesh of the same recipe (orders {{4,6,8,12}} by seed, {w.dofs} DOF), "
-                      f"{steps} steps after 1 warm-up step, {el:.1f} s, OpenMP threads={cores}", **host_cpu()}
+                      f"{steps} steps after 1 warm-up step, {el:.1f} s, OpenMP threads={cores}, "
+                      "gcc -O3 -march=native", **host_cpu()}
 
 
 def advect2d_flops_per_element(n: int, s: int, sweeps: float, vel_terms: int) -> float:
@@ -273,9 +286,15 @@ def bench_c4(args, torch, P, W, stream):
     {4, 6, 8, 12} by seed, swirl velocity, eight Fourier modes, periodic,
     boundary rows (HARD), RK4, dt = 2.107e-5.  Order buckets run as
     separate launches captured in one HIP graph per two steps, with the
-    advect block shape per bucket picked by the autotuner at the first step."""
+    advect block shape per bucket picked by the autotuner at the first step.
+
+    Stated error: 100 steps forward, the velocity reversed, 100 steps back;
+    the exact result of that round trip is the initial field, and the L2
+    norm of the difference (the paper's norm, eq. 5.2) is the scheme's error
+    over 200 steps."""
+    prec = {"fp64": P.SL_PREC_FP64, "fp32r": P.SL_PREC_FP32_REFINED, "bf16r": P.SL_PREC_BF16_REFINED}[args.precision]
     w = W.c4(nsteps=args.warmup + args.steps)
-    m = P.from_mixed_workload(w, stream=stream.cuda_stream)
+    m = P.from_mixed_workload(w, stream=stream.cuda_stream, precision=prec)
     opts = dict(rk=w.rk, constraints=W.BOUNDARY, mode=w.mode)
     m.step(w.dt, max(2, args.warmup), **opts)  # autotune, capture, warm up
     torch.cuda.synchronize()
@@ -284,12 +303,45 @@ def bench_c4(args, torch, P, W, stream):
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     rc, phi, st = m.read()
-    # one eager step with per-step events (profiling bypasses the graph)
+    lat = step_latency(torch, m, w.dt, opts, samples=min(100, max(10, args.steps)))
+    # per-kernel HIP events on the mesh's stream around every launch (the
+    # profiled steps run the same launches without the graph)
+    m.read()
+    nprof = max(4, min(args.steps, 20))
     P.sl_set_profiling(m.h, True)
-    m.step(w.dt, 4, **opts)
-    t_eager, c_eager = P.sl_kernel_time(m.h, P.KER_ADV2D)
+    m.step(w.dt, nprof, **opts)
+    t_step, c_step = P.sl_kernel_time(m.h, P.KER_ADV2D)
+    buckets = []
+    for b in range(len(set(w.orders.tolist()))):
+        n, K_b, vt, sw = P.sl_bucket_stats(m.h, b)
+        ta, ca = P.sl_kernel_time(m.h, P.KER_MIX_ADV + b)
+        tc, cc = P.sl_kernel_time(m.h, P.KER_MIX_CON + b)
+        fl = advect2d_flops_per_element(n, 4, sw, vt) * K_b
+        adv_us = ta / max(ca, 1) * 1e3
+        buckets.append({"n": n, "elements": K_b, "vel_terms": vt, "remap_sweeps_mean": sw,
+                        "advect_us": adv_us, "constrain_us": tc / max(cc, 1) * 1e3,
+                        "advect_flops": fl, "advect_TFLOPs": fl / (adv_us * 1e-6) / 1e12})
     P.sl_set_profiling(m.h, False)
+    m.read()
     m.close()
+    # stated error: round trip under the steady swirl
+    rt = 100
+    wr = W.c4(nsteps=rt)
+    mr = P.from_mixed_workload(wr, stream=stream.cuda_stream, precision=prec)
+    mr.step(wr.dt, rt, **opts)
+    mr.set_velocity(-wr.velocity())
+    mr.step(wr.dt, rt, **opts)
+    rrc, back, _ = mr.read()
+    mr.close()
+    wr.exact = lambda x, y, t: wr.u0(x, y)
+    l2 = wr.l2_error(back, 0.0)
+    l2_ref = wr.l2_error(np.zeros_like(back), 0.0)
+
+    # the dominant kernel: the longest launch of the step (the advect of the
+    # highest-order bucket; its constrain launches are a fraction of it)
+    dom = max(buckets, key=lambda d: d["advect_us"])
+    assert dom["advect_us"] >= max(d["constrain_us"] for d in buckets)
+    ach = dom["advect_flops"] / (dom["advect_us"] * 1e-6)
     counts = {int(n) - 1: int((w.orders == n).sum()) for n in sorted(set(w.orders.tolist()))}
     out = {
         "metric": METRIC, "value": w.dofs * args.steps / el, "unit": "DOF-updates/s", "n_gpus": 1,
@@ -298,10 +350,23 @@ def bench_c4(args, torch, P, W, stream):
         "config": {"workload": "2D mixed-order batch: 316x316 quads on [0,1]^2, order per element from {4,6,8,12} "
                                "by seed, swirl a=(sin^2(pi x)sin(2pi y), -sin^2(pi y)sin(2pi x)), eight Fourier "
                                "modes, periodic, boundary HARD, RK4, graph-captured buckets, autotuned shapes",
-                   "K": w.K, "dofs": w.dofs, "dt": w.dt, "elements_per_order": counts},
-        "status": P.status_string(rc), "remap_sweeps_mean": st.remap_sweeps_mean,
-        "eager_step_ms": t_eager / max(c_eager, 1),
+                   "K": w.K, "dofs": w.dofs, "dt": w.dt, "elements_per_order": counts,
+                   "precision": args.precision},
+        "status": P.status_string(rc),
+        "l2_error": l2, "l2_error_note": f"forward {rt} steps, velocity reversed, {rt} steps back; exact result "
+                                         f"= u0 (paper's L2 norm, eq. 5.2; the norm of u0 itself is {l2_ref:.3g})",
+        "round_trip_status": P.status_string(rrc),
+        "step_latency": lat,
+        "remap_sweeps_mean": st.remap_sweeps_mean,
+        "eager_step_ms": t_step / max(c_step, 1),
         "graph_step_ms": el / args.steps * 1e3,
+        "buckets": buckets,
+        "roofline": {"kernel": f"k_advect2d (n={dom['n']} bucket)", "bound": "alu", "achieved": ach / 1e12,
+                     "peak": FP64_VALU_PEAK / 1e12, "unit": "TFLOP/s", "frac": ach / FP64_VALU_PEAK,
+                     "traffic": measured_traffic(f"k_advect2d_n{dom['n']}", "sl2d_kernels.h",
+                                                 "sl2d_c4_mixed_316x316.md") if args.precision == "fp64" else None,
+                     "avg_launch_us": dom["advect_us"], "algorithmic_flops_per_launch": dom["advect_flops"],
+                     "elements_per_launch": dom["elements"], "remap_sweeps_mean": dom["remap_sweeps_mean"]},
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline_mixed(W.c4(kx=16, nsteps=1))
@@ -513,60 +578,12 @@ def bench_c2bw(args, torch, P, W, stream):
     print(json.dumps(out))
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000)
-    ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--workload", choices=["c1", "c2", "c2bw", "c3", "c4", "serve"], default="c2",
-                    help="c1: the small 1D configuration (144 DOF), a launch-latency probe; "
-                         "c2: the headline 1D configuration (default); c2bw: the C2 problem with boundary "
-                         "rows only on K=2^22 elements, a probe of the HBM side; "
-                         "c3: the 2D rotation configuration; "
-                         "c4: the 2D mixed-order batch; "
-                         "serve: a Poisson stream of independent problems through the request loop")
-    ap.add_argument("--requests", type=int, default=48, help="serve: number of requests")
-    ap.add_argument("--slots", type=int, default=8, help="serve: requests on the device at once")
-    ap.add_argument("--budget-gib", type=float, default=32.0, help="serve: device memory budget")
-    ap.add_argument("--precision", choices=["fp64", "fp32r", "bf16r"], default="fp64",
-                    help="c3 only: fp32r stores and applies the remap preconditioner in FP32, bf16r with BF16 "
-                         "entries and operands and FP32 sums (FP64 residuals in both)")
-    ap.add_argument("--copy-mib", type=int, default=0,
-                    help="first run one plain device copy of this many MiB (calibrates HBM counters)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU path is a design note, not a build target.", file=sys.stderr)
-        sys.exit(2)
-
-    import torch
-    import paper_1910_06476_amd as P
-    import workloads as W
-
-    if not torch.cuda.is_available():
-        print("no GPU visible", file=sys.stderr)
-        sys.exit(1)
-    torch.cuda.set_device(0)
-    stream = torch.cuda.current_stream()
-    if args.copy_mib > 0:
-        nel = args.copy_mib * (1 << 20) // 8
-        src = torch.ones(nel, dtype=torch.float64, device="cuda")
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-    if args.workload == "c3":
-        return bench_c3(args, torch, P, W, stream)
-    if args.workload == "serve":
-        return bench_serve(args, torch, P, W)
-    if args.workload == "c4":
-        return bench_c4(args, torch, P, W, stream)
-    if args.workload == "c2bw":
-        return bench_c2bw(args, torch, P, W, stream)
-    if args.workload == "c1":
-        return bench_c1(args, torch, P, W, stream)
+def bench_c2(args, torch, P, W, stream):
+    """1D variable-velocity advection a(x) = 1 + sin(pi x)/2 on [0,2]
+    periodic, K = 65536 elements of order 16 (17 Gauss-Legendre nodes,
+    1,114,112 DOF), u0 = exp(-40 (x-1)^2), RK4, boundary + mass + energy
+    constraints (HARD, the paper's energy stop 1e-8), dt = 0.2 * min node gap
+    * dx / 1.5, FP64."""
     w = W.c2()
     m = P.from_workload(w, stream=stream.cuda_stream)
     opts = dict(rk=w.rk, constraints=w.cmask, mode=w.mode, energy_maxit=w.energy_maxit, energy_tol=w.energy_tol)
@@ -624,9 +641,6 @@ def main():
                    "K": w.K, "n": w.n, "dofs": w.dofs, "dt": w.dt, "rk": w.rk, "constraints": "B+M+E",
                    "energy_tol": w.energy_tol},
         "l2_error": l2, "l2_time": T, "status": P.status_string(rc), "max_picard": st.max_picard,
-        "status_note": "HARD energy row: where the energy correction exceeds the tolerance (the Gaussian's "
-                       "peak elements) the Picard map is 2-periodic; the 2-cycle rule stops and flags it, "
-                       "as the oracle does",
         "step_latency": lat,
         "roofline": roof,
     }
@@ -634,6 +648,63 @@ def main():
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out))
 
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--workload", choices=["c1", "c2", "c2bw", "c3", "c4", "serve"], default="c4",
+                    help="c4: the 2D mixed-order batch, the largest configuration (default); "
+                         "c1: the small 1D configuration (144 DOF), a launch-latency probe; "
+                         "c2: the 1D configuration with boundary, mass and energy rows; c2bw: the C2 problem "
+                         "with boundary rows only on K=2^22 elements, a probe of the HBM side; "
+                         "c3: the 2D rotation configuration; "
+                         "serve: a Poisson stream of independent problems through the request loop")
+    ap.add_argument("--requests", type=int, default=48, help="serve: number of requests")
+    ap.add_argument("--slots", type=int, default=8, help="serve: requests on the device at once")
+    ap.add_argument("--budget-gib", type=float, default=32.0, help="serve: device memory budget")
+    ap.add_argument("--precision", choices=["fp64", "fp32r", "bf16r"], default="fp64",
+                    help="c3 and c4: fp32r stores and applies the remap preconditioner in FP32, bf16r with BF16 "
+                         "entries and operands and FP32 sums (FP64 residuals in both)")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="first run one plain device copy of this many MiB (calibrates HBM counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
+              "the multi-GPU path is a design note, not a build target.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1910_06476_amd as P
+    import workloads as W
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    if args.copy_mib > 0:
+        nel = args.copy_mib * (1 << 20) // 8
+        src = torch.ones(nel, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    if args.workload == "c3":
+        return bench_c3(args, torch, P, W, stream)
+    if args.workload == "serve":
+        return bench_serve(args, torch, P, W)
+    if args.workload == "c4":
+        return bench_c4(args, torch, P, W, stream)
+    if args.workload == "c2bw":
+        return bench_c2bw(args, torch, P, W, stream)
+    if args.workload == "c1":
+        return bench_c1(args, torch, P, W, stream)
+    return bench_c2(args, torch, P, W, stream)
 
 if __name__ == "__main__":
     main()

@@ -231,12 +231,25 @@ sl_status sl_node_coords(int32_t nodes, int32_t n, double* xi, double* w);
 sl_status sl_device_field(sl_mesh* m, double** d_phi, void** stream);
 
 /* Per-kernel timing with HIP events on the mesh's stream.  When enabled,
- * every kernel launch of sl_step is bracketed by events; sl_kernel_time
- * synchronises and returns the summed milliseconds and the launch count of
- * kernel 'which' (0 = 1D advect, 1 = 1D constrain, 2 = 2D advect+solve,
- * 3 = 2D constrain) since the last reset.  Errors: SL_E_INVALID. */
+ * every kernel launch of sl_step is bracketed by events (a mixed-order mesh
+ * then steps without its captured graph); sl_kernel_time synchronises and
+ * returns the summed milliseconds and the launch count of kernel 'which'
+ * since the last reset: 0 = 1D advect, 1 = 1D constrain, 2 = 2D advect+solve
+ * (a mixed-order mesh: its whole step), 3 = 2D constrain, 4 + b = the
+ * advect+solve of bucket b of a mixed-order mesh, 20 + b = its constrain
+ * (buckets in ascending order, b < 16).  Errors: SL_E_INVALID. */
 sl_status sl_set_profiling(sl_mesh* m, int32_t enable);
 sl_status sl_kernel_time(sl_mesh* m, int32_t which, double* total_ms, int64_t* launches);
+
+/* Per order bucket of a mixed-order mesh (bucket 0 of a uniform mesh is the
+ * whole mesh): its nodes per direction n, element count, velocity series
+ * terms per direction the kernels evaluate, and its mean remap (eq. 5.4)
+ * sweeps per element and step since the last sl_read (call it before
+ * sl_read, which resets the statistics; 0 in 1D).  Synchronises the mesh's
+ * stream.  Any output pointer may be NULL.  Errors: SL_E_INVALID,
+ * SL_E_DEVICE. */
+sl_status sl_bucket_stats(sl_mesh* m, int32_t bucket, int32_t* n, int32_t* count, int32_t* vel_terms,
+                          double* sweeps_mean);
 
 /* Device bytes a mesh with descriptor d holds (all its buffers, and
  * ghost_rows rows of ghost values for a GHOST mesh), for admission by

@@ -35,6 +35,21 @@ def build(force: bool = True) -> str:
     return _LIB
 
 
+def use_native_build() -> str:
+    """Compile the oracle with -O3 -march=native (still no fast-math) for the
+    host this process runs on, into a temporary directory, and load that
+    build from now on.  Used by the benchmark's CPU baseline: the machine
+    code is the host's own, so the build happens where it is timed."""
+    global _LIB, _lib
+    import tempfile
+    out = os.path.join(tempfile.mkdtemp(prefix="sl_oracle_"), "liboracle_native.so")
+    subprocess.check_call(
+        ["gcc", "-O3", "-march=native", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-D_DEFAULT_SOURCE",
+         "-o", out, _SRC, "-lm"])
+    _LIB, _lib = out, None
+    return out
+
+
 class Params(ctypes.Structure):
     _fields_ = [
         ("dim", ctypes.c_int32), ("kx", ctypes.c_int32), ("ky", ctypes.c_int32),

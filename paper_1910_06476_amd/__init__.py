@@ -28,12 +28,13 @@ SL_C_BOUNDARY, SL_C_MASS, SL_C_ENERGY = 1, 2, 4
 SL_MODE_HARD, SL_MODE_SOFT = 0, 1
 SL_IFACE_INTERP, SL_IFACE_BACKTRACK = 0, 1
 KER_ADV1D, KER_CON1D, KER_ADV2D, KER_CON2D = 0, 1, 2, 3
+KER_MIX_ADV, KER_MIX_CON = 4, 20  # + bucket index (mixed-order meshes)
 
 EXPORTS = ["sl_create_mesh", "sl_set_velocity", "sl_set_ghost", "sl_ghost_count", "sl_step", "sl_read",
            "sl_destroy_mesh", "sl_status_string", "sl_max_dt", "sl_node_coords", "sl_device_field",
            "sl_set_profiling", "sl_kernel_time", "sl_mesh_bytes", "sl_server_create", "sl_server_submit",
            "sl_server_progress", "sl_server_drain", "sl_server_result", "sl_server_latency",
-           "sl_server_destroy", "sl_step1d_static"]
+           "sl_server_destroy", "sl_step1d_static", "sl_bucket_stats"]
 
 
 class MeshDesc(ctypes.Structure):
@@ -123,6 +124,8 @@ def lib():
         L.sl_server_latency.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
         L.sl_server_destroy.argtypes = [vp]
         i32, f64 = ctypes.c_int32, ctypes.c_double
+        ip = ctypes.POINTER(ctypes.c_int32)
+        L.sl_bucket_stats.argtypes = [vp, i32, ip, ip, ip, dp]
         L.sl_step1d_static.argtypes = [i32, i32, i32, i32, i32, f64, f64, vp, vp, vp, vp, f64, vp, f64, i32,
                                        ctypes.POINTER(StepOpts), vp, vp, vp]
         for name in EXPORTS:
@@ -242,6 +245,16 @@ def sl_kernel_time(m, which: int):
     cnt = ctypes.c_int64()
     _check(lib().sl_kernel_time(m, which, ctypes.byref(ms), ctypes.byref(cnt)), "sl_kernel_time")
     return ms.value, cnt.value
+
+
+def sl_bucket_stats(m, bucket: int):
+    """(n, element count, velocity series terms, mean remap sweeps per element
+    and step since the last sl_read) of one order bucket."""
+    n, K, vt = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    sw = ctypes.c_double()
+    _check(lib().sl_bucket_stats(m, int(bucket), ctypes.byref(n), ctypes.byref(K), ctypes.byref(vt),
+                                 ctypes.byref(sw)), "sl_bucket_stats")
+    return n.value, K.value, vt.value, sw.value
 
 
 class Mesh:

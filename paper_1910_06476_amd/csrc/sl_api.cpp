@@ -27,6 +27,7 @@ struct sl_mesh {
     int32_t* flag_part;
     int32_t* vdeg_d;
     int nblocks;
+    int nslice;  // statistics slices of nblocks blocks each: one per bucket of a mixed mesh, else 1
     int vdeg;
     // host state
     bool has_velocity;
@@ -59,6 +60,24 @@ struct sl_mesh {
     double graph_dt;
     sl_step_opts graph_opts;
 };
+
+// per-kernel timing events (profiling): before and after a launch of kernel k
+void ev_begin(sl_mesh* m, int k)
+{
+    if (!m->profiling) return;
+    hipEvent_t a, b;
+    (void)hipEventCreate(&a);
+    (void)hipEventCreate(&b);
+    (void)hipEventRecord(a, m->stream);
+    m->pending[k].push_back(a);
+    m->pending[k].push_back(b);
+}
+
+void ev_end(sl_mesh* m, int k)
+{
+    if (!m->profiling) return;
+    (void)hipEventRecord(m->pending[k].back(), m->stream);
+}
 
 namespace {
 
@@ -314,8 +333,9 @@ size_t mixed_bytes(const sl_mesh_desc* d, const MixedPlan& P)
 {
     const size_t K = (size_t)d->kx * d->ky;
     const size_t dbl = 3 * P.dofs + 2 * 2 * P.dofs + 2 * P.dofs + 2 * P.nrec + P.ntab + P.ninterp +
-                       (size_t)P.nblocks * kStatSlots;
-    const size_t ints = 2 * (size_t)P.nblocks + 1 + K + (size_t)MixMeta::size((int)K) + K * MixFace::kPer;
+                       (size_t)P.nbk * P.nblocks * kStatSlots;
+    const size_t ints =
+        2 * (size_t)P.nbk * P.nblocks + 1 + K + (size_t)MixMeta::size((int)K) + K * MixFace::kPer;
     return dbl * sizeof(double) + ints * sizeof(int32_t);
 }
 
@@ -335,8 +355,9 @@ Step2DArgs bucket_args(const sl_mesh* m, int b, double dt, const sl_step_opts& o
     B.vface = m->vface + m->recOff[b];
     B.tab = m->tab + m->tabOff[b];
     B.gnow = B.gnext = m->vface;
-    B.flag_part = m->flag_part;
-    B.stat_part = m->stat_part;
+    // each bucket keeps its block statistics in a slice of its own
+    B.flag_part = m->flag_part + (size_t)b * 2 * m->nblocks;
+    B.stat_part = m->stat_part + (size_t)b * m->nblocks * kStatSlots;
     B.nblk = m->nblocks;
     B.vdeg = m->bdeg[b];
     B.rstride = 4 * n;
@@ -366,16 +387,22 @@ Step2DArgs bucket_args(const sl_mesh* m, int b, double dt, const sl_step_opts& o
 }
 
 // one step of every bucket: all advects (each writes its records), then all
-// constraints (each reads the neighbours' records)
-int mixed_launch_step(const sl_mesh* m, std::vector<Step2DArgs>& B, double* src, double* dst)
+// constraints (each reads the neighbours' records); with profiling every
+// launch is bracketed by events
+int mixed_launch_step(sl_mesh* m, std::vector<Step2DArgs>& B, double* src, double* dst)
 {
     for (int b = 0; b < m->nbk; ++b) {
         B[b].phi = src + m->bOff[b];
         B[b].phi_out = dst + m->bOff[b];
+        ev_begin(m, KER_MIX_ADV + b);
         if (launch_advect2d(m->bn[b], B[b], m->stream)) return 1;
+        ev_end(m, KER_MIX_ADV + b);
     }
-    for (int b = 0; b < m->nbk; ++b)
+    for (int b = 0; b < m->nbk; ++b) {
+        ev_begin(m, KER_MIX_CON + b);
         if (launch_constrain2d_mixed(m->bn[b], B[b], m->stream)) return 1;
+        ev_end(m, KER_MIX_CON + b);
+    }
     return 0;
 }
 
@@ -410,8 +437,8 @@ sl_status mixed_autotune(sl_mesh* m, double dt, const sl_step_opts& opt)
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc != SL_OK) return rc;
-    if (hipMemsetAsync(m->stat_part, 0, (size_t)m->nblocks * kStatSlots * sizeof(double), m->stream) ||
-        hipMemsetAsync(m->flag_part, 0, (size_t)2 * m->nblocks * sizeof(int32_t), m->stream))
+    if (hipMemsetAsync(m->stat_part, 0, (size_t)m->nslice * m->nblocks * kStatSlots * sizeof(double), m->stream) ||
+        hipMemsetAsync(m->flag_part, 0, (size_t)m->nslice * 2 * m->nblocks * sizeof(int32_t), m->stream))
         return SL_E_DEVICE;
     return SL_OK;
 }
@@ -441,9 +468,6 @@ sl_status sl_node_coords(int32_t nodes, int32_t n, double* xi, double* w)
     if (!xi || !w || n < 1 || n > kMaxTableN) return SL_E_INVALID;
     return node_rule(nodes, n, xi, w) ? SL_OK : SL_E_INVALID;
 }
-
-static void ev_begin(sl_mesh* m, int k);
-static void ev_end(sl_mesh* m, int k);
 
 // mixed-order mesh: buckets, tables, interpolation matrices, meta data and
 // the initial field in bucket layout (validated by mixed_plan)
@@ -585,11 +609,12 @@ static sl_status create_mixed(const sl_mesh_desc* d, sl_mesh** out)
         m->own_stream = true;
     }
     m->nblocks = P.nblocks;
+    m->nslice = P.nbk;
     ok = dalloc(&m->phi, P.dofs) && dalloc(&m->phi2, P.dofs) && dalloc(&m->phihat, P.dofs) &&
          dalloc(&m->rec, P.nrec) && dalloc(&m->aN, 2 * P.dofs) && dalloc(&m->aM, 2 * P.dofs) &&
          dalloc(&m->divN, P.dofs) && dalloc(&m->divM, P.dofs) && dalloc(&m->vface, P.nrec) &&
-         dalloc(&m->tab, P.ntab) && dalloc(&m->stat_part, (size_t)m->nblocks * kStatSlots) &&
-         dalloc(&m->flag_part, (size_t)2 * m->nblocks) && dalloc(&m->vdeg_d, 1) && dalloc(&m->elems_d, (size_t)K) &&
+         dalloc(&m->tab, P.ntab) && dalloc(&m->stat_part, (size_t)m->nslice * m->nblocks * kStatSlots) &&
+         dalloc(&m->flag_part, (size_t)m->nslice * 2 * m->nblocks) && dalloc(&m->vdeg_d, 1) && dalloc(&m->elems_d, (size_t)K) &&
          dalloc(&m->mix_d, meta.size()) && dalloc(&m->interp_d, interp.size()) && dalloc(&m->nbr_d, nbr.size());
     if (!ok) { release(m); delete m; return SL_E_NOMEM; }
     std::vector<double> u((size_t)P.dofs);
@@ -602,8 +627,8 @@ static sl_status create_mixed(const sl_mesh_desc* d, sl_mesh** out)
         hipMemcpyAsync(m->elems_d, elems.data(), elems.size() * sizeof(int32_t), hipMemcpyHostToDevice, m->stream),
         hipMemcpyAsync(m->mix_d, meta.data(), meta.size() * sizeof(int32_t), hipMemcpyHostToDevice, m->stream),
         hipMemcpyAsync(m->interp_d, interp.data(), interp.size() * sizeof(double), hipMemcpyHostToDevice, m->stream),
-        hipMemsetAsync(m->stat_part, 0, (size_t)m->nblocks * kStatSlots * sizeof(double), m->stream),
-        hipMemsetAsync(m->flag_part, 0, (size_t)2 * m->nblocks * sizeof(int32_t), m->stream),
+        hipMemsetAsync(m->stat_part, 0, (size_t)m->nslice * m->nblocks * kStatSlots * sizeof(double), m->stream),
+        hipMemsetAsync(m->flag_part, 0, (size_t)m->nslice * 2 * m->nblocks * sizeof(int32_t), m->stream),
         hipStreamSynchronize(m->stream)};
     for (hipError_t x : r)
         if (x != hipSuccess) { release(m); delete m; return SL_E_DEVICE; }
@@ -765,6 +790,7 @@ sl_status sl_create_mesh(const sl_mesh_desc* d, sl_mesh** out)
     }
     const BufSizes z = buffer_sizes(m->dim, m->kx, m->ky, n);
     m->nblocks = z.nblocks;
+    m->nslice = 1;
     bool ok = dalloc(&m->phi, z.nf) && dalloc(&m->phi2, z.nf) && dalloc(&m->phihat, z.nf) &&
               dalloc(&m->rec, z.nrec) && dalloc(&m->aN, z.nf * m->dim) && dalloc(&m->aM, z.ncoef) &&
               dalloc(&m->divN, z.nf) && dalloc(&m->divM, z.nf) && dalloc(&m->vface, z.nvf) &&
@@ -908,22 +934,6 @@ double sl_max_dt(const sl_mesh* m, double cfl)
     return dt * cfl;
 }
 
-static void ev_begin(sl_mesh* m, int k)
-{
-    if (!m->profiling) return;
-    hipEvent_t a, b;
-    (void)hipEventCreate(&a);
-    (void)hipEventCreate(&b);
-    (void)hipEventRecord(a, m->stream);
-    m->pending[k].push_back(a);
-    m->pending[k].push_back(b);
-}
-
-static void ev_end(sl_mesh* m, int k)
-{
-    if (!m->profiling) return;
-    (void)hipEventRecord(m->pending[k].back(), m->stream);
-}
 
 sl_status sl_step(sl_mesh* m, double dt, int32_t nsteps, const sl_step_opts* o)
 {
@@ -1058,14 +1068,15 @@ sl_status sl_read(sl_mesh* m, double* u_out, sl_stats* st)
     } else if (dst && hipMemcpy(dst, m->phi, nf * sizeof(double), hipMemcpyDeviceToHost)) {
         return SL_E_DEVICE;
     }
-    std::vector<double> sp((size_t)m->nblocks * kStatSlots);
-    std::vector<int32_t> fp((size_t)2 * m->nblocks);
+    const int nb = m->nslice * m->nblocks;
+    std::vector<double> sp((size_t)nb * kStatSlots);
+    std::vector<int32_t> fp((size_t)2 * nb);
     if (hipMemcpy(sp.data(), m->stat_part, sp.size() * sizeof(double), hipMemcpyDeviceToHost)) return SL_E_DEVICE;
     if (hipMemcpy(fp.data(), m->flag_part, fp.size() * sizeof(int32_t), hipMemcpyDeviceToHost)) return SL_E_DEVICE;
     int flags = 0;
     for (int32_t f : fp) flags |= f;
     double rb = 0, rm = 0, re = 0, pic = 0, swsum = 0, swmax = 0, rres = 0;
-    for (int b = 0; b < m->nblocks; ++b) {
+    for (int b = 0; b < nb; ++b) {
         rb = std::max(rb, sp[b * kStatSlots + 0]);
         rm = std::max(rm, sp[b * kStatSlots + 1]);
         re = std::max(re, sp[b * kStatSlots + 2]);
@@ -1164,6 +1175,28 @@ sl_status sl_kernel_time(sl_mesh* m, int32_t which, double* total_ms, int64_t* l
     v.clear();
     if (total_ms) *total_ms = m->ktime[which];
     if (launches) *launches = m->kcount[which];
+    return SL_OK;
+}
+
+sl_status sl_bucket_stats(sl_mesh* m, int32_t bucket, int32_t* n, int32_t* count, int32_t* vel_terms,
+                          double* sweeps_mean)
+{
+    const ApiHold hold;
+    if (!m || bucket < 0 || bucket >= (m->mixed ? m->nbk : 1)) return SL_E_INVALID;
+    if (hipStreamSynchronize(m->stream)) return SL_E_DEVICE;
+    const int b = m->mixed ? bucket : 0;
+    const int K = m->mixed ? m->bK[b] : m->K;
+    std::vector<double> sp((size_t)m->nblocks * kStatSlots);
+    if (hipMemcpy(sp.data(), m->stat_part + (size_t)b * m->nblocks * kStatSlots, sp.size() * sizeof(double),
+                  hipMemcpyDeviceToHost))
+        return SL_E_DEVICE;
+    double sw = 0.0;
+    for (int k = 0; k < m->nblocks; ++k) sw += sp[(size_t)k * kStatSlots + 4];
+    const int64_t dsteps = m->steps - m->steps_read;
+    if (n) *n = m->mixed ? m->bn[b] : m->n;
+    if (count) *count = K;
+    if (vel_terms) *vel_terms = m->mixed ? m->bdeg[b] + 1 : vel_terms_used(m);
+    if (sweeps_mean) *sweeps_mean = dsteps > 0 ? sw / ((double)dsteps * K) : 0.0;
     return SL_OK;
 }
 

@@ -51,7 +51,13 @@ struct RKTab {
 };
 bool rk_tableau(int order, RKTab* T);
 
-enum { KER_ADV1D = 0, KER_CON1D = 1, KER_ADV2D = 2, KER_CON2D = 3, KER_COUNT = 4 };
+// timed kernels (sl_kernel_time): the uniform-mesh kernels, the whole step of
+// a mixed-order mesh (KER_ADV2D), and per bucket b its advect (KER_MIX_ADV +
+// b) and constrain (KER_MIX_CON + b) launches
+enum {
+    KER_ADV1D = 0, KER_CON1D = 1, KER_ADV2D = 2, KER_CON2D = 3,
+    KER_MIX_ADV = 4, KER_MIX_CON = 4 + kMaxBuckets, KER_COUNT = 4 + 2 * kMaxBuckets
+};
 enum { FLAG_NONFINITE = 1, FLAG_CONTAIN = 2, FLAG_SINGULAR = 4, FLAG_NOCONV = 8 };
 
 // Per-block statistics slots: [resid_boundary, resid_mass, resid_energy,
