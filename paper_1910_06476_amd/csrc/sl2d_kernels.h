@@ -1486,24 +1486,28 @@ void adv_launch(const Step2DArgs& A, dim3 grid, hipStream_t s)
     else hipLaunchKernelGGL((k_advect2d<N, PR, false>), grid, dim3(kBlock2), 0, s, A);
 }
 
+// Every block of an advect or constrain launch owns a row of the per-block
+// statistics and flags, which hold A.nblk rows: a launch with more blocks is
+// refused on the host (it would write past them).
 template <int N, int BSEL>
-void adv_shape(const Step2DArgs& A, hipStream_t s)
+int adv_shape(const Step2DArgs& A, hipStream_t s)
 {
     using S = Shape2<N, BSEL>;
-    hipLaunchKernelGGL((k_advect2d<N, 0, false, BSEL>), dim3((A.K + S::E - 1) / S::E), dim3(S::BS), 0, s, A);
+    const int grid = (A.K + S::E - 1) / S::E;
+    if (grid > A.nblk) return 1;
+    hipLaunchKernelGGL((k_advect2d<N, 0, false, BSEL>), dim3(grid), dim3(S::BS), 0, s, A);
+    return hipGetLastError() == hipSuccess ? 0 : 1;
 }
 
 template <int N>
 int adv_n(const Step2DArgs& A, hipStream_t s)
 {
     // the alternative block shapes exist for the FP64 boundary-rows kernel
-    if (A.bs != 0 && A.precision == SL_PREC_FP64 && !A.targets) {
-        if (A.bs == 1) adv_shape<N, 1>(A, s);
-        else adv_shape<N, 2>(A, s);
-        return hipGetLastError() == hipSuccess ? 0 : 1;
-    }
+    if (A.bs != 0 && A.precision == SL_PREC_FP64 && !A.targets)
+        return A.bs == 1 ? adv_shape<N, 1>(A, s) : adv_shape<N, 2>(A, s);
     constexpr int E = kBlock2 / (N * N);
     const dim3 grid((A.K + E - 1) / E);
+    if ((int)grid.x > A.nblk) return 1;
     if (A.precision == SL_PREC_FP32_REFINED) adv_launch<N, 1>(A, grid, s);
     else if (A.precision == SL_PREC_BF16_REFINED) adv_launch<N, 2>(A, grid, s);
     else adv_launch<N, 0>(A, grid, s);
@@ -1515,6 +1519,7 @@ int con_n(const Step2DArgs& A, hipStream_t s)
 {
     constexpr int E = kBlock2 / (N * N);
     const int nchunk = (A.K + E - 1) / E;
+    if (nchunk > A.nblk) return 1;
     static std::atomic<int> cap_bt[kMaxDevices], cap[kMaxDevices];
     if (A.cmask & (SL_C_MASS | SL_C_ENERGY)) {
         hipLaunchKernelGGL(k_constrain2d_me<N>, dim3(nchunk), dim3(kBlock2), 0, s, A);
@@ -1604,6 +1609,7 @@ int con_mixed_n(const Step2DArgs& A, hipStream_t s)
 {
     constexpr int E = kBlock2 / (N * N);
     const int nchunk = (A.K + E - 1) / E;
+    if (nchunk > A.nblk) return 1;
     static std::atomic<int> cap[kMaxDevices];
     const int r = resident_blocks(k_constrain2d_mixed<N>, cap);
     hipLaunchKernelGGL(k_constrain2d_mixed<N>, dim3(nchunk < r ? nchunk : r), dim3(kBlock2), 0, s, A);
