@@ -102,3 +102,38 @@ def test_basecase_independent_of_integrator_for_constant_velocity(ora):
         outs.append(phi)
     for o in outs[1:]:
         np.testing.assert_allclose(o, outs[0], atol=1e-13)
+
+
+def _l2(ora, w, phi):
+    return _paper_norms(ora, w, phi, w.nsteps * w.dt)[0]
+
+
+def test_dirichlet_more_accurate_than_periodic(ora):
+    """Section 5.1 (Fig. fig:1_3): Basecase with exact inflow (Dirichlet)
+    values against periodic, H = 4, T = 10: the Dirichlet error is lower at
+    every P (here by about 10x; the paper's figure shows it slightly lower)."""
+    for P in (4, 6, 8):
+        r = []
+        for bc in (W.PERIODIC, W.GHOST):
+            w = W.x1(P=P, H=4, rk=1)
+            w.bc = bc
+            phi, st = ora.run_workload(w)
+            assert st.flags == 0
+            r.append(_l2(ora, w, phi))
+        assert r[1] < r[0], (P, r)
+
+
+def test_first_order_bounded_by_time_error_at_small_step(ora):
+    """Section 5.2 (Fig. fig:2_2b): with dt = 1e-4 the first-order Basecase
+    converges spectrally up to P = 8, where its error is O(1e-4), and is then
+    bound by the time integration; the second-order Basecase keeps
+    converging."""
+    e1, e2 = {}, {}
+    for P in (4, 8, 11):
+        for rk, out in ((1, e1), (2, e2)):
+            w = W.x6(P=P, H=4, rk=rk, cmask=W.BOUNDARY)
+            w.dt, w.nsteps = 1e-4, 10000
+            phi, _ = ora.run_workload(w)
+            out[P] = _l2(ora, w, phi)
+    assert e1[4] / e1[8] > 30 and 1e-4 < e1[8] < 1e-3 and e1[8] / e1[11] < 1.5
+    assert e2[11] < e1[11] / 10
