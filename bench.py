@@ -66,17 +66,17 @@ def advect_bytes_per_element(n: int, targets: bool, vel_terms: int) -> float:
     and the nodal velocity (+ the nodal divergence and the face speed with
     targets) and the velocity series coefficients that are evaluated; write
     phihat and the element record (the two traces, + the six target entries
-    with targets)."""
+    and the element's mean with targets)."""
     rd = 8.0 * n * (3 if targets else 2) + 8.0 * vel_terms + (8.0 if targets else 0.0)
-    wr = 8.0 * n + (64.0 if targets else 16.0)
+    wr = 8.0 * n + (72.0 if targets else 16.0)
     return rd + wr
 
 
 def constrain_bytes_per_element(n: int, targets: bool = True) -> float:
     """read phihat, the element record entries in use (the two traces, + the
-    targets' six; the neighbours' are cache hits) and one face speed; write
-    phi."""
-    return 8.0 * n + (64.0 if targets else 16.0) + 8.0 + 8.0 * n
+    targets' six and the element's mean; the neighbours' are cache hits) and
+    one face speed; write phi."""
+    return 8.0 * n + (72.0 if targets else 16.0) + 8.0 + 8.0 * n
 
 
 def measured_traffic(kernel: str, source: str = "sl1d.hip", profile: str = "sl1d_c2_K65536_n17.md"):
@@ -175,21 +175,32 @@ def cpu_baseline_mixed(w, budget_s: float = 12.0):
                       rk=w.rk, cmask=W.BOUNDARY, mode=w.mode, energy_maxit=0, vel_kind=0, x0=w.x0, x1=w.x1,
                       y0=w.y0, y1=w.y1, energy_tol=0.0)
     a = w.velocity()
-    t0 = time.perf_counter()
     phi, _ = oracle.step_mixed(p, w.orders, w.initial(), a=a, dt=w.dt, nsteps=1)
-    one = time.perf_counter() - t0
-    steps = max(1, min(50, int(budget_s / max(one, 1e-3))))
+    # every call first builds the per-element tables: size the sample from
+    # the marginal cost of a step (calls of 1 and 5 steps), so that the
+    # tables take a small part of it
+    t0 = time.perf_counter()
+    oracle.step_mixed(p, w.orders, phi, a=a, dt=w.dt, nsteps=1)
+    t1 = time.perf_counter()
+    oracle.step_mixed(p, w.orders, phi, a=a, dt=w.dt, nsteps=5)
+    t5 = time.perf_counter() - t1
+    t1 -= t0
+    per = max((t5 - t1) / 4, 1e-4)
+    setup = max(t1 - per, 0.0)
+    steps = max(1, min(2000, int(max(budget_s - setup, per) / per)))
     t0 = time.perf_counter()
     oracle.step_mixed(p, w.orders, phi, a=a, dt=w.dt, nsteps=steps)
     el = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    one_thread = single_thread_rate(lambda: oracle.step_mixed(p, w.orders, phi, a=a, dt=w.dt, nsteps=1), w.dofs,
-                                    el / steps * cores)
+    # one thread: a call of k1 steps, about 4 s of stepping, set-up included
+    k1 = max(1, min(steps, int(4.0 / (per * cores))))
+    one_thread = single_thread_rate(lambda: oracle.step_mixed(p, w.orders, phi, a=a, dt=w.dt, nsteps=k1),
+                                    w.dofs * k1, setup + k1 * per * cores)
     return {"value": w.dofs * steps / el, "unit": "DOF-updates/s", "cores": cores, "kind": "oracle",
             "single_thread_value": one_thread,
             "sample": f"a {w.kx}x{w.ky} mesh of the same recipe (orders {{4,6,8,12}} by seed, {w.dofs} DOF), "
-                      f"{steps} steps after 1 warm-up step, {el:.1f} s, OpenMP threads={cores}, "
-                      "gcc -O3 -march=native", **host_cpu()}
+                      f"{steps} steps in one call after 3 warm-up calls, {el:.1f} s (the call's table set-up, "
+                      f"about {setup:.1f} s, included), OpenMP threads={cores}, gcc -O3 -march=native", **host_cpu()}
 
 
 def advect2d_flops_per_element(n: int, s: int, sweeps: float, vel_terms: int) -> float:
@@ -229,33 +240,60 @@ def step_latency(torch, m, dt, opts, samples=200):
     return {"p50_us": pick(0.50), "p99_us": pick(0.99), "samples": samples}
 
 
+def profiled_window(P, m, dt, nsteps, opts, kinds, acc=None):
+    """Run nsteps steps with per-kernel timing: each launch of a kernel in
+    `kinds` is timed by the start and end its own dispatch records (the
+    interval a kernel trace reports).  Adds (total ms, launches) per kind to
+    acc.
+
+    The device's clocks drift within a run: they rise from idle over the
+    first few hundred launches and fall under sustained FP64 load.  The bench
+    lines therefore time one window just before the timed region and one of
+    the same length just after it; with a drift close to linear over the
+    timed region, their pooled average is the timed region's."""
+    acc = {} if acc is None else acc
+    P.sl_set_profiling(m.h, True)
+    m.step(dt, nsteps, **opts)
+    for k in kinds:
+        t, c = P.sl_kernel_time(m.h, k)
+        a = acc.get(k, (0.0, 0))
+        acc[k] = (a[0] + t, a[1] + c)
+    P.sl_set_profiling(m.h, False)
+    return acc
+
+
+def avg_us(acc, k):
+    t, c = acc[k]
+    return t / max(c, 1) * 1e3
+
+
 def bench_c3(args, torch, P, W, stream):
     """2D rotation workload (256x256, order 8, RK4, ghost inflow, boundary HARD)."""
     w = W.c3(nsteps=args.warmup + args.steps)
     prec = {"fp64": P.SL_PREC_FP64, "fp32r": P.SL_PREC_FP32_REFINED, "bf16r": P.SL_PREC_BF16_REFINED}[args.precision]
     m = P.from_workload(w, stream=stream.cuda_stream, precision=prec)
-    m.set_ghost(w.ghost_rows(0.0, args.warmup + 2 * args.steps + 20))
+    nprof = max(5, min(args.steps, 20))
+    nlat = min(100, max(10, args.steps))
+    # inflow rows for every step the run takes (and one more time level)
+    m.set_ghost(w.ghost_rows(0.0, args.warmup + args.steps + 2 * nprof + nlat + 2))
     opts = dict(rk=w.rk, constraints=w.cmask, mode=w.mode)
     m.step(w.dt, args.warmup, **opts)
+    kinds = [P.KER_ADV2D, P.KER_CON2D]
+    acc = profiled_window(P, m, w.dt, nprof, opts, kinds)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     m.step(w.dt, args.steps, **opts)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    profiled_window(P, m, w.dt, nprof, opts, kinds, acc)
     rc, phi, st = m.read()
-    T = (args.warmup + args.steps) * w.dt
+    T = st.t
     l2 = w.l2_error(phi, T)
     sweeps = st.remap_sweeps_mean  # defect-correction sweeps per element and step, measured
-    lat = step_latency(torch, m, w.dt, opts, samples=min(100, max(10, args.steps)))
-    nprof = max(5, min(args.steps, 20))
-    P.sl_set_profiling(m.h, True)
-    m.step(w.dt, nprof, **opts)
-    t_adv, c_adv = P.sl_kernel_time(m.h, P.KER_ADV2D)
-    t_con, c_con = P.sl_kernel_time(m.h, P.KER_CON2D)
-    P.sl_set_profiling(m.h, False)
+    lat = step_latency(torch, m, w.dt, opts, samples=nlat)
     m.close()
-    adv_avg = t_adv / max(c_adv, 1) * 1e-3
-    con_avg = t_con / max(c_con, 1) * 1e-3
+    adv_avg = avg_us(acc, P.KER_ADV2D) * 1e-6
+    con_avg = avg_us(acc, P.KER_CON2D) * 1e-6
     fl = advect2d_flops_per_element(w.n, 4, sweeps, st.vel_terms) * w.K
     ach = fl / adv_avg
     out = {
@@ -297,31 +335,28 @@ def bench_c4(args, torch, P, W, stream):
     m = P.from_mixed_workload(w, stream=stream.cuda_stream, precision=prec)
     opts = dict(rk=w.rk, constraints=W.BOUNDARY, mode=w.mode)
     m.step(w.dt, max(2, args.warmup), **opts)  # autotune, capture, warm up
+    nb = len(set(w.orders.tolist()))
+    kinds = [P.KER_ADV2D] + [P.KER_MIX_ADV + b for b in range(nb)] + [P.KER_MIX_CON + b for b in range(nb)]
+    # per-kernel timing around the timed region (the profiled steps run the
+    # graph's launches one by one)
+    nprof = max(4, min(args.steps, 20))
+    acc = profiled_window(P, m, w.dt, nprof, opts, kinds)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     m.step(w.dt, args.steps, **opts)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    profiled_window(P, m, w.dt, nprof, opts, kinds, acc)
     rc, phi, st = m.read()
     lat = step_latency(torch, m, w.dt, opts, samples=min(100, max(10, args.steps)))
-    # per-kernel HIP events on the mesh's stream around every launch (the
-    # profiled steps run the same launches without the graph)
-    m.read()
-    nprof = max(4, min(args.steps, 20))
-    P.sl_set_profiling(m.h, True)
-    m.step(w.dt, nprof, **opts)
-    t_step, c_step = P.sl_kernel_time(m.h, P.KER_ADV2D)
     buckets = []
-    for b in range(len(set(w.orders.tolist()))):
+    for b in range(nb):
         n, K_b, vt, sw = P.sl_bucket_stats(m.h, b)
-        ta, ca = P.sl_kernel_time(m.h, P.KER_MIX_ADV + b)
-        tc, cc = P.sl_kernel_time(m.h, P.KER_MIX_CON + b)
         fl = advect2d_flops_per_element(n, 4, sw, vt) * K_b
-        adv_us = ta / max(ca, 1) * 1e3
+        adv_us = avg_us(acc, P.KER_MIX_ADV + b)
         buckets.append({"n": n, "elements": K_b, "vel_terms": vt, "remap_sweeps_mean": sw,
-                        "advect_us": adv_us, "constrain_us": tc / max(cc, 1) * 1e3,
+                        "advect_us": adv_us, "constrain_us": avg_us(acc, P.KER_MIX_CON + b),
                         "advect_flops": fl, "advect_TFLOPs": fl / (adv_us * 1e-6) / 1e12})
-    P.sl_set_profiling(m.h, False)
     m.read()
     m.close()
     # stated error: round trip under the steady swirl
@@ -358,7 +393,7 @@ def bench_c4(args, torch, P, W, stream):
         "round_trip_status": P.status_string(rrc),
         "step_latency": lat,
         "remap_sweeps_mean": st.remap_sweeps_mean,
-        "eager_step_ms": t_step / max(c_step, 1),
+        "eager_step_ms": avg_us(acc, P.KER_ADV2D) / 1e3,
         "graph_step_ms": el / args.steps * 1e3,
         "buckets": buckets,
         "roofline": {"kernel": f"k_advect2d (n={dom['n']} bucket)", "bound": "alu", "achieved": ach / 1e12,
@@ -528,23 +563,21 @@ def bench_c2bw(args, torch, P, W, stream):
     m = P.from_workload(w, stream=stream.cuda_stream)
     opts = dict(rk=w.rk, constraints=w.cmask, mode=w.mode)
     m.step(w.dt, warm, **opts)
+    kinds = [P.KER_ADV1D, P.KER_CON1D]
+    acc = profiled_window(P, m, w.dt, 10, opts, kinds)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     m.step(w.dt, steps, **opts)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    P.sl_set_profiling(m.h, True)
-    m.step(w.dt, 20, **opts)
-    t_adv, c_adv = P.sl_kernel_time(m.h, P.KER_ADV1D)
-    t_con, c_con = P.sl_kernel_time(m.h, P.KER_CON1D)
-    P.sl_set_profiling(m.h, False)
+    profiled_window(P, m, w.dt, 10, opts, kinds, acc)
     rc, phi, st = m.read()
-    T = (warm + steps + 20) * w.dt
+    T = st.t
     l2 = w.l2_error(phi, T)
     m.close()
 
-    adv_avg = t_adv / max(c_adv, 1) * 1e-3
-    con_avg = t_con / max(c_con, 1) * 1e-3
+    adv_avg = avg_us(acc, P.KER_ADV1D) * 1e-6
+    con_avg = avg_us(acc, P.KER_CON1D) * 1e-6
     by_a = advect_bytes_per_element(w.n, False, st.vel_terms) * w.K
     by_c = constrain_bytes_per_element(w.n, False) * w.K
     fl_a = advect_flops_per_element(w.n, 4, 3, False, st.vel_terms) * w.K
@@ -589,25 +622,23 @@ def bench_c2(args, torch, P, W, stream):
     opts = dict(rk=w.rk, constraints=w.cmask, mode=w.mode, energy_maxit=w.energy_maxit, energy_tol=w.energy_tol)
 
     m.step(w.dt, args.warmup, **opts)
+    kinds = [P.KER_ADV1D, P.KER_CON1D]
+    nprof = max(10, min(args.steps, 200))
+    acc = profiled_window(P, m, w.dt, nprof, opts, kinds)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     m.step(w.dt, args.steps, **opts)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    profiled_window(P, m, w.dt, nprof, opts, kinds, acc)
     rc, phi, st = m.read()
-    T = (args.warmup + args.steps) * w.dt
+    T = st.t
     l2 = w.l2_error(phi, T)
     lat = step_latency(torch, m, w.dt, opts, samples=min(200, max(10, args.steps)))
-
-    # per-kernel HIP-event timing on the mesh's stream (a second pass)
-    nprof = max(10, min(args.steps, 200))
-    P.sl_set_profiling(m.h, True)
-    m.step(w.dt, nprof, **opts)
-    t_adv, c_adv = P.sl_kernel_time(m.h, P.KER_ADV1D)
-    t_con, c_con = P.sl_kernel_time(m.h, P.KER_CON1D)
-    P.sl_set_profiling(m.h, False)
     m.read()
     m.close()
+    t_adv, c_adv = acc[P.KER_ADV1D]
+    t_con, c_con = acc[P.KER_CON1D]
 
     s_stages = 4
     nq = 3

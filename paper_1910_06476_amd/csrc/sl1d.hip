@@ -1068,11 +1068,11 @@ void launch_adv_na(const Step1DArgs& A, dim3 grid, hipStream_t s)
 {
     const bool rk4 = A.rk.s == 4;  // the classical tableau, the only 4-stage one
     if (A.cons) {
-        if (rk4) hipLaunchKernelGGL((k_advect1d<N, true, NA, 4>), grid, dim3(kBlock), 0, s, A);
-        else hipLaunchKernelGGL((k_advect1d<N, true, NA, 0>), grid, dim3(kBlock), 0, s, A);
+        if (rk4) launch_timed((k_advect1d<N, true, NA, 4>), grid, dim3(kBlock), 0, s, A);
+        else launch_timed((k_advect1d<N, true, NA, 0>), grid, dim3(kBlock), 0, s, A);
     } else {
-        if (rk4) hipLaunchKernelGGL((k_advect1d<N, false, NA, 4>), grid, dim3(kBlock), 0, s, A);
-        else hipLaunchKernelGGL((k_advect1d<N, false, NA, 0>), grid, dim3(kBlock), 0, s, A);
+        if (rk4) launch_timed((k_advect1d<N, false, NA, 4>), grid, dim3(kBlock), 0, s, A);
+        else launch_timed((k_advect1d<N, false, NA, 0>), grid, dim3(kBlock), 0, s, A);
     }
 }
 
@@ -1094,7 +1094,7 @@ template <int N>
 int launch_con_n(const Step1DArgs& A, hipStream_t s)
 {
     dim3 grid((A.K + kConElems - 1) / kConElems);
-    hipLaunchKernelGGL(k_constrain1d<N>, grid, dim3(kConBlock), 0, s, A);
+    launch_timed(k_constrain1d<N>, grid, dim3(kConBlock), 0, s, A);
     return hipGetLastError() == hipSuccess ? 0 : 1;
 }
 

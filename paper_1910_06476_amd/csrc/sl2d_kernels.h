@@ -1482,8 +1482,8 @@ int facevel_n(int kx, int ky, int periodic, const double* aN, const double* tab,
 template <int N, int PR>
 void adv_launch(const Step2DArgs& A, dim3 grid, hipStream_t s)
 {
-    if (A.targets) hipLaunchKernelGGL((k_advect2d<N, PR, true>), grid, dim3(kBlock2), 0, s, A);
-    else hipLaunchKernelGGL((k_advect2d<N, PR, false>), grid, dim3(kBlock2), 0, s, A);
+    if (A.targets) launch_timed((k_advect2d<N, PR, true>), grid, dim3(kBlock2), 0, s, A);
+    else launch_timed((k_advect2d<N, PR, false>), grid, dim3(kBlock2), 0, s, A);
 }
 
 // Every block of an advect or constrain launch owns a row of the per-block
@@ -1495,7 +1495,7 @@ int adv_shape(const Step2DArgs& A, hipStream_t s)
     using S = Shape2<N, BSEL>;
     const int grid = (A.K + S::E - 1) / S::E;
     if (grid > A.nblk) return 1;
-    hipLaunchKernelGGL((k_advect2d<N, 0, false, BSEL>), dim3(grid), dim3(S::BS), 0, s, A);
+    launch_timed((k_advect2d<N, 0, false, BSEL>), dim3(grid), dim3(S::BS), 0, s, A);
     return hipGetLastError() == hipSuccess ? 0 : 1;
 }
 
@@ -1522,13 +1522,13 @@ int con_n(const Step2DArgs& A, hipStream_t s)
     if (nchunk > A.nblk) return 1;
     static std::atomic<int> cap_bt[kMaxDevices], cap[kMaxDevices];
     if (A.cmask & (SL_C_MASS | SL_C_ENERGY)) {
-        hipLaunchKernelGGL(k_constrain2d_me<N>, dim3(nchunk), dim3(kBlock2), 0, s, A);
+        launch_timed(k_constrain2d_me<N>, dim3(nchunk), dim3(kBlock2), 0, s, A);
     } else if (A.iface == SL_IFACE_BACKTRACK) {
         const int r = resident_blocks(k_constrain2d<N, true>, cap_bt);
-        hipLaunchKernelGGL((k_constrain2d<N, true>), dim3(nchunk < r ? nchunk : r), dim3(kBlock2), 0, s, A);
+        launch_timed((k_constrain2d<N, true>), dim3(nchunk < r ? nchunk : r), dim3(kBlock2), 0, s, A);
     } else {
         const int r = resident_blocks(k_constrain2d<N, false>, cap);
-        hipLaunchKernelGGL((k_constrain2d<N, false>), dim3(nchunk < r ? nchunk : r), dim3(kBlock2), 0, s, A);
+        launch_timed((k_constrain2d<N, false>), dim3(nchunk < r ? nchunk : r), dim3(kBlock2), 0, s, A);
     }
     return hipGetLastError() == hipSuccess ? 0 : 1;
 }
@@ -1612,7 +1612,7 @@ int con_mixed_n(const Step2DArgs& A, hipStream_t s)
     if (nchunk > A.nblk) return 1;
     static std::atomic<int> cap[kMaxDevices];
     const int r = resident_blocks(k_constrain2d_mixed<N>, cap);
-    hipLaunchKernelGGL(k_constrain2d_mixed<N>, dim3(nchunk < r ? nchunk : r), dim3(kBlock2), 0, s, A);
+    launch_timed(k_constrain2d_mixed<N>, dim3(nchunk < r ? nchunk : r), dim3(kBlock2), 0, s, A);
     return hipGetLastError() == hipSuccess ? 0 : 1;
 }
 

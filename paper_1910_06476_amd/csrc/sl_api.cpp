@@ -61,22 +61,39 @@ struct sl_mesh {
     sl_step_opts graph_opts;
 };
 
-// per-kernel timing events (profiling): before and after a launch of kernel k
-void ev_begin(sl_mesh* m, int k)
+thread_local LaunchEvents sl::tl_timed_launch;
+
+// per-kernel timing events (profiling) for kernel k.  A bracket around one
+// launch (one_launch) hands its pair to that launch, which records the
+// dispatch's own start and end (launch_timed); a bracket around several
+// launches records the pair on the stream before and after them.
+void ev_begin(sl_mesh* m, int k, bool one_launch)
 {
     if (!m->profiling) return;
     hipEvent_t a, b;
     (void)hipEventCreate(&a);
     (void)hipEventCreate(&b);
-    (void)hipEventRecord(a, m->stream);
+    if (one_launch)
+        tl_timed_launch = LaunchEvents{a, b};
+    else
+        (void)hipEventRecord(a, m->stream);
     m->pending[k].push_back(a);
     m->pending[k].push_back(b);
 }
 
-void ev_end(sl_mesh* m, int k)
+void ev_end(sl_mesh* m, int k, bool one_launch)
 {
     if (!m->profiling) return;
-    (void)hipEventRecord(m->pending[k].back(), m->stream);
+    if (!one_launch) {
+        (void)hipEventRecord(m->pending[k].back(), m->stream);
+    } else if (tl_timed_launch.start) {
+        // no launch took the pair: it carries no time
+        tl_timed_launch = LaunchEvents{};
+        for (int i = 0; i < 2; ++i) {
+            (void)hipEventDestroy(m->pending[k].back());
+            m->pending[k].pop_back();
+        }
+    }
 }
 
 namespace {
@@ -394,14 +411,14 @@ int mixed_launch_step(sl_mesh* m, std::vector<Step2DArgs>& B, double* src, doubl
     for (int b = 0; b < m->nbk; ++b) {
         B[b].phi = src + m->bOff[b];
         B[b].phi_out = dst + m->bOff[b];
-        ev_begin(m, KER_MIX_ADV + b);
+        ev_begin(m, KER_MIX_ADV + b, true);
         if (launch_advect2d(m->bn[b], B[b], m->stream)) return 1;
-        ev_end(m, KER_MIX_ADV + b);
+        ev_end(m, KER_MIX_ADV + b, true);
     }
     for (int b = 0; b < m->nbk; ++b) {
-        ev_begin(m, KER_MIX_CON + b);
+        ev_begin(m, KER_MIX_CON + b, true);
         if (launch_constrain2d_mixed(m->bn[b], B[b], m->stream)) return 1;
-        ev_end(m, KER_MIX_CON + b);
+        ev_end(m, KER_MIX_CON + b, true);
     }
     return 0;
 }
@@ -734,9 +751,9 @@ static sl_status step_mixed(sl_mesh* m, double dt, int32_t nsteps, const sl_step
             if (hipGraphLaunch(m->gexec, m->stream)) return SL_E_DEVICE;
     }
     for (; done < nsteps; ++done) {
-        ev_begin(m, KER_ADV2D);
+        ev_begin(m, KER_ADV2D, false);
         if (mixed_launch_step(m, B, m->phi, m->phi2)) return SL_E_DEVICE;
-        ev_end(m, KER_ADV2D);
+        ev_end(m, KER_ADV2D, false);
         // the graph captured m->phi as its input: bring the field back there
         if (hipMemcpyAsync(m->phi, m->phi2, m->dofs * sizeof(double), hipMemcpyDeviceToDevice, m->stream))
             return SL_E_DEVICE;
@@ -1006,12 +1023,12 @@ sl_status sl_step(sl_mesh* m, double dt, int32_t nsteps, const sl_step_opts* o)
             B.phi = m->phi;
             B.phi_out = m->phi2;
             if (opt.iface == SL_IFACE_BACKTRACK && launch_backtrace2d(m->n, B, m->stream)) return SL_E_DEVICE;
-            ev_begin(m, KER_ADV2D);
+            ev_begin(m, KER_ADV2D, true);
             if (launch_advect2d(m->n, B, m->stream)) return SL_E_DEVICE;
-            ev_end(m, KER_ADV2D);
-            ev_begin(m, KER_CON2D);
+            ev_end(m, KER_ADV2D, true);
+            ev_begin(m, KER_CON2D, true);
             if (launch_constrain2d(m->n, B, m->stream)) return SL_E_DEVICE;
-            ev_end(m, KER_CON2D);
+            ev_end(m, KER_CON2D, true);
             std::swap(m->phi, m->phi2);
             m->t += dt;
             m->steps += 1;
@@ -1043,12 +1060,12 @@ sl_status sl_step(sl_mesh* m, double dt, int32_t nsteps, const sl_step_opts* o)
         }
         A.phi = m->phi;
         A.phi_out = m->phi2;
-        ev_begin(m, KER_ADV1D);
+        ev_begin(m, KER_ADV1D, true);
         if (launch_advect1d(m->n, A, m->stream)) return SL_E_DEVICE;
-        ev_end(m, KER_ADV1D);
-        ev_begin(m, KER_CON1D);
+        ev_end(m, KER_ADV1D, true);
+        ev_begin(m, KER_CON1D, true);
         if (launch_constrain1d(m->n, A, m->stream)) return SL_E_DEVICE;
-        ev_end(m, KER_CON1D);
+        ev_end(m, KER_CON1D, true);
         std::swap(m->phi, m->phi2);
         m->t += dt;
         m->steps += 1;

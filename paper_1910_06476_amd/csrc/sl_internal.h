@@ -1,6 +1,7 @@
 // Internal declarations shared by the host runtime and the HIP kernels.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -127,6 +128,28 @@ struct CaptureHold {
     ~CaptureHold();
     int saved;
 };
+
+// Per-kernel timing: the pair of events that the next timed launch made on
+// this thread records itself, with the dispatch's own start and end
+// timestamps (the interval a kernel trace reports, free of the packets and
+// fences that events recorded on the stream around it add), or none.  Set
+// just before one launch and taken by it.
+struct LaunchEvents {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+extern thread_local LaunchEvents tl_timed_launch;
+
+template <typename F, typename... Args>
+inline void launch_timed(F kernel, dim3 grid, dim3 block, uint32_t shm, hipStream_t s, Args... args)
+{
+    const LaunchEvents ev = tl_timed_launch;
+    if (ev.start) {
+        tl_timed_launch = LaunchEvents{};
+        hipExtLaunchKernelGGL(kernel, grid, block, shm, s, ev.start, ev.stop, 0u, args...);
+    } else {
+        hipLaunchKernelGGL(kernel, grid, block, shm, s, args...);
+    }
+}
 
 // Step options within their documented ranges.
 bool step_opts_valid(const sl_step_opts& opt);
