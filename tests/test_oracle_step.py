@@ -6,6 +6,8 @@
   are all exact, and the exact field satisfies every constraint row;
 * the 2D remap with constant velocity factorises (V = A (x) B), so a
   separable field steps like the outer product of two 1D steps;
+* the mass targets integrate a flux cubic in t exactly with the tableau's
+  quadrature (RK3, RK4);
 * constants are preserved by any divergence-free nodal velocity;
 * mirror symmetry x -> L - x, a -> -a;
 * HARD mass rows make the global mass telescope (periodic);
@@ -80,6 +82,24 @@ def test_polynomial_reproduction_1d_mass_energy(ora, rk):
     # the stop is strict (|phi^(k) - phi^(k-1)| < tol), so tol = 0 always runs
     # the full count even when an exact fixed point is reached
     assert st.max_picard == 6
+
+
+@pytest.mark.parametrize("mode", [W.HARD, W.SOFT])
+@pytest.mark.parametrize("rk", [3, 4])
+def test_mass_target_quadrature_exact_for_cubic_flux(ora, rk, mode):
+    """A cubic moved at constant speed: the face values, and with them the
+    mass fluxes, are cubic in t, which the tableau's own quadrature (Simpson's
+    weights for Kutta's third order and for RK4) integrates exactly, while
+    equal weights at the same abscissae would not.  After one step every
+    element whose inflow face is interior is exact; the inflow element's
+    stage values come from ghost rows that are linear in t."""
+    w = _poly_workload(1, 6, 3, rk=rk, cmask=W.BOUNDARY | W.MASS, mode=mode)
+    w.nsteps = 1
+    phi, st = ora.run_workload(w)
+    ex = w.exact_at(w.dt)
+    err = np.abs((phi - ex).reshape(w.K, w.n))
+    assert err[1:].max() < 1e-12 * max(1.0, np.abs(ex).max())
+    assert st.flags == 0
 
 
 @pytest.mark.parametrize("mode", [W.HARD, W.SOFT])
