@@ -876,104 +876,175 @@ int resident_blocks(Kern kernel, std::atomic<int>* cache)
     return c;
 }
 
+// Elements per chunk of the persistent boundary-row solves: as many as two
+// nodes per lane hold, with every edge point of the chunk on a lane of its
+// own (at n = 13: three elements, against one per block with a lane per
+// node; more elements in flight per compute unit, and a third of the
+// barriers per element).  Node work runs on "virtual lanes" v = t + 256 k,
+// k < PASS.
+template <int N> struct ConShape {
+    static constexpr int ND = N * N, NB = 4 * N;
+    static constexpr int E = (2 * kBlock2) / ND < kBlock2 / NB ? (2 * kBlock2) / ND : kBlock2 / NB;
+    static constexpr int PASS = (E * ND + kBlock2 - 1) / kBlock2;
+    static_assert(E >= 1 && PASS <= 2 && E * NB <= kBlock2, "constrain chunk shape");
+};
+
+// The rows' solution for the chunk's elements once the face values are in
+// s_fv and d_B - C_B phihat in s_rb (edge lane te, tt):
+//   phi = phihat + C_B^T z, z = Q (d_B - C_B phihat), Q = (C_B C_B^T)^+
+// (HARD) or (I + C_B C_B^T)^{-1} (SOFT); then phi is stored and the edge
+// lanes take the largest boundary-row residual of the result.
+template <int N>
+__device__ __forceinline__ void con_chunk_solve(const Step2DArgs& A, const double* s_q, double (*s_rb)[4 * N],
+                                                double (*s_d)[4 * N], const double (*s_fv)[4 * N],
+                                                double (*s_y)[N * N], const double (&ph)[ConShape<N>::PASS],
+                                                const int (&vslot)[ConShape<N>::PASS],
+                                                const int (&vp)[ConShape<N>::PASS],
+                                                const double (&lc)[ConShape<N>::PASS][4], int base, int nel,
+                                                bool bnd, int te, int tt, bool edge, int& fl,
+                                                unsigned long long& rmax)
+{
+    using O = Off2<N>;
+    using S = ConShape<N>;
+    constexpr int ND = S::ND, NB = S::NB, E = S::E, PASS = S::PASS;
+    if (bnd) {
+        if (edge) {
+            double z = 0.0;
+            // a partial unroll: the loads of a full one hold too many VGPRs
+#pragma unroll 8
+            for (int q = 0; q < NB; ++q) z = fma(s_q[tt * NB + q], s_rb[te][q], z);
+            s_d[te][tt] = z;
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int k = 0; k < PASS; ++k) {
+        const int slot = vslot[k];
+        if (slot < E) {
+            const int p = vp[k], i = p % N, j = p / N;
+            double phi = ph[k];
+            if (bnd)
+                phi = ph[k] + lc[k][0] * s_d[slot][j] + lc[k][1] * s_d[slot][N + j] + lc[k][2] * s_d[slot][2 * N + i] +
+                      lc[k][3] * s_d[slot][3 * N + i];
+            s_y[slot][p] = phi;
+            if (base + slot < nel) {
+                if (!isfinite(phi)) fl |= FLAG_NONFINITE;
+                A.phi_out[(size_t)(base + slot) * ND + p] = phi;
+            }
+        }
+    }
+    __syncthreads();
+    if (bnd && edge && base + te < nel) {
+        const double* tab = A.tab;
+        const int side = tt / N, k = tt % N;
+        const double* lv = tab + ((side & 1) ? O::L1 : O::L0);
+        double tr = 0.0;
+        if (side < 2)
+            for (int c = 0; c < N; ++c) tr = fma(lv[c], s_y[te][c + N * k], tr);
+        else
+            for (int c = 0; c < N; ++c) tr = fma(lv[c], s_y[te][k + N * c], tr);
+        rmax = abs_bits(tr - s_fv[te][tt]);
+    }
+}
+
+// The chunk's node lanes: element slot, node, the C_B^T coefficients
+// l0(xi_i), l1(xi_i), l0(xi_j), l1(xi_j), and phi-hat
+template <int N>
+__device__ __forceinline__ void con_chunk_nodes(const Step2DArgs& A, int t, int (&vslot)[ConShape<N>::PASS],
+                                                int (&vp)[ConShape<N>::PASS], double (&lc)[ConShape<N>::PASS][4])
+{
+    using O = Off2<N>;
+    using S = ConShape<N>;
+#pragma unroll
+    for (int k = 0; k < S::PASS; ++k) {
+        const int v = t + kBlock2 * k;
+        vslot[k] = v / S::ND;
+        vp[k] = v - vslot[k] * S::ND;
+        const int i = vp[k] % N, j = vp[k] / N;
+        lc[k][0] = A.tab[O::L0 + i];
+        lc[k][1] = A.tab[O::L1 + i];
+        lc[k][2] = A.tab[O::L0 + j];
+        lc[k][3] = A.tab[O::L1 + j];
+    }
+}
+
+template <int N>
+__device__ __forceinline__ void con_chunk_load(const Step2DArgs& A, int base, int nel,
+                                               const int (&vslot)[ConShape<N>::PASS],
+                                               const int (&vp)[ConShape<N>::PASS], double (&ph)[ConShape<N>::PASS])
+{
+    using S = ConShape<N>;
+#pragma unroll
+    for (int k = 0; k < S::PASS; ++k) {
+        const int li = base + vslot[k];
+        ph[k] = (vslot[k] < S::E && li < nel) ? A.phihat[(size_t)li * S::ND + vp[k]] : 0.0;
+    }
+}
+
 template <int N, bool BT>
 __global__ __launch_bounds__(kBlock2) void k_constrain2d(Step2DArgs A)
 {
     using O = Off2<N>;
-    constexpr int ND = N * N;
-    constexpr int E = kBlock2 / ND;
-    constexpr int NQ = 16 * N * N;
+    using S = ConShape<N>;
+    constexpr int ND = S::ND, NB = S::NB, E = S::E, PASS = S::PASS, NQ = 16 * ND;
     __shared__ double s_q[NQ];
     // per element: z, d_B - C_B phihat, d_B, phi
-    __shared__ double s_d[E][4 * N], s_rb[E][4 * N], s_fv[E][4 * N], s_y[E][ND];
+    __shared__ double s_d[E][NB], s_rb[E][NB], s_fv[E][NB], s_y[E][ND];
     __shared__ int s_flag;
     __shared__ unsigned long long s_stat;
 
     const int t = threadIdx.x;
-    const int slot = t / ND, p = t - slot * ND;
-    const bool inblk = slot < E;
-    const double* __restrict__ tab = A.tab;
     const int kx = A.kx, ky = A.ky, K = A.K;
     const bool bnd = (A.cmask & SL_C_BOUNDARY) != 0;
-    const double* Qg = tab + (A.mode == SL_MODE_HARD ? O::QH : O::QS);
+    const double* Qg = A.tab + (A.mode == SL_MODE_HARD ? O::QH : O::QS);
     for (int k = t; k < NQ; k += kBlock2) s_q[k] = Qg[k];
     if (t == 0) {
         s_flag = 0;
         s_stat = 0ull;
     }
-    const int i = p % N, j = p / N;
-    const double l0i = tab[O::L0 + i], l1i = tab[O::L1 + i], l0j = tab[O::L0 + j], l1j = tab[O::L1 + j];
+    int vslot[PASS], vp[PASS];
+    double lc[PASS][4];
+    con_chunk_nodes<N>(A, t, vslot, vp, lc);
+    const int te = t / NB, tt = t - te * NB;  // edge lane: element slot, edge point
+    const bool edge = te < E;
     const int nchunk = (K + E - 1) / E;
+    int fl = 0;
+    unsigned long long rmax = 0ull;  // this lane's largest boundary-row residual
 
     for (int chunk = blockIdx.x; chunk < nchunk; chunk += gridDim.x) {
-        const int e = chunk * E + slot;
-        const bool live = inblk && e < K;
-        const int ee = live ? e : 0;
-        const size_t g = (size_t)ee * ND + p;
-        const double ph = live ? A.phihat[g] : 0.0;
+        const int base = chunk * E;
+        double ph[PASS];
+        con_chunk_load<N>(A, base, K, vslot, vp, ph);
 
         // face value at the element's edge point tt: upwind of its own trace
         // and the neighbour's matching trace (eq. 4.12a); ghost values at the
         // domain boundary
-        for (int tt = p; inblk && tt < 4 * N; tt += ND) {
+        if (edge) {
+            const int ee = base + te < K ? base + te : 0;
             int nbe, nbt, gidx;
             bool high;
             face_partner2<N>(ee, tt, kx, ky, A.periodic, nbe, nbt, gidx, high);
             // offered face values: the traces, or with backtracking (BT) the
             // record's last 4n slots; the residual takes the own trace
-            const int fo = BT ? A.rstride - 4 * N : 0;
+            const int fo = BT ? A.rstride - NB : 0;
             const double trace = A.rec[(size_t)ee * A.rstride + tt];
             const double mine = BT ? A.rec[(size_t)ee * A.rstride + fo + tt] : trace;
             const double other = nbe >= 0 ? A.rec[(size_t)nbe * A.rstride + fo + nbt] : A.gnext[gidx];
-            const double vn = A.vface[(size_t)ee * 4 * N + tt];
+            const double vn = A.vface[(size_t)ee * NB + tt];
             const double lo = high ? other : mine, hi = high ? mine : other;
             const double dv = upwind2(vn, lo, hi);
-            s_fv[slot][tt] = dv;
-            s_rb[slot][tt] = dv - trace;
+            s_fv[te][tt] = dv;
+            s_rb[te][tt] = dv - trace;
         }
         __syncthreads();
-
-        // phi = phihat + C_B^T z, z = Q (d_B - C_B phihat), Q = (C_B C_B^T)^+
-        // (HARD) or (I + C_B C_B^T)^{-1} (SOFT); lanes t < 4n form z, then
-        // every node applies C_B^T (four products)
-        double phi = ph;
-        if (bnd) {
-            for (int tt = p; inblk && tt < 4 * N; tt += ND) {
-                double z = 0.0;
-                // a partial unroll: the loads of a full one held 126 VGPRs
-                // (four waves per SIMD), this 68 (seven)
-#pragma unroll 8
-                for (int q = 0; q < 4 * N; ++q) z = fma(s_q[tt * 4 * N + q], s_rb[slot][q], z);
-                s_d[slot][tt] = z;
-            }
-            __syncthreads();
-            if (inblk)
-                phi = ph + l0i * s_d[slot][j] + l1i * s_d[slot][N + j] + l0j * s_d[slot][2 * N + i] +
-                      l1j * s_d[slot][3 * N + i];
-        }
-        if (inblk) s_y[slot][p] = phi;
-        __syncthreads();
-        int fl = 0;
-        unsigned long long rmax = 0ull;  // this lane's largest boundary-row residual
-        if (live) {
-            if (!isfinite(phi)) fl |= FLAG_NONFINITE;
-            A.phi_out[g] = phi;
-            for (int tt = p; bnd && tt < 4 * N; tt += ND) {
-                const int side = tt / N, k = tt % N;
-                const double* lv = tab + ((side & 1) ? O::L1 : O::L0);
-                double tr = 0.0;
-                if (side < 2)
-                    for (int c = 0; c < N; ++c) tr = fma(lv[c], s_y[slot][c + N * k], tr);
-                else
-                    for (int c = 0; c < N; ++c) tr = fma(lv[c], s_y[slot][k + N * c], tr);
-                const unsigned long long r = abs_bits(tr - s_fv[slot][tt]);
-                rmax = r > rmax ? r : rmax;
-            }
-        }
-        slot_max<1>(&s_stat, 0, rmax);  // one block-wide slot: one atomic per wave
-        if (fl) atomicOr(&s_flag, fl);
+        unsigned long long r = 0ull;
+        con_chunk_solve<N>(A, s_q, s_rb, s_d, s_fv, s_y, ph, vslot, vp, lc, base, K, bnd, te, tt, edge, fl, r);
+        rmax = r > rmax ? r : rmax;
         __syncthreads();  // s_fv, s_rb, s_d, s_y are rewritten by the next chunk
     }
+    slot_max<1>(&s_stat, 0, rmax);  // one block-wide slot: one atomic per wave
+    if (fl) atomicOr(&s_flag, fl);
+    __syncthreads();
     if (t == 0) {
         if (s_flag) A.flag_part[A.nblk + blockIdx.x] |= s_flag;
         double* sp = A.stat_part + (size_t)blockIdx.x * kStatSlots;
@@ -1364,39 +1435,39 @@ template <int N>
 __global__ __launch_bounds__(kBlock2) void k_constrain2d_mixed(Step2DArgs A)
 {
     using O = Off2<N>;
-    constexpr int ND = N * N, E = kBlock2 / ND, NB = 4 * N, NQ = 16 * ND;
+    using S = ConShape<N>;
+    constexpr int ND = S::ND, NB = S::NB, E = S::E, PASS = S::PASS, NQ = 16 * ND;
     __shared__ double s_q[NQ];
     __shared__ double s_d[E][NB], s_rb[E][NB], s_fv[E][NB], s_y[E][ND];
     __shared__ int s_flag;
     __shared__ unsigned long long s_stat;
 
     const int t = threadIdx.x;
-    const int slot = t / ND, p = t - slot * ND;
-    const bool inblk = slot < E;
-    const double* __restrict__ tab = A.tab;
-    const int K_b = A.K, Kall = A.kx * A.ky;
-    const int* meta = A.mix + 2 * Kall;
-    const double* Qg = tab + (A.mode == SL_MODE_HARD ? O::QH : O::QS);
+    const int K_b = A.K;
+    const double* Qg = A.tab + (A.mode == SL_MODE_HARD ? O::QH : O::QS);
     for (int k = t; k < NQ; k += kBlock2) s_q[k] = Qg[k];
     if (t == 0) {
         s_flag = 0;
         s_stat = 0ull;
     }
-    const int i = p % N, j = p / N;
-    const double l0i = tab[O::L0 + i], l1i = tab[O::L1 + i], l0j = tab[O::L0 + j], l1j = tab[O::L1 + j];
+    int vslot[PASS], vp[PASS];
+    double lc[PASS][4];
+    con_chunk_nodes<N>(A, t, vslot, vp, lc);
+    const int te = t / NB, tt = t - te * NB;  // edge lane: element slot, edge point
+    const bool edge = te < E;
+    const int side = tt / N, k = tt % N;
+    const bool high = side == 0 || side == 2;  // e is the high side of its left and bottom faces
     const int nchunk = (K_b + E - 1) / E;
+    int fl = 0;
+    unsigned long long rmax = 0ull;  // this lane's largest boundary-row residual
 
     for (int chunk = blockIdx.x; chunk < nchunk; chunk += gridDim.x) {
-        const int li = chunk * E + slot;  // index within the bucket
-        const bool live = inblk && li < K_b;
-        const int ll = live ? li : 0;
-        const size_t g = (size_t)ll * ND + p;
-        const double ph = live ? A.phihat[g] : 0.0;
-        const double* myrec = A.rec + (size_t)ll * NB;
+        const int base = chunk * E;
+        double ph[PASS];
+        con_chunk_load<N>(A, base, K_b, vslot, vp, ph);
 
-        for (int tt = p; inblk && tt < NB; tt += ND) {
-            const int side = tt / N, k = tt % N;
-            const bool high = side == 0 || side == 2;  // e is the high side of its left and bottom faces
+        if (edge) {
+            const int ll = base + te < K_b ? base + te : 0;  // index within the bucket
             // the neighbour's trace row from the face partner table (one load
             // where the topology lookup took a chain of four)
             const int32_t* f = A.nbr + (size_t)ll * MixFace::kPer + side * MixFace::kField;
@@ -1409,48 +1480,21 @@ __global__ __launch_bounds__(kBlock2) void k_constrain2d_mixed(Step2DArgs A)
                 const double* M = A.interp + f[MixFace::kInterpOff];
                 for (int q = 0; q < n2; ++q) other = fma(M[k * n2 + q], tr2[q], other);
             }
-            const double mine = myrec[tt];
+            const double mine = A.rec[(size_t)ll * NB + tt];
             const double vn = A.vface[(size_t)ll * NB + tt];
             const double dv = upwind2(vn, high ? other : mine, high ? mine : other);
-            s_fv[slot][tt] = dv;
-            s_rb[slot][tt] = dv - mine;
+            s_fv[te][tt] = dv;
+            s_rb[te][tt] = dv - mine;
         }
         __syncthreads();
-
-        double phi = ph;
-        for (int tt = p; inblk && tt < NB; tt += ND) {
-            double z = 0.0;
-#pragma unroll 8
-            for (int q = 0; q < NB; ++q) z = fma(s_q[tt * NB + q], s_rb[slot][q], z);
-            s_d[slot][tt] = z;
-        }
-        __syncthreads();
-        if (inblk)
-            phi = ph + l0i * s_d[slot][j] + l1i * s_d[slot][N + j] + l0j * s_d[slot][2 * N + i] +
-                  l1j * s_d[slot][3 * N + i];
-        if (inblk) s_y[slot][p] = phi;
-        __syncthreads();
-        int fl = 0;
-        unsigned long long rmax = 0ull;  // this lane's largest boundary-row residual
-        if (live) {
-            if (!isfinite(phi)) fl |= FLAG_NONFINITE;
-            A.phi_out[g] = phi;
-            for (int tt = p; tt < NB; tt += ND) {
-                const int side = tt / N, k = tt % N;
-                const double* lv = tab + ((side & 1) ? O::L1 : O::L0);
-                double tr = 0.0;
-                if (side < 2)
-                    for (int c = 0; c < N; ++c) tr = fma(lv[c], s_y[slot][c + N * k], tr);
-                else
-                    for (int c = 0; c < N; ++c) tr = fma(lv[c], s_y[slot][k + N * c], tr);
-                const unsigned long long r = abs_bits(tr - s_fv[slot][tt]);
-                rmax = r > rmax ? r : rmax;
-            }
-        }
-        slot_max<1>(&s_stat, 0, rmax);  // one block-wide slot: one atomic per wave
-        if (fl) atomicOr(&s_flag, fl);
+        unsigned long long r = 0ull;
+        con_chunk_solve<N>(A, s_q, s_rb, s_d, s_fv, s_y, ph, vslot, vp, lc, base, K_b, true, te, tt, edge, fl, r);
+        rmax = r > rmax ? r : rmax;
         __syncthreads();  // s_fv, s_rb, s_d, s_y are rewritten by the next chunk
     }
+    slot_max<1>(&s_stat, 0, rmax);  // one block-wide slot: one atomic per wave
+    if (fl) atomicOr(&s_flag, fl);
+    __syncthreads();
     if (t == 0) {
         if (s_flag) A.flag_part[A.nblk + blockIdx.x] |= s_flag;
         double* sp = A.stat_part + (size_t)blockIdx.x * kStatSlots;
@@ -1514,21 +1558,33 @@ int adv_n(const Step2DArgs& A, hipStream_t s)
     return hipGetLastError() == hipSuccess ? 0 : 1;
 }
 
+// grid of a persistent constrain launch over nchunk chunks: no more blocks
+// than are resident at once (r), nor than the per-block partials hold
+inline int con_grid(int nchunk, int r, int nblk)
+{
+    int g = nchunk < r ? nchunk : r;
+    return g < nblk ? g : nblk;
+}
+
 template <int N>
 int con_n(const Step2DArgs& A, hipStream_t s)
 {
-    constexpr int E = kBlock2 / (N * N);
-    const int nchunk = (A.K + E - 1) / E;
-    if (nchunk > A.nblk) return 1;
     static std::atomic<int> cap_bt[kMaxDevices], cap[kMaxDevices];
+    if (A.nblk < 1) return 1;
     if (A.cmask & (SL_C_MASS | SL_C_ENERGY)) {
+        constexpr int E = kBlock2 / (N * N);
+        const int nchunk = (A.K + E - 1) / E;
+        if (nchunk > A.nblk) return 1;
         launch_timed(k_constrain2d_me<N>, dim3(nchunk), dim3(kBlock2), 0, s, A);
-    } else if (A.iface == SL_IFACE_BACKTRACK) {
+        return hipGetLastError() == hipSuccess ? 0 : 1;
+    }
+    const int nchunk = (A.K + ConShape<N>::E - 1) / ConShape<N>::E;
+    if (A.iface == SL_IFACE_BACKTRACK) {
         const int r = resident_blocks(k_constrain2d<N, true>, cap_bt);
-        launch_timed((k_constrain2d<N, true>), dim3(nchunk < r ? nchunk : r), dim3(kBlock2), 0, s, A);
+        launch_timed((k_constrain2d<N, true>), dim3(con_grid(nchunk, r, A.nblk)), dim3(kBlock2), 0, s, A);
     } else {
         const int r = resident_blocks(k_constrain2d<N, false>, cap);
-        launch_timed((k_constrain2d<N, false>), dim3(nchunk < r ? nchunk : r), dim3(kBlock2), 0, s, A);
+        launch_timed((k_constrain2d<N, false>), dim3(con_grid(nchunk, r, A.nblk)), dim3(kBlock2), 0, s, A);
     }
     return hipGetLastError() == hipSuccess ? 0 : 1;
 }
@@ -1607,12 +1663,11 @@ int facevel_mixed_n(int K_b, int bucket, int kx, int ky, const int32_t* elems, c
 template <int N>
 int con_mixed_n(const Step2DArgs& A, hipStream_t s)
 {
-    constexpr int E = kBlock2 / (N * N);
-    const int nchunk = (A.K + E - 1) / E;
-    if (nchunk > A.nblk) return 1;
+    if (A.nblk < 1) return 1;
+    const int nchunk = (A.K + ConShape<N>::E - 1) / ConShape<N>::E;
     static std::atomic<int> cap[kMaxDevices];
     const int r = resident_blocks(k_constrain2d_mixed<N>, cap);
-    launch_timed(k_constrain2d_mixed<N>, dim3(nchunk < r ? nchunk : r), dim3(kBlock2), 0, s, A);
+    launch_timed(k_constrain2d_mixed<N>, dim3(con_grid(nchunk, r, A.nblk)), dim3(kBlock2), 0, s, A);
     return hipGetLastError() == hipSuccess ? 0 : 1;
 }
 
