@@ -4,6 +4,7 @@
 #pragma once
 #include <atomic>
 #include <type_traits>
+#include <utility>
 
 #include "sl2d_ops.h"
 
@@ -357,7 +358,8 @@ __device__ double backtrace2(const Step2DArgs& A, const double* cu, const double
 // face values it offers.
 // ---------------------------------------------------------------------------
 // block shapes of the advect kernel: 0 = 256 lanes, 1 = the fewest whole
-// waves that hold one element, 2 = 512 lanes
+// waves that hold one element, 2 = 512 lanes.  With one element per block
+// the residual takes the iterate by row broadcasts (resid_bcast).
 template <int N, int BSEL> struct Shape2 {
     static constexpr int ND = N * N;
     static constexpr int BS = BSEL == 0 ? kBlock2 : BSEL == 1 ? ((ND + 63) / 64) * 64 : 2 * kBlock2;
@@ -442,6 +444,47 @@ __device__ __forceinline__ void slot_max(unsigned long long* dst, int slot, unsi
 __device__ __forceinline__ unsigned long long abs_bits(double v)
 {
     return (unsigned long long)__double_as_longlong(fabs(v));
+}
+
+// Lane K of each row of 16 lanes, broadcast to the whole row (DPP
+// row_newbcast on a 64-bit value: one VALU move, no LDS access)
+template <int K>
+__device__ __forceinline__ double row_bcast(double v)
+{
+    const long long r = __builtin_amdgcn_update_dpp(0ll, __builtin_bit_cast(long long, v), 0x150 + K, 0xf, 0xf, true);
+    return __builtin_bit_cast(double, r);
+}
+
+// Residual product (V x)_p = sum_m b_m sum_l a_l x[m][l] of one particle,
+// for blocks that hold one element: every row of 16 lanes then belongs to
+// it, and each lane keeps iterate value 16 c + (lane % 16) of the chunks c
+// a row of x touches, so each product takes its x from a row broadcast
+// instead of an LDS read (2 reads per row of x instead of n).  Same
+// operations in the same order as the LDS form.
+template <int N, int M, int... L>
+__device__ __forceinline__ double resid_row(const double (&a)[N], double xa, double xb,
+                                            std::integer_sequence<int, L...>)
+{
+    constexpr int C0 = (N * M) >> 4;
+    double inner = 0.0;
+    ((inner = fma(a[L], row_bcast<(N * M + L) & 15>(((N * M + L) >> 4) == C0 ? xa : xb), inner)), ...);
+    return inner;
+}
+
+template <int N, int... M>
+__device__ __forceinline__ double resid_bcast(const double (&a)[N], const double (&b)[N], const double* x, int k16,
+                                              std::integer_sequence<int, M...>)
+{
+    constexpr int ND = N * N;
+    double vx = 0.0;
+    // the chunk values past the iterate's end are clamped to its last entry
+    // (in bounds; no product takes them)
+    ((vx = fma(b[M],
+               resid_row<N, M>(a, x[min(16 * ((N * M) >> 4) + k16, ND - 1)],
+                               x[min(16 * ((N * M + N - 1) >> 4) + k16, ND - 1)], std::make_integer_sequence<int, N>{}),
+               vx)),
+     ...);
+    return vx;
 }
 
 template <int N, int PR, bool TGT, int BSEL = 0>
@@ -768,12 +811,22 @@ __global__ __launch_bounds__((Shape2<N, BSEL>::BS)) void k_advect2d(Step2DArgs A
     for (int it = 0; it < A.refine; ++it) {
         // residual r_p = phi*_p - (V x)_p, (V x)_p = sum_m b_m sum_l a_l x[m][l]
         double vx = 0.0;
+        if constexpr (E == 1) {
+            // every lane of the block takes part (the row broadcasts read
+            // from idle lanes too)
+            vx = resid_bcast<N>(a, b, s_x[0], t & 15, std::make_integer_sequence<int, N>{});
+            // an empty use in every lane: the products stay where the
+            // broadcasts are, instead of sinking into the store's branch
+            // with every broadcast value live until then
+            asm volatile("" : : "v"(vx));
+        } else {
 #pragma unroll
-        for (int m = 0; m < N; ++m) {
-            double inner = 0.0;
+            for (int m = 0; m < N; ++m) {
+                double inner = 0.0;
 #pragma unroll
-            for (int l = 0; l < N; ++l) inner = fma(a[l], s_x[sl][l + N * m], inner);
-            vx = fma(b[m], inner, vx);
+                for (int l = 0; l < N; ++l) inner = fma(a[l], s_x[sl][l + N * m], inner);
+                vx = fma(b[m], inner, vx);
+            }
         }
         if (inblk) s_r[slot][q] = sq - vx;
         __syncthreads();  // s_x is no longer read in this sweep
