@@ -446,13 +446,18 @@ __device__ __forceinline__ unsigned long long abs_bits(double v)
     return (unsigned long long)__double_as_longlong(fabs(v));
 }
 
-// Lane K of each row of 16 lanes, broadcast to the whole row (DPP
-// row_newbcast on a 64-bit value: one VALU move, no LDS access)
+// acc += x' * a, where x' is lane K of this lane's row of 16 lanes (DPP
+// row_newbcast on the 64-bit source of one v_fmac_f64: the broadcast costs
+// no instruction of its own; the compiler does not fold a separate
+// broadcast move into the FMA).  The s_nop gives the two wait states a DPP
+// read needs after a VALU write of its source, whatever the compiler placed
+// before.  Register operands only.  Volatile: kept where every lane runs it.
 template <int K>
-__device__ __forceinline__ double row_bcast(double v)
+__device__ __forceinline__ void fmac_bcast(double& acc, double x, double a)
 {
-    const long long r = __builtin_amdgcn_update_dpp(0ll, __builtin_bit_cast(long long, v), 0x150 + K, 0xf, 0xf, true);
-    return __builtin_bit_cast(double, r);
+    asm volatile("s_nop 1\n\tv_fmac_f64_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+                 : "+v"(acc)
+                 : "v"(x), "v"(a), "n"(K));
 }
 
 // Residual product (V x)_p = sum_m b_m sum_l a_l x[m][l] of one particle,
@@ -460,14 +465,14 @@ __device__ __forceinline__ double row_bcast(double v)
 // it, and each lane keeps iterate value 16 c + (lane % 16) of the chunks c
 // a row of x touches, so each product takes its x from a row broadcast
 // instead of an LDS read (2 reads per row of x instead of n).  Same
-// operations in the same order as the LDS form.
+// products and sums in the same order as the LDS form.
 template <int N, int M, int... L>
 __device__ __forceinline__ double resid_row(const double (&a)[N], double xa, double xb,
                                             std::integer_sequence<int, L...>)
 {
     constexpr int C0 = (N * M) >> 4;
     double inner = 0.0;
-    ((inner = fma(a[L], row_bcast<(N * M + L) & 15>(((N * M + L) >> 4) == C0 ? xa : xb), inner)), ...);
+    (fmac_bcast<(N * M + L) & 15>(inner, ((N * M + L) >> 4) == C0 ? xa : xb, a[L]), ...);
     return inner;
 }
 
