@@ -411,10 +411,10 @@ def bench_c4(args, torch, P, W, stream):
 def serve_stream(W, count, seed):
     """Seeded request mix of the serving configuration: dim 1 or 2 (p = 1/2);
     K uniform in [64, 65536] (2D: kx = ky = round(sqrt K)); order N uniform in
-    {4..16} (2D: {4..10}, the 2D order limit); 1D u0 the C2 Gaussian or a
-    random sine field, 2D the C3 hill with its exact inflow; velocity of C2
-    (1D) or C3 (2D); 10..500 steps; 2D requests FP64 or FP32-refined
-    (p = 1/2).  Inputs are built only when a request is submitted."""
+    {4..16}; 1D u0 the C2 Gaussian or a random sine field, 2D the C3 hill
+    with its exact inflow; velocity of C2 (1D) or C3 (2D); 10..500 steps; 2D
+    requests FP64 or FP32-refined (p = 1/2; order 16 runs in FP64 only).
+    Inputs are built only when a request is submitted."""
     rng = np.random.default_rng(seed)
     specs = []
     for i in range(count):
@@ -426,8 +426,9 @@ def serve_stream(W, count, seed):
             specs.append(dict(dim=1, K=K, n=N + 1, steps=steps, sine=bool(rng.integers(0, 2)), prec=0, seed=i))
         else:
             k = max(1, int(round(math.sqrt(K))))
-            N = int(rng.integers(4, 11))
-            specs.append(dict(dim=2, K=k * k, kx=k, n=N + 1, steps=steps, prec=int(rng.integers(0, 2)), seed=i))
+            N = int(rng.integers(4, 17))
+            prec = int(rng.integers(0, 2))
+            specs.append(dict(dim=2, K=k * k, kx=k, n=N + 1, steps=steps, prec=prec if N < 16 else 0, seed=i))
     return specs
 
 
@@ -500,7 +501,7 @@ def bench_serve(args, torch, P, W):
         "warmup": 0, "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64 (2D requests half FP32-refined)", "data": "synthetic",
         "config": {"workload": f"serving: {count} seeded Poisson arrivals of 1D (C2 velocity) and 2D (C3 rotation) "
-                               "problems, K in [64,65536], N in 4..16 (2D 4..10), 10-500 steps, boundary rows",
+                               "problems, K in [64,65536], N in 4..16, 10-500 steps, boundary rows",
                    "slots": args.slots, "hbm_budget_gib": args.budget_gib, "arrival_rate_per_s": rate,
                    "closed_loop_dof_per_s": capacity},
         "step_latency": {"p50_ms": p50, "p99_ms": p99, "samples": samples},

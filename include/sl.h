@@ -66,7 +66,8 @@ enum { SL_IFACE_INTERP = 0, SL_IFACE_BACKTRACK = 1 };
  *   dim        1 or 2
  *   kx, ky     elements per direction (ky = 1 in 1D); kx * ky <= 2^26
  *   order      polynomial order N >= 1 (n = N + 1 nodes per direction);
- *              1D: N <= 16, 2D: N <= 12
+ *              1D: N <= 16, 2D: N <= 16 (2D N = 16: FP64 and boundary
+ *              rows only)
  *   nodes      SL_NODES_GL (default) or SL_NODES_CG (paper, eq. gaussquad)
  *   bc         SL_BC_PERIODIC, or SL_BC_GHOST (inflow values from sl_set_ghost
  *              on every side), or in 2D SL_BC_PERIODIC_X / SL_BC_PERIODIC_Y
@@ -78,12 +79,12 @@ enum { SL_IFACE_INTERP = 0, SL_IFACE_BACKTRACK = 1 };
  *              and applied in FP32, or with BF16 entries and operands and
  *              FP32 accumulation, while residuals and iterates stay FP64, so
  *              the solve still converges to the FP64 solution, in more
- *              sweeps; 1D rejects both)
+ *              sweeps; 1D and 2D order 16 reject both)
  *   x0,x1,y0,y1 box (y ignored in 1D), x1 > x0, y1 > y0
  *   u0         host, K * n^dim initial values (layout above)
  *   stream     hipStream_t to run on, or NULL for a stream the mesh creates
  *   orders     NULL, or (2D, periodic) host array of K per-element orders
- *              N_e in 1..12 for a mixed-order mesh: element e then has
+ *              N_e in 1..16 for a mixed-order mesh: element e then has
  *              n_e = N_e + 1 nodes per direction, `order` is ignored, and
  *              every per-node array (u0, velocity components, the field of
  *              sl_read) holds the elements one after another, n_e^2 values
@@ -194,7 +195,8 @@ int32_t sl_ghost_count(const sl_mesh* m);
  * SL_E_STATE (no velocity, or ghost mesh without ghost values),
  * SL_E_INVALID (dt <= 0, nsteps < 0, bad options; 1D: more rows than n;
  * 2D HARD with boundary rows: more mass/energy rows than (n-2)^2, the
- * dimension of the null space of the 4n boundary rows of rank 4n-4),
+ * dimension of the null space of the 4n boundary rows of rank 4n-4; 2D
+ * order 16: mass or energy rows),
  * SL_E_CFL (max |a_d| dt > gap_d dx_d for some direction d, gap =
  * distance from the element edge to the first node: the paper's time-step
  * restriction, eq. 1d_delt_condition and eq. 2d_delt_condition, which admits

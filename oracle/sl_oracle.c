@@ -1177,7 +1177,7 @@ int ora_step(const ora_params* p, const double* a, const double* div, const doub
              double dt, int nsteps, double* phi, const uint8_t* want, ora_stats* st)
 {
     if (p->dim != 1 && p->dim != 2) return 1;
-    if (p->n < 1 || p->n > 16 * (p->dim == 1 ? 4 : 1)) return 1;
+    if (p->n < 1 || p->n > (p->dim == 1 ? 64 : 17)) return 1;
     if (p->kx < 1 || p->ky < 1 || (p->dim == 1 && p->ky != 1)) return 1;
     if (p->bc < 0 || p->bc > (p->dim == 1 ? 1 : 3)) return 1;
     if (want && nsteps != 1) return 1;
@@ -1451,7 +1451,7 @@ int ora_step_mixed(const ora_params* p, const int32_t* orders, const double* a, 
     size_t* off = malloc(sizeof(size_t) * (K + 1));
     off[0] = 0;
     for (int e = 0; e < K; ++e) {
-        if (orders[e] < 2 || orders[e] > 16) { free(off); return 1; }
+        if (orders[e] < 2 || orders[e] > 17) { free(off); return 1; }
         off[e + 1] = off[e] + (size_t)orders[e] * orders[e];
     }
     size_t tot = off[K];

@@ -40,7 +40,9 @@ int advect2d_elems(int n, int bs)
 int blocks2d(int n, int K)
 {
     if (n < 2 || n > kMax2D) return 0;
-    const int E = kBlock2 / (n * n);  // elements per block, both kernels
+    // elements per block of the 256-lane shape, or one above 16 nodes per
+    // direction (both kernels take no fewer)
+    const int E = kBlock2 / (n * n) > 0 ? kBlock2 / (n * n) : 1;
     return (K + E - 1) / E;
 }
 
@@ -52,6 +54,7 @@ const Ops2D* ops2d(int n)
     case 2: return ops2d_2(); case 3: return ops2d_3(); case 4: return ops2d_4(); case 5: return ops2d_5();
     case 6: return ops2d_6(); case 7: return ops2d_7(); case 8: return ops2d_8(); case 9: return ops2d_9();
     case 10: return ops2d_10(); case 11: return ops2d_11(); case 12: return ops2d_12(); case 13: return ops2d_13();
+    case 14: return ops2d_14(); case 15: return ops2d_15(); case 16: return ops2d_16(); case 17: return ops2d_17();
     default: return nullptr;
     }
 }

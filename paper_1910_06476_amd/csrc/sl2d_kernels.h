@@ -1607,6 +1607,11 @@ int adv_n(const Step2DArgs& A, hipStream_t s)
     // the alternative block shapes exist for the FP64 boundary-rows kernel
     if (A.bs != 0 && A.precision == SL_PREC_FP64 && !A.targets)
         return A.bs == 1 ? adv_shape<N, 1>(A, s) : adv_shape<N, 2>(A, s);
+    // the 256-lane shape (and the reduced-precision and target variants,
+    // which exist for it only) holds no element above 16 nodes per direction
+    if constexpr (N * N > kBlock2) {
+        return 1;
+    } else {
     constexpr int E = kBlock2 / (N * N);
     const dim3 grid((A.K + E - 1) / E);
     if ((int)grid.x > A.nblk) return 1;
@@ -1614,6 +1619,7 @@ int adv_n(const Step2DArgs& A, hipStream_t s)
     else if (A.precision == SL_PREC_BF16_REFINED) adv_launch<N, 2>(A, grid, s);
     else adv_launch<N, 0>(A, grid, s);
     return hipGetLastError() == hipSuccess ? 0 : 1;
+    }
 }
 
 // grid of a persistent constrain launch over nchunk chunks: no more blocks
@@ -1630,11 +1636,15 @@ int con_n(const Step2DArgs& A, hipStream_t s)
     static std::atomic<int> cap_bt[kMaxDevices], cap[kMaxDevices];
     if (A.nblk < 1) return 1;
     if (A.cmask & (SL_C_MASS | SL_C_ENERGY)) {
-        constexpr int E = kBlock2 / (N * N);
-        const int nchunk = (A.K + E - 1) / E;
-        if (nchunk > A.nblk) return 1;
-        launch_timed(k_constrain2d_me<N>, dim3(nchunk), dim3(kBlock2), 0, s, A);
-        return hipGetLastError() == hipSuccess ? 0 : 1;
+        if constexpr (N * N > kBlock2) {
+            return 1;  // one lane per node: up to 16 nodes per direction
+        } else {
+            constexpr int E = kBlock2 / (N * N);
+            const int nchunk = (A.K + E - 1) / E;
+            if (nchunk > A.nblk) return 1;
+            launch_timed(k_constrain2d_me<N>, dim3(nchunk), dim3(kBlock2), 0, s, A);
+            return hipGetLastError() == hipSuccess ? 0 : 1;
+        }
     }
     const int nchunk = (A.K + ConShape<N>::E - 1) / ConShape<N>::E;
     if (A.iface == SL_IFACE_BACKTRACK) {

@@ -33,5 +33,9 @@ const Ops2D* ops2d_10();
 const Ops2D* ops2d_11();
 const Ops2D* ops2d_12();
 const Ops2D* ops2d_13();
+const Ops2D* ops2d_14();
+const Ops2D* ops2d_15();
+const Ops2D* ops2d_16();
+const Ops2D* ops2d_17();
 
 }  // namespace sl

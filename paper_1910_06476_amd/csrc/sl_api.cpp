@@ -496,6 +496,9 @@ static sl_status create_mixed(const sl_mesh_desc* d, sl_mesh** out)
     if (d->form != SL_FORM_ADVECTIVE && d->form != SL_FORM_CONSERVATIVE) return SL_E_INVALID;
     if (d->precision != SL_PREC_FP64 && d->precision != SL_PREC_FP32_REFINED && d->precision != SL_PREC_BF16_REFINED)
         return SL_E_INVALID;
+    // above 16 nodes per direction the 2D kernels are FP64 only
+    for (int b = 0; b < P.nbk; ++b)
+        if (P.bn[b] > kMax2DFull && d->precision != SL_PREC_FP64) return SL_E_INVALID;
     if (!(d->x1 > d->x0) || !(d->y1 > d->y0) || !std::isfinite(d->x0) || !std::isfinite(d->x1) ||
         !std::isfinite(d->y0) || !std::isfinite(d->y1))
         return SL_E_INVALID;
@@ -781,7 +784,8 @@ sl_status sl_create_mesh(const sl_mesh_desc* d, sl_mesh** out)
         return SL_E_INVALID;
     if (d->form != SL_FORM_ADVECTIVE && d->form != SL_FORM_CONSERVATIVE) return SL_E_INVALID;
     if (d->precision != SL_PREC_FP64 &&
-        !((d->precision == SL_PREC_FP32_REFINED || d->precision == SL_PREC_BF16_REFINED) && d->dim == 2))
+        !((d->precision == SL_PREC_FP32_REFINED || d->precision == SL_PREC_BF16_REFINED) && d->dim == 2 &&
+          n <= kMax2DFull))
         return SL_E_INVALID;
     if (!(d->x1 > d->x0) || (d->dim == 2 && !(d->y1 > d->y0))) return SL_E_INVALID;
     if (!std::isfinite(d->x0) || !std::isfinite(d->x1)) return SL_E_INVALID;
@@ -978,6 +982,10 @@ sl_status sl_step(sl_mesh* m, double dt, int32_t nsteps, const sl_step_opts* o)
     // exact solution (SOFT, the stacked least squares, always has one)
     if (m->dim == 2 && opt.mode == SL_MODE_HARD && (opt.constraints & SL_C_BOUNDARY) &&
         rows - 2 > (m->n - 2) * (m->n - 2))
+        return SL_E_INVALID;
+    // above 16 nodes per direction a 2D step takes boundary rows only (the
+    // mass and energy rows run one lane per node)
+    if (m->dim == 2 && !m->mixed && m->n > kMax2DFull && (opt.constraints & (SL_C_MASS | SL_C_ENERGY)))
         return SL_E_INVALID;
 
     if (m->mixed) return step_mixed(m, dt, nsteps, opt);

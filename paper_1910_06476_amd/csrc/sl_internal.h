@@ -11,7 +11,10 @@ namespace sl {
 
 constexpr int kMaxTableN = 32;
 constexpr int kMax1D = 17;  // nodes per element in 1D (order 16)
-constexpr int kMax2D = 13;  // nodes per direction in 2D (order 12)
+constexpr int kMax2D = 17;  // nodes per direction in 2D (order 16)
+// Above 16 nodes per direction (n^2 > 256 particles) a 2D element takes a
+// block of its own in the advect, in FP64 with boundary rows only
+constexpr int kMax2DFull = 16;
 constexpr int kMaxBuckets = 16;  // distinct orders of a mixed-order mesh
 
 struct Tables {

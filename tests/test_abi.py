@@ -100,7 +100,7 @@ def test_mesh_bytes_host_only(sl):
     g3 = sl.sl_mesh_bytes(2, 16, 16, 4, bc=sl.SL_BC_GHOST, ghost_rows=3)
     assert g3 - g0 == 3 * 2 * 5 * (16 + 16) * 8
     with pytest.raises(sl.SLError):
-        sl.sl_mesh_bytes(2, 4, 4, 13)  # 14 nodes per direction: beyond the 2D limit
+        sl.sl_mesh_bytes(2, 4, 4, 17)  # 18 nodes per direction: beyond the 2D limit
     with pytest.raises(sl.SLError):
         sl.sl_mesh_bytes(1, 4, 2, 4)   # 1D with ky != 1
 

@@ -131,13 +131,44 @@ def test_rk_orders_parity(rk):
     assert rel_l2(g, o) <= TOL, rel_l2(g, o)
 
 
-@pytest.mark.parametrize("n", list(range(2, 14)))
+@pytest.mark.parametrize("n", list(range(2, 18)))
 def test_orders_parity(n):
     w = _swirl_case(4, 5, n, bc=W.GHOST)
     announce(f"2d n={n}")
     g, st, rc = run_gpu(w)
     o, ost = run_oracle(w)
     assert rel_l2(g, o) <= TOL, rel_l2(g, o)
+
+
+@pytest.mark.parametrize("mode", [W.HARD, W.SOFT])
+@pytest.mark.parametrize("bc", [W.PERIODIC, W.PERIODIC_X])
+def test_order_16_parity(bc, mode):
+    """17 nodes per direction (289 particles): one element per 320-lane
+    block in the advect, two nodes per lane in the boundary-row solve."""
+    w = _swirl_case(3, 2, 17, bc=bc, mode=mode, form=W.CONSERVATIVE)
+    announce(f"2d n=17 bc={bc} mode={mode}")
+    g, st, rc = run_gpu(w)
+    o, ost = run_oracle(w)
+    assert rc == 0
+    assert rel_l2(g, o) <= TOL, rel_l2(g, o)
+
+
+def test_order_16_refuses_what_it_does_not_run():
+    """Order 16 in 2D: FP64 with boundary rows only; the rest is refused
+    before any launch."""
+    import paper_1910_06476_amd as P
+    w = _swirl_case(2, 2, 17, bc=W.PERIODIC)
+    with pytest.raises(P.SLError):
+        P.Mesh(2, 2, 2, 16, w.initial(), precision=P.SL_PREC_FP32_REFINED)
+    m = P.from_workload(w)
+    try:
+        with pytest.raises(P.SLError):
+            m.step(w.dt, 1, rk=4, constraints=W.BOUNDARY | W.MASS, mode=W.HARD)
+        m.step(w.dt, 1, rk=4, constraints=W.BOUNDARY, mode=W.HARD)
+        rc, out, st = m.read()
+        assert rc == 0 and st.steps == 1
+    finally:
+        m.close()
 
 
 @pytest.mark.parametrize("kx,ky", [(1, 1), (1, 2), (2, 1), (3, 1), (2, 2), (5, 7), (11, 3)])

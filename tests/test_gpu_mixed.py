@@ -77,9 +77,10 @@ def test_c4_orders_reduced_precision_preconditioner_parity(precision):
 
 @pytest.mark.parametrize("seed", [2, 3])
 def test_all_orders_parity(seed):
-    """Every order 1..12 present: thirteen... twelve buckets, all pairs of
-    interpolation matrices."""
-    w = _case(7, 6, tuple(range(1, 13)), seed=seed, nsteps=2)
+    """Orders drawn from 1..16 on 64 elements: up to sixteen buckets (order
+    16 with 289 particles per element in 320-lane blocks) and the
+    interpolation matrices between every pair present."""
+    w = _case(8, 8, tuple(range(1, 17)), seed=seed, nsteps=2)
     announce(f"mixed all orders seed={seed}")
     g, st, rc = _gpu(w)
     o, ost = _oracle(w)
@@ -209,8 +210,10 @@ def test_mixed_statistics_and_validation():
         m.close()
     with pytest.raises(P.SLError):  # ghost boundaries are not offered on mixed meshes
         P.Mesh(2, 2, 2, 3, np.zeros(4 * 16), bc=P.SL_BC_GHOST, orders=[3, 3, 3, 3])
-    with pytest.raises(P.SLError):  # order 13 is beyond the 2D limit
-        P.Mesh(2, 2, 2, 3, np.zeros(3 * 16 + 14 * 14), orders=[3, 3, 3, 13])
+    with pytest.raises(P.SLError):  # order 17 is beyond the 2D limit
+        P.Mesh(2, 2, 2, 3, np.zeros(3 * 16 + 18 * 18), orders=[3, 3, 3, 17])
+    with pytest.raises(P.SLError):  # order 16 runs in FP64 only
+        P.Mesh(2, 2, 2, 3, np.zeros(3 * 16 + 17 * 17), orders=[3, 3, 3, 16], precision=P.SL_PREC_FP32_REFINED)
 
 
 def test_distinct_meshes_step_concurrently():

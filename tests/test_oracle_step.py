@@ -103,7 +103,7 @@ def test_mass_target_quadrature_exact_for_cubic_flux(ora, rk, mode):
 
 
 @pytest.mark.parametrize("mode", [W.HARD, W.SOFT])
-@pytest.mark.parametrize("n,deg", [(3, 2), (5, 4), (5, 2)])
+@pytest.mark.parametrize("n,deg", [(3, 2), (5, 4), (5, 2), (17, 16), (17, 9)])
 def test_polynomial_reproduction_2d(ora, n, deg, mode):
     w = _poly_workload(2, n, deg, mode=mode)
     phi, st = ora.run_workload(w)
