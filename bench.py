@@ -449,17 +449,13 @@ def serve_submit(S, W, sp):
     return rid, w.K * w.nd * w.nsteps
 
 
-def bench_serve(args, torch, P, W):
-    """Serving: a seeded Poisson stream of independent problems through the
-    request loop (continuous batching).  First a closed-loop pass (all
-    submitted at once) measures the capacity; then the open-loop stream
-    arrives at 0.8x that capacity.  value = DOF-updates/s of the open loop,
-    with the per-step latency p50/p99 of its requests."""
-    count = args.requests
-    specs = serve_stream(W, count, seed=2024)
+def serve_pass(args, P, W, specs, batch):
+    """One serving measurement of the request stream `specs`: a closed-loop
+    pass (all submitted at once) for the capacity, then an open loop of
+    seeded Poisson arrivals at 0.8x that capacity."""
+    count = len(specs)
     budget = int(args.budget_gib * (1 << 30))
-    # closed loop
-    with P.Server(max_active=args.slots, hbm_budget=budget) as S:
+    with P.Server(max_active=args.slots, hbm_budget=budget, batch=batch) as S:
         t0 = time.perf_counter()
         ids, work = [], 0
         for sp in specs:
@@ -472,12 +468,11 @@ def bench_serve(args, torch, P, W):
         for rid in ids:
             S.result(rid)
     capacity = work / closed
-    # open loop: Poisson arrivals at 0.8x capacity (mean work per request / rate)
     rng = np.random.default_rng(7)
     rate = 0.8 * capacity / (work / count)          # requests per second
     arrivals = np.cumsum(rng.exponential(1.0 / rate, size=count))
     statuses = []
-    with P.Server(max_active=args.slots, hbm_budget=budget) as S:
+    with P.Server(max_active=args.slots, hbm_budget=budget, batch=batch) as S:
         t0 = time.perf_counter()
         ids, i = [], 0
         while i < count or S.progress() != (0, 0):
@@ -490,25 +485,46 @@ def bench_serve(args, torch, P, W):
                 time.sleep(min(5e-4, arrivals[i] - now))
         wall = time.perf_counter() - t0
         p50, p99, samples, dof = S.latency()
+        launches, member_steps = S.batching()
         lat_req = []
         for rid in ids:
             rc, _, _, tm = S.result(rid)
             statuses.append(rc)
             lat_req.append(tm.total_us)
     lat_req.sort()
+    return {"value": dof / wall, "closed_loop_dof_per_s": capacity, "arrival_rate_per_s": rate,
+            "step_latency": {"p50_ms": p50, "p99_ms": p99, "samples": samples},
+            "request_latency_ms": {"p50": lat_req[len(lat_req) // 2] / 1e3,
+                                   "p99": lat_req[min(len(lat_req) - 1, int(0.99 * len(lat_req)))] / 1e3},
+            "failed_requests": int(sum(1 for r in statuses if r not in (P.SL_OK,))), "wall_s": wall,
+            "group_steps": launches, "request_steps_per_group_step": member_steps / launches if launches else None}
+
+
+def bench_serve(args, torch, P, W):
+    """Serving: a seeded Poisson stream of independent problems through the
+    request loop (continuous batching).  The requests of one kernel variant
+    are stepped together, one launch of each step kernel per group step;
+    the same stream with every request on its own stream is measured beside
+    it.  value = DOF-updates/s of the batched open loop, with the per-step
+    latency p50/p99 of its requests."""
+    specs = serve_stream(W, args.requests, seed=2024)
+    b = serve_pass(args, P, W, specs, True)
+    u = serve_pass(args, P, W, specs, False)
     out = {
-        "metric": METRIC, "value": dof / wall, "unit": "DOF-updates/s", "n_gpus": 1, "steps": int(samples),
-        "warmup": 0, "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64 (2D requests half FP32-refined)", "data": "synthetic",
-        "config": {"workload": f"serving: {count} seeded Poisson arrivals of 1D (C2 velocity) and 2D (C3 rotation) "
-                               "problems, K in [64,65536], N in 4..16, 10-500 steps, boundary rows",
-                   "slots": args.slots, "hbm_budget_gib": args.budget_gib, "arrival_rate_per_s": rate,
-                   "closed_loop_dof_per_s": capacity},
-        "step_latency": {"p50_ms": p50, "p99_ms": p99, "samples": samples},
-        "request_latency_ms": {"p50": lat_req[len(lat_req) // 2] / 1e3,
-                               "p99": lat_req[min(len(lat_req) - 1, int(0.99 * len(lat_req)))] / 1e3},
-        "failed_requests": int(sum(1 for r in statuses if r not in (P.SL_OK,))),
-        "wall_s": wall,
+        "metric": METRIC, "value": b["value"], "unit": "DOF-updates/s", "n_gpus": 1,
+        "steps": int(b["step_latency"]["samples"]), "warmup": 0, "ms_per_step": None, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64 (2D requests half FP32-refined)", "data": "synthetic",
+        "config": {"workload": f"serving: {args.requests} seeded Poisson arrivals of 1D (C2 velocity) and 2D (C3 "
+                               "rotation) problems, K in [64,65536], N in 4..16, 10-500 steps, boundary rows",
+                   "slots": args.slots, "hbm_budget_gib": args.budget_gib,
+                   "arrival_rate_per_s": b["arrival_rate_per_s"],
+                   "closed_loop_dof_per_s": b["closed_loop_dof_per_s"]},
+        "step_latency": b["step_latency"], "request_latency_ms": b["request_latency_ms"],
+        "failed_requests": b["failed_requests"], "wall_s": b["wall_s"],
+        "batching": {"group_steps": b["group_steps"],
+                     "request_steps_per_group_step": b["request_steps_per_group_step"]},
+        "unbatched": {k: u[k] for k in ("value", "closed_loop_dof_per_s", "step_latency", "request_latency_ms",
+                                        "failed_requests", "wall_s")},
     }
     print(json.dumps(out))
 

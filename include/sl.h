@@ -308,16 +308,25 @@ sl_status sl_step1d_static(int32_t K, int32_t order, int32_t nodes, int32_t bc, 
  * all host arrays are copied at submission.  Requests wait in arrival order
  * and are admitted while fewer than max_active run and the device memory
  * they need (sl_mesh_bytes) fits within hbm_budget.  An admitted request
- * gets its own mesh and stream, and all its steps are queued at once, so
- * the work of the admitted requests overlaps on the device.  Results do not
- * depend on what else runs: every kernel is deterministic and per mesh.
- * One server is used from one host thread.
+ * gets its own mesh.  Requests whose steps share a kernel variant (same
+ * dimension and order; boundary rows; interpolated face values; 2D order
+ * 3 and up; the same advect variant) are stepped together: each step of
+ * the group is one launch of each step kernel over the elements of all its
+ * members with steps left, on the server's stream, and members join and
+ * leave between such steps.  Other requests queue all their steps at once
+ * on their own stream.  The work of the admitted requests overlaps on the
+ * device.  Results do not depend on what else runs: every kernel is
+ * deterministic, and a block of a batched launch works for one request on
+ * its own buffers, so a field is the same, bit for bit, alone and in any
+ * mix.  One server is used from one host thread.
  * ------------------------------------------------------------------------ */
 typedef struct sl_server sl_server;
 
+enum { SL_SERVER_NO_BATCH = 1 };
+
 typedef struct {
     int32_t max_active;   /* requests on the device at once, 1..64 */
-    int32_t reserved;     /* 0 */
+    int32_t flags;        /* 0, or SL_SERVER_NO_BATCH: every request on its own stream */
     size_t hbm_budget;    /* bytes of device memory admitted requests may hold */
 } sl_server_desc;
 
@@ -341,7 +350,8 @@ typedef struct {
     int64_t admit_seq;    /* order of admission among the server's requests (0 first), -1 if never admitted */
 } sl_request_timing;
 
-/* Errors: SL_E_INVALID (max_active outside 1..64, zero budget), SL_E_NOMEM. */
+/* Errors: SL_E_INVALID (max_active outside 1..64, zero budget, unknown
+ * flags), SL_E_NOMEM, SL_E_DEVICE. */
 sl_status sl_server_create(const sl_server_desc* d, sl_server** out);
 
 /* Queue a request; *id names it in sl_server_result.  Errors: SL_E_INVALID
@@ -369,10 +379,16 @@ sl_status sl_server_result(sl_server* s, int64_t id, double* u_out, sl_stats* st
 
 /* Per-step device latency over all retired requests' steps (the time
  * between the events that bracket consecutive steps of one request, so it
- * includes waiting behind the other requests' work): p50 and p99 in ms; the
+ * includes waiting behind the other requests' work; for batched requests,
+ * the time of the group step that carried it): p50 and p99 in ms; the
  * number of samples and the DOF-updates of the retired requests.  Errors:
  * SL_E_INVALID. */
 sl_status sl_server_latency(sl_server* s, double p50_p99[2], int64_t* samples, int64_t* dof_updates);
+
+/* Batched steps so far: the number of group steps launched (one launch of
+ * each step kernel each) and the request steps they carried.  Errors:
+ * SL_E_INVALID. */
+sl_status sl_server_batching(sl_server* s, int64_t* launches, int64_t* member_steps);
 
 /* Wait for active requests, free everything.  Errors: SL_E_INVALID. */
 sl_status sl_server_destroy(sl_server* s);

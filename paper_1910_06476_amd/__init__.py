@@ -27,6 +27,7 @@ SL_PREC_FP64, SL_PREC_FP32_REFINED, SL_PREC_BF16_REFINED = 0, 1, 2
 SL_C_BOUNDARY, SL_C_MASS, SL_C_ENERGY = 1, 2, 4
 SL_MODE_HARD, SL_MODE_SOFT = 0, 1
 SL_IFACE_INTERP, SL_IFACE_BACKTRACK = 0, 1
+SL_SERVER_NO_BATCH = 1
 KER_ADV1D, KER_CON1D, KER_ADV2D, KER_CON2D = 0, 1, 2, 3
 KER_MIX_ADV, KER_MIX_CON = 4, 20  # + bucket index (mixed-order meshes)
 
@@ -34,7 +35,7 @@ EXPORTS = ["sl_create_mesh", "sl_set_velocity", "sl_set_ghost", "sl_ghost_count"
            "sl_destroy_mesh", "sl_status_string", "sl_max_dt", "sl_node_coords", "sl_device_field",
            "sl_set_profiling", "sl_kernel_time", "sl_mesh_bytes", "sl_server_create", "sl_server_submit",
            "sl_server_progress", "sl_server_drain", "sl_server_result", "sl_server_latency",
-           "sl_server_destroy", "sl_step1d_static", "sl_bucket_stats"]
+           "sl_server_destroy", "sl_step1d_static", "sl_bucket_stats", "sl_server_batching"]
 
 
 class MeshDesc(ctypes.Structure):
@@ -65,7 +66,7 @@ class Stats(ctypes.Structure):
 
 
 class ServerDesc(ctypes.Structure):
-    _fields_ = [("max_active", ctypes.c_int32), ("reserved", ctypes.c_int32), ("hbm_budget", ctypes.c_size_t)]
+    _fields_ = [("max_active", ctypes.c_int32), ("flags", ctypes.c_int32), ("hbm_budget", ctypes.c_size_t)]
 
 
 class Request(ctypes.Structure):
@@ -123,6 +124,7 @@ def lib():
         L.sl_server_result.argtypes = [vp, ctypes.c_int64, dp, ctypes.POINTER(Stats), ctypes.POINTER(RequestTiming)]
         L.sl_server_latency.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
         L.sl_server_destroy.argtypes = [vp]
+        L.sl_server_batching.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
         i32, f64 = ctypes.c_int32, ctypes.c_double
         ip = ctypes.POINTER(ctypes.c_int32)
         L.sl_bucket_stats.argtypes = [vp, i32, ip, ip, ip, dp]
@@ -333,9 +335,10 @@ class Server:
     independent problems; see include/sl.h).  Host arrays are copied at
     submission, so the caller's arrays may be reused at once."""
 
-    def __init__(self, max_active=8, hbm_budget=8 << 30):
+    def __init__(self, max_active=8, hbm_budget=8 << 30, batch=True):
         h = ctypes.c_void_p()
-        _check(lib().sl_server_create(ctypes.byref(ServerDesc(int(max_active), 0, int(hbm_budget))),
+        flags = 0 if batch else SL_SERVER_NO_BATCH
+        _check(lib().sl_server_create(ctypes.byref(ServerDesc(int(max_active), flags, int(hbm_budget))),
                                       ctypes.byref(h)), "sl_server_create")
         self.h = h
         self._sizes = {}
@@ -379,6 +382,12 @@ class Server:
         n, dof = ctypes.c_int64(), ctypes.c_int64()
         _check(lib().sl_server_latency(self.h, _dp(pp), ctypes.byref(n), ctypes.byref(dof)), "sl_server_latency")
         return float(pp[0]), float(pp[1]), int(n.value), int(dof.value)
+
+    def batching(self):
+        """(group steps launched, request steps they carried)."""
+        n, m = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().sl_server_batching(self.h, ctypes.byref(n), ctypes.byref(m)), "sl_server_batching")
+        return int(n.value), int(m.value)
 
     def close(self):
         if self.h:

@@ -18,6 +18,7 @@
 //             targets, and the constrained least squares (eq. matrix_a) as
 //             a small Gram/Schur system per element, with the energy row
 //             linearised by Picard iteration.
+#include "sl_batch.h"
 #include "sl_internal.h"
 
 namespace sl {
@@ -401,7 +402,7 @@ __global__ void k_prep1d(int K, int periodic, int has_div, const double* __restr
 // default allocation to hold five waves per SIMD at order 16 with a short
 // velocity series.)
 template <int N, bool CONS, int NA, int RKS>
-__global__ __launch_bounds__(kBlock) void k_advect1d(Step1DArgs A)
+__device__ __forceinline__ void advect1d_body(const Step1DArgs& A, const int bid)
 {
     const Tab<RKS> RK{A.rk};
     constexpr int L = N + 1;
@@ -423,7 +424,7 @@ __global__ __launch_bounds__(kBlock) void k_advect1d(Step1DArgs A)
     const int sl = inblk ? slot : 0;
     const bool node = i < N;
     const int in = node ? i : 0;
-    const int e = blockIdx.x * E + slot;
+    const int e = bid * E + slot;
     const bool live = inblk && e < A.K;
     const double* __restrict__ tab = A.tab;
     const size_t g = (size_t)(live ? e : 0) * N + in;
@@ -671,7 +672,24 @@ __global__ __launch_bounds__(kBlock) void k_advect1d(Step1DArgs A)
     }
     if (fl) atomicOr(&s_flag, fl);
     __syncthreads();
-    if (t == 0 && s_flag) A.flag_part[blockIdx.x] |= s_flag;
+    if (t == 0 && s_flag) A.flag_part[bid] |= s_flag;
+}
+
+template <int N, bool CONS, int NA, int RKS>
+__global__ __launch_bounds__(kBlock) void k_advect1d(Step1DArgs A)
+{
+    advect1d_body<N, CONS, NA, RKS>(A, blockIdx.x);
+}
+
+// One step of several meshes in one launch: the blocks of request r are
+// start[r] .. start[r + 1] - 1, each running the kernel above on the
+// request's own arguments As[r] (its own buffers and statistics)
+template <int N, bool CONS, int NA, int RKS>
+__global__ __launch_bounds__(kBlock) void k_advect1d_batch(const Step1DArgs* __restrict__ As,
+                                                           const int* __restrict__ start, int nreq)
+{
+    const int r = batch_request(start, nreq, blockIdx.x);
+    advect1d_body<N, CONS, NA, RKS>(As[r], blockIdx.x - start[r]);
 }
 
 // ---------------------------------------------------------------------------
@@ -703,7 +721,7 @@ __device__ __forceinline__ double pair_max(double v) { return fmax(v, lane_swap<
 // launch (2048 waves) is resident at once; with four lanes per element its
 // 4096 waves at three per SIMD needed a second, mostly idle round.
 template <int N>
-__global__ __launch_bounds__(kConBlock) void k_constrain1d(Step1DArgs A)
+__device__ __forceinline__ void constrain1d_body(const Step1DArgs& A, const int bid)
 {
     using O = Off<N>;
     constexpr int NP = (N + kConQ - 1) / kConQ;
@@ -718,7 +736,7 @@ __global__ __launch_bounds__(kConBlock) void k_constrain1d(Step1DArgs A)
     __shared__ int s_fq[kConElems];
     const int t = threadIdx.x;
     const int le = t / kConQ, r = t % kConQ;
-    const int e0 = blockIdx.x * kConElems;
+    const int e0 = bid * kConElems;
     const int K = A.K;
     const int e = e0 + le;
     const bool live = e < K;
@@ -1042,14 +1060,28 @@ __global__ __launch_bounds__(kConBlock) void k_constrain1d(Step1DArgs A)
         double m = 0.0;
 #pragma unroll
         for (int q = 0; q < kConElems; ++q) m = fmax(m, s_st[q][t]);
-        double* sp = A.stat_part + (size_t)blockIdx.x * kStatSlots;
+        double* sp = A.stat_part + (size_t)bid * kStatSlots;
         sp[t] = fmax(sp[t], m);
     } else if (t == 4) {
         int f = 0;
 #pragma unroll
         for (int q = 0; q < kConElems; ++q) f |= s_fq[q];
-        if (f) A.flag_part[A.nblk + blockIdx.x] |= f;
+        if (f) A.flag_part[A.nblk + bid] |= f;
     }
+}
+
+template <int N>
+__global__ __launch_bounds__(kConBlock) void k_constrain1d(Step1DArgs A)
+{
+    constrain1d_body<N>(A, blockIdx.x);
+}
+
+template <int N>
+__global__ __launch_bounds__(kConBlock) void k_constrain1d_batch(const Step1DArgs* __restrict__ As,
+                                                                 const int* __restrict__ start, int nreq)
+{
+    const int r = batch_request(start, nreq, blockIdx.x);
+    constrain1d_body<N>(As[r], blockIdx.x - start[r]);
 }
 
 template <int N>
@@ -1095,6 +1127,49 @@ int launch_con_n(const Step1DArgs& A, hipStream_t s)
 {
     dim3 grid((A.K + kConElems - 1) / kConElems);
     launch_timed(k_constrain1d<N>, grid, dim3(kConBlock), 0, s, A);
+    return hipGetLastError() == hipSuccess ? 0 : 1;
+}
+
+// batched launches: the advect's template variant is chosen as for one
+// mesh (launch_adv_n) from A0, which every member shares (advect1d_variant)
+template <int N, int NA>
+void launch_adv_batch_na(const Step1DArgs& A0, const Step1DArgs* As, const int* start, int nreq, int nblocks,
+                         hipStream_t s)
+{
+    const bool rk4 = A0.rk.s == 4;
+    const dim3 grid(nblocks), block(kBlock);
+    if (A0.cons) {
+        if (rk4) hipLaunchKernelGGL((k_advect1d_batch<N, true, NA, 4>), grid, block, 0, s, As, start, nreq);
+        else hipLaunchKernelGGL((k_advect1d_batch<N, true, NA, 0>), grid, block, 0, s, As, start, nreq);
+    } else {
+        if (rk4) hipLaunchKernelGGL((k_advect1d_batch<N, false, NA, 4>), grid, block, 0, s, As, start, nreq);
+        else hipLaunchKernelGGL((k_advect1d_batch<N, false, NA, 0>), grid, block, 0, s, As, start, nreq);
+    }
+}
+
+// number of velocity series terms the advect evaluates (launch_adv_n's choice)
+template <int N>
+int adv_terms_n(int vdeg)
+{
+    const int need = vdeg + 1;
+    return (N > 4 && need <= 4) ? 4 : (N > 8 && need <= 8) ? 8 : N;
+}
+
+template <int N>
+int launch_adv_batch_n(const Step1DArgs& A0, const Step1DArgs* As, const int* start, int nreq, int nblocks,
+                       hipStream_t s)
+{
+    const int na = adv_terms_n<N>(A0.vdeg);
+    if (na == 4) launch_adv_batch_na<N, (N > 4 ? 4 : N)>(A0, As, start, nreq, nblocks, s);
+    else if (na == 8) launch_adv_batch_na<N, (N > 8 ? 8 : N)>(A0, As, start, nreq, nblocks, s);
+    else launch_adv_batch_na<N, N>(A0, As, start, nreq, nblocks, s);
+    return hipGetLastError() == hipSuccess ? 0 : 1;
+}
+
+template <int N>
+int launch_con_batch_n(const Step1DArgs* As, const int* start, int nreq, int nblocks, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_constrain1d_batch<N>, dim3(nblocks), dim3(kConBlock), 0, s, As, start, nreq);
     return hipGetLastError() == hipSuccess ? 0 : 1;
 }
 
@@ -1155,5 +1230,55 @@ int launch_constrain1d(int n, const Step1DArgs& A, hipStream_t s)
     default: return 1;
     }
 }
+
+#define SL1D_CASES(F)                                                                                    \
+    case 2: return F(2); case 3: return F(3); case 4: return F(4); case 5: return F(5);                  \
+    case 6: return F(6); case 7: return F(7); case 8: return F(8); case 9: return F(9);                  \
+    case 10: return F(10); case 11: return F(11); case 12: return F(12); case 13: return F(13);           \
+    case 14: return F(14); case 15: return F(15); case 16: return F(16); case 17: return F(17);
+
+// template variant of the advect for A: the members of one batched launch
+// share it (series terms evaluated, form, the classical RK4 tableau or not)
+int advect1d_variant(int n, const Step1DArgs& A)
+{
+    int na = -1;
+    switch (n) {
+#define TERMS(N) \
+    case N: na = adv_terms_n<N>(A.vdeg); break;
+        TERMS(2) TERMS(3) TERMS(4) TERMS(5) TERMS(6) TERMS(7) TERMS(8) TERMS(9)
+        TERMS(10) TERMS(11) TERMS(12) TERMS(13) TERMS(14) TERMS(15) TERMS(16) TERMS(17)
+#undef TERMS
+    default: break;
+    }
+    if (na < 0) return -1;
+    return na * 4 + (A.cons ? 2 : 0) + (A.rk.s == 4 ? 1 : 0);
+}
+
+int advect1d_blocks(int n, int K) { return (K + kBlock / (n + 1) - 1) / (kBlock / (n + 1)); }
+
+int constrain1d_blocks(int K) { return (K + kConElems - 1) / kConElems; }
+
+int launch_advect1d_batch(int n, const Step1DArgs& A0, const Step1DArgs* As, const int* start, int nreq,
+                          int nblocks, hipStream_t s)
+{
+    switch (n) {
+#define ADVB(N) launch_adv_batch_n<N>(A0, As, start, nreq, nblocks, s)
+        SL1D_CASES(ADVB)
+#undef ADVB
+    default: return 1;
+    }
+}
+
+int launch_constrain1d_batch(int n, const Step1DArgs* As, const int* start, int nreq, int nblocks, hipStream_t s)
+{
+    switch (n) {
+#define CONB(N) launch_con_batch_n<N>(As, start, nreq, nblocks, s)
+        SL1D_CASES(CONB)
+#undef CONB
+    default: return 1;
+    }
+}
+#undef SL1D_CASES
+
 
 }  // namespace sl

@@ -61,6 +61,33 @@ const Ops2D* ops2d(int n)
 
 }  // namespace
 
+int advect2d_blocks(int n, int bs, int K)
+{
+    const int E = advect2d_elems(n, bs);
+    return E > 0 ? (K + E - 1) / E : 0;
+}
+
+// elements per chunk of the boundary-row solve (ConShape in the kernels)
+int constrain2d_chunks(int n, int K)
+{
+    const int a = 2 * kBlock2 / (n * n), b = kBlock2 / (4 * n);
+    const int E = a < b ? a : b;
+    return E > 0 ? (K + E - 1) / E : 0;
+}
+
+int launch_advect2d_batch(int n, const Step2DArgs& A0, const Step2DArgs* As, const int* start, int nreq,
+                          int nblocks, hipStream_t s)
+{
+    const Ops2D* o = ops2d(n);
+    return o ? o->adv_batch(A0, As, start, nreq, nblocks, s) : 1;
+}
+
+int launch_constrain2d_batch(int n, const Step2DArgs* As, const int* start, int nreq, int nblocks, hipStream_t s)
+{
+    const Ops2D* o = ops2d(n);
+    return o ? o->con_batch(As, start, nreq, nblocks, s) : 1;
+}
+
 int launch_prep2d(int n, int K, int has_div, int cons, const double* aN, double* aM, double* divN, double* divM,
                   const double* tab, double dx, double dy, double vscale, int* vdeg, hipStream_t s)
 {

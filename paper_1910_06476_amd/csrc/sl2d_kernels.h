@@ -7,6 +7,7 @@
 #include <utility>
 
 #include "sl2d_ops.h"
+#include "sl_batch.h"
 
 namespace sl {
 namespace {
@@ -492,8 +493,8 @@ __device__ __forceinline__ double resid_bcast(const double (&a)[N], const double
     return vx;
 }
 
-template <int N, int PR, bool TGT, int BSEL = 0>
-__global__ __launch_bounds__((Shape2<N, BSEL>::BS)) void k_advect2d(Step2DArgs A)
+template <int N, int PR, bool TGT, int BSEL>
+__device__ __forceinline__ void advect2d_body(const Step2DArgs& A, const int bid)
 {
     using O = Off2<N>;
     using PP = Prec<PR>;
@@ -515,7 +516,7 @@ __global__ __launch_bounds__((Shape2<N, BSEL>::BS)) void k_advect2d(Step2DArgs A
     const int slot = t / ND, q = t - slot * ND;
     const bool inblk = slot < E;
     const int sl = inblk ? slot : 0;
-    const int e = blockIdx.x * E + slot;
+    const int e = bid * E + slot;
     const bool live = inblk && e < A.K;
     const double* __restrict__ tab = A.tab;
     const int K = A.K;
@@ -680,8 +681,8 @@ __global__ __launch_bounds__((Shape2<N, BSEL>::BS)) void k_advect2d(Step2DArgs A
                         if constexpr (Shape2<N, BSEL>::E == 1) {
                             // one element per block: its coefficients have a block-uniform
                             // address and are read through the scalar cache, not LDS
-                            const double* gu = A.aM + (size_t)blockIdx.x * ND;
-                            const double* C3[3] = {gu, gu + (size_t)K * ND, A.divM + (size_t)blockIdx.x * ND};
+                            const double* gu = A.aM + (size_t)bid * ND;
+                            const double* C3[3] = {gu, gu + (size_t)K * ND, A.divM + (size_t)bid * ND};
                             cheb2_eval<N, 3>(C3, x, y, d, o);
                         } else {
                             const double* C3[3] = {s_cu[sl], s_cv[sl], s_cd[sl]};
@@ -693,7 +694,7 @@ __global__ __launch_bounds__((Shape2<N, BSEL>::BS)) void k_advect2d(Step2DArgs A
                     } else {
                         double o[2];
                         if constexpr (Shape2<N, BSEL>::E == 1) {
-                            const double* gu = A.aM + (size_t)blockIdx.x * ND;
+                            const double* gu = A.aM + (size_t)bid * ND;
                             const double* C2[2] = {gu, gu + (size_t)K * ND};
                             cheb2_eval<N, 2>(C2, x, y, d, o);
                         } else {
@@ -895,13 +896,30 @@ __global__ __launch_bounds__((Shape2<N, BSEL>::BS)) void k_advect2d(Step2DArgs A
     if (fl) atomicOr(&s_flag, fl);
     __syncthreads();
     if (t == 0) {
-        if (s_flag) A.flag_part[blockIdx.x] |= s_flag;
+        if (s_flag) A.flag_part[bid] |= s_flag;
         // one block owns each slot row; launches on the stream are ordered
-        double* sp = A.stat_part + (size_t)blockIdx.x * kStatSlots;
+        double* sp = A.stat_part + (size_t)bid * kStatSlots;
         sp[4] += (double)s_sw_sum;
         sp[5] = fmax(sp[5], (double)s_sw_max);
         sp[6] = fmax(sp[6], __longlong_as_double((long long)s_res));
     }
+}
+
+template <int N, int PR, bool TGT, int BSEL = 0>
+__global__ __launch_bounds__((Shape2<N, BSEL>::BS)) void k_advect2d(Step2DArgs A)
+{
+    advect2d_body<N, PR, TGT, BSEL>(A, blockIdx.x);
+}
+
+// One step of several meshes in one launch: the blocks of request r are
+// start[r] .. start[r + 1] - 1, each running the kernel above on the
+// request's own arguments As[r] (boundary rows only)
+template <int N, int PR, int BSEL>
+__global__ __launch_bounds__((Shape2<N, BSEL>::BS)) void k_advect2d_batch(const Step2DArgs* __restrict__ As,
+                                                                          const int* __restrict__ start, int nreq)
+{
+    const int r = batch_request(start, nreq, blockIdx.x);
+    advect2d_body<N, PR, false, BSEL>(As[r], blockIdx.x - start[r]);
 }
 
 // ---------------------------------------------------------------------------
@@ -1039,8 +1057,10 @@ __device__ __forceinline__ void con_chunk_load(const Step2DArgs& A, int base, in
     }
 }
 
+// chunks c0, c0 + stride, ... of the launch; the block's statistics go to
+// row sidx of the per-block partials
 template <int N, bool BT>
-__global__ __launch_bounds__(kBlock2) void k_constrain2d(Step2DArgs A)
+__device__ __forceinline__ void constrain2d_body(const Step2DArgs& A, const int c0, const int stride, const int sidx)
 {
     using O = Off2<N>;
     using S = ConShape<N>;
@@ -1069,7 +1089,7 @@ __global__ __launch_bounds__(kBlock2) void k_constrain2d(Step2DArgs A)
     int fl = 0;
     unsigned long long rmax = 0ull;  // this lane's largest boundary-row residual
 
-    for (int chunk = blockIdx.x; chunk < nchunk; chunk += gridDim.x) {
+    for (int chunk = c0; chunk < nchunk; chunk += stride) {
         const int base = chunk * E;
         double ph[PASS];
         con_chunk_load<N>(A, base, K, vslot, vp, ph);
@@ -1104,10 +1124,28 @@ __global__ __launch_bounds__(kBlock2) void k_constrain2d(Step2DArgs A)
     if (fl) atomicOr(&s_flag, fl);
     __syncthreads();
     if (t == 0) {
-        if (s_flag) A.flag_part[A.nblk + blockIdx.x] |= s_flag;
-        double* sp = A.stat_part + (size_t)blockIdx.x * kStatSlots;
+        if (s_flag) A.flag_part[A.nblk + sidx] |= s_flag;
+        double* sp = A.stat_part + (size_t)sidx * kStatSlots;
         sp[0] = fmax(sp[0], __longlong_as_double((long long)s_stat));
     }
+}
+
+template <int N, bool BT>
+__global__ __launch_bounds__(kBlock2) void k_constrain2d(Step2DArgs A)
+{
+    constrain2d_body<N, BT>(A, blockIdx.x, gridDim.x, blockIdx.x);
+}
+
+// batched: one chunk per block, block start[r] + c doing chunk c of request
+// r, whose statistics row c is then its own (a request has no more chunks
+// than partial rows from four nodes per direction on)
+template <int N>
+__global__ __launch_bounds__(kBlock2) void k_constrain2d_batch(const Step2DArgs* __restrict__ As,
+                                                               const int* __restrict__ start, int nreq)
+{
+    const int r = batch_request(start, nreq, blockIdx.x);
+    const int c = blockIdx.x - start[r];
+    constrain2d_body<N, false>(As[r], c, 1 << 30, c);
 }
 
 // ---------------------------------------------------------------------------
@@ -1657,6 +1695,36 @@ int con_n(const Step2DArgs& A, hipStream_t s)
     return hipGetLastError() == hipSuccess ? 0 : 1;
 }
 
+// batched launches (boundary rows, interpolated face values): the advect's
+// variant (precision, block shape) is A0's, which every member shares
+template <int N>
+int adv_batch_n(const Step2DArgs& A0, const Step2DArgs* As, const int* start, int nreq, int nblocks, hipStream_t s)
+{
+    const dim3 grid(nblocks);
+    if (A0.targets) return 1;
+    if (A0.bs == 1 && A0.precision == SL_PREC_FP64) {
+        hipLaunchKernelGGL((k_advect2d_batch<N, 0, 1>), grid, dim3(Shape2<N, 1>::BS), 0, s, As, start, nreq);
+    } else if constexpr (N * N > kBlock2) {
+        return 1;
+    } else {
+        if (A0.bs != 0) return 1;
+        if (A0.precision == SL_PREC_FP32_REFINED)
+            hipLaunchKernelGGL((k_advect2d_batch<N, 1, 0>), grid, dim3(kBlock2), 0, s, As, start, nreq);
+        else if (A0.precision == SL_PREC_BF16_REFINED)
+            hipLaunchKernelGGL((k_advect2d_batch<N, 2, 0>), grid, dim3(kBlock2), 0, s, As, start, nreq);
+        else
+            hipLaunchKernelGGL((k_advect2d_batch<N, 0, 0>), grid, dim3(kBlock2), 0, s, As, start, nreq);
+    }
+    return hipGetLastError() == hipSuccess ? 0 : 1;
+}
+
+template <int N>
+int con_batch_n(const Step2DArgs* As, const int* start, int nreq, int nblocks, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_constrain2d_batch<N>, dim3(nblocks), dim3(kBlock2), 0, s, As, start, nreq);
+    return hipGetLastError() == hipSuccess ? 0 : 1;
+}
+
 // backtracking interface values (eq. 4.11), a launch of their own before
 // the advect kernel: one lane per edge point (4n per element, floor(256/4n)
 // elements per block).  phi^n and the velocity (and divergence) series of
@@ -1748,7 +1816,7 @@ int con_mixed_n(const Step2DArgs& A, hipStream_t s)
     const Ops2D* ops2d_##N()                                                                                \
     {                                                                                                       \
         static const Ops2D t = {prep_n<N>, facevel_n<N>, facevel_mixed_n<N>, con_mixed_n<N>,                \
-                                adv_n<N>,  con_n<N>,     bt_n<N>};                                          \
+                                adv_n<N>,  con_n<N>,     bt_n<N>,           adv_batch_n<N>, con_batch_n<N>}; \
         return &t;                                                                                          \
     }                                                                                                       \
     }

@@ -956,12 +956,13 @@ double sl_max_dt(const sl_mesh* m, double cfl)
 }
 
 
-sl_status sl_step(sl_mesh* m, double dt, int32_t nsteps, const sl_step_opts* o)
+}  // extern "C"
+
+namespace {
+
+// validation of a step (before any launch; the mesh is unchanged on error)
+sl_status step_check(const sl_mesh* m, double dt, int32_t nsteps, const sl_step_opts& opt)
 {
-    const ApiHold hold;
-    if (!m) return SL_E_INVALID;
-    sl_step_opts opt = {4, SL_C_BOUNDARY, SL_MODE_HARD, 50, 3, SL_IFACE_INTERP, 1e-8};
-    if (o) opt = *o;
     if (!(dt > 0) || !std::isfinite(dt) || nsteps < 0) return SL_E_INVALID;
     if (!step_opts_valid(opt)) return SL_E_INVALID;
     if (m->mixed && opt.iface != SL_IFACE_INTERP) return SL_E_INVALID;
@@ -987,69 +988,52 @@ sl_status sl_step(sl_mesh* m, double dt, int32_t nsteps, const sl_step_opts* o)
     // mass and energy rows run one lane per node)
     if (m->dim == 2 && !m->mixed && m->n > kMax2DFull && (opt.constraints & (SL_C_MASS | SL_C_ENERGY)))
         return SL_E_INVALID;
+    return SL_OK;
+}
 
-    if (m->mixed) return step_mixed(m, dt, nsteps, opt);
-    if (m->dim == 2) {
-        Step2DArgs B;
-        std::memset(&B, 0, sizeof(B));
-        rk_tableau(opt.rk, &B.rk);
-        B.aN = m->aN; B.aM = m->aM; B.divN = m->divN; B.divM = m->divM; B.vface = m->vface; B.tab = m->tab;
-        B.rec = m->rec; B.phihat = m->phihat;
-        B.flag_part = m->flag_part; B.stat_part = m->stat_part; B.nblk = m->nblocks; B.vdeg = m->vdeg;
-        B.kx = m->kx; B.ky = m->ky; B.K = m->K; B.periodic = periodic_mask(m->bc);
-        B.cons = m->form == SL_FORM_CONSERVATIVE; B.cmask = opt.constraints; B.mode = opt.mode;
-        B.refine = 60;  // cap on defect-correction sweeps of the remap solve
-        B.precision = m->precision;
-        B.targets = (opt.constraints & (SL_C_MASS | SL_C_ENERGY)) != 0;
-        // volume terms of the balance laws: advective form for mass and
-        // energy, conservative form for energy only
-        B.vol = B.targets && (B.cons ? (opt.constraints & SL_C_ENERGY) != 0 : 1);
-        B.rstride = (B.targets ? 12 * m->n + 3 : 4 * m->n) + (opt.iface == SL_IFACE_BACKTRACK ? 4 * m->n : 0);
-        // from n = 12 on one element fills a 256-lane block only to 66% or
-        // less: the advect (FP64, boundary rows) takes the block of the
-        // fewest whole waves that hold one element instead (192 lanes at
-        // n = 13; measured 13% faster).  A block then still holds one
-        // element, so the per-block partials stay sized as they are.
-        B.bs = (m->n >= 12 && m->precision == SL_PREC_FP64 && !B.targets) ? 1 : 0;
-        B.sumW = 0.0;
-        for (int j = 0; j < m->n; ++j)
-            for (int i = 0; i < m->n; ++i) B.sumW += m->dx * m->dy * m->T.w[i] * m->T.w[j];
-        B.emaxit = opt.energy_maxit; B.etol = opt.energy_tol;
-        B.iface = opt.iface;
-        B.dx = m->dx; B.dy = m->dy;
-        B.invdx = 1.0 / m->dx; B.invdy = 1.0 / m->dy; B.dt = dt;
-        B.vzero = 1e-12 * std::max(m->amax[0], m->amax[1]);
-        for (int s = 0; s < nsteps; ++s) {
-            if (m->bc != SL_BC_PERIODIC) {
-                const long r0 = std::min<long>(m->ghost_step, m->ghost_rows - 1);
-                const long r1 = std::min<long>(m->ghost_step + 1, m->ghost_rows - 1);
-                B.gnow = m->ghost + r0 * sl_ghost_count(m);
-                B.gnext = m->ghost + r1 * sl_ghost_count(m);
-            } else {
-                B.gnow = B.gnext = m->vface;
-            }
-            B.phi = m->phi;
-            B.phi_out = m->phi2;
-            if (opt.iface == SL_IFACE_BACKTRACK && launch_backtrace2d(m->n, B, m->stream)) return SL_E_DEVICE;
-            ev_begin(m, KER_ADV2D, true);
-            if (launch_advect2d(m->n, B, m->stream)) return SL_E_DEVICE;
-            ev_end(m, KER_ADV2D, true);
-            ev_begin(m, KER_CON2D, true);
-            if (launch_constrain2d(m->n, B, m->stream)) return SL_E_DEVICE;
-            ev_end(m, KER_CON2D, true);
-            std::swap(m->phi, m->phi2);
-            m->t += dt;
-            m->steps += 1;
-            m->ghost_step += 1;
-        }
-        return SL_OK;
-    }
+// launch arguments of a uniform 2D mesh's steps, but the per-step fields
+void args2d(const sl_mesh* m, double dt, const sl_step_opts& opt, Step2DArgs* Bp)
+{
+    Step2DArgs& B = *Bp;
+    std::memset(&B, 0, sizeof(B));
+    rk_tableau(opt.rk, &B.rk);
+    B.aN = m->aN; B.aM = m->aM; B.divN = m->divN; B.divM = m->divM; B.vface = m->vface; B.tab = m->tab;
+    B.rec = m->rec; B.phihat = m->phihat;
+    B.flag_part = m->flag_part; B.stat_part = m->stat_part; B.nblk = m->nblocks; B.vdeg = m->vdeg;
+    B.kx = m->kx; B.ky = m->ky; B.K = m->K; B.periodic = periodic_mask(m->bc);
+    B.cons = m->form == SL_FORM_CONSERVATIVE; B.cmask = opt.constraints; B.mode = opt.mode;
+    B.refine = 60;  // cap on defect-correction sweeps of the remap solve
+    B.precision = m->precision;
+    B.targets = (opt.constraints & (SL_C_MASS | SL_C_ENERGY)) != 0;
+    // volume terms of the balance laws: advective form for mass and
+    // energy, conservative form for energy only
+    B.vol = B.targets && (B.cons ? (opt.constraints & SL_C_ENERGY) != 0 : 1);
+    B.rstride = (B.targets ? 12 * m->n + 3 : 4 * m->n) + (opt.iface == SL_IFACE_BACKTRACK ? 4 * m->n : 0);
+    // from n = 12 on one element fills a 256-lane block only to 66% or
+    // less: the advect (FP64, boundary rows) takes the block of the
+    // fewest whole waves that hold one element instead (192 lanes at
+    // n = 13; measured 13% faster).  A block then still holds one
+    // element, so the per-block partials stay sized as they are.
+    B.bs = (m->n >= 12 && m->precision == SL_PREC_FP64 && !B.targets) ? 1 : 0;
+    B.sumW = 0.0;
+    for (int j = 0; j < m->n; ++j)
+        for (int i = 0; i < m->n; ++i) B.sumW += m->dx * m->dy * m->T.w[i] * m->T.w[j];
+    B.emaxit = opt.energy_maxit; B.etol = opt.energy_tol;
+    B.iface = opt.iface;
+    B.dx = m->dx; B.dy = m->dy;
+    B.invdx = 1.0 / m->dx; B.invdy = 1.0 / m->dy; B.dt = dt;
+    B.vzero = 1e-12 * std::max(m->amax[0], m->amax[1]);
+}
 
-    Step1DArgs A;
+// launch arguments of a 1D mesh's steps, but the per-step fields; false if
+// the constant block of the KKT system is singular
+bool args1d(const sl_mesh* m, double dt, const sl_step_opts& opt, Step1DArgs* Ap)
+{
+    Step1DArgs& A = *Ap;
     std::memset(&A, 0, sizeof(A));
     if (!step1d_setup(m->T, m->n, m->dx, m->bc == SL_BC_PERIODIC, m->form == SL_FORM_CONSERVATIVE, opt,
                       m->amax[0], &A))
-        return SL_E_INVALID;
+        return false;
     A.aN = m->aN; A.aM = m->aM; A.divN = m->divN; A.divM = m->divM; A.vface = m->vface; A.tab = m->tab;
     A.aM4 = m->aM + (size_t)m->K * m->n;
     A.divM4 = m->aM + (size_t)m->K * (m->n + 4);
@@ -1057,36 +1041,120 @@ sl_status sl_step(sl_mesh* m, double dt, int32_t nsteps, const sl_step_opts* o)
     A.flag_part = m->flag_part; A.stat_part = m->stat_part; A.nblk = m->nblocks; A.vdeg = m->vdeg;
     A.K = m->K;
     A.dt = dt;
-    for (int s = 0; s < nsteps; ++s) {
-        if (m->bc != SL_BC_PERIODIC) {
-            const long r0 = std::min<long>(m->ghost_step, m->ghost_rows - 1);
-            const long r1 = std::min<long>(m->ghost_step + 1, m->ghost_rows - 1);
-            A.gnow = m->ghost + r0 * sl_ghost_count(m);
-            A.gnext = m->ghost + r1 * sl_ghost_count(m);
-        } else {
-            A.gnow = A.gnext = m->vface;  // unused for periodic meshes (valid address)
+    return true;
+}
+
+// the per-step fields of the next step: phi^n, phi^{n+1} and the ghost rows
+// at t^n and t^{n+1}
+template <typename Args>
+void step_fields(const sl_mesh* m, Args* A)
+{
+    if (m->bc != SL_BC_PERIODIC) {
+        const long r0 = std::min<long>(m->ghost_step, m->ghost_rows - 1);
+        const long r1 = std::min<long>(m->ghost_step + 1, m->ghost_rows - 1);
+        A->gnow = m->ghost + r0 * sl_ghost_count(m);
+        A->gnext = m->ghost + r1 * sl_ghost_count(m);
+    } else {
+        A->gnow = A->gnext = m->vface;  // unused for periodic meshes (valid address)
+    }
+    A->phi = m->phi;
+    A->phi_out = m->phi2;
+}
+
+// a step launched: the new field becomes phi^n
+void commit(sl_mesh* m, double dt)
+{
+    std::swap(m->phi, m->phi2);
+    m->t += dt;
+    m->steps += 1;
+    m->ghost_step += 1;
+}
+
+}  // namespace
+
+sl_status sl::step_prepare(sl_mesh* m, double dt, const sl_step_opts& opt, StepLaunch* L)
+{
+    const sl_status rc = step_check(m, dt, 1, opt);
+    if (rc != SL_OK) return rc;
+    L->dim = m->dim;
+    L->n = m->n;
+    L->variant = -1;
+    if (m->mixed || m->profiling) return SL_OK;
+    if (m->dim == 1) {
+        if (!args1d(m, dt, opt, &L->a1)) return SL_E_INVALID;
+        step_fields(m, &L->a1);
+        L->variant = advect1d_variant(m->n, L->a1);
+        L->adv_blocks = advect1d_blocks(m->n, m->K);
+        L->con_blocks = constrain1d_blocks(m->K);
+        return SL_OK;
+    }
+    args2d(m, dt, opt, &L->a2);
+    step_fields(m, &L->a2);
+    // batched: boundary rows, interpolated face values, and a constrain with
+    // no more chunks than the per-block partials hold (from n = 4 on)
+    if (L->a2.targets || opt.iface != SL_IFACE_INTERP || m->n < 4) return SL_OK;
+    L->variant = L->a2.precision * 4 + L->a2.bs;
+    L->adv_blocks = advect2d_blocks(m->n, L->a2.bs, m->K);
+    L->con_blocks = constrain2d_chunks(m->n, m->K);
+    if (L->adv_blocks > m->nblocks || L->con_blocks > m->nblocks) L->variant = -1;
+    return SL_OK;
+}
+
+void sl::step_commit(sl_mesh* m, double dt) { commit(m, dt); }
+
+extern "C" {
+
+sl_status sl_step(sl_mesh* m, double dt, int32_t nsteps, const sl_step_opts* o)
+{
+    const ApiHold hold;
+    if (!m) return SL_E_INVALID;
+    sl_step_opts opt = {4, SL_C_BOUNDARY, SL_MODE_HARD, 50, 3, SL_IFACE_INTERP, 1e-8};
+    if (o) opt = *o;
+    const sl_status rc = step_check(m, dt, nsteps, opt);
+    if (rc != SL_OK) return rc;
+
+    if (m->mixed) return step_mixed(m, dt, nsteps, opt);
+    if (m->dim == 2) {
+        Step2DArgs B;
+        args2d(m, dt, opt, &B);
+        for (int s = 0; s < nsteps; ++s) {
+            step_fields(m, &B);
+            if (opt.iface == SL_IFACE_BACKTRACK && launch_backtrace2d(m->n, B, m->stream)) return SL_E_DEVICE;
+            ev_begin(m, KER_ADV2D, true);
+            if (launch_advect2d(m->n, B, m->stream)) return SL_E_DEVICE;
+            ev_end(m, KER_ADV2D, true);
+            ev_begin(m, KER_CON2D, true);
+            if (launch_constrain2d(m->n, B, m->stream)) return SL_E_DEVICE;
+            ev_end(m, KER_CON2D, true);
+            commit(m, dt);
         }
-        A.phi = m->phi;
-        A.phi_out = m->phi2;
+        return SL_OK;
+    }
+
+    Step1DArgs A;
+    if (!args1d(m, dt, opt, &A)) return SL_E_INVALID;
+    for (int s = 0; s < nsteps; ++s) {
+        step_fields(m, &A);
         ev_begin(m, KER_ADV1D, true);
         if (launch_advect1d(m->n, A, m->stream)) return SL_E_DEVICE;
         ev_end(m, KER_ADV1D, true);
         ev_begin(m, KER_CON1D, true);
         if (launch_constrain1d(m->n, A, m->stream)) return SL_E_DEVICE;
         ev_end(m, KER_CON1D, true);
-        std::swap(m->phi, m->phi2);
-        m->t += dt;
-        m->steps += 1;
-        m->ghost_step += 1;
+        commit(m, dt);
     }
     return SL_OK;
 }
 
-sl_status sl_read(sl_mesh* m, double* u_out, sl_stats* st)
+}  // extern "C"
+
+namespace {
+
+// sl_read; sync = false when the caller knows the mesh's work is done
+// (its stream may hold later work of other meshes)
+sl_status read_impl(sl_mesh* m, double* u_out, sl_stats* st, bool sync)
 {
-    const ApiHold hold;
-    if (!m) return SL_E_INVALID;
-    if (hipStreamSynchronize(m->stream)) return SL_E_DEVICE;
+    if (sync && hipStreamSynchronize(m->stream)) return SL_E_DEVICE;
     const size_t nf = m->mixed ? m->dofs : (size_t)m->K * m->nd;
     std::vector<double> host;
     double* dst = u_out;
@@ -1165,6 +1233,22 @@ sl_status sl_read(sl_mesh* m, double* u_out, sl_stats* st)
     if (flags & FLAG_SINGULAR) return SL_E_SINGULAR;
     if (flags & FLAG_NOCONV) return SL_E_NOCONV;
     return SL_OK;
+}
+
+}  // namespace
+
+sl_status sl::read_settled(sl_mesh* m, double* u_out, sl_stats* st)
+{
+    return m ? read_impl(m, u_out, st, false) : SL_E_INVALID;
+}
+
+extern "C" {
+
+sl_status sl_read(sl_mesh* m, double* u_out, sl_stats* st)
+{
+    const ApiHold hold;
+    if (!m) return SL_E_INVALID;
+    return read_impl(m, u_out, st, true);
 }
 
 sl_status sl_device_field(sl_mesh* m, double** d_phi, void** stream)

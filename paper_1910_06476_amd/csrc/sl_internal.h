@@ -163,6 +163,17 @@ bool step_opts_valid(const sl_step_opts& opt);
 bool step1d_setup(const Tables& T, int n, double dx, int periodic, int cons, const sl_step_opts& opt, double amax,
                   Step1DArgs* A);
 
+// Batched 1D steps: one launch of each kernel steps several meshes, block
+// offsets start[0..nreq] (start[0] = 0, start[nreq] = nblocks) and the
+// members' arguments As in device memory; A0 a host copy of one member's.
+// The members share n and advect1d_variant; n >= 2.
+int advect1d_variant(int n, const Step1DArgs& A);
+int advect1d_blocks(int n, int K);
+int constrain1d_blocks(int K);
+int launch_advect1d_batch(int n, const Step1DArgs& A0, const Step1DArgs* As, const int* start, int nreq,
+                          int nblocks, hipStream_t s);
+int launch_constrain1d_batch(int n, const Step1DArgs* As, const int* start, int nreq, int nblocks, hipStream_t s);
+
 // vscale: mesh-wide max |a|, the floor of the noise threshold of the
 // velocity series' effective degree
 int launch_prep1d(int n, int K, int periodic, int has_div, const double* aN, double* aM, double* divN,
@@ -253,6 +264,39 @@ int launch_constrain2d(int n, const Step2DArgs& A, hipStream_t s);
 // backtracking interface values into the record's last 4n slots (A.phi is phi^n)
 int launch_backtrace2d(int n, const Step2DArgs& A, hipStream_t s);
 int blocks2d(int n, int K);
+
+// Batched 2D steps (boundary rows, interpolated face values, n >= 4): as
+// the 1D ones; the members share n, precision and advect block shape.
+// The constrain runs one block per chunk of constrain2d_chunks.
+int advect2d_blocks(int n, int bs, int K);
+int constrain2d_chunks(int n, int K);
+int launch_advect2d_batch(int n, const Step2DArgs& A0, const Step2DArgs* As, const int* start, int nreq,
+                          int nblocks, hipStream_t s);
+int launch_constrain2d_batch(int n, const Step2DArgs* As, const int* start, int nreq, int nblocks, hipStream_t s);
+
+// One step of a uniform mesh as launch arguments, for launches that step
+// several meshes at once (the request loop's batches).  step_prepare
+// validates as sl_step (nothing changes on error) and fills L: variant < 0
+// if this step cannot join a batch (mixed-order mesh, profiling, 2D target
+// or backtracking rows, 2D below four nodes per direction); otherwise the
+// arguments of the step from the mesh's current field, its advect variant
+// and the block counts of both kernels.  step_commit records the launched
+// step on the mesh (field, time, ghost row).
+struct StepLaunch {
+    int dim, n;
+    int variant;  // 1D: advect1d_variant; 2D: precision * 4 + advect block shape
+    int adv_blocks, con_blocks;
+    Step1DArgs a1;
+    Step2DArgs a2;
+};
+sl_status step_prepare(sl_mesh* m, double dt, const sl_step_opts& opt, StepLaunch* L);
+void step_commit(sl_mesh* m, double dt);
+// sl_read without waiting on the mesh's stream: for a caller that has seen
+// the mesh's last step complete (the stream may hold other meshes' work)
+sl_status read_settled(sl_mesh* m, double* u_out, sl_stats* st);
+// sl_read without waiting on the mesh's stream: for a caller that has seen
+// the mesh's last step complete (the stream may hold other meshes' work)
+sl_status read_settled(sl_mesh* m, double* u_out, sl_stats* st);
 
 // 2D boundary tables (4n x 4n, row-major): Qhard = (C_B C_B^T)^+,
 // Qsoft = (I + C_B C_B^T)^{-1}; and the reference mass row w (x) w (n^2)

@@ -112,6 +112,9 @@ def test_server_host_side_validation(sl):
         sl.Server(max_active=0)
     with pytest.raises(sl.SLError):
         sl.Server(max_active=65)
+    h = ctypes.c_void_p()
+    assert sl.lib().sl_server_create(ctypes.byref(sl.ServerDesc(2, 2, 1 << 20)), ctypes.byref(h)) == sl.SL_E_INVALID
+    sl.Server(max_active=2, batch=False).close()
     s = sl.Server(max_active=2, hbm_budget=1 << 20)
     try:
         n = 5

@@ -1,7 +1,8 @@
 """GPU tests of the request loop (sl_server_*): each result is the same
 alone and in the mix (bit for bit: every kernel is deterministic and works
-per mesh), admission by slots and memory budget, failure isolation,
-latency statistics, and one request against the oracle."""
+per mesh), batched and one stream per request alike, batches that carry
+several requests' steps per launch, admission by slots and memory budget,
+failure isolation, latency statistics, and one request against the oracle."""
 import math
 
 import numpy as np
@@ -77,6 +78,59 @@ def test_alone_and_in_the_mix_are_identical(max_active):
         assert rc0 == rc1
         assert np.array_equal(f0, f1)
         assert st0.flags == st1.flags and st0.max_picard == st1.max_picard
+
+
+def _run(reqs, max_active, batch):
+    import paper_1910_06476_amd as P
+    with P.Server(max_active=max_active, batch=batch) as S:
+        ids = [_submit(S, w, p) for w, p in reqs]
+        S.drain()
+        out = [S.result(i) for i in ids]
+        return out, S.batching()
+
+
+@pytest.mark.parametrize("seed", [11, 12])
+def test_batched_and_unbatched_are_identical(seed):
+    """The same mix through batched launches and through one stream per
+    request: the same fields, bit for bit, and the same statistics."""
+    reqs = _requests(seed=seed, count=10)
+    announce(f"serve batched vs unbatched seed={seed}")
+    a, (launches_a, steps_a) = _run(reqs, 6, True)
+    b, (launches_b, steps_b) = _run(reqs, 6, False)
+    assert launches_b == 0 and steps_b == 0
+    assert steps_a > 0
+    for (rc0, f0, st0, _), (rc1, f1, st1, _) in zip(a, b):
+        assert rc0 == rc1 == 0
+        assert np.array_equal(f0, f1)
+        assert st0.flags == st1.flags and st0.max_picard == st1.max_picard
+        assert st0.steps == st1.steps
+
+
+@pytest.mark.parametrize("dim", [1, 2])
+def test_requests_of_one_variant_share_launches(dim):
+    """Requests of one kernel variant admitted together are stepped by
+    shared launches: one group step per step of the longest request, each
+    carrying every request that still has steps left; each result equals
+    the request stepped alone."""
+    import paper_1910_06476_amd as P
+    rng = np.random.default_rng(dim)
+    reqs = []
+    for i in range(5):
+        steps = int(rng.integers(3, 9))
+        if dim == 1:
+            w = W.c2(K=int(rng.integers(20, 400)), n=13, nsteps=steps, cmask=W.BOUNDARY)
+        else:
+            k = int(rng.integers(3, 10))
+            w = W.c3(kx=k, ky=k, n=9, nsteps=steps)
+        reqs.append((w, 0))
+    announce(f"serve one variant dim={dim}")
+    out, (launches, member_steps) = _run(reqs, 8, True)
+    assert member_steps == sum(w.nsteps for w, _ in reqs)
+    assert launches == max(w.nsteps for w, _ in reqs)
+    for (w, p), (rc, f, st, _) in zip(reqs, out):
+        rc0, f0, st0, _ = _alone(w, p)
+        assert rc == rc0 == 0
+        assert np.array_equal(f, f0)
 
 
 def test_memory_budget_admits_in_order():
