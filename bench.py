@@ -458,11 +458,11 @@ def serve_pass(args, P, W, specs, batch):
     with P.Server(max_active=args.slots, hbm_budget=budget, batch=batch) as S:
         t0 = time.perf_counter()
         ids, work = [], 0
+        S.progress()
         for sp in specs:
             rid, wk = serve_submit(S, W, sp)
             ids.append(rid)
             work += wk
-            S.progress()
         S.drain()
         closed = time.perf_counter() - t0
         for rid in ids:
@@ -473,16 +473,17 @@ def serve_pass(args, P, W, specs, batch):
     arrivals = np.cumsum(rng.exponential(1.0 / rate, size=count))
     statuses = []
     with P.Server(max_active=args.slots, hbm_budget=budget, batch=batch) as S:
+        S.progress()  # the server's loop runs on its own threads from here
         t0 = time.perf_counter()
         ids, i = [], 0
-        while i < count or S.progress() != (0, 0):
+        while i < count:
             now = time.perf_counter() - t0
             while i < count and arrivals[i] <= now:
                 ids.append(serve_submit(S, W, specs[i])[0])
                 i += 1
-            S.progress()
-            if i < count and arrivals[i] > now:
-                time.sleep(min(5e-4, arrivals[i] - now))
+            if i < count:
+                time.sleep(max(0.0, arrivals[i] - (time.perf_counter() - t0)))
+        S.drain()
         wall = time.perf_counter() - t0
         p50, p99, samples, dof = S.latency()
         launches, member_steps = S.batching()

@@ -308,17 +308,26 @@ sl_status sl_step1d_static(int32_t K, int32_t order, int32_t nodes, int32_t bc, 
  * all host arrays are copied at submission.  Requests wait in arrival order
  * and are admitted while fewer than max_active run and the device memory
  * they need (sl_mesh_bytes) fits within hbm_budget.  An admitted request
- * gets its own mesh.  Requests whose steps share a kernel variant (same
- * dimension and order; boundary rows; interpolated face values; 2D order
- * 3 and up; the same advect variant) are stepped together: each step of
- * the group is one launch of each step kernel over the elements of all its
- * members with steps left, on the server's stream, and members join and
- * leave between such steps.  Other requests queue all their steps at once
- * on their own stream.  The work of the admitted requests overlaps on the
- * device.  Results do not depend on what else runs: every kernel is
- * deterministic, and a block of a batched launch works for one request on
- * its own buffers, so a field is the same, bit for bit, alone and in any
- * mix.  One server is used from one host thread.
+ * gets its own mesh, carved from one block of a device arena that the
+ * server allocates once, at its first admission (hbm_budget plus 8.25 KiB
+ * per slot, at most 90% of the device memory then free), and one of the
+ * server's streams (one per slot).  Requests whose steps share a kernel
+ * variant (same dimension and order; boundary rows; interpolated face
+ * values; 2D order 3 and up; the same advect variant) are stepped
+ * together: each step of the group is one launch of each step kernel over
+ * the elements of all its members with steps left, on the group's stream,
+ * and members join and leave between such steps.  Other requests queue all
+ * their steps at once on their own stream.  The work of the admitted
+ * requests overlaps on the device.  Results do not depend on what else
+ * runs: every kernel is deterministic, and a block of a batched launch
+ * works for one request on its own buffers, so a field is the same, bit
+ * for bit, alone and in any mix.
+ *
+ * The loop (admission, set-up, stepping, retirement) runs on two host
+ * threads of the server's own, started by the first sl_server_progress or
+ * sl_server_drain; the caller only submits and collects.  Calls on one
+ * server may come from several host threads, except sl_server_destroy,
+ * which no other call on that server may overlap.
  * ------------------------------------------------------------------------ */
 typedef struct sl_server sl_server;
 
@@ -359,15 +368,18 @@ sl_status sl_server_create(const sl_server_desc* d, sl_server** out);
  * not NULL), SL_E_NOMEM (it could never fit the budget, or host memory). */
 sl_status sl_server_submit(sl_server* s, const sl_request* r, int64_t* id);
 
-/* Non-blocking: retire finished requests (field and statistics copied to
- * host memory, mesh freed), then admit waiting ones in arrival order.  A
- * request whose set-up or step validation fails is finished with that
- * status.  *active / *waiting (may be NULL) receive the counts after the
- * call.  Errors: SL_E_INVALID, SL_E_DEVICE. */
+/* Non-blocking: starts the loop at the first call, then reports.  The loop
+ * retires finished requests (field and statistics copied to host memory,
+ * mesh freed) and admits waiting ones in arrival order; a request whose
+ * set-up or step validation fails is finished with that status.  *active
+ * (requests holding a slot: in set-up, stepping, or being retired) and
+ * *waiting (may be NULL) receive the counts.  Errors: SL_E_INVALID, and
+ * the loop's first device error (SL_E_DEVICE), which stops it; SL_E_NOMEM
+ * if its threads cannot start. */
 sl_status sl_server_progress(sl_server* s, int32_t* active, int32_t* waiting);
 
-/* Run progress until nothing is active or waiting, blocking on the oldest
- * active request in between.  Errors: those of sl_server_progress. */
+/* Start the loop if needed and block until nothing is active or waiting.
+ * Errors: those of sl_server_progress. */
 sl_status sl_server_drain(sl_server* s);
 
 /* Result of a finished request: the field (host, K * n^dim doubles; may be
@@ -390,7 +402,8 @@ sl_status sl_server_latency(sl_server* s, double p50_p99[2], int64_t* samples, i
  * SL_E_INVALID. */
 sl_status sl_server_batching(sl_server* s, int64_t* launches, int64_t* member_steps);
 
-/* Wait for active requests, free everything.  Errors: SL_E_INVALID. */
+/* Stop the loop (a set-up in progress is completed first), wait for the
+ * device work already queued, free everything.  Errors: SL_E_INVALID. */
 sl_status sl_server_destroy(sl_server* s);
 
 #ifdef __cplusplus

@@ -333,7 +333,9 @@ def sl_mesh_bytes(dim, kx, ky, order, bc=SL_BC_PERIODIC, ghost_rows=0) -> int:
 class Server:
     """Request loop over the sl_server_* entry points (continuous batching of
     independent problems; see include/sl.h).  Host arrays are copied at
-    submission, so the caller's arrays may be reused at once."""
+    submission, so the caller's arrays may be reused at once.  The first
+    progress() or drain() starts the server's own loop threads; after that
+    requests advance without further calls."""
 
     def __init__(self, max_active=8, hbm_budget=8 << 30, batch=True):
         h = ctypes.c_void_p()

@@ -20,6 +20,7 @@ struct sl_mesh {
     double x0, x1, y0, y1, dx, dy;
     hipStream_t stream;
     bool own_stream;
+    BumpBlock* bump;  // buffers carved from this block (not freed here), or null: allocated
     Tables T;
     TabOff off;
     // device buffers
@@ -62,6 +63,7 @@ struct sl_mesh {
 };
 
 thread_local LaunchEvents sl::tl_timed_launch;
+thread_local BumpBlock* sl::tl_bump = nullptr;
 
 // per-kernel timing events (profiling) for kernel k.  A bracket around one
 // launch (one_launch) hands its pair to that launch, which records the
@@ -110,18 +112,18 @@ int vel_terms_used(const sl_mesh* m)
 }
 
 template <typename T>
-void dfree(T*& p)
+void dfree(const sl_mesh* m, T*& p)
 {
-    if (p) (void)hipFree(p);
+    if (p && !m->bump) (void)hipFree(p);
     p = nullptr;
 }
 
 void release(sl_mesh* m)
 {
-    dfree(m->phi); dfree(m->phi2); dfree(m->phihat); dfree(m->rec); dfree(m->eloc); dfree(m->aN);
-    dfree(m->aM); dfree(m->divN); dfree(m->divM); dfree(m->vface); dfree(m->tab); dfree(m->ghost);
-    dfree(m->stat_part); dfree(m->flag_part); dfree(m->vdeg_d);
-    dfree(m->elems_d); dfree(m->mix_d); dfree(m->interp_d); dfree(m->nbr_d);
+    dfree(m, m->phi); dfree(m, m->phi2); dfree(m, m->phihat); dfree(m, m->rec); dfree(m, m->eloc); dfree(m, m->aN);
+    dfree(m, m->aM); dfree(m, m->divN); dfree(m, m->divM); dfree(m, m->vface); dfree(m, m->tab); dfree(m, m->ghost);
+    dfree(m, m->stat_part); dfree(m, m->flag_part); dfree(m, m->vdeg_d);
+    dfree(m, m->elems_d); dfree(m, m->mix_d); dfree(m, m->interp_d); dfree(m, m->nbr_d);
     if (m->gexec) (void)hipGraphExecDestroy(m->gexec);
     if (m->graph) (void)hipGraphDestroy(m->graph);
     m->gexec = nullptr;
@@ -139,9 +141,16 @@ bool all_finite(const double* p, size_t n)
 }
 
 template <typename T>
-bool dalloc(T** p, size_t count)
+bool dalloc(const sl_mesh* m, T** p, size_t count)
 {
     if (count == 0) count = 1;
+    if (BumpBlock* b = m->bump) {
+        const size_t at = (b->used + 255) / 256 * 256, bytes = count * sizeof(T);
+        if (at > b->size || bytes > b->size - at) return false;
+        *p = reinterpret_cast<T*>(b->base + at);
+        b->used = at + bytes;
+        return true;
+    }
     return hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T)) == hipSuccess;
 }
 
@@ -506,6 +515,7 @@ static sl_status create_mixed(const sl_mesh_desc* d, sl_mesh** out)
     if (!all_finite(d->u0, P.dofs)) return SL_E_NONFINITE;
     sl_mesh* m = new (std::nothrow) sl_mesh();
     if (!m) return SL_E_NOMEM;
+    m->bump = tl_bump;
     m->mixed = true;
     m->dim = 2; m->kx = d->kx; m->ky = d->ky; m->K = K;
     m->family = d->nodes; m->bc = d->bc; m->form = d->form; m->precision = d->precision;
@@ -630,12 +640,12 @@ static sl_status create_mixed(const sl_mesh_desc* d, sl_mesh** out)
     }
     m->nblocks = P.nblocks;
     m->nslice = P.nbk;
-    ok = dalloc(&m->phi, P.dofs) && dalloc(&m->phi2, P.dofs) && dalloc(&m->phihat, P.dofs) &&
-         dalloc(&m->rec, P.nrec) && dalloc(&m->aN, 2 * P.dofs) && dalloc(&m->aM, 2 * P.dofs) &&
-         dalloc(&m->divN, P.dofs) && dalloc(&m->divM, P.dofs) && dalloc(&m->vface, P.nrec) &&
-         dalloc(&m->tab, P.ntab) && dalloc(&m->stat_part, (size_t)m->nslice * m->nblocks * kStatSlots) &&
-         dalloc(&m->flag_part, (size_t)m->nslice * 2 * m->nblocks) && dalloc(&m->vdeg_d, 1) && dalloc(&m->elems_d, (size_t)K) &&
-         dalloc(&m->mix_d, meta.size()) && dalloc(&m->interp_d, interp.size()) && dalloc(&m->nbr_d, nbr.size());
+    ok = dalloc(m, &m->phi, P.dofs) && dalloc(m, &m->phi2, P.dofs) && dalloc(m, &m->phihat, P.dofs) &&
+         dalloc(m, &m->rec, P.nrec) && dalloc(m, &m->aN, 2 * P.dofs) && dalloc(m, &m->aM, 2 * P.dofs) &&
+         dalloc(m, &m->divN, P.dofs) && dalloc(m, &m->divM, P.dofs) && dalloc(m, &m->vface, P.nrec) &&
+         dalloc(m, &m->tab, P.ntab) && dalloc(m, &m->stat_part, (size_t)m->nslice * m->nblocks * kStatSlots) &&
+         dalloc(m, &m->flag_part, (size_t)m->nslice * 2 * m->nblocks) && dalloc(m, &m->vdeg_d, 1) && dalloc(m, &m->elems_d, (size_t)K) &&
+         dalloc(m, &m->mix_d, meta.size()) && dalloc(m, &m->interp_d, interp.size()) && dalloc(m, &m->nbr_d, nbr.size());
     if (!ok) { release(m); delete m; return SL_E_NOMEM; }
     std::vector<double> u((size_t)P.dofs);
     for (int e = 0; e < K; ++e)
@@ -792,6 +802,7 @@ sl_status sl_create_mesh(const sl_mesh_desc* d, sl_mesh** out)
 
     sl_mesh* m = new (std::nothrow) sl_mesh();
     if (!m) return SL_E_NOMEM;
+    m->bump = tl_bump;
     m->dim = d->dim; m->kx = d->kx; m->ky = d->ky; m->n = n;
     m->nd = d->dim == 1 ? n : n * n;
     m->K = d->kx * d->ky;
@@ -812,11 +823,11 @@ sl_status sl_create_mesh(const sl_mesh_desc* d, sl_mesh** out)
     const BufSizes z = buffer_sizes(m->dim, m->kx, m->ky, n);
     m->nblocks = z.nblocks;
     m->nslice = 1;
-    bool ok = dalloc(&m->phi, z.nf) && dalloc(&m->phi2, z.nf) && dalloc(&m->phihat, z.nf) &&
-              dalloc(&m->rec, z.nrec) && dalloc(&m->aN, z.nf * m->dim) && dalloc(&m->aM, z.ncoef) &&
-              dalloc(&m->divN, z.nf) && dalloc(&m->divM, z.nf) && dalloc(&m->vface, z.nvf) &&
-              dalloc(&m->tab, z.ntab) && dalloc(&m->stat_part, z.nstat) && dalloc(&m->flag_part, z.nflag) &&
-              dalloc(&m->vdeg_d, 1);
+    bool ok = dalloc(m, &m->phi, z.nf) && dalloc(m, &m->phi2, z.nf) && dalloc(m, &m->phihat, z.nf) &&
+              dalloc(m, &m->rec, z.nrec) && dalloc(m, &m->aN, z.nf * m->dim) && dalloc(m, &m->aM, z.ncoef) &&
+              dalloc(m, &m->divN, z.nf) && dalloc(m, &m->divM, z.nf) && dalloc(m, &m->vface, z.nvf) &&
+              dalloc(m, &m->tab, z.ntab) && dalloc(m, &m->stat_part, z.nstat) && dalloc(m, &m->flag_part, z.nflag) &&
+              dalloc(m, &m->vdeg_d, 1);
     if (!ok) { release(m); delete m; return SL_E_NOMEM; }
 
     std::vector<double> tab(m->off.total, 0.0);
@@ -936,8 +947,8 @@ sl_status sl_set_ghost(sl_mesh* m, const double* g, int32_t nrows)
     for (int32_t r = 0; r < nrows; ++r)
         if (!all_finite(g + r * per + lo, hi - lo)) return SL_E_NONFINITE;
     if (hipStreamSynchronize(m->stream)) return SL_E_DEVICE;
-    dfree(m->ghost);
-    if (!dalloc(&m->ghost, cnt)) { m->ghost_rows = 0; return SL_E_NOMEM; }
+    dfree(m, m->ghost);
+    if (!dalloc(m, &m->ghost, cnt)) { m->ghost_rows = 0; return SL_E_NOMEM; }
     if (hipMemcpyAsync(m->ghost, g, cnt * sizeof(double), hipMemcpyHostToDevice, m->stream)) return SL_E_DEVICE;
     m->ghost_rows = nrows;
     m->ghost_step = 0;

@@ -142,6 +142,16 @@ struct LaunchEvents {
 };
 extern thread_local LaunchEvents tl_timed_launch;
 
+// A block of device memory that meshes created on this thread carve their
+// buffers from (256-byte aligned, in order) instead of allocating them; the
+// block's owner frees it after the meshes are destroyed.  Set around a
+// mesh's creation and set-up by the request loop; null elsewhere.
+struct BumpBlock {
+    char* base = nullptr;
+    size_t size = 0, used = 0;
+};
+extern thread_local BumpBlock* tl_bump;
+
 template <typename F, typename... Args>
 inline void launch_timed(F kernel, dim3 grid, dim3 block, uint32_t shm, hipStream_t s, Args... args)
 {
