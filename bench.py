@@ -432,7 +432,50 @@ def serve_stream(W, count, seed):
     return specs
 
 
-def serve_submit(S, W, sp):
+def serve_stream_small(W, count, seed):
+    """Seeded stream of small requests, where requests of one kernel variant
+    meet on the device: 1D (p = 1/2) with K uniform in [64, 1024] and N in
+    {8, 16}, the C2 velocity and u0; 2D with kx = ky uniform in [4, 12] and
+    N in {6, 8}, the C3 problem; FP64; 20..200 steps."""
+    rng = np.random.default_rng(seed)
+    specs = []
+    for i in range(count):
+        steps = int(rng.integers(20, 201))
+        if int(rng.integers(1, 3)) == 1:
+            K = int(rng.integers(64, 1025))
+            specs.append(dict(dim=1, K=K, n=int(rng.choice([8, 16])) + 1, steps=steps, sine=False, prec=0, seed=i))
+        else:
+            k = int(rng.integers(4, 13))
+            specs.append(dict(dim=2, K=k * k, kx=k, n=int(rng.choice([6, 8])) + 1, steps=steps, prec=0, seed=i))
+    return specs
+
+
+def serve_closed(P, W, specs, slots, budget, batch):
+    """Capacity of the request loop on `specs` (all inputs built first, then
+    submitted at once): DOF-updates/s, step latency, group-step sharing."""
+    built = []
+    for sp in specs:
+        built.append(serve_inputs(W, sp))
+    with P.Server(max_active=slots, hbm_budget=budget, batch=batch) as S:
+        S.progress()
+        t0 = time.perf_counter()
+        ids, work = [], 0
+        for args_, kw, wk in built:
+            ids.append(S.submit(*args_, **kw))
+            work += wk
+        S.drain()
+        wall = time.perf_counter() - t0
+        p50, p99, samples, dof = S.latency()
+        launches, member_steps = S.batching()
+        for rid in ids:
+            S.result(rid)
+    return {"dof_per_s": dof / wall, "wall_s": wall, "step_p50_ms": p50, "step_p99_ms": p99,
+            "request_steps_per_group_step": member_steps / launches if launches else None}
+
+
+def serve_inputs(W, sp):
+    """Positional and keyword arguments of Server.submit for one spec, and
+    its DOF-updates."""
     if sp["dim"] == 1:
         w = W.c2(K=sp["K"], n=sp["n"], nsteps=sp["steps"], cmask=W.BOUNDARY)
         u0 = W.random_field_1d(w.K, w.n, sp["seed"], x0=w.x0, x1=w.x1) if sp["sine"] else w.initial()
@@ -443,10 +486,14 @@ def serve_submit(S, W, sp):
         u0 = w.initial()
         a, _ = w.velocity()
         ghost = w.ghost_rows(0.0, w.nsteps)
-    rid = S.submit(w.dim, w.kx, w.ky, w.n - 1, u0, a, dt=w.dt, nsteps=w.nsteps, ghost=ghost, nodes=w.family,
-                   bc=w.bc, form=w.form, precision=sp["prec"], x0=w.x0, x1=w.x1, y0=w.y0, y1=w.y1, rk=w.rk,
-                   constraints=w.cmask, mode=w.mode)
-    return rid, w.K * w.nd * w.nsteps
+    kw = dict(dt=w.dt, nsteps=w.nsteps, ghost=ghost, nodes=w.family, bc=w.bc, form=w.form, precision=sp["prec"],
+              x0=w.x0, x1=w.x1, y0=w.y0, y1=w.y1, rk=w.rk, constraints=w.cmask, mode=w.mode)
+    return (w.dim, w.kx, w.ky, w.n - 1, u0, a), kw, w.K * w.nd * w.nsteps
+
+
+def serve_submit(S, W, sp):
+    pos, kw, wk = serve_inputs(W, sp)
+    return S.submit(*pos, **kw), wk
 
 
 def serve_pass(args, P, W, specs, batch):
@@ -503,14 +550,24 @@ def serve_pass(args, P, W, specs, batch):
 
 def bench_serve(args, torch, P, W):
     """Serving: a seeded Poisson stream of independent problems through the
-    request loop (continuous batching).  The requests of one kernel variant
-    are stepped together, one launch of each step kernel per group step;
-    the same stream with every request on its own stream is measured beside
-    it.  value = DOF-updates/s of the batched open loop, with the per-step
-    latency p50/p99 of its requests."""
+    request loop (continuous batching).  Small requests of one kernel
+    variant are stepped together, one launch of each step kernel per group
+    step; the same stream with every request on its own stream is measured
+    beside it.  value = DOF-updates/s of the batched open loop, with the
+    per-step latency p50/p99 of its requests.  A stream of small requests,
+    where batching carries several requests per launch, is measured both
+    ways as well (closed loop)."""
     specs = serve_stream(W, args.requests, seed=2024)
+    # untimed pass first: the first launch of each kernel loads its code and
+    # the clocks rise from idle, a cost the first measured pass would carry
+    serve_closed(P, W, specs, args.slots, int(args.budget_gib * (1 << 30)), True)
     b = serve_pass(args, P, W, specs, True)
     u = serve_pass(args, P, W, specs, False)
+    small = serve_stream_small(W, 256, seed=77)
+    budget = int(args.budget_gib * (1 << 30))
+    serve_closed(P, W, small, 32, budget, True)  # untimed, as above
+    sb = serve_closed(P, W, small, 32, budget, True)
+    su = serve_closed(P, W, small, 32, budget, False)
     out = {
         "metric": METRIC, "value": b["value"], "unit": "DOF-updates/s", "n_gpus": 1,
         "steps": int(b["step_latency"]["samples"]), "warmup": 0, "ms_per_step": None, "higher_is_better": True,
@@ -526,6 +583,9 @@ def bench_serve(args, torch, P, W):
                      "request_steps_per_group_step": b["request_steps_per_group_step"]},
         "unbatched": {k: u[k] for k in ("value", "closed_loop_dof_per_s", "step_latency", "request_latency_ms",
                                         "failed_requests", "wall_s")},
+        "small_requests": {"workload": "256 small requests (1D K in [64,1024], N in {8,16}; 2D 4x4..12x12, N in "
+                                       "{6,8}; FP64; 20-200 steps), all submitted at once, 32 slots",
+                           "batched": sb, "unbatched": su},
     }
     print(json.dumps(out))
 

@@ -311,21 +311,25 @@ sl_status sl_step1d_static(int32_t K, int32_t order, int32_t nodes, int32_t bc, 
  * gets its own mesh, carved from one block of a device arena that the
  * server allocates once, at its first admission (hbm_budget plus 8.25 KiB
  * per slot, at most 90% of the device memory then free), and one of the
- * server's streams (one per slot).  Requests whose steps share a kernel
- * variant (same dimension and order; boundary rows; interpolated face
- * values; 2D order 3 and up; the same advect variant) are stepped
- * together: each step of the group is one launch of each step kernel over
- * the elements of all its members with steps left, on the group's stream,
- * and members join and leave between such steps.  Other requests queue all
- * their steps at once on their own stream.  The work of the admitted
+ * server's streams (one per slot).  Small requests (whose advect launch
+ * has fewer than 2048 workgroups, so that alone they leave the device
+ * partly idle) whose steps share a kernel variant (same dimension and
+ * order; boundary rows; interpolated face values; 2D order 3 and up; the
+ * same advect variant) are stepped together: each step of the group is
+ * one launch of each step kernel over the elements of all its members
+ * with steps left, on the group's stream, and members join and leave
+ * between such steps.  Other requests queue all their steps at once on
+ * their own stream.  The work of the admitted
  * requests overlaps on the device.  Results do not depend on what else
  * runs: every kernel is deterministic, and a block of a batched launch
  * works for one request on its own buffers, so a field is the same, bit
  * for bit, alone and in any mix.
  *
- * The loop (admission, set-up, stepping, retirement) runs on two host
- * threads of the server's own, started by the first sl_server_progress or
- * sl_server_drain; the caller only submits and collects.  Calls on one
+ * The loop (admission, set-up, stepping, retirement) runs on host threads
+ * of the server's own (one for set-up and retirement, with up to three
+ * helpers while it sets up several requests at once; one feeding the
+ * device), started by the first sl_server_progress or sl_server_drain;
+ * the caller only submits and collects.  Calls on one
  * server may come from several host threads, except sl_server_destroy,
  * which no other call on that server may overlap.
  * ------------------------------------------------------------------------ */

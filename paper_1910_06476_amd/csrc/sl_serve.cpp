@@ -5,11 +5,13 @@
 // step count and options.  Requests wait in arrival order and are admitted
 // while a slot is free and the device memory they need fits the budget.
 //
-// The loop runs on two host threads of the server's own, started by the
-// first sl_server_progress or sl_server_drain:
+// The loop runs on host threads of the server's own, started by the first
+// sl_server_progress or sl_server_drain:
 // * the worker sets requests up (mesh, velocity, ghost rows) and retires
 //   finished ones (field and statistics to host memory, mesh freed).  All
-//   requests admissible at one moment are set up, then published together.
+//   requests admissible at one moment are set up (on up to four threads at
+//   once) and then published together, so that requests of one kernel
+//   variant submitted together start in the same tick.
 // * the feeder notices finished requests and keeps every group's steps
 //   queued on the device.
 // The caller's own thread only submits and collects, so the device stays fed
@@ -21,8 +23,10 @@
 // one per slot, kept for the server's life.  Admission and retirement thus
 // allocate and free no device memory (freeing would wait for the device).
 //
-// Batched requests: admitted requests whose steps share a kernel variant
-// (dimension, nodes per direction, advect variant) form a group, and the
+// Batched requests: admitted requests small enough that their own advect
+// launch leaves the device partly idle (fewer than kBatchBlocks blocks) and
+// whose steps share a kernel variant (dimension, nodes per direction, advect
+// variant) form a group, and the
 // feeder steps each group in ticks: one tick is one launch of each step
 // kernel over the elements of all members with steps left, every block
 // working for one member on that member's own buffers (the kernels' batched
@@ -33,15 +37,17 @@
 // launch arguments of a batched tick travel to the device through a ring of
 // pinned host slots.
 //
-// Other requests (steps that cannot join a batch, or a server created with
-// SL_SERVER_NO_BATCH) queue all their steps at admission on their own
-// stream, with an event after each, so they overlap with everything else.
+// Other requests (larger ones, steps that cannot join a batch, or a server
+// created with SL_SERVER_NO_BATCH) queue all their steps at admission on
+// their own stream, with an event after each, so they overlap with
+// everything else.
 //
 // Locking: the device hold (sl::ApiHold) is always taken before the
 // server's mutex, never after.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -65,6 +71,8 @@ constexpr double kAheadMs = 2.0;              // ... enough for about this much 
 constexpr int kStages = 32;                   // pinned argument slots
 constexpr size_t kBlockSlack = 8192;          // per request: the 256-byte alignment of its buffers
 constexpr auto kFeedPoll = std::chrono::microseconds(100);
+constexpr int kSetupThreads = 4;              // threads setting up one admission batch
+constexpr int kBatchBlocks = 2048;            // batched: advect launches below this many blocks
 
 double now_us()
 {
@@ -363,7 +371,7 @@ void prepare(bool batch, Request* r)
     if (rc == SL_OK && r->ghost_rows > 0) rc = sl_set_ghost(r->mesh, r->ghost.data(), r->ghost_rows);
     sl::tl_bump = nullptr;
     if (rc == SL_OK) rc = sl::step_prepare(r->mesh, r->dt, r->opts, &r->L);  // validates the options
-    r->batched = rc == SL_OK && batch && r->nsteps > 0 && r->L.variant >= 0;
+    r->batched = rc == SL_OK && batch && r->nsteps > 0 && r->L.variant >= 0 && r->L.adv_blocks < kBatchBlocks;
     if (rc == SL_OK && r->batched) {
         if (hipEventCreateWithFlags(&r->ready, hipEventDisableTiming) != hipSuccess ||
             hipEventRecord(r->ready, r->stream) != hipSuccess)
@@ -372,6 +380,31 @@ void prepare(bool batch, Request* r)
         rc = launch_all(r);
     }
     r->setup_rc = rc;
+}
+
+// set up a batch of reserved requests on up to kSetupThreads threads (this
+// one included; the helpers take the device hold themselves)
+void prepare_all(int device, bool batch, const std::vector<Request*>& rs)
+{
+    std::atomic<size_t> next{0};
+    auto run = [&] {
+        for (size_t k; (k = next.fetch_add(1)) < rs.size();) prepare(batch, rs[k]);
+    };
+    std::vector<std::thread> helpers;
+    const size_t nh = std::min(rs.size(), (size_t)kSetupThreads) - 1;
+    for (size_t h = 0; h < nh; ++h) {
+        try {
+            helpers.emplace_back([&, device] {
+                (void)hipSetDevice(device);
+                const sl::ApiHold hold;
+                run();
+            });
+        } catch (...) {
+            break;  // fewer helpers: this thread does the rest
+        }
+    }
+    run();
+    for (std::thread& t : helpers) t.join();
 }
 
 // give back what an admitted request holds (under the lock)
@@ -670,7 +703,7 @@ void worker_loop(sl_server* s)
         if (batch.empty()) continue;
         const bool batching = s->batch;
         lk.unlock();
-        for (Request* r : batch) prepare(batching, r);
+        prepare_all(s->device, batching, batch);
         lk.lock();
         for (Request* r : batch) publish(s, r);
         s->cv_feed.notify_one();
@@ -701,22 +734,19 @@ void feeder_loop(sl_server* s)
 }
 
 // start the loop's threads once (under the device hold and the lock); if
-// the second cannot start, the server is stopped for good
+// one cannot start, the server is stopped for good
 sl_status start_loop(sl_server* s)
 {
     if (s->started) return s->stop ? SL_E_NOMEM : SL_OK;
     if (hipGetDevice(&s->device) != hipSuccess) return SL_E_DEVICE;
-    try {
-        s->worker = std::thread(worker_loop, s);
-    } catch (...) {
-        return SL_E_NOMEM;
-    }
     s->started = true;
     try {
+        s->worker = std::thread(worker_loop, s);
         s->feeder = std::thread(feeder_loop, s);
     } catch (...) {
-        s->stop = true;  // the worker sees it and ends; destroy joins it
+        s->stop = true;  // the threads started see it and end; destroy joins them
         s->cv_work.notify_all();
+        s->cv_feed.notify_all();
         return SL_E_NOMEM;
     }
     return SL_OK;
