@@ -1200,30 +1200,39 @@ sl_status read_impl(sl_mesh* m, double* u_out, sl_stats* st, bool sync)
         std::memset(st, 0, sizeof(*st));
         st->t = m->t;
         st->steps = m->steps;
-        double M = 0, E = 0;
-        if (m->mixed) {
-            double wq[kMax2D + 1][kMaxTableN] = {};
-            double xq[kMaxTableN];
-            for (int b = 0; b < m->nbk; ++b) node_rule(m->family, m->bn[b], xq, wq[m->bn[b]]);
-            for (int e = 0; e < m->K; ++e) {
-                const int n = m->orders[e];
-                for (int p = 0; p < n * n; ++p) {
-                    const double W = m->dx * m->dy * wq[n][p % n] * wq[n][p / n];
-                    const double v = dst[m->uoff[e] + p];
-                    M += W * v;
-                    E += W * v * v;
-                }
-            }
-        } else {
-            for (int e = 0; e < m->K; ++e)
-                for (int p = 0; p < m->nd; ++p) {
-                    const int i = p % m->n, j = p / m->n;
-                    const double W = m->dx * m->T.w[i] * (m->dim == 2 ? m->dy * m->T.w[j] : 1.0);
-                    const double v = dst[(size_t)e * m->nd + p];
-                    M += W * v;
-                    E += W * v * v;
-                }
+        // mass and energy on the device, the block sums into phihat (free
+        // between steps), summed here in a fixed order
+        struct Seg {
+            const double* phi;
+            size_t nf;
+            int n;
+            const double* w;
+        };
+        std::vector<Seg> seg;
+        if (m->mixed)
+            for (int b = 0; b < m->nbk; ++b)
+                seg.push_back({m->phi + m->bOff[b], (size_t)m->bK[b] * m->bn[b] * m->bn[b], m->bn[b],
+                               m->tab + m->tabOff[b] + tab_offsets(2, m->bn[b]).w});
+        else
+            seg.push_back({m->phi, nf, m->n, m->tab + m->off.w});
+        size_t np = 0;
+        for (const Seg& g : seg) {
+            if (g.nf && launch_moments(g.phi, g.nf, g.n, m->dim, g.w, m->phihat + 2 * np, m->stream)) return SL_E_DEVICE;
+            np += g.nf ? (size_t)moments_blocks(g.nf) : 0;
         }
+        std::vector<double> part(2 * np);
+        if (np && (hipMemcpyAsync(part.data(), m->phihat, part.size() * sizeof(double), hipMemcpyDeviceToHost,
+                                  m->stream) != hipSuccess ||
+                   hipStreamSynchronize(m->stream) != hipSuccess))
+            return SL_E_DEVICE;
+        double M = 0, E = 0;
+        for (size_t k = 0; k < np; ++k) {
+            M += part[2 * k];
+            E += part[2 * k + 1];
+        }
+        const double h = m->dim == 2 ? m->dx * m->dy : m->dx;
+        M *= h;
+        E *= h;
         st->mass = M;
         st->energy = E;
         st->resid_boundary = rb;

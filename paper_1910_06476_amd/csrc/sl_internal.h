@@ -152,6 +152,12 @@ struct BumpBlock {
 };
 extern thread_local BumpBlock* tl_bump;
 
+// Mass and energy partial sums of nf nodes of order n (sl_moments.hip):
+// moments_blocks(nf) blocks each write (sum w phi, sum w phi^2) to
+// part[2b], part[2b + 1]; w is the device copy of the node weights.
+int moments_blocks(size_t nf);
+int launch_moments(const double* phi, size_t nf, int n, int dim, const double* w, double* part, hipStream_t s);
+
 template <typename F, typename... Args>
 inline void launch_timed(F kernel, dim3 grid, dim3 block, uint32_t shm, hipStream_t s, Args... args)
 {
