@@ -395,6 +395,39 @@ template <> struct Prec<2> {
     __device__ static A get(S v) { return __uint_as_float((unsigned int)v << 16); }
 };
 
+// v = max(v, the v of the lane that DPP control CTRL selects), one VALU
+// instruction (the compiler does not fold a separate DPP move into the
+// max); lanes in rows outside the row mask keep their v.  The s_nop gives
+// the two wait states a DPP read needs after a VALU write of its source.
+#define SL_DPP_MAX_U32(v, CTRL) asm volatile("s_nop 1\n\tv_max_u32_dpp %0, %0, %0 " CTRL : "+v"(v))
+
+// Maximum over the 64 lanes of a wave, left in lane 63: butterflies within
+// quads (quad_perm [1,0,3,2], [2,3,0,1]), then half-rows and rows (mirror),
+// then across rows (broadcast of lane 15 into rows 1 and 3, of lane 31 into
+// rows 2 and 3).  VALU data movement only, none through the LDS unit.
+// Every lane of the wave runs it.
+__device__ __forceinline__ unsigned wave_max_u32(unsigned v)
+{
+    SL_DPP_MAX_U32(v, "quad_perm:[1,0,3,2] row_mask:0xf bank_mask:0xf");
+    SL_DPP_MAX_U32(v, "quad_perm:[2,3,0,1] row_mask:0xf bank_mask:0xf");
+    SL_DPP_MAX_U32(v, "row_half_mirror row_mask:0xf bank_mask:0xf");
+    SL_DPP_MAX_U32(v, "row_mirror row_mask:0xf bank_mask:0xf");
+    SL_DPP_MAX_U32(v, "row_bcast:15 row_mask:0xa bank_mask:0xf");
+    SL_DPP_MAX_U32(v, "row_bcast:31 row_mask:0xc bank_mask:0xf");
+    return v;
+}
+
+// The same for 64-bit values, exactly: the upper words first, then the
+// lower words of the lanes whose upper word is the maximum (32-bit maxima
+// only, no 64-bit compares).
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
+{
+    const unsigned hi = (unsigned)(v >> 32);
+    const unsigned top = (unsigned)__builtin_amdgcn_readlane((int)wave_max_u32(hi), 63);
+    const unsigned lo = wave_max_u32(hi == top ? (unsigned)v : 0u);
+    return ((unsigned long long)top << 32) | lo;
+}
+
 // Maximum of the bit patterns `bits` (non-negative doubles, and NaN above
 // them, order as their bits) over the lanes of each element slot present in
 // one 64-lane wave, published to dst[slot] with one LDS atomic per slot
@@ -402,43 +435,22 @@ template <> struct Prec<2> {
 // wave spans at most two slots (n^2 >= 64), or with every lane in slot 0
 // (the constrain kernels' block-wide residual).  Every lane of the wave calls
 // it; lanes without a value pass 0.
-// max with the value DPP control CTRL brings to this lane (rows outside
-// ROWMASK keep their own value), on both 32-bit halves of a 64-bit word
-template <int CTRL, int ROWMASK>
-__device__ __forceinline__ unsigned long long dpp_max_u64(unsigned long long v)
-{
-    const int lo = (int)(unsigned)v, hi = (int)(v >> 32);
-    const int l2 = __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROWMASK, 0xF, false);
-    const int h2 = __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROWMASK, 0xF, false);
-    const unsigned long long o = ((unsigned long long)(unsigned)h2 << 32) | (unsigned)l2;
-    return o > v ? o : v;
-}
-
-// Maximum over the 64 lanes of a wave, left in lane 63: butterflies within
-// quads (quad_perm [1,0,3,2], [2,3,0,1]), then half-rows and rows (mirror),
-// then across rows (broadcast of lane 15 into rows 1 and 3, of lane 31 into
-// rows 2 and 3).  VALU data movement only, none through the LDS unit.
-__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
-{
-    v = dpp_max_u64<0xB1, 0xF>(v);
-    v = dpp_max_u64<0x4E, 0xF>(v);
-    v = dpp_max_u64<0x141, 0xF>(v);
-    v = dpp_max_u64<0x140, 0xF>(v);
-    v = dpp_max_u64<0x142, 0xA>(v);
-    v = dpp_max_u64<0x143, 0xC>(v);
-    return v;
-}
-
-// (the slots sit S words apart in dst)
+// (the slots sit S words apart in dst).
 template <int E, int S = 1>
 __device__ __forceinline__ void slot_max(unsigned long long* dst, int slot, unsigned long long bits)
 {
-    const int first = __builtin_amdgcn_readfirstlane(slot);  // every lane is active here: lane 0's slot
-    const unsigned long long a = wave_max_u64(slot == first ? bits : 0ull);
-    const unsigned long long b = wave_max_u64(slot == first + 1 ? bits : 0ull);
-    if ((threadIdx.x & 63) == 63) {
-        if (first < E && a) atomicMax(&dst[first * S], a);
-        if (first + 1 < E && b) atomicMax(&dst[(first + 1) * S], b);
+    if constexpr (E == 1) {
+        // one slot: lanes outside it pass 0
+        const unsigned long long a = wave_max_u64(bits);
+        if ((threadIdx.x & 63) == 63 && a) atomicMax(&dst[0], a);
+    } else {
+        const int first = __builtin_amdgcn_readfirstlane(slot);  // every lane is active here: lane 0's slot
+        const unsigned long long a = wave_max_u64(slot == first ? bits : 0ull);
+        const unsigned long long b = wave_max_u64(slot == first + 1 ? bits : 0ull);
+        if ((threadIdx.x & 63) == 63) {
+            if (first < E && a) atomicMax(&dst[first * S], a);
+            if (first + 1 < E && b) atomicMax(&dst[(first + 1) * S], b);
+        }
     }
 }
 
