@@ -479,13 +479,69 @@ __device__ __forceinline__ void fmac_bcast(double& acc, double x, double a)
 // a row of x touches, so each product takes its x from a row broadcast
 // instead of an LDS read (2 reads per row of x instead of n).  Same
 // products and sums in the same order as the LDS form.
+// Up to four of them in one asm block, with one s_nop for the block: inside
+// it only the accumulator is written, never a broadcast source.
+template <int K0, int K1, int K2, int K3>
+__device__ __forceinline__ void fmac_bcast4(double& acc, double x0, double a0, double x1, double a1, double x2,
+                                            double a2, double x3, double a3)
+{
+    asm volatile("s_nop 1\n\t"
+                 "v_fmac_f64_dpp %0, %1, %2 row_newbcast:%9 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f64_dpp %0, %3, %4 row_newbcast:%10 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f64_dpp %0, %5, %6 row_newbcast:%11 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f64_dpp %0, %7, %8 row_newbcast:%12 row_mask:0xf bank_mask:0xf"
+                 : "+v"(acc)
+                 : "v"(x0), "v"(a0), "v"(x1), "v"(a1), "v"(x2), "v"(a2), "v"(x3), "v"(a3), "n"(K0), "n"(K1),
+                   "n"(K2), "n"(K3));
+}
+template <int K0, int K1, int K2>
+__device__ __forceinline__ void fmac_bcast3(double& acc, double x0, double a0, double x1, double a1, double x2,
+                                            double a2)
+{
+    asm volatile("s_nop 1\n\t"
+                 "v_fmac_f64_dpp %0, %1, %2 row_newbcast:%7 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f64_dpp %0, %3, %4 row_newbcast:%8 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f64_dpp %0, %5, %6 row_newbcast:%9 row_mask:0xf bank_mask:0xf"
+                 : "+v"(acc)
+                 : "v"(x0), "v"(a0), "v"(x1), "v"(a1), "v"(x2), "v"(a2), "n"(K0), "n"(K1), "n"(K2));
+}
+template <int K0, int K1>
+__device__ __forceinline__ void fmac_bcast2(double& acc, double x0, double a0, double x1, double a1)
+{
+    asm volatile("s_nop 1\n\t"
+                 "v_fmac_f64_dpp %0, %1, %2 row_newbcast:%5 row_mask:0xf bank_mask:0xf\n\t"
+                 "v_fmac_f64_dpp %0, %3, %4 row_newbcast:%6 row_mask:0xf bank_mask:0xf"
+                 : "+v"(acc)
+                 : "v"(x0), "v"(a0), "v"(x1), "v"(a1), "n"(K0), "n"(K1));
+}
+
+// products L0.. of row M of the residual, four to an asm block
+template <int N, int M, int L0>
+__device__ __forceinline__ void resid_row_from(double& inner, const double (&a)[N], double xa, double xb)
+{
+    constexpr int C0 = (N * M) >> 4;
+    auto X = [&](int l) { return ((N * M + l) >> 4) == C0 ? xa : xb; };
+    constexpr int R = N - L0;
+    if constexpr (R >= 4) {
+        fmac_bcast4<(N * M + L0) & 15, (N * M + L0 + 1) & 15, (N * M + L0 + 2) & 15, (N * M + L0 + 3) & 15>(
+            inner, X(L0), a[L0], X(L0 + 1), a[L0 + 1], X(L0 + 2), a[L0 + 2], X(L0 + 3), a[L0 + 3]);
+        resid_row_from<N, M, L0 + 4>(inner, a, xa, xb);
+    } else if constexpr (R == 3) {
+        fmac_bcast3<(N * M + L0) & 15, (N * M + L0 + 1) & 15, (N * M + L0 + 2) & 15>(
+            inner, X(L0), a[L0], X(L0 + 1), a[L0 + 1], X(L0 + 2), a[L0 + 2]);
+    } else if constexpr (R == 2) {
+        fmac_bcast2<(N * M + L0) & 15, (N * M + L0 + 1) & 15>(inner, X(L0), a[L0], X(L0 + 1), a[L0 + 1]);
+    } else if constexpr (R == 1) {
+        fmac_bcast<(N * M + L0) & 15>(inner, X(L0), a[L0]);
+    }
+}
+
 template <int N, int M, int... L>
 __device__ __forceinline__ double resid_row(const double (&a)[N], double xa, double xb,
                                             std::integer_sequence<int, L...>)
 {
-    constexpr int C0 = (N * M) >> 4;
     double inner = 0.0;
-    (fmac_bcast<(N * M + L) & 15>(inner, ((N * M + L) >> 4) == C0 ? xa : xb, a[L]), ...);
+    resid_row_from<N, M, 0>(inner, a, xa, xb);
     return inner;
 }
 
@@ -824,8 +880,11 @@ __device__ __forceinline__ void advect2d_body(const Step2DArgs& A, const int bid
     __syncthreads();
     bool conv = !live;
     int sweeps = A.refine;   // sweeps this element needed
-    double lastrel = 0.0;    // its estimated error left, relative to max |phi*|
     double prev = 0.0;       // max |y| of the previous sweep
+    // |y| of the last sweep taken and of the one before it (the estimated
+    // error left is formed from them once, after the loop)
+    double eny_last = 0.0, prev_last = 0.0;
+    bool had_prev = false;
     for (int it = 0; it < A.refine; ++it) {
         // residual r_p = phi*_p - (V x)_p, (V x)_p = sum_m b_m sum_l a_l x[m][l]
         double vx = 0.0;
@@ -862,9 +921,9 @@ __device__ __forceinline__ void advect2d_body(const Step2DArgs& A, const int bid
             const double eny = __longlong_as_double((long long)s_nrm[it & 1][slot]);
             if (P32 && eny > 0.0) e2 = ref_exp(eny);
             if (!conv) {
-                // estimated error left: the correction times the observed contraction
-                const double left = (it > 0 && prev > 0.0) ? fmin(eny, eny * eny / prev) : eny;
-                lastrel = ref > 0.0 ? left / ref : 0.0;
+                eny_last = eny;
+                prev_last = prev;
+                had_prev = it > 0;
                 // Stop when the correction is below 2^-44 of max |phi*|, or
                 // when the observed contraction q = |y_k| / |y_{k-1}| <= 1/2
                 // puts the remaining error (about q |y_k|) below 2^-50 of it.
@@ -879,7 +938,22 @@ __device__ __forceinline__ void advect2d_body(const Step2DArgs& A, const int bid
             }
             prev = eny;
         }
-        if (__syncthreads_and(conv)) break;
+        if constexpr (E == 1) {
+            // conv is the element's, the same in all its lanes, and lane 0
+            // of every wave is one of them: each wave breaks alike with no
+            // barrier (the barriers above order every LDS access of the
+            // next sweep)
+            if (__builtin_amdgcn_readfirstlane(conv)) break;
+        } else {
+            if (__syncthreads_and(conv)) break;
+        }
+    }
+    // estimated error left after the last sweep taken: its correction times
+    // the observed contraction, relative to max |phi*|
+    double lastrel = 0.0;
+    if (inblk && ref > 0.0) {
+        const double left = (had_prev && prev_last > 0.0) ? fmin(eny_last, eny_last * eny_last / prev_last) : eny_last;
+        lastrel = left / ref;
     }
 
     // edge traces of the remapped polynomial (eq. 2dx/2dy_bnd_interpolate):
