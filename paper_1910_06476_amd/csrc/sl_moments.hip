@@ -13,20 +13,25 @@ namespace sl {
 namespace {
 
 constexpr int kMomBlock = 256;
-constexpr int kMomMaxBlocks = 256;
+constexpr int kMomMaxBlocks = 2048;
 
 __global__ __launch_bounds__(kMomBlock) void k_moments(const double* __restrict__ phi, int64_t nf, int n, int dim,
                                                        const double* __restrict__ w, double* __restrict__ part)
 {
     __shared__ double sm[kMomBlock], se[kMomBlock];
-    const int64_t nd = dim == 1 ? n : (int64_t)n * n;
+    const int nd = dim == 1 ? n : n * n;
+    const int64_t stride = (int64_t)gridDim.x * kMomBlock;
+    const int step = (int)(stride % nd);  // the node index advances by this, modulo nd
+    int64_t g = (int64_t)blockIdx.x * kMomBlock + threadIdx.x;
+    int p = (int)(g % nd);
     double M = 0.0, E = 0.0;
-    for (int64_t g = (int64_t)blockIdx.x * kMomBlock + threadIdx.x; g < nf; g += (int64_t)gridDim.x * kMomBlock) {
-        const int p = (int)(g % nd);
+    for (; g < nf; g += stride) {
         const double W = dim == 1 ? w[p] : w[p % n] * w[p / n];
         const double v = phi[g];
         M = fma(W, v, M);
         E = fma(W * v, v, E);
+        p += step;
+        if (p >= nd) p -= nd;
     }
     sm[threadIdx.x] = M;
     se[threadIdx.x] = E;
