@@ -1659,8 +1659,22 @@ __global__ __launch_bounds__(kBlock2) void k_constrain2d_mixed(Step2DArgs A)
             if (n2 == N) {
                 other = tr2[k];
             } else {
-                const double* M = A.interp + f[MixFace::kInterpOff];
-                for (int q = 0; q < n2; ++q) other = fma(M[k * n2 + q], tr2[q], other);
+                // the interpolation in groups of 4 whose loads are independent (one
+                // latency per group): indices clamped to the row, terms past its
+                // end multiplied by zero (the same sum)
+                const double* M = A.interp + f[MixFace::kInterpOff] + k * n2;
+                for (int q0 = 0; q0 < n2; q0 += 4) {
+                    double mv[4], tv[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int q = q0 + u, qq = q < n2 ? q : n2 - 1;
+                        mv[u] = M[qq];
+                        tv[u] = tr2[qq];
+                        if (q >= n2) tv[u] = 0.0;
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) other = fma(mv[u], tv[u], other);
+                }
             }
             const double mine = A.rec[(size_t)ll * NB + tt];
             const double vn = A.vface[(size_t)ll * NB + tt];
