@@ -128,6 +128,12 @@ int launch_constrain2d(int n, const Step2DArgs& A, hipStream_t s)
     return o ? o->con(A, s) : 1;
 }
 
+int launch_targets2d(int n, const Step2DArgs& A, hipStream_t s)
+{
+    const Ops2D* o = ops2d(n);
+    return o ? o->tgt(A, s) : 1;
+}
+
 int launch_backtrace2d(int n, const Step2DArgs& A, hipStream_t s)
 {
     const Ops2D* o = ops2d(n);

@@ -62,7 +62,7 @@ __device__ __forceinline__ double cheb2(const double* __restrict__ C, double x, 
 // for particles inside their element); then (D+1)^2 FMAs per series against
 // Clenshaw's 2(D+1)^2, and the D+1 row sums of every series are independent
 // of each other.
-template <int N, int D, int NC>
+template <int N, int D, int NC, bool LEAN = false>
 __device__ __forceinline__ void cheb2_direct(const double* const (&C)[NC], double x, double y, double (&out)[NC])
 {
     static_assert(D < N, "degree");
@@ -78,29 +78,51 @@ __device__ __forceinline__ void cheb2_direct(const double* const (&C)[NC], doubl
         tx[k] = fma(x2, tx[k - 1], -tx[k - 2]);
         ty[k] = fma(y2, ty[k - 1], -ty[k - 2]);
     }
+    if constexpr (LEAN) {
+        // row by row: at most D + 1 coefficients of each series in flight
+        // (the unrolled sums load all of them at once, which in the
+        // backtraces held the kernels' registers); the same sums
+        double acc[NC];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-        double acc = 0.0;
-#pragma unroll
+        for (int c = 0; c < NC; ++c) acc[c] = 0.0;
+#pragma unroll 1
         for (int l = 0; l <= D; ++l) {
-            double row = 0.0;
+            const double tyl = l == 0 ? 1.0 : l == 1 ? y : ty[l];
 #pragma unroll
-            for (int k = 0; k <= D; ++k) row = fma(C[c][N * l + k], tx[k], row);
-            acc = fma(ty[l], row, acc);
+            for (int c = 0; c < NC; ++c) {
+                double row = 0.0;
+#pragma unroll
+                for (int k = 0; k <= D; ++k) row = fma(C[c][N * l + k], tx[k], row);
+                acc[c] = fma(tyl, row, acc[c]);
+            }
         }
-        out[c] = acc;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) out[c] = acc[c];
+    } else {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            double acc = 0.0;
+#pragma unroll
+            for (int l = 0; l <= D; ++l) {
+                double row = 0.0;
+#pragma unroll
+                for (int k = 0; k <= D; ++k) row = fma(C[c][N * l + k], tx[k], row);
+                acc = fma(ty[l], row, acc);
+            }
+            out[c] = acc;
+        }
     }
 }
 
 // the same at a run-time degree d: compile-time degrees up to 7 (the
 // effective degree of a resolved velocity), Clenshaw beyond
-template <int N, int NC>
+template <int N, int NC, bool LEAN = false>
 __device__ __forceinline__ void cheb2_eval(const double* const (&C)[NC], double x, double y, int d, double (&out)[NC])
 {
 #define SL_CHEB2_CASE(DD)                                         \
     if constexpr (N > DD)                                        \
         if (d == DD) {                                           \
-            cheb2_direct<N, DD, NC>(C, x, y, out);               \
+            cheb2_direct<N, DD, NC, LEAN>(C, x, y, out);         \
             return;                                              \
         }
     SL_CHEB2_CASE(0) SL_CHEB2_CASE(1) SL_CHEB2_CASE(2) SL_CHEB2_CASE(3)
@@ -302,14 +324,14 @@ __device__ double backtrace2(const Step2DArgs& A, const double* cu, const double
                 if (A.cons) {
                     const double* C3[3] = {cu, cv, cd};
                     double o[3];
-                    cheb2_eval<N, 3>(C3, x, y, A.vdeg, o);
+                    cheb2_eval<N, 3, true>(C3, x, y, A.vdeg, o);
                     ks[st] = -o[0] * A.invdx;
                     kr[st] = -o[1] * A.invdy;
                     kq[st] = -o[2] * qq;
                 } else {
                     const double* C2[2] = {cu, cv};
                     double o[2];
-                    cheb2_eval<N, 2>(C2, x, y, A.vdeg, o);
+                    cheb2_eval<N, 2, true>(C2, x, y, A.vdeg, o);
                     ks[st] = -o[0] * A.invdx;
                     kr[st] = -o[1] * A.invdy;
                     kq[st] = 0.0;
@@ -329,7 +351,9 @@ __device__ double backtrace2(const Step2DArgs& A, const double* cu, const double
     lag_row<N>(A.tab, s, ls);
     lag_row<N>(A.tab, r, lr);
     double acc = 0.0;
-#pragma unroll
+    // row by row: unrolled, the n^2 loads of f are invariant in a caller's
+    // loop over traces and were hoisted out of it, all held in registers
+#pragma unroll 1
     for (int j = 0; j < N; ++j) {
         double in = 0.0;
 #pragma unroll
@@ -638,28 +662,7 @@ __device__ __forceinline__ void advect2d_body(const Step2DArgs& A, const int bid
             cmean /= sw;
         }
         if (live && q == 0) rec[3 * NB + 2] = cmean;
-        // upwind edge points: stage sums of the backtraced values about c
-        for (int tt = q; live && tt < NB; tt += ND) {
-            const int side = tt / N, k = tt % N;
-            const double vn = A.vface[(size_t)e * NB + tt];
-            // e is upwind where the flow leaves it: left/bottom faces for
-            // vn < 0, right/top faces for vn > 0
-            const bool up = (side == 0 || side == 2) ? vn < 0.0 : vn > 0.0;
-            double fm = 0.0, fe = 0.0;
-            if (up) {
-                const double s = side == 0 ? 0.0 : side == 1 ? 1.0 : tab[O::XI + k];
-                const double r = side == 2 ? 0.0 : side == 3 ? 1.0 : tab[O::XI + k];
-                for (int c = 0; c < T.nq; ++c) {
-                    const double v =
-                        backtrace2<N>(A, s_cu[slot], s_cv[slot], s_cd[slot], s_x[slot], T.cu[c] * A.dt, s, r, out);
-                    const double dv = v - cmean;
-                    fm = fma(T.bu[c], dv, fm);
-                    fe = fma(T.bu[c], dv * dv, fe);
-                }
-            }
-            rec[NB + tt] = fm;
-            rec[2 * NB + tt] = fe;
-        }
+        // (the stage sums at the upwind edge points: k_targets2d)
         // local mass and deviation energy with the volume terms of the
         // balance laws: mass +div phi (advective form); deviation energy
         // +div psi^2 (advective), -div (psi^2 + 2 c psi) (conservative)
@@ -671,6 +674,7 @@ __device__ __forceinline__ void advect2d_body(const Step2DArgs& A, const int bid
             ce = Wp * dn * dn;
             if (A.vol && dv_p != 0.0) {
                 double vm = 0.0, vd = 0.0, ve = 0.0;
+#pragma unroll 1
                 for (int c = 0; c < T.nq; ++c) {
                     const double v = backtrace2<N>(A, s_cu[slot], s_cv[slot], s_cd[slot], s_x[slot],
                                                    T.cu[c] * A.dt, tab[O::XI + ii], tab[O::XI + jj], out);
@@ -1884,6 +1888,93 @@ int bt_n(const Step2DArgs& A, hipStream_t s)
     return hipGetLastError() == hipSuccess ? 0 : 1;
 }
 
+// The advect's mass and energy targets at the upwind edge points (eq. 4.14
+// with the energy about the element's mean), a launch of their own before
+// the advect kernel with targets, one lane per edge point as in
+// k_backtrace2d: for each of the tableau's distinct abscissae, phi^n at the
+// foot of the characteristic through the point, and the quadrature sums of
+// its deviation from the element's mean and of that deviation squared, into
+// the record's second and third 4n slots (zero at the other points).  The
+// same operations, in the same order, as in the advect, where these traces
+// held the kernel's registers (one or two waves per SIMD) with a third of
+// its lanes at work.
+template <int N>
+__global__ __launch_bounds__(kBlock2) void k_targets2d(Step2DArgs A)
+{
+    using O = Off2<N>;
+    constexpr int ND = N * N, NB = 4 * N, EB = kBlock2 / NB;
+    __shared__ double s_f[EB][ND], s_cu[EB][ND], s_cv[EB][ND], s_cd[EB][ND];
+    __shared__ double s_mean[EB];
+    __shared__ int s_flag;
+    const int t = threadIdx.x;
+    const int e0 = blockIdx.x * EB;
+    if (t == 0) s_flag = 0;
+    const size_t KND = (size_t)A.K * ND;
+    const double* __restrict__ tab = A.tab;
+    for (int k = t; k < EB * ND; k += kBlock2) {
+        const int le = k / ND, q = k - le * ND, e = e0 + le;
+        const bool live = e < A.K;
+        const size_t g = (size_t)(live ? e : 0) * ND + q;
+        const int ii = q % N, jj = q / N;
+        const bool used = live && ii <= A.vdeg && jj <= A.vdeg;
+        s_f[le][q] = live ? A.phi[g] : 0.0;
+        s_cu[le][q] = used ? A.aM[g] : 0.0;
+        s_cv[le][q] = used ? A.aM[KND + g] : 0.0;
+        s_cd[le][q] = (used && A.cons) ? A.divM[g] : 0.0;
+    }
+    __syncthreads();
+    // the element's mean at t^n, as the advect forms it
+    if (t < EB) {
+        double cmean = 0.0, sw = 0.0;
+        for (int pp = 0; pp < ND; ++pp) {
+            const double wq = tab[O::W + pp % N] * tab[O::W + pp / N];
+            cmean = fma(wq, s_f[t][pp], cmean);
+            sw += wq;
+        }
+        s_mean[t] = cmean / sw;
+    }
+    __syncthreads();
+    const RKTab& T = A.rk;
+    const int le = t / NB, tt = t - le * NB, e = e0 + le;
+    bool out = false;
+    if (le < EB && e < A.K) {
+        const int side = tt / N, k = tt % N;
+        const double vn = A.vface[(size_t)e * NB + tt];
+        // e is upwind where the flow leaves it: left/bottom faces for
+        // vn < 0, right/top faces for vn > 0
+        const bool up = (side == 0 || side == 2) ? vn < 0.0 : vn > 0.0;
+        double fm = 0.0, fe = 0.0;
+        if (up) {
+            const double cmean = s_mean[le];
+            const double s = side == 0 ? 0.0 : side == 1 ? 1.0 : tab[O::XI + k];
+            const double r = side == 2 ? 0.0 : side == 3 ? 1.0 : tab[O::XI + k];
+            // one trace at a time: interleaved, they would hold the registers of all
+#pragma unroll 1
+            for (int c = 0; c < T.nq; ++c) {
+                const double v = backtrace2<N>(A, s_cu[le], s_cv[le], s_cd[le], s_f[le], T.cu[c] * A.dt, s, r, out);
+                const double dv = v - cmean;
+                fm = fma(T.bu[c], dv, fm);
+                fe = fma(T.bu[c], dv * dv, fe);
+            }
+        }
+        double* rec = A.rec + (size_t)e * A.rstride;
+        rec[NB + tt] = fm;
+        rec[2 * NB + tt] = fe;
+    }
+    if (out) atomicOr(&s_flag, FLAG_CONTAIN);
+    __syncthreads();
+    // the advect kernel's flag slots; several blocks may share one
+    if (t == 0 && s_flag) atomicOr(&A.flag_part[blockIdx.x % A.nblk], s_flag);
+}
+
+template <int N>
+int tgt_n(const Step2DArgs& A, hipStream_t s)
+{
+    constexpr int EB = kBlock2 / (4 * N);
+    hipLaunchKernelGGL(k_targets2d<N>, dim3((A.K + EB - 1) / EB), dim3(kBlock2), 0, s, A);
+    return hipGetLastError() == hipSuccess ? 0 : 1;
+}
+
 template <int N>
 int facevel_mixed_n(int K_b, int bucket, int kx, int ky, const int32_t* elems, const int32_t* mix,
                     const double* aN_all, const double* tab_all, const double* interp, double vzero, double* vface,
@@ -1915,8 +2006,8 @@ int con_mixed_n(const Step2DArgs& A, hipStream_t s)
     namespace sl {                                                                                          \
     const Ops2D* ops2d_##N()                                                                                \
     {                                                                                                       \
-        static const Ops2D t = {prep_n<N>, facevel_n<N>, facevel_mixed_n<N>, con_mixed_n<N>,                \
-                                adv_n<N>,  con_n<N>,     bt_n<N>,           adv_batch_n<N>, con_batch_n<N>}; \
+        static const Ops2D t = {prep_n<N>, facevel_n<N>, facevel_mixed_n<N>, con_mixed_n<N>, adv_n<N>,      \
+                                con_n<N>,  bt_n<N>,      tgt_n<N>,           adv_batch_n<N>, con_batch_n<N>}; \
         return &t;                                                                                          \
     }                                                                                                       \
     }

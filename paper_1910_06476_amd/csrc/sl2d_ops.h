@@ -18,6 +18,7 @@ struct Ops2D {
     int (*adv)(const Step2DArgs& A, hipStream_t s);
     int (*con)(const Step2DArgs& A, hipStream_t s);
     int (*bt)(const Step2DArgs& A, hipStream_t s);
+    int (*tgt)(const Step2DArgs& A, hipStream_t s);
     int (*adv_batch)(const Step2DArgs& A0, const Step2DArgs* As, const int* start, int nreq, int nblocks,
                      hipStream_t s);
     int (*con_batch)(const Step2DArgs* As, const int* start, int nreq, int nblocks, hipStream_t s);

@@ -1131,6 +1131,7 @@ sl_status sl_step(sl_mesh* m, double dt, int32_t nsteps, const sl_step_opts* o)
         for (int s = 0; s < nsteps; ++s) {
             step_fields(m, &B);
             if (opt.iface == SL_IFACE_BACKTRACK && launch_backtrace2d(m->n, B, m->stream)) return SL_E_DEVICE;
+            if (B.targets && launch_targets2d(m->n, B, m->stream)) return SL_E_DEVICE;
             ev_begin(m, KER_ADV2D, true);
             if (launch_advect2d(m->n, B, m->stream)) return SL_E_DEVICE;
             ev_end(m, KER_ADV2D, true);

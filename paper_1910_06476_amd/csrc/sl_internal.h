@@ -279,6 +279,10 @@ int launch_advect2d(int n, const Step2DArgs& A, hipStream_t s);
 int launch_constrain2d(int n, const Step2DArgs& A, hipStream_t s);
 // backtracking interface values into the record's last 4n slots (A.phi is phi^n)
 int launch_backtrace2d(int n, const Step2DArgs& A, hipStream_t s);
+// the advect's mass and energy targets at the upwind edge points (the stage
+// sums of the backtraced values about the element's mean), a launch before
+// the advect kernel with targets
+int launch_targets2d(int n, const Step2DArgs& A, hipStream_t s);
 int blocks2d(int n, int K);
 
 // Batched 2D steps (boundary rows, interpolated face values, n >= 4): as
