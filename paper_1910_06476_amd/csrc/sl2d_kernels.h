@@ -364,8 +364,7 @@ __device__ double backtrace2(const Step2DArgs& A, const double* cu, const double
 }
 
 // ---------------------------------------------------------------------------
-// advect + remap (eq. 5.4 by defect correction) + edge traces, and with TGT
-// the local parts of the mass and energy targets
+// advect + remap (eq. 5.4 by defect correction) + edge traces
 //
 // One lane per particle (n^2 lanes per element, floor(256/n^2) elements per
 // block).  With PR = 1 the separable preconditioner is stored and applied in
@@ -374,13 +373,8 @@ __device__ double backtrace2(const Step2DArgs& A, const double* cu, const double
 // refinement).  PR = 0 is FP64 throughout.
 //
 // Record of element e (stride A.rstride): its 4n edge traces of phi-hat;
-// with TGT also, per edge point where e is upwind, sum_q bu_q (v_q - c) and
-// sum_q bu_q (v_q - c)^2 of the backtraced stage values v_q (4n each) about
-// the element's mean c at t^n, then M^n + dt sum_q bu_q V_q,
-// sum W (phi^n - c)^2 + dt sum_q bu_q V'_q with the volume terms V, V' of
-// the mass and deviation energy balance laws (eq. 4.14 generalised to the
-// RK quadrature), and c; with backtracking interface values, last, the 4n
-// face values it offers.
+// with mass or energy rows the 8n + 3 target terms of k_targets2d; with
+// backtracking interface values, last, the 4n face values it offers.
 // ---------------------------------------------------------------------------
 // block shapes of the advect kernel: 0 = 256 lanes, 1 = the fewest whole
 // waves that hold one element, 2 = 512 lanes.  With one element per block
@@ -585,7 +579,7 @@ __device__ __forceinline__ double resid_bcast(const double (&a)[N], const double
     return vx;
 }
 
-template <int N, int PR, bool TGT, int BSEL>
+template <int N, int PR, int BSEL>
 __device__ __forceinline__ void advect2d_body(const Step2DArgs& A, const int bid)
 {
     using O = Off2<N>;
@@ -622,7 +616,6 @@ __device__ __forceinline__ void advect2d_body(const Step2DArgs& A, const int bid
     if (t < E * 2) s_nrm[t / E][t % E] = 0ull;
     if (t < E) s_ref[t] = 0ull;
 
-    const bool need_div = A.cons || (TGT && A.vol);
     double phi_p = 0.0, u_p = 0.0, v_p = 0.0, dv_p = 0.0;
     {
         const size_t g = (size_t)(live ? e : 0) * ND + (inblk ? q : 0);
@@ -630,7 +623,7 @@ __device__ __forceinline__ void advect2d_body(const Step2DArgs& A, const int bid
             phi_p = A.phi[g];
             u_p = A.aN[g];
             v_p = A.aN[(size_t)K * ND + g];
-            if (need_div) dv_p = A.divN[g];
+            if (A.cons) dv_p = A.divN[g];
         }
         if (inblk) {
             // only the coefficients within the effective degree are read
@@ -638,71 +631,12 @@ __device__ __forceinline__ void advect2d_body(const Step2DArgs& A, const int bid
             s_cu[slot][q] = used ? A.aM[g] : 0.0;
             s_cv[slot][q] = used ? A.aM[(size_t)K * ND + g] : 0.0;
             if (A.cons) s_cd[slot][q] = used ? A.divM[g] : 0.0;
-            if (TGT) s_x[slot][q] = phi_p;  // phi^n for the backtraces
         }
     }
     __syncthreads();
 
     const RKTab& T = A.rk;
     bool out = false;
-
-    if constexpr (TGT) {
-        double* rec = A.rec + (size_t)(live ? e : 0) * A.rstride;
-        // the element's mean at t^n, c = M^n / sum W: the energy balance is
-        // taken for the deviation phi - c (the same law as for phi^2 in the
-        // PDE, computed from differences of like size)
-        double cmean = 0.0;
-        {
-            double sw = 0.0;
-            for (int pp = 0; pp < ND; ++pp) {
-                const double wq = tab[O::W + pp % N] * tab[O::W + pp / N];
-                cmean = fma(wq, s_x[sl][pp], cmean);
-                sw += wq;
-            }
-            cmean /= sw;
-        }
-        if (live && q == 0) rec[3 * NB + 2] = cmean;
-        // (the stage sums at the upwind edge points: k_targets2d)
-        // local mass and deviation energy with the volume terms of the
-        // balance laws: mass +div phi (advective form); deviation energy
-        // +div psi^2 (advective), -div (psi^2 + 2 c psi) (conservative)
-        double cm = 0.0, ce = 0.0;
-        if (live) {
-            const double Wp = A.dx * A.dy * tab[O::W + ii] * tab[O::W + jj];
-            const double dn = phi_p - cmean;
-            cm = Wp * phi_p;
-            ce = Wp * dn * dn;
-            if (A.vol && dv_p != 0.0) {
-                double vm = 0.0, vd = 0.0, ve = 0.0;
-#pragma unroll 1
-                for (int c = 0; c < T.nq; ++c) {
-                    const double v = backtrace2<N>(A, s_cu[slot], s_cv[slot], s_cd[slot], s_x[slot],
-                                                   T.cu[c] * A.dt, tab[O::XI + ii], tab[O::XI + jj], out);
-                    const double dv = v - cmean;
-                    vm = fma(T.bu[c], v, vm);
-                    vd = fma(T.bu[c], dv, vd);
-                    ve = fma(T.bu[c], dv * dv, ve);
-                }
-                if (!A.cons) cm += A.dt * Wp * dv_p * vm;
-                ce += A.dt * Wp * dv_p * (A.cons ? -fma(2.0 * cmean, vd, ve) : ve);
-            }
-        }
-        if (inblk) {
-            s_r[slot][q] = cm;
-            s_f[slot][q] = ce;
-        }
-        __syncthreads();
-        if (live && q == 0) {
-            double M = 0.0, En = 0.0;
-            for (int p = 0; p < ND; ++p) {
-                M += s_r[slot][p];
-                En += s_f[slot][p];
-            }
-            rec[3 * NB] = M;
-            rec[3 * NB + 1] = En;
-        }
-        __syncthreads();  // s_x, s_r, s_f are reused below
-    }
 
     // forward motion of the particle (eq. 5.1 tensor interpolant of the velocity)
     const int d = A.vdeg;
@@ -995,10 +929,10 @@ __device__ __forceinline__ void advect2d_body(const Step2DArgs& A, const int bid
     }
 }
 
-template <int N, int PR, bool TGT, int BSEL = 0>
+template <int N, int PR, int BSEL = 0>
 __global__ __launch_bounds__((Shape2<N, BSEL>::BS)) void k_advect2d(Step2DArgs A)
 {
-    advect2d_body<N, PR, TGT, BSEL>(A, blockIdx.x);
+    advect2d_body<N, PR, BSEL>(A, blockIdx.x);
 }
 
 // One step of several meshes in one launch: the blocks of request r are
@@ -1009,7 +943,7 @@ __global__ __launch_bounds__((Shape2<N, BSEL>::BS)) void k_advect2d_batch(const 
                                                                           const int* __restrict__ start, int nreq)
 {
     const int r = batch_request(start, nreq, blockIdx.x);
-    advect2d_body<N, PR, false, BSEL>(As[r], blockIdx.x - start[r]);
+    advect2d_body<N, PR, BSEL>(As[r], blockIdx.x - start[r]);
 }
 
 // ---------------------------------------------------------------------------
@@ -1726,8 +1660,7 @@ int facevel_n(int kx, int ky, int periodic, const double* aN, const double* tab,
 template <int N, int PR>
 void adv_launch(const Step2DArgs& A, dim3 grid, hipStream_t s)
 {
-    if (A.targets) launch_timed((k_advect2d<N, PR, true>), grid, dim3(kBlock2), 0, s, A);
-    else launch_timed((k_advect2d<N, PR, false>), grid, dim3(kBlock2), 0, s, A);
+    launch_timed((k_advect2d<N, PR>), grid, dim3(kBlock2), 0, s, A);
 }
 
 // Every block of an advect or constrain launch owns a row of the per-block
@@ -1739,18 +1672,18 @@ int adv_shape(const Step2DArgs& A, hipStream_t s)
     using S = Shape2<N, BSEL>;
     const int grid = (A.K + S::E - 1) / S::E;
     if (grid > A.nblk) return 1;
-    launch_timed((k_advect2d<N, 0, false, BSEL>), dim3(grid), dim3(S::BS), 0, s, A);
+    launch_timed((k_advect2d<N, 0, BSEL>), dim3(grid), dim3(S::BS), 0, s, A);
     return hipGetLastError() == hipSuccess ? 0 : 1;
 }
 
 template <int N>
 int adv_n(const Step2DArgs& A, hipStream_t s)
 {
-    // the alternative block shapes exist for the FP64 boundary-rows kernel
-    if (A.bs != 0 && A.precision == SL_PREC_FP64 && !A.targets)
+    // the alternative block shapes exist for the FP64 kernel
+    if (A.bs != 0 && A.precision == SL_PREC_FP64)
         return A.bs == 1 ? adv_shape<N, 1>(A, s) : adv_shape<N, 2>(A, s);
-    // the 256-lane shape (and the reduced-precision and target variants,
-    // which exist for it only) holds no element above 16 nodes per direction
+    // the 256-lane shape (and the reduced-precision variants, which exist
+    // for it only) holds no element above 16 nodes per direction
     if constexpr (N * N > kBlock2) {
         return 1;
     } else {
@@ -1888,22 +1821,33 @@ int bt_n(const Step2DArgs& A, hipStream_t s)
     return hipGetLastError() == hipSuccess ? 0 : 1;
 }
 
-// The advect's mass and energy targets at the upwind edge points (eq. 4.14
-// with the energy about the element's mean), a launch of their own before
-// the advect kernel with targets, one lane per edge point as in
-// k_backtrace2d: for each of the tableau's distinct abscissae, phi^n at the
-// foot of the characteristic through the point, and the quadrature sums of
-// its deviation from the element's mean and of that deviation squared, into
-// the record's second and third 4n slots (zero at the other points).  The
-// same operations, in the same order, as in the advect, where these traces
-// held the kernel's registers (one or two waves per SIMD) with a third of
-// its lanes at work.
+// The local parts of the mass and energy targets (eq. 4.14 with the energy
+// taken for the deviation from the element's mean, generalised to the RK
+// quadrature), a launch of their own before the advect with mass or energy
+// rows; EB = floor(256 / 4n) elements per block, one lane per edge point.
+// Into record slots of element e, after its 4n edge traces:
+//   [4n, 8n)   per edge point where e is upwind, sum_q bu_q (v_q - c), and
+//   [8n, 12n)  sum_q bu_q (v_q - c)^2, of phi^n at the foot v_q of the
+//              characteristic through the point for each of the tableau's
+//              distinct abscissae, about the element's mean c at t^n (zero
+//              at the other points);
+//   12n        M^n + dt sum_q bu_q V_q,
+//   12n + 1    sum W (phi^n - c)^2 + dt sum_q bu_q V'_q, with the volume
+//              terms V, V' of the mass and deviation energy balance laws
+//              (mass: +div phi in advective form; deviation energy: +div psi^2
+//              advective, -div (psi^2 + 2 c psi) conservative), each node's
+//              share summed in node order;
+//   12n + 2    c.
+// In the advect these backtraces held the kernel's registers (two waves per
+// SIMD in place of four) for every step with targets, whether the flow has
+// volume terms or not.
 template <int N>
 __global__ __launch_bounds__(kBlock2) void k_targets2d(Step2DArgs A)
 {
     using O = Off2<N>;
     constexpr int ND = N * N, NB = 4 * N, EB = kBlock2 / NB;
     __shared__ double s_f[EB][ND], s_cu[EB][ND], s_cv[EB][ND], s_cd[EB][ND];
+    __shared__ double s_m[EB][ND], s_e[EB][ND];
     __shared__ double s_mean[EB];
     __shared__ int s_flag;
     const int t = threadIdx.x;
@@ -1923,7 +1867,8 @@ __global__ __launch_bounds__(kBlock2) void k_targets2d(Step2DArgs A)
         s_cd[le][q] = (used && A.cons) ? A.divM[g] : 0.0;
     }
     __syncthreads();
-    // the element's mean at t^n, as the advect forms it
+    // the element's mean at t^n, c = M^n / sum W: the energy balance is
+    // taken for the deviation phi - c, computed from differences of like size
     if (t < EB) {
         double cmean = 0.0, sw = 0.0;
         for (int pp = 0; pp < ND; ++pp) {
@@ -1936,33 +1881,78 @@ __global__ __launch_bounds__(kBlock2) void k_targets2d(Step2DArgs A)
     __syncthreads();
     const RKTab& T = A.rk;
     const int le = t / NB, tt = t - le * NB, e = e0 + le;
+    const bool live = le < EB && e < A.K;
     bool out = false;
-    if (le < EB && e < A.K) {
-        const int side = tt / N, k = tt % N;
-        const double vn = A.vface[(size_t)e * NB + tt];
-        // e is upwind where the flow leaves it: left/bottom faces for
-        // vn < 0, right/top faces for vn > 0
-        const bool up = (side == 0 || side == 2) ? vn < 0.0 : vn > 0.0;
-        double fm = 0.0, fe = 0.0;
-        if (up) {
-            const double cmean = s_mean[le];
-            const double s = side == 0 ? 0.0 : side == 1 ? 1.0 : tab[O::XI + k];
-            const double r = side == 2 ? 0.0 : side == 3 ? 1.0 : tab[O::XI + k];
-            // one trace at a time: interleaved, they would hold the registers of all
+    if (live) {
+        const double cmean = s_mean[le];
+        double* rec = A.rec + (size_t)e * A.rstride;
+        // work items of lane tt: its edge point, then the nodes tt, tt + 4n, ...
+        // (one backtrace call site for both: two would hold the registers of both)
 #pragma unroll 1
-            for (int c = 0; c < T.nq; ++c) {
-                const double v = backtrace2<N>(A, s_cu[le], s_cv[le], s_cd[le], s_f[le], T.cu[c] * A.dt, s, r, out);
-                const double dv = v - cmean;
-                fm = fma(T.bu[c], dv, fm);
-                fe = fma(T.bu[c], dv * dv, fe);
+        for (int it = tt; it < NB + ND; it += NB) {
+            const bool edge = it < NB;
+            const int q = edge ? 0 : it - NB;
+            const int ii = q % N, jj = q / N;
+            double s, r, dv_p = 0.0;
+            bool act;
+            if (edge) {
+                const int side = tt / N, k = tt % N;
+                const double vn = A.vface[(size_t)e * NB + tt];
+                // e is upwind where the flow leaves it: left/bottom faces
+                // for vn < 0, right/top faces for vn > 0
+                act = (side == 0 || side == 2) ? vn < 0.0 : vn > 0.0;
+                s = side == 0 ? 0.0 : side == 1 ? 1.0 : tab[O::XI + k];
+                r = side == 2 ? 0.0 : side == 3 ? 1.0 : tab[O::XI + k];
+            } else {
+                // volume terms where the velocity has a divergence at the node
+                if (A.vol) dv_p = A.divN[(size_t)e * ND + q];
+                act = dv_p != 0.0;
+                s = tab[O::XI + ii];
+                r = tab[O::XI + jj];
+            }
+            double vm = 0.0, vd = 0.0, ve = 0.0;
+            if (act) {
+                // one trace at a time: interleaved, they would hold the registers of all
+#pragma unroll 1
+                for (int c = 0; c < T.nq; ++c) {
+                    const double v = backtrace2<N>(A, s_cu[le], s_cv[le], s_cd[le], s_f[le], T.cu[c] * A.dt, s, r, out);
+                    const double dv = v - cmean;
+                    vm = fma(T.bu[c], v, vm);
+                    vd = fma(T.bu[c], dv, vd);
+                    ve = fma(T.bu[c], dv * dv, ve);
+                }
+            }
+            if (edge) {
+                rec[NB + tt] = vd;
+                rec[2 * NB + tt] = ve;
+            } else {
+                // the node's share of the local mass and deviation energy
+                const double phi_p = s_f[le][q];
+                const double Wp = A.dx * A.dy * tab[O::W + ii] * tab[O::W + jj];
+                const double dn = phi_p - cmean;
+                double cm = Wp * phi_p, ce = Wp * dn * dn;
+                if (act) {
+                    if (!A.cons) cm += A.dt * Wp * dv_p * vm;
+                    ce += A.dt * Wp * dv_p * (A.cons ? -fma(2.0 * cmean, vd, ve) : ve);
+                }
+                s_m[le][q] = cm;
+                s_e[le][q] = ce;
             }
         }
-        double* rec = A.rec + (size_t)e * A.rstride;
-        rec[NB + tt] = fm;
-        rec[2 * NB + tt] = fe;
     }
     if (out) atomicOr(&s_flag, FLAG_CONTAIN);
     __syncthreads();
+    if (t < EB && e0 + t < A.K) {
+        double M = 0.0, En = 0.0;
+        for (int p = 0; p < ND; ++p) {
+            M += s_m[t][p];
+            En += s_e[t][p];
+        }
+        double* rec = A.rec + (size_t)(e0 + t) * A.rstride;
+        rec[3 * NB] = M;
+        rec[3 * NB + 1] = En;
+        rec[3 * NB + 2] = s_mean[t];
+    }
     // the advect kernel's flag slots; several blocks may share one
     if (t == 0 && s_flag) atomicOr(&A.flag_part[blockIdx.x % A.nblk], s_flag);
 }

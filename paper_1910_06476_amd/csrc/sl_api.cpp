@@ -1021,11 +1021,11 @@ void args2d(const sl_mesh* m, double dt, const sl_step_opts& opt, Step2DArgs* Bp
     B.vol = B.targets && (B.cons ? (opt.constraints & SL_C_ENERGY) != 0 : 1);
     B.rstride = (B.targets ? 12 * m->n + 3 : 4 * m->n) + (opt.iface == SL_IFACE_BACKTRACK ? 4 * m->n : 0);
     // from n = 12 on one element fills a 256-lane block only to 66% or
-    // less: the advect (FP64, boundary rows) takes the block of the
-    // fewest whole waves that hold one element instead (192 lanes at
-    // n = 13; measured 13% faster).  A block then still holds one
-    // element, so the per-block partials stay sized as they are.
-    B.bs = (m->n >= 12 && m->precision == SL_PREC_FP64 && !B.targets) ? 1 : 0;
+    // less: the advect (FP64) takes the block of the fewest whole waves
+    // that hold one element instead (192 lanes at n = 13; measured 13%
+    // faster).  A block then still holds one element, so the per-block
+    // partials stay sized as they are.
+    B.bs = (m->n >= 12 && m->precision == SL_PREC_FP64) ? 1 : 0;
     B.sumW = 0.0;
     for (int j = 0; j < m->n; ++j)
         for (int i = 0; i < m->n; ++i) B.sumW += m->dx * m->dy * m->T.w[i] * m->T.w[j];

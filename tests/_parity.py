@@ -15,7 +15,9 @@ def opts_dict(w, **over):
     return d
 
 
-def run_gpu(w, phi0=None, nsteps=None, precision=0, ghost=None, **over):
+def run_gpu(w, phi0=None, nsteps=None, precision=0, ghost=None, div=None, **over):
+    """div: nodal divergence handed to the mesh, or None (the derivative of
+    the velocity's interpolant, formed on the device)."""
     import paper_1910_06476_amd as P
     nsteps = w.nsteps if nsteps is None else nsteps
     u0 = w.initial() if phi0 is None else phi0
@@ -23,7 +25,7 @@ def run_gpu(w, phi0=None, nsteps=None, precision=0, ghost=None, **over):
                x0=w.x0, x1=w.x1, y0=w.y0, y1=w.y1)
     try:
         a, _ = w.velocity()
-        m.set_velocity(a)
+        m.set_velocity(a, div)
         if w.bc != W.PERIODIC:
             m.set_ghost(w.ghost_rows(0.0, nsteps) if ghost is None else ghost)
         m.step(w.dt, nsteps, **opts_dict(w, **over))
@@ -33,7 +35,7 @@ def run_gpu(w, phi0=None, nsteps=None, precision=0, ghost=None, **over):
     return out, st, rc
 
 
-def run_oracle(w, phi0=None, nsteps=None, ghost=None, want=None, **over):
+def run_oracle(w, phi0=None, nsteps=None, ghost=None, want=None, div=None, **over):
     nsteps = w.nsteps if nsteps is None else nsteps
     u0 = w.initial() if phi0 is None else phi0
     kw = {}
@@ -55,7 +57,7 @@ def run_oracle(w, phi0=None, nsteps=None, ghost=None, want=None, **over):
     g = None
     if w.bc != W.PERIODIC:
         g = w.ghost_rows(0.0, nsteps) if ghost is None else ghost
-    return oracle.step(p, u0, a=a, ghost=g, dt=w.dt, nsteps=nsteps, want=want)
+    return oracle.step(p, u0, a=a, div=div, ghost=g, dt=w.dt, nsteps=nsteps, want=want)
 
 
 def rel_l2(x, ref):
