@@ -16,9 +16,9 @@ roofline of the dominant kernel (HIP events on the mesh's stream around
 every launch, algorithmic flop count per element from the functions below),
 and the CPU oracle timed on a bounded sample.  Other workloads: --workload
 c2 (the 1D configuration with boundary, mass and energy rows), c3 (2D
-rotation, --precision fp64 / fp32r / bf16r), c2bw (HBM probe), c1 (launch
-latency), serve (a Poisson stream of independent problems through the
-request loop).
+rotation, --precision fp64 / fp32r / bf16r, --constraints b / bm / bme),
+c2bw (HBM probe), c1 (launch latency), serve (a Poisson stream of
+independent problems through the request loop).
 """
 from __future__ import annotations
 
@@ -141,7 +141,9 @@ def native_oracle():
     return oracle
 
 
-def cpu_baseline(w, budget_s: float = 12.0):
+def cpu_baseline(w, budget_s: float = 12.0, div=None):
+    """The oracle on the full mesh of `w` (div: the nodal divergence the
+    device was given, else None for the interpolant's)."""
     import workloads as W
     oracle = native_oracle()
     p = oracle.params_from(w)
@@ -149,16 +151,16 @@ def cpu_baseline(w, budget_s: float = 12.0):
     phi = w.initial()
     ghost = w.bc != W.PERIODIC  # inflow rows from the exact solution, as on the device
     t0 = time.perf_counter()
-    phi, _ = oracle.step(p, phi, a=a, ghost=w.ghost_rows(0.0, 1) if ghost else None, dt=w.dt, nsteps=1)
+    phi, _ = oracle.step(p, phi, a=a, div=div, ghost=w.ghost_rows(0.0, 1) if ghost else None, dt=w.dt, nsteps=1)
     one = time.perf_counter() - t0
     steps = max(1, min(50, int(budget_s / max(one, 1e-3))))
     g = w.ghost_rows(w.dt, steps) if ghost else None
     t0 = time.perf_counter()
-    oracle.step(p, phi, a=a, ghost=g, dt=w.dt, nsteps=steps)
+    oracle.step(p, phi, a=a, div=div, ghost=g, dt=w.dt, nsteps=steps)
     el = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     g1 = w.ghost_rows(0.0, 1) if ghost else None
-    one_thread = single_thread_rate(lambda: oracle.step(p, phi, a=a, ghost=g1, dt=w.dt, nsteps=1), w.dofs,
+    one_thread = single_thread_rate(lambda: oracle.step(p, phi, a=a, div=div, ghost=g1, dt=w.dt, nsteps=1), w.dofs,
                                     el / steps * cores)
     return {"value": w.dofs * steps / el, "unit": "DOF-updates/s", "cores": cores, "kind": "oracle",
             "single_thread_value": one_thread,
@@ -267,18 +269,30 @@ def avg_us(acc, k):
     return t / max(c, 1) * 1e3
 
 
+C3_ROWS = {"b": ("boundary HARD", "B"), "bm": ("boundary+mass HARD", "B+M"),
+           "bme": ("boundary+mass+energy HARD, energy stop 1e-8", "B+M+E")}
+
+
 def bench_c3(args, torch, P, W, stream):
-    """2D rotation workload (256x256, order 8, RK4, ghost inflow, boundary HARD)."""
+    """2D rotation workload (256x256, order 8, RK4, ghost inflow), boundary
+    rows HARD, or with --constraints bm / bme also the mass (and energy)
+    rows: their targets kernel backtraces phi^n from the upwind edge points
+    (and from every node where the divergence is nonzero).  The mesh gets
+    the flow's exact divergence, zero."""
     w = W.c3(nsteps=args.warmup + args.steps)
+    w.cmask = {"b": W.BOUNDARY, "bm": W.BOUNDARY | W.MASS, "bme": W.BOUNDARY | W.MASS | W.ENERGY}[args.constraints]
     prec = {"fp64": P.SL_PREC_FP64, "fp32r": P.SL_PREC_FP32_REFINED, "bf16r": P.SL_PREC_BF16_REFINED}[args.precision]
     m = P.from_workload(w, stream=stream.cuda_stream, precision=prec)
+    a, div = w.velocity()
+    m.set_velocity(a, div)
+    targets = args.constraints != "b"
     nprof = max(5, min(args.steps, 20))
     nlat = min(100, max(10, args.steps))
     # inflow rows for every step the run takes (and one more time level)
     m.set_ghost(w.ghost_rows(0.0, args.warmup + args.steps + 2 * nprof + nlat + 2))
-    opts = dict(rk=w.rk, constraints=w.cmask, mode=w.mode)
+    opts = dict(rk=w.rk, constraints=w.cmask, mode=w.mode, energy_maxit=w.energy_maxit, energy_tol=w.energy_tol)
     m.step(w.dt, args.warmup, **opts)
-    kinds = [P.KER_ADV2D, P.KER_CON2D]
+    kinds = [P.KER_ADV2D, P.KER_CON2D] + ([P.KER_TGT2D] if targets else [])
     acc = profiled_window(P, m, w.dt, nprof, opts, kinds)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -301,8 +315,9 @@ def bench_c3(args, torch, P, W, stream):
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": el / args.steps * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "2D rotation a=(-(y-1/2),x-1/2) on [0,1]^2, 256x256, order 8 (81 nodes/elem), "
-                               "Gaussian hill, RK4, ghost inflow from the exact solution, boundary HARD",
-                   "K": w.K, "n": w.n, "dofs": w.dofs, "dt": w.dt},
+                               "Gaussian hill, RK4, ghost inflow from the exact solution, " + C3_ROWS[args.constraints][0],
+                   "K": w.K, "n": w.n, "dofs": w.dofs, "dt": w.dt, "constraints": C3_ROWS[args.constraints][1],
+                   "divergence": "exact (zero)"},
         "l2_error": l2, "l2_time": T, "status": P.status_string(rc), "precision": args.precision,
         "step_latency": lat,
         "remap_sweeps_mean": sweeps, "remap_sweeps_max": st.remap_sweeps_max, "refine_resid": st.refine_resid,
@@ -310,12 +325,15 @@ def bench_c3(args, torch, P, W, stream):
         "roofline": {"kernel": "sl2d_advect", "bound": "alu", "achieved": ach / 1e12,
                      "peak": FP64_VALU_PEAK / 1e12, "unit": "TFLOP/s", "frac": ach / FP64_VALU_PEAK,
                      "traffic": measured_traffic("k_advect2d", "sl2d_kernels.h", "sl2d_c3_256x256_n9.md")
-                     if args.precision == "fp64" else None,
+                     if args.precision == "fp64" and not targets else None,
                      "avg_launch_us": adv_avg * 1e6, "algorithmic_flops_per_launch": fl,
                      "kernels_us": {"sl2d_advect": adv_avg * 1e6, "sl2d_constrain": con_avg * 1e6}},
     }
+    if targets:
+        out["roofline"]["kernels_us"]["sl2d_targets"] = avg_us(acc, P.KER_TGT2D)
+        out["max_picard"] = st.max_picard
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(w)
+        out["cpu_baseline"] = cpu_baseline(w, div=div)
     print(json.dumps(out))
 
 
@@ -775,6 +793,8 @@ def main():
     ap.add_argument("--requests", type=int, default=48, help="serve: number of requests")
     ap.add_argument("--slots", type=int, default=8, help="serve: requests on the device at once")
     ap.add_argument("--budget-gib", type=float, default=32.0, help="serve: device memory budget")
+    ap.add_argument("--constraints", choices=["b", "bm", "bme"], default="b",
+                    help="c3: boundary rows (default), + mass, + mass and energy (HARD)")
     ap.add_argument("--precision", choices=["fp64", "fp32r", "bf16r"], default="fp64",
                     help="c3 and c4: fp32r stores and applies the remap preconditioner in FP32, bf16r with BF16 "
                          "entries and operands and FP32 sums (FP64 residuals in both)")

@@ -239,7 +239,9 @@ sl_status sl_device_field(sl_mesh* m, double** d_phi, void** stream);
  * since the last reset: 0 = 1D advect, 1 = 1D constrain, 2 = 2D advect+solve
  * (a mixed-order mesh: its whole step), 3 = 2D constrain, 4 + b = the
  * advect+solve of bucket b of a mixed-order mesh, 20 + b = its constrain
- * (buckets in ascending order, b < 16).  Errors: SL_E_INVALID. */
+ * (buckets in ascending order, b < 16), 36 = the 2D targets of mass and
+ * energy rows, 37 = the 2D face backtraces of SL_IFACE_BACKTRACK (uniform
+ * 2D meshes).  Errors: SL_E_INVALID. */
 sl_status sl_set_profiling(sl_mesh* m, int32_t enable);
 sl_status sl_kernel_time(sl_mesh* m, int32_t which, double* total_ms, int64_t* launches);
 

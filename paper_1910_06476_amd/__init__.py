@@ -30,6 +30,7 @@ SL_IFACE_INTERP, SL_IFACE_BACKTRACK = 0, 1
 SL_SERVER_NO_BATCH = 1
 KER_ADV1D, KER_CON1D, KER_ADV2D, KER_CON2D = 0, 1, 2, 3
 KER_MIX_ADV, KER_MIX_CON = 4, 20  # + bucket index (mixed-order meshes)
+KER_TGT2D, KER_BT2D = 36, 37  # uniform 2D: mass/energy targets, face backtraces
 
 EXPORTS = ["sl_create_mesh", "sl_set_velocity", "sl_set_ghost", "sl_ghost_count", "sl_step", "sl_read",
            "sl_destroy_mesh", "sl_status_string", "sl_max_dt", "sl_node_coords", "sl_device_field",

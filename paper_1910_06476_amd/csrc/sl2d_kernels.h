@@ -1817,7 +1817,7 @@ template <int N>
 int bt_n(const Step2DArgs& A, hipStream_t s)
 {
     constexpr int EB = kBlock2 / (4 * N);
-    hipLaunchKernelGGL(k_backtrace2d<N>, dim3((A.K + EB - 1) / EB), dim3(kBlock2), 0, s, A);
+    launch_timed(k_backtrace2d<N>, dim3((A.K + EB - 1) / EB), dim3(kBlock2), 0, s, A);
     return hipGetLastError() == hipSuccess ? 0 : 1;
 }
 
@@ -1847,14 +1847,17 @@ __global__ __launch_bounds__(kBlock2) void k_targets2d(Step2DArgs A)
     using O = Off2<N>;
     constexpr int ND = N * N, NB = 4 * N, EB = kBlock2 / NB;
     __shared__ double s_f[EB][ND], s_cu[EB][ND], s_cv[EB][ND], s_cd[EB][ND];
-    __shared__ double s_m[EB][ND], s_e[EB][ND];
-    __shared__ double s_mean[EB];
+    __shared__ double s_m[EB][ND], s_e[EB][ND], s_dv[EB][ND];
+    __shared__ double s_mean[EB], s_tw[N], s_txi[N];  // + the weights and nodes
     __shared__ int s_flag;
     const int t = threadIdx.x;
     const int e0 = blockIdx.x * EB;
     if (t == 0) s_flag = 0;
+    if (t < N) {
+        s_tw[t] = A.tab[O::W + t];
+        s_txi[t] = A.tab[O::XI + t];
+    }
     const size_t KND = (size_t)A.K * ND;
-    const double* __restrict__ tab = A.tab;
     for (int k = t; k < EB * ND; k += kBlock2) {
         const int le = k / ND, q = k - le * ND, e = e0 + le;
         const bool live = e < A.K;
@@ -1865,6 +1868,7 @@ __global__ __launch_bounds__(kBlock2) void k_targets2d(Step2DArgs A)
         s_cu[le][q] = used ? A.aM[g] : 0.0;
         s_cv[le][q] = used ? A.aM[KND + g] : 0.0;
         s_cd[le][q] = (used && A.cons) ? A.divM[g] : 0.0;
+        s_dv[le][q] = (live && A.vol) ? A.divN[g] : 0.0;
     }
     __syncthreads();
     // the element's mean at t^n, c = M^n / sum W: the energy balance is
@@ -1872,7 +1876,7 @@ __global__ __launch_bounds__(kBlock2) void k_targets2d(Step2DArgs A)
     if (t < EB) {
         double cmean = 0.0, sw = 0.0;
         for (int pp = 0; pp < ND; ++pp) {
-            const double wq = tab[O::W + pp % N] * tab[O::W + pp / N];
+            const double wq = s_tw[pp % N] * s_tw[pp / N];
             cmean = fma(wq, s_f[t][pp], cmean);
             sw += wq;
         }
@@ -1901,14 +1905,14 @@ __global__ __launch_bounds__(kBlock2) void k_targets2d(Step2DArgs A)
                 // e is upwind where the flow leaves it: left/bottom faces
                 // for vn < 0, right/top faces for vn > 0
                 act = (side == 0 || side == 2) ? vn < 0.0 : vn > 0.0;
-                s = side == 0 ? 0.0 : side == 1 ? 1.0 : tab[O::XI + k];
-                r = side == 2 ? 0.0 : side == 3 ? 1.0 : tab[O::XI + k];
+                s = side == 0 ? 0.0 : side == 1 ? 1.0 : s_txi[k];
+                r = side == 2 ? 0.0 : side == 3 ? 1.0 : s_txi[k];
             } else {
                 // volume terms where the velocity has a divergence at the node
-                if (A.vol) dv_p = A.divN[(size_t)e * ND + q];
+                dv_p = s_dv[le][q];
                 act = dv_p != 0.0;
-                s = tab[O::XI + ii];
-                r = tab[O::XI + jj];
+                s = s_txi[ii];
+                r = s_txi[jj];
             }
             double vm = 0.0, vd = 0.0, ve = 0.0;
             if (act) {
@@ -1928,7 +1932,7 @@ __global__ __launch_bounds__(kBlock2) void k_targets2d(Step2DArgs A)
             } else {
                 // the node's share of the local mass and deviation energy
                 const double phi_p = s_f[le][q];
-                const double Wp = A.dx * A.dy * tab[O::W + ii] * tab[O::W + jj];
+                const double Wp = A.dx * A.dy * s_tw[ii] * s_tw[jj];
                 const double dn = phi_p - cmean;
                 double cm = Wp * phi_p, ce = Wp * dn * dn;
                 if (act) {
@@ -1960,9 +1964,15 @@ __global__ __launch_bounds__(kBlock2) void k_targets2d(Step2DArgs A)
 template <int N>
 int tgt_n(const Step2DArgs& A, hipStream_t s)
 {
-    constexpr int EB = kBlock2 / (4 * N);
-    hipLaunchKernelGGL(k_targets2d<N>, dim3((A.K + EB - 1) / EB), dim3(kBlock2), 0, s, A);
-    return hipGetLastError() == hipSuccess ? 0 : 1;
+    // mass and energy rows are taken up to 16 nodes per direction (the
+    // constrain kernel's one lane per node)
+    if constexpr (N * N > kBlock2) {
+        return 1;
+    } else {
+        constexpr int EB = kBlock2 / (4 * N);
+        launch_timed(k_targets2d<N>, dim3((A.K + EB - 1) / EB), dim3(kBlock2), 0, s, A);
+        return hipGetLastError() == hipSuccess ? 0 : 1;
+    }
 }
 
 template <int N>

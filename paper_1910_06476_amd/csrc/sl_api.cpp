@@ -1130,8 +1130,16 @@ sl_status sl_step(sl_mesh* m, double dt, int32_t nsteps, const sl_step_opts* o)
         args2d(m, dt, opt, &B);
         for (int s = 0; s < nsteps; ++s) {
             step_fields(m, &B);
-            if (opt.iface == SL_IFACE_BACKTRACK && launch_backtrace2d(m->n, B, m->stream)) return SL_E_DEVICE;
-            if (B.targets && launch_targets2d(m->n, B, m->stream)) return SL_E_DEVICE;
+            if (opt.iface == SL_IFACE_BACKTRACK) {
+                ev_begin(m, KER_BT2D, true);
+                if (launch_backtrace2d(m->n, B, m->stream)) return SL_E_DEVICE;
+                ev_end(m, KER_BT2D, true);
+            }
+            if (B.targets) {
+                ev_begin(m, KER_TGT2D, true);
+                if (launch_targets2d(m->n, B, m->stream)) return SL_E_DEVICE;
+                ev_end(m, KER_TGT2D, true);
+            }
             ev_begin(m, KER_ADV2D, true);
             if (launch_advect2d(m->n, B, m->stream)) return SL_E_DEVICE;
             ev_end(m, KER_ADV2D, true);

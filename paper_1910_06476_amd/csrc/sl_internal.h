@@ -56,11 +56,13 @@ struct RKTab {
 bool rk_tableau(int order, RKTab* T);
 
 // timed kernels (sl_kernel_time): the uniform-mesh kernels, the whole step of
-// a mixed-order mesh (KER_ADV2D), and per bucket b its advect (KER_MIX_ADV +
-// b) and constrain (KER_MIX_CON + b) launches
+// a mixed-order mesh (KER_ADV2D), per bucket b its advect (KER_MIX_ADV + b)
+// and constrain (KER_MIX_CON + b) launches, and the uniform 2D mesh's
+// targets (KER_TGT2D) and face backtrace (KER_BT2D) launches
 enum {
     KER_ADV1D = 0, KER_CON1D = 1, KER_ADV2D = 2, KER_CON2D = 3,
-    KER_MIX_ADV = 4, KER_MIX_CON = 4 + kMaxBuckets, KER_COUNT = 4 + 2 * kMaxBuckets
+    KER_MIX_ADV = 4, KER_MIX_CON = 4 + kMaxBuckets, KER_TGT2D = 4 + 2 * kMaxBuckets, KER_BT2D = KER_TGT2D + 1,
+    KER_COUNT = KER_BT2D + 1
 };
 enum { FLAG_NONFINITE = 1, FLAG_CONTAIN = 2, FLAG_SINGULAR = 4, FLAG_NOCONV = 8 };
 

@@ -24,14 +24,14 @@ def _need_gpu():
     P.lib()
 
 
-def _run(w, nsteps, kinds, profiling, mixed=False, ghost=False):
+def _run(w, nsteps, kinds, profiling, mixed=False, ghost=False, **over):
     import torch
     import paper_1910_06476_amd as P
     m = P.from_mixed_workload(w) if mixed else P.from_workload(w)
     try:
         if ghost:
             m.set_ghost(w.ghost_rows(0.0, nsteps))
-        opts = dict(rk=w.rk, constraints=W.BOUNDARY, mode=w.mode) if mixed else opts_dict(w)
+        opts = dict(rk=w.rk, constraints=W.BOUNDARY, mode=w.mode) if mixed else opts_dict(w, **over)
         if profiling:
             P.sl_set_profiling(m.h, True)
         torch.cuda.synchronize()
@@ -45,9 +45,9 @@ def _run(w, nsteps, kinds, profiling, mixed=False, ghost=False):
     return np.asarray(out), rc, times, wall_ms
 
 
-def _check(w, nsteps, kinds, mixed=False, ghost=False):
-    a, rc_a, _, _ = _run(w, nsteps, kinds, False, mixed, ghost)
-    b, rc_b, times, wall = _run(w, nsteps, kinds, True, mixed, ghost)
+def _check(w, nsteps, kinds, mixed=False, ghost=False, **over):
+    a, rc_a, _, _ = _run(w, nsteps, kinds, False, mixed, ghost, **over)
+    b, rc_b, times, wall = _run(w, nsteps, kinds, True, mixed, ghost, **over)
     assert rc_a == rc_b == 0
     assert np.array_equal(a, b)
     total = 0.0
@@ -70,6 +70,14 @@ def test_profiled_2d_steps():
     w = W.c3(kx=16, nsteps=5)
     announce("profiling 2D 16x16 n=9 ghost inflow 5 steps")
     _check(w, 5, [P.KER_ADV2D, P.KER_CON2D], ghost=True)
+
+
+def test_profiled_2d_targets_and_backtraces():
+    import paper_1910_06476_amd as P
+    w = W.c3(kx=16, nsteps=5)
+    w.cmask = W.BOUNDARY | W.MASS | W.ENERGY
+    announce("profiling 2D 16x16 n=9 B+M+E backtracked faces 5 steps")
+    _check(w, 5, [P.KER_ADV2D, P.KER_CON2D, P.KER_TGT2D, P.KER_BT2D], ghost=True, iface=P.SL_IFACE_BACKTRACK)
 
 
 def test_profiled_mixed_steps():
