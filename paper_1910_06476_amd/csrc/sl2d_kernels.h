@@ -1184,7 +1184,8 @@ __global__ __launch_bounds__(kBlock2) void k_constrain2d_batch(const Step2DArgs*
 // Woodbury for SOFT (Q = (I + C_B C_B^T)^{-1}), i.e. the paper's stacked
 // least squares.  Without boundary rows P = I and base = phi-hat.  P W is a
 // per-mesh table.
-// One block handles floor(256/n^2) elements, one lane per node.
+// Persistent: each block takes chunks of floor(256/n^2) elements (one lane
+// per node), blockIdx.x, blockIdx.x + gridDim.x, ..., with Q staged once.
 // ---------------------------------------------------------------------------
 template <int N>
 __global__ __launch_bounds__(kBlock2) void k_constrain2d_me(Step2DArgs A)
@@ -1205,9 +1206,6 @@ __global__ __launch_bounds__(kBlock2) void k_constrain2d_me(Step2DArgs A)
     const int slot = t / ND, p = t - slot * ND;
     const bool inblk = slot < E;
     const int sl = inblk ? slot : 0;
-    const int e = blockIdx.x * E + slot;
-    const bool live = inblk && e < A.K;
-    const int ee = live ? e : 0;
     const double* __restrict__ tab = A.tab;
     const bool bnd = (A.cmask & SL_C_BOUNDARY) != 0;
     const bool mass = (A.cmask & SL_C_MASS) != 0;
@@ -1224,242 +1222,262 @@ __global__ __launch_bounds__(kBlock2) void k_constrain2d_me(Step2DArgs A)
     const int i = p % N, j = p / N;
     const double l0i = tab[O::L0 + i], l1i = tab[O::L1 + i], l0j = tab[O::L0 + j], l1j = tab[O::L1 + j];
     const double Wp = A.dx * A.dy * tab[O::W + i] * tab[O::W + j];
-    const double* rec = A.rec + (size_t)ee * A.rstride;
-    const double ph = live ? A.phihat[(size_t)ee * ND + p] : 0.0;
-    const double cme = rec[3 * NB + 2];  // the element's mean at t^n
-
-    // face values (eq. 4.12a) and the face terms of the targets: inflow
-    // positive, the upwind side's stage sums (own, neighbour's or ghost)
-    const RKTab& T = A.rk;
-    for (int tt = p; inblk && tt < NB; tt += ND) {
-        int nbe, nbt, gidx;
-        bool high;
-        face_partner2<N>(ee, tt, A.kx, A.ky, A.periodic, nbe, nbt, gidx, high);
-        const double vn = A.vface[(size_t)ee * NB + tt];
-        // offered face values: the traces, or with backtracking the record's
-        // last NB slots
-        const int fo = A.iface == SL_IFACE_BACKTRACK ? A.rstride - NB : 0;
-        const double mine = rec[fo + tt];
-        const double other = nbe >= 0 ? A.rec[(size_t)nbe * A.rstride + fo + nbt] : A.gnext[gidx];
-        s_fv[slot][tt] = upwind2(vn, high ? other : mine, high ? mine : other);
-        double fm = 0.0, fe = 0.0;
-        if (vn != 0.0) {
-            const bool up = high ? vn < 0.0 : vn > 0.0;
-            // sum_q b_q v_q and sum_q b_q (v_q - c)^2 about this element's
-            // mean c; a neighbour's sums are about its own mean c', so with
-            // delta = c' - c: S2 + delta (2 S1 + delta) and S1 + c'
-            double sm, se;
-            if (up) {
-                sm = rec[NB + tt] + cme;
-                se = rec[2 * NB + tt];
-            } else if (nbe >= 0) {
-                const double* rn = A.rec + (size_t)nbe * A.rstride;
-                const double s1 = rn[NB + nbt], cn = rn[3 * NB + 2], dl = cn - cme;
-                sm = s1 + cn;
-                se = fma(dl, fma(2.0, s1, dl), rn[2 * NB + nbt]);
-            } else {
-                // inflow from outside: ghost values, linear in time
-                sm = se = 0.0;
-                for (int c = 0; c < T.nq; ++c) {
-                    const double g = (1.0 - T.cu[c]) * A.gnow[gidx] + T.cu[c] * A.gnext[gidx];
-                    sm = fma(T.bu[c], g, sm);
-                    se = fma(T.bu[c], (g - cme) * (g - cme), se);
-                }
-            }
-            const int side = tt / N, k = tt % N;
-            const double fw = (side < 2 ? A.dy : A.dx) * tab[O::W + k];
-            const double sg = high ? vn : -vn;
-            fm = sg * fw * sm;
-            fe = sg * fw * se;
-        }
-        s_tr[slot][tt] = fm;
-        s_w[slot][tt] = fe;
-    }
-    __syncthreads();
-    if (live && p == 0) {
-        double fm = 0.0, fe = 0.0;
-        for (int tt = 0; tt < NB; ++tt) {
-            fm += s_tr[slot][tt];
-            fe += s_w[slot][tt];
-        }
-        const double Mn = rec[3 * NB] + A.dt * fm, Ed = rec[3 * NB + 1] + A.dt * fe;
-        s_tgt[slot][0] = Mn;
-        s_tgt[slot][1] = Ed;
-        s_tgt[slot][2] = Ed + cme * (2.0 * Mn - cme * A.sumW);
-    }
-    __syncthreads();
-    // M^{n+1}, the deviation energy Ed^{n+1} = sum W (phi - c)^2 and the
-    // energy E^{n+1} = Ed + 2 c M - c^2 sum W of phi^2
-    const double Mt = s_tgt[sl][0], Edt = s_tgt[sl][1], Et = s_tgt[sl][2];
-
-    // element-wise sums of up to NDOT per-node values, in a fixed order
-    auto dots = [&](int k, const double* vals) {
-        if (inblk)
-            for (int c = 0; c < k; ++c) s_red[slot][c][p] = vals[c];
-        __syncthreads();
-        for (int c = p; inblk && c < k; c += ND) {
-            double s = 0.0;
-            for (int r = 0; r < ND; ++r) s += s_red[slot][c][r];
-            s_dot[slot][c] = s;
-        }
-        __syncthreads();
-    };
-    // C_B^T Q (h - C_B v) at this node, v in s_v; h = d_B (face values) or 0
-    auto cbt_q = [&](bool with_data) -> double {
-        for (int tt = p; inblk && tt < NB; tt += ND) {
-            const int side = tt / N, k = tt % N;
-            const double* lv = tab + ((side & 1) ? O::L1 : O::L0);
-            double tr = 0.0;
-            if (side < 2)
-                for (int c = 0; c < N; ++c) tr = fma(lv[c], s_v[slot][c + N * k], tr);
-            else
-                for (int c = 0; c < N; ++c) tr = fma(lv[c], s_v[slot][k + N * c], tr);
-            s_tr[slot][tt] = (with_data ? s_fv[slot][tt] : 0.0) - tr;
-        }
-        __syncthreads();
-        for (int tt = p; inblk && tt < NB; tt += ND) {
-            double z = 0.0;
-#pragma unroll 8
-            for (int c = 0; c < NB; ++c) z = fma(s_q[tt * NB + c], s_tr[slot][c], z);
-            s_w[slot][tt] = z;
-        }
-        __syncthreads();
-        const double r = l0i * s_w[sl][j] + l1i * s_w[sl][N + j] + l0j * s_w[sl][2 * N + i] +
-                         l1j * s_w[sl][3 * N + i];
-        __syncthreads();  // s_v, s_tr, s_w are rewritten by the next call
-        return r;
-    };
-
-    // boundary rows: base = phihat + C_B^T Q (d_B - C_B phihat)
-    double base = ph;
-    if (bnd) {
-        if (inblk) s_v[slot][p] = ph;
-        __syncthreads();
-        base = ph + cbt_q(true);
-    }
     // mass row: Z_M = P W from the table (P W is W without boundary rows)
     const double zm = bnd ? A.dx * A.dy * tab[(soft ? O::ZMS : O::ZMH) + p] : Wp;
-    const double shift = soft ? 1.0 : 0.0;
+    const int nchunk = (A.K + E - 1) / E;
     int fl = 0;
-    double gb = 0.0, gz = 0.0;
-    double cur = base;
-    if (mass) {
-        const double v[2] = {Wp * base, Wp * zm};
-        dots(2, v);
-        gb = s_dot[sl][0];
-        gz = s_dot[sl][1];
-        const double S = gz + shift;
-        if (!(S != 0.0) || !isfinite(S)) fl |= FLAG_SINGULAR;
-        cur = base + zm * ((Mt - gb) / S);
-    }
-    double prev = cur;
-    int picard = 0;
-    // the energy row (section "Local energy conservation").  SOFT: the
-    // paper's linearisation sum W phi^(k-1) phi = E^{n+1}, stacked.  HARD:
-    // its fixed point, reached by Newton's linearisation of the same row,
-    // written for y = phi - sh with the target Tt:
-    //   sum W y^(k-1) y = (Tt + sum W (y^(k-1))^2) / 2,
-    // with a mass row as the deviation from the element's mean (sh = c,
-    // Tt = Ed^{n+1}: the same constraint on the mass row's level set),
-    // otherwise sh = 0, Tt = E^{n+1}.  Stop when max |phi^(k) - phi^(k-1)|
-    // < tol (strict, as printed).  Where the linearised row lies in the span
-    // of the others the sweep makes no change (singular if the row is not
-    // met).
-    const bool devf = !soft && mass;
-    const double sh = devf ? cme : 0.0;
-    if (energy) {
-        const double Tt = devf ? Edt : Et;
-        bool done = !live, conv = false;
-        for (int k = 1; k <= A.emaxit; ++k) {
-            const double yv = prev - sh;
-            const double gE = Wp * yv;
-            if (inblk) s_v[slot][p] = gE;
-            __syncthreads();
-            const double zE = bnd ? gE + cbt_q(false) : gE;
-            double sig_m = 0.0, sig_e = 0.0, numer;
-            bool ok;
-            if (mass) {
-                const double v[5] = {Wp * zE, gE * zm, gE * zE, gE * (base - sh), gE * yv};
-                dots(5, v);
-                const double a11 = gz + shift, a12 = s_dot[sl][0], a21 = s_dot[sl][1], a22 = s_dot[sl][2] + shift;
-                const double r1 = Mt - gb;
-                const double r2 = (soft ? Et : 0.5 * (Tt + s_dot[sl][4])) - s_dot[sl][3];
-                const double det = a11 * a22 - a12 * a21;
-                numer = a11 * r2 - a21 * r1;
-                ok = det != 0.0 && isfinite(det);
-                sig_m = ok ? (r1 * a22 - a12 * r2) / det : 0.0;
-                sig_e = ok ? numer / det : 0.0;
-            } else {
-                const double v[3] = {gE * zE, gE * (base - sh), gE * yv};
-                dots(3, v);
-                const double S = s_dot[sl][0] + shift;
-                numer = (soft ? Et : 0.5 * (Tt + s_dot[sl][2])) - s_dot[sl][1];
-                ok = S != 0.0 && isfinite(S);
-                sig_e = ok ? numer / S : 0.0;
-            }
-            const double nxt = ok ? base + zm * sig_m + zE * sig_e : prev;
-            const bool act = inblk && !done;
-            if (act && !ok && numer != 0.0) fl |= FLAG_SINGULAR;
-            if constexpr (ND >= 64) {
-                slot_max<E, 2>(&s_mx[0][0], slot, act ? abs_bits(nxt - prev) : 0ull);
-            } else if (act) {
-                atomicMax(&s_mx[slot][0], abs_bits(nxt - prev));
-            }
-            __syncthreads();
-            if (inblk && !done) {
-                const double diff = __longlong_as_double((long long)s_mx[slot][0]);
-                prev = nxt;
-                picard = k;
-                if (diff < A.etol) {
-                    conv = true;
-                    done = true;
-                }
-            }
-            const bool all = __syncthreads_and(done);
-            if (t < 2 * E) s_mx[t / 2][t % 2] = 0ull;
-            __syncthreads();
-            if (all) break;
-        }
-        if (live && !conv && A.etol > 0.0) fl |= FLAG_NOCONV;
-    }
 
-    // store, residuals: boundary (traces of phi vs the face values), mass,
-    // energy
-    const double phi = prev;
-    if (live) {
-        if (!isfinite(phi)) fl |= FLAG_NONFINITE;
-        A.phi_out[(size_t)e * ND + p] = phi;
-    }
-    if (inblk) s_v[slot][p] = phi;
-    {
-        // energy residual of the row as imposed: HARD with a mass row in the
-        // deviation form, otherwise sum W phi^2 against E^{n+1}
-        const double v[2] = {Wp * phi, Wp * (phi - sh) * (phi - sh)};
-        dots(2, v);  // its first barrier also publishes s_v
-    }
-    unsigned long long rmax = 0ull;  // this lane's largest boundary-row residual
-    if (live) {
-        for (int tt = p; bnd && tt < NB; tt += ND) {
-            const int side = tt / N, k = tt % N;
-            const double* lv = tab + ((side & 1) ? O::L1 : O::L0);
-            double tr = 0.0;
-            if (side < 2)
-                for (int c = 0; c < N; ++c) tr = fma(lv[c], s_v[slot][c + N * k], tr);
-            else
-                for (int c = 0; c < N; ++c) tr = fma(lv[c], s_v[slot][k + N * c], tr);
-            const unsigned long long r = abs_bits(tr - s_fv[slot][tt]);
-            rmax = r > rmax ? r : rmax;
+    // persistent: chunks of E elements, blockIdx.x + c gridDim.x for c = 0, 1, ...
+    for (int chunk = blockIdx.x; chunk < nchunk; chunk += gridDim.x) {
+        const int e = chunk * E + slot;
+        const bool live = inblk && e < A.K;
+        const int ee = live ? e : 0;
+        const double* rec = A.rec + (size_t)ee * A.rstride;
+        const double ph = live ? A.phihat[(size_t)ee * ND + p] : 0.0;
+        const double cme = rec[3 * NB + 2];  // the element's mean at t^n
+
+        // the element's local mass and deviation energy terms, loaded with the
+        // face data below: every load of the chunk is issued before the first
+        // wait (one memory latency per chunk)
+        const double Mloc = rec[3 * NB], Eloc = rec[3 * NB + 1];
+
+        // face values (eq. 4.12a) and the face terms of the targets: inflow
+        // positive, the upwind side's stage sums (own, neighbour's or ghost)
+        const RKTab& T = A.rk;
+        for (int tt = p; inblk && tt < NB; tt += ND) {
+            int nbe, nbt, gidx;
+            bool high;
+            face_partner2<N>(ee, tt, A.kx, A.ky, A.periodic, nbe, nbt, gidx, high);
+            const double vn = A.vface[(size_t)ee * NB + tt];
+            // offered face values: the traces, or with backtracking the record's
+            // last NB slots
+            const int fo = A.iface == SL_IFACE_BACKTRACK ? A.rstride - NB : 0;
+            const double mine = rec[fo + tt];
+            const double other = nbe >= 0 ? A.rec[(size_t)nbe * A.rstride + fo + nbt] : A.gnext[gidx];
+            // both sides' stage sums, whichever is upwind: the choice waits
+            // for vn, the loads do not
+            const double* rn = A.rec + (size_t)(nbe >= 0 ? nbe : ee) * A.rstride;
+            const double s1o = rec[NB + tt], s2o = rec[2 * NB + tt];
+            const double s1n = rn[NB + nbt], s2n = rn[2 * NB + nbt], cn = rn[3 * NB + 2];
+            const double g0 = nbe >= 0 ? 0.0 : A.gnow[gidx];
+            const double fwt = tab[O::W + tt % N];
+            s_fv[slot][tt] = upwind2(vn, high ? other : mine, high ? mine : other);
+            double fm = 0.0, fe = 0.0;
+            if (vn != 0.0) {
+                const bool up = high ? vn < 0.0 : vn > 0.0;
+                // sum_q b_q v_q and sum_q b_q (v_q - c)^2 about this element's
+                // mean c; a neighbour's sums are about its own mean c', so with
+                // delta = c' - c: S2 + delta (2 S1 + delta) and S1 + c'
+                double sm, se;
+                if (up) {
+                    sm = s1o + cme;
+                    se = s2o;
+                } else if (nbe >= 0) {
+                    const double dl = cn - cme;
+                    sm = s1n + cn;
+                    se = fma(dl, fma(2.0, s1n, dl), s2n);
+                } else {
+                    // inflow from outside: ghost values, linear in time
+                    sm = se = 0.0;
+                    for (int c = 0; c < T.nq; ++c) {
+                        const double g = (1.0 - T.cu[c]) * g0 + T.cu[c] * other;
+                        sm = fma(T.bu[c], g, sm);
+                        se = fma(T.bu[c], (g - cme) * (g - cme), se);
+                    }
+                }
+                const int side = tt / N;
+                const double fw = (side < 2 ? A.dy : A.dx) * fwt;
+                const double sg = high ? vn : -vn;
+                fm = sg * fw * sm;
+                fe = sg * fw * se;
+            }
+            s_tr[slot][tt] = fm;
+            s_w[slot][tt] = fe;
         }
-    }
-    slot_max<1>(&s_stat[0], 0, rmax);  // one block-wide slot: one atomic per wave
-    if (live) {
-        if (p == 0) {
-            if (mass) atomicMax(&s_stat[1], (unsigned long long)__double_as_longlong(fabs(s_dot[slot][0] - Mt)));
-            if (energy)
-                atomicMax(&s_stat[2],
-                          (unsigned long long)__double_as_longlong(fabs(s_dot[slot][1] - (devf ? Edt : Et))));
-            atomicMax(&s_pic, picard);
+        __syncthreads();
+        if (live && p == 0) {
+            double fm = 0.0, fe = 0.0;
+            for (int tt = 0; tt < NB; ++tt) {
+                fm += s_tr[slot][tt];
+                fe += s_w[slot][tt];
+            }
+            const double Mn = Mloc + A.dt * fm, Ed = Eloc + A.dt * fe;
+            s_tgt[slot][0] = Mn;
+            s_tgt[slot][1] = Ed;
+            s_tgt[slot][2] = Ed + cme * (2.0 * Mn - cme * A.sumW);
         }
+        __syncthreads();
+        // M^{n+1}, the deviation energy Ed^{n+1} = sum W (phi - c)^2 and the
+        // energy E^{n+1} = Ed + 2 c M - c^2 sum W of phi^2
+        const double Mt = s_tgt[sl][0], Edt = s_tgt[sl][1], Et = s_tgt[sl][2];
+
+        // element-wise sums of up to NDOT per-node values, in a fixed order
+        auto dots = [&](int k, const double* vals) {
+            if (inblk)
+                for (int c = 0; c < k; ++c) s_red[slot][c][p] = vals[c];
+            __syncthreads();
+            for (int c = p; inblk && c < k; c += ND) {
+                double s = 0.0;
+                for (int r = 0; r < ND; ++r) s += s_red[slot][c][r];
+                s_dot[slot][c] = s;
+            }
+            __syncthreads();
+        };
+        // C_B^T Q (h - C_B v) at this node, v in s_v; h = d_B (face values) or 0
+        auto cbt_q = [&](bool with_data) -> double {
+            for (int tt = p; inblk && tt < NB; tt += ND) {
+                const int side = tt / N, k = tt % N;
+                const double* lv = tab + ((side & 1) ? O::L1 : O::L0);
+                double tr = 0.0;
+                if (side < 2)
+                    for (int c = 0; c < N; ++c) tr = fma(lv[c], s_v[slot][c + N * k], tr);
+                else
+                    for (int c = 0; c < N; ++c) tr = fma(lv[c], s_v[slot][k + N * c], tr);
+                s_tr[slot][tt] = (with_data ? s_fv[slot][tt] : 0.0) - tr;
+            }
+            __syncthreads();
+            for (int tt = p; inblk && tt < NB; tt += ND) {
+                double z = 0.0;
+    #pragma unroll 8
+                for (int c = 0; c < NB; ++c) z = fma(s_q[tt * NB + c], s_tr[slot][c], z);
+                s_w[slot][tt] = z;
+            }
+            __syncthreads();
+            const double r = l0i * s_w[sl][j] + l1i * s_w[sl][N + j] + l0j * s_w[sl][2 * N + i] +
+                             l1j * s_w[sl][3 * N + i];
+            __syncthreads();  // s_v, s_tr, s_w are rewritten by the next call
+            return r;
+        };
+
+        // boundary rows: base = phihat + C_B^T Q (d_B - C_B phihat)
+        double base = ph;
+        if (bnd) {
+            if (inblk) s_v[slot][p] = ph;
+            __syncthreads();
+            base = ph + cbt_q(true);
+        }
+        const double shift = soft ? 1.0 : 0.0;
+        double gb = 0.0, gz = 0.0;
+        double cur = base;
+        if (mass) {
+            const double v[2] = {Wp * base, Wp * zm};
+            dots(2, v);
+            gb = s_dot[sl][0];
+            gz = s_dot[sl][1];
+            const double S = gz + shift;
+            if (!(S != 0.0) || !isfinite(S)) fl |= FLAG_SINGULAR;
+            cur = base + zm * ((Mt - gb) / S);
+        }
+        double prev = cur;
+        int picard = 0;
+        // the energy row (section "Local energy conservation").  SOFT: the
+        // paper's linearisation sum W phi^(k-1) phi = E^{n+1}, stacked.  HARD:
+        // its fixed point, reached by Newton's linearisation of the same row,
+        // written for y = phi - sh with the target Tt:
+        //   sum W y^(k-1) y = (Tt + sum W (y^(k-1))^2) / 2,
+        // with a mass row as the deviation from the element's mean (sh = c,
+        // Tt = Ed^{n+1}: the same constraint on the mass row's level set),
+        // otherwise sh = 0, Tt = E^{n+1}.  Stop when max |phi^(k) - phi^(k-1)|
+        // < tol (strict, as printed).  Where the linearised row lies in the span
+        // of the others the sweep makes no change (singular if the row is not
+        // met).
+        const bool devf = !soft && mass;
+        const double sh = devf ? cme : 0.0;
+        if (energy) {
+            const double Tt = devf ? Edt : Et;
+            bool done = !live, conv = false;
+            for (int k = 1; k <= A.emaxit; ++k) {
+                const double yv = prev - sh;
+                const double gE = Wp * yv;
+                if (inblk) s_v[slot][p] = gE;
+                __syncthreads();
+                const double zE = bnd ? gE + cbt_q(false) : gE;
+                double sig_m = 0.0, sig_e = 0.0, numer;
+                bool ok;
+                if (mass) {
+                    const double v[5] = {Wp * zE, gE * zm, gE * zE, gE * (base - sh), gE * yv};
+                    dots(5, v);
+                    const double a11 = gz + shift, a12 = s_dot[sl][0], a21 = s_dot[sl][1], a22 = s_dot[sl][2] + shift;
+                    const double r1 = Mt - gb;
+                    const double r2 = (soft ? Et : 0.5 * (Tt + s_dot[sl][4])) - s_dot[sl][3];
+                    const double det = a11 * a22 - a12 * a21;
+                    numer = a11 * r2 - a21 * r1;
+                    ok = det != 0.0 && isfinite(det);
+                    sig_m = ok ? (r1 * a22 - a12 * r2) / det : 0.0;
+                    sig_e = ok ? numer / det : 0.0;
+                } else {
+                    const double v[3] = {gE * zE, gE * (base - sh), gE * yv};
+                    dots(3, v);
+                    const double S = s_dot[sl][0] + shift;
+                    numer = (soft ? Et : 0.5 * (Tt + s_dot[sl][2])) - s_dot[sl][1];
+                    ok = S != 0.0 && isfinite(S);
+                    sig_e = ok ? numer / S : 0.0;
+                }
+                const double nxt = ok ? base + zm * sig_m + zE * sig_e : prev;
+                const bool act = inblk && !done;
+                if (act && !ok && numer != 0.0) fl |= FLAG_SINGULAR;
+                if constexpr (ND >= 64) {
+                    slot_max<E, 2>(&s_mx[0][0], slot, act ? abs_bits(nxt - prev) : 0ull);
+                } else if (act) {
+                    atomicMax(&s_mx[slot][0], abs_bits(nxt - prev));
+                }
+                __syncthreads();
+                if (inblk && !done) {
+                    const double diff = __longlong_as_double((long long)s_mx[slot][0]);
+                    prev = nxt;
+                    picard = k;
+                    if (diff < A.etol) {
+                        conv = true;
+                        done = true;
+                    }
+                }
+                const bool all = __syncthreads_and(done);
+                if (t < 2 * E) s_mx[t / 2][t % 2] = 0ull;
+                __syncthreads();
+                if (all) break;
+            }
+            if (live && !conv && A.etol > 0.0) fl |= FLAG_NOCONV;
+        }
+
+        // store, residuals: boundary (traces of phi vs the face values), mass,
+        // energy
+        const double phi = prev;
+        if (live) {
+            if (!isfinite(phi)) fl |= FLAG_NONFINITE;
+            A.phi_out[(size_t)e * ND + p] = phi;
+        }
+        if (inblk) s_v[slot][p] = phi;
+        {
+            // energy residual of the row as imposed: HARD with a mass row in the
+            // deviation form, otherwise sum W phi^2 against E^{n+1}
+            const double v[2] = {Wp * phi, Wp * (phi - sh) * (phi - sh)};
+            dots(2, v);  // its first barrier also publishes s_v
+        }
+        unsigned long long rmax = 0ull;  // this lane's largest boundary-row residual
+        if (live) {
+            for (int tt = p; bnd && tt < NB; tt += ND) {
+                const int side = tt / N, k = tt % N;
+                const double* lv = tab + ((side & 1) ? O::L1 : O::L0);
+                double tr = 0.0;
+                if (side < 2)
+                    for (int c = 0; c < N; ++c) tr = fma(lv[c], s_v[slot][c + N * k], tr);
+                else
+                    for (int c = 0; c < N; ++c) tr = fma(lv[c], s_v[slot][k + N * c], tr);
+                const unsigned long long r = abs_bits(tr - s_fv[slot][tt]);
+                rmax = r > rmax ? r : rmax;
+            }
+        }
+        slot_max<1>(&s_stat[0], 0, rmax);  // one block-wide slot: one atomic per wave
+        if (live) {
+            if (p == 0) {
+                if (mass) atomicMax(&s_stat[1], (unsigned long long)__double_as_longlong(fabs(s_dot[slot][0] - Mt)));
+                if (energy)
+                    atomicMax(&s_stat[2],
+                              (unsigned long long)__double_as_longlong(fabs(s_dot[slot][1] - (devf ? Edt : Et))));
+                atomicMax(&s_pic, picard);
+            }
+        }
+        __syncthreads();  // the chunk's shared rows are rewritten by the next
     }
     if (fl) atomicOr(&s_flag, fl);
     __syncthreads();
@@ -1717,7 +1735,9 @@ int con_n(const Step2DArgs& A, hipStream_t s)
             constexpr int E = kBlock2 / (N * N);
             const int nchunk = (A.K + E - 1) / E;
             if (nchunk > A.nblk) return 1;
-            launch_timed(k_constrain2d_me<N>, dim3(nchunk), dim3(kBlock2), 0, s, A);
+            static std::atomic<int> cap_me[kMaxDevices];
+            const int r = resident_blocks(k_constrain2d_me<N>, cap_me);
+            launch_timed(k_constrain2d_me<N>, dim3(con_grid(nchunk, r, A.nblk)), dim3(kBlock2), 0, s, A);
             return hipGetLastError() == hipSuccess ? 0 : 1;
         }
     }
