@@ -1861,8 +1861,11 @@ int bt_n(const Step2DArgs& A, hipStream_t s)
 // In the advect these backtraces held the kernel's registers (two waves per
 // SIMD in place of four) for every step with targets, whether the flow has
 // volume terms or not.
+// Three waves per SIMD (at most 168 VGPRs, a few spilled slots at n = 9):
+// C3 with mass rows 300 -> 266 us against two waves at 235 VGPRs; at four
+// waves the spills cost more than the occupancy gains (376 us).
 template <int N>
-__global__ __launch_bounds__(kBlock2) void k_targets2d(Step2DArgs A)
+__global__ __launch_bounds__(kBlock2, 3) void k_targets2d(Step2DArgs A)
 {
     using O = Off2<N>;
     constexpr int ND = N * N, NB = 4 * N, EB = kBlock2 / NB;
@@ -1939,6 +1942,9 @@ __global__ __launch_bounds__(kBlock2) void k_targets2d(Step2DArgs A)
                 // one trace at a time: interleaved, they would hold the registers of all
 #pragma unroll 1
                 for (int c = 0; c < T.nq; ++c) {
+                    // no LDS value is kept in registers from one trace to
+                    // the next (they would be held through all of them)
+                    __asm__ __volatile__("" ::: "memory");
                     const double v = backtrace2<N>(A, s_cu[le], s_cv[le], s_cd[le], s_f[le], T.cu[c] * A.dt, s, r, out);
                     const double dv = v - cmean;
                     vm = fma(T.bu[c], v, vm);
