@@ -62,7 +62,7 @@ __device__ __forceinline__ double cheb2(const double* __restrict__ C, double x, 
 // for particles inside their element); then (D+1)^2 FMAs per series against
 // Clenshaw's 2(D+1)^2, and the D+1 row sums of every series are independent
 // of each other.
-template <int N, int D, int NC, bool LEAN = false>
+template <int N, int D, int NC, int LR = 0>
 __device__ __forceinline__ void cheb2_direct(const double* const (&C)[NC], double x, double y, double (&out)[NC])
 {
     static_assert(D < N, "degree");
@@ -78,22 +78,35 @@ __device__ __forceinline__ void cheb2_direct(const double* const (&C)[NC], doubl
         tx[k] = fma(x2, tx[k - 1], -tx[k - 2]);
         ty[k] = fma(y2, ty[k - 1], -ty[k - 2]);
     }
-    if constexpr (LEAN) {
-        // row by row: at most D + 1 coefficients of each series in flight
-        // (the unrolled sums load all of them at once, which in the
-        // backtraces held the kernels' registers); the same sums
+    if constexpr (LR > 0) {
+        // LR rows at a time: at most LR (D + 1) coefficients of each series
+        // in flight (the unrolled sums load all of them at once, which in
+        // the backtraces held the kernels' registers, and for coefficients
+        // read through the scalar cache took more scalar registers than
+        // there are); the same sums.  T_l(y) is carried by its recurrence
+        // from T_0 = 1 and T_{-1} = y (then T_1 = 2y - y = y exactly), the
+        // same values as ty[].
         double acc[NC];
 #pragma unroll
         for (int c = 0; c < NC; ++c) acc[c] = 0.0;
+        double tyl = 1.0, tym = y;
 #pragma unroll 1
-        for (int l = 0; l <= D; ++l) {
-            const double tyl = l == 0 ? 1.0 : l == 1 ? y : ty[l];
+        for (int l0 = 0; l0 <= D; l0 += LR) {
 #pragma unroll
-            for (int c = 0; c < NC; ++c) {
-                double row = 0.0;
+            for (int r = 0; r < LR; ++r) {
+                const int l = l0 + r;
+                if (l <= D) {
 #pragma unroll
-                for (int k = 0; k <= D; ++k) row = fma(C[c][N * l + k], tx[k], row);
-                acc[c] = fma(tyl, row, acc[c]);
+                    for (int c = 0; c < NC; ++c) {
+                        double row = 0.0;
+#pragma unroll
+                        for (int k = 0; k <= D; ++k) row = fma(C[c][N * l + k], tx[k], row);
+                        acc[c] = fma(tyl, row, acc[c]);
+                    }
+                    const double tyn = fma(y2, tyl, -tym);
+                    tym = tyl;
+                    tyl = tyn;
+                }
             }
         }
 #pragma unroll
@@ -116,13 +129,13 @@ __device__ __forceinline__ void cheb2_direct(const double* const (&C)[NC], doubl
 
 // the same at a run-time degree d: compile-time degrees up to 7 (the
 // effective degree of a resolved velocity), Clenshaw beyond
-template <int N, int NC, bool LEAN = false>
+template <int N, int NC, int LR = 0>
 __device__ __forceinline__ void cheb2_eval(const double* const (&C)[NC], double x, double y, int d, double (&out)[NC])
 {
 #define SL_CHEB2_CASE(DD)                                         \
     if constexpr (N > DD)                                        \
         if (d == DD) {                                           \
-            cheb2_direct<N, DD, NC, LEAN>(C, x, y, out);         \
+            cheb2_direct<N, DD, NC, LR>(C, x, y, out);           \
             return;                                              \
         }
     SL_CHEB2_CASE(0) SL_CHEB2_CASE(1) SL_CHEB2_CASE(2) SL_CHEB2_CASE(3)
@@ -324,14 +337,14 @@ __device__ double backtrace2(const Step2DArgs& A, const double* cu, const double
                 if (A.cons) {
                     const double* C3[3] = {cu, cv, cd};
                     double o[3];
-                    cheb2_eval<N, 3, true>(C3, x, y, A.vdeg, o);
+                    cheb2_eval<N, 3, 1>(C3, x, y, A.vdeg, o);
                     ks[st] = -o[0] * A.invdx;
                     kr[st] = -o[1] * A.invdy;
                     kq[st] = -o[2] * qq;
                 } else {
                     const double* C2[2] = {cu, cv};
                     double o[2];
-                    cheb2_eval<N, 2, true>(C2, x, y, A.vdeg, o);
+                    cheb2_eval<N, 2, 1>(C2, x, y, A.vdeg, o);
                     ks[st] = -o[0] * A.invdx;
                     kr[st] = -o[1] * A.invdy;
                     kq[st] = 0.0;
@@ -579,6 +592,13 @@ __device__ __forceinline__ double resid_bcast(const double (&a)[N], const double
     return vx;
 }
 
+// rows of the velocity series per batch in one-element advect blocks (0:
+// all at once).  Measured on the C4 recipe (degree-5 series, per launch):
+// one row at a time n = 9 174 -> 168 us, n = 7 84 -> 82 us (no spilled
+// scalar registers); at n = 13 the unrolled sums stay faster (330 us against
+// 334 one row and 337 two rows at a time).
+template <int N> constexpr int kSeriesRows = N >= 13 ? 0 : 1;
+
 template <int N, int PR, int BSEL>
 __device__ __forceinline__ void advect2d_body(const Step2DArgs& A, const int bid)
 {
@@ -689,7 +709,7 @@ __device__ __forceinline__ void advect2d_body(const Step2DArgs& A, const int bid
                             // address and are read through the scalar cache, not LDS
                             const double* gu = A.aM + (size_t)bid * ND;
                             const double* C3[3] = {gu, gu + (size_t)K * ND, A.divM + (size_t)bid * ND};
-                            cheb2_eval<N, 3>(C3, x, y, d, o);
+                            cheb2_eval<N, 3, kSeriesRows<N>>(C3, x, y, d, o);
                         } else {
                             const double* C3[3] = {s_cu[sl], s_cv[sl], s_cd[sl]};
                             cheb2_eval<N, 3>(C3, x, y, d, o);
@@ -702,7 +722,7 @@ __device__ __forceinline__ void advect2d_body(const Step2DArgs& A, const int bid
                         if constexpr (Shape2<N, BSEL>::E == 1) {
                             const double* gu = A.aM + (size_t)bid * ND;
                             const double* C2[2] = {gu, gu + (size_t)K * ND};
-                            cheb2_eval<N, 2>(C2, x, y, d, o);
+                            cheb2_eval<N, 2, kSeriesRows<N>>(C2, x, y, d, o);
                         } else {
                             const double* C2[2] = {s_cu[sl], s_cv[sl]};
                             cheb2_eval<N, 2>(C2, x, y, d, o);
