@@ -291,22 +291,29 @@ __global__ void k_facevel2d(int kx, int ky, int periodic, const double* __restri
 // (no division, exact at the nodes)
 // ---------------------------------------------------------------------------
 template <int N>
-__device__ __forceinline__ void lag_row(const double* __restrict__ tab, double x, double (&l)[N])
+__device__ __forceinline__ void lag_row(const double* __restrict__ xi, const double* __restrict__ lam, double x,
+                                        double (&l)[N])
 {
-    using O = Off2<N>;
     double pre[N];
     double acc = 1.0;
 #pragma unroll
     for (int k = 0; k < N; ++k) {
         pre[k] = acc;
-        acc *= (x - tab[O::XI + k]);
+        acc *= (x - xi[k]);
     }
     acc = 1.0;
 #pragma unroll
     for (int k = N - 1; k >= 0; --k) {
-        l[k] = tab[O::LAM + k] * pre[k] * acc;
-        acc *= (x - tab[O::XI + k]);
+        l[k] = lam[k] * pre[k] * acc;
+        acc *= (x - xi[k]);
     }
+}
+
+template <int N>
+__device__ __forceinline__ void lag_row(const double* __restrict__ tab, double x, double (&l)[N])
+{
+    using O = Off2<N>;
+    lag_row<N>(tab + O::XI, tab + O::LAM, x, l);
 }
 
 // phi^n (nodal values f of one element, in LDS) carried back along the
@@ -314,9 +321,11 @@ __device__ __forceinline__ void lag_row(const double* __restrict__ tab, double x
 // phi^n at the foot, times the source factor of the conservative form.  The
 // trace uses the same explicit RK tableau as the particles (eq. 4.11 in 2D);
 // `out` is set when a stage position leaves the element.
+// xi, lam: the nodes and barycentric weights (the table's, or a copy in LDS)
 template <int N>
 __device__ double backtrace2(const Step2DArgs& A, const double* cu, const double* cv, const double* cd,
-                             const double* f, double h, double s, double r, bool& out)
+                             const double* f, double h, double s, double r, bool& out, const double* xi,
+                             const double* lam)
 {
     const RKTab& T = A.rk;
     double qf = 1.0;
@@ -361,8 +370,8 @@ __device__ double backtrace2(const Step2DArgs& A, const double* cu, const double
         out |= outside2(s) || outside2(r);
     }
     double ls[N], lr[N];
-    lag_row<N>(A.tab, s, ls);
-    lag_row<N>(A.tab, r, lr);
+    lag_row<N>(xi, lam, s, ls);
+    lag_row<N>(xi, lam, r, lr);
     double acc = 0.0;
     // row by row: unrolled, the n^2 loads of f are invariant in a caller's
     // loop over traces and were hoisted out of it, all held in registers
@@ -1843,7 +1852,8 @@ __global__ __launch_bounds__(kBlock2) void k_backtrace2d(Step2DArgs A)
         if (up) {
             const double s = side == 0 ? 0.0 : side == 1 ? 1.0 : A.tab[O::XI + k];
             const double r = side == 2 ? 0.0 : side == 3 ? 1.0 : A.tab[O::XI + k];
-            v = backtrace2<N>(A, s_cu[le], s_cv[le], s_cd[le], s_f[le], A.dt, s, r, out);
+            v = backtrace2<N>(A, s_cu[le], s_cv[le], s_cd[le], s_f[le], A.dt, s, r, out, A.tab + O::XI,
+                              A.tab + O::LAM);
         }
         A.rec[(size_t)e * A.rstride + (A.rstride - NB) + tt] = v;
     }
@@ -1891,7 +1901,7 @@ __global__ __launch_bounds__(kBlock2, 3) void k_targets2d(Step2DArgs A)
     constexpr int ND = N * N, NB = 4 * N, EB = kBlock2 / NB;
     __shared__ double s_f[EB][ND], s_cu[EB][ND], s_cv[EB][ND], s_cd[EB][ND];
     __shared__ double s_m[EB][ND], s_e[EB][ND], s_dv[EB][ND];
-    __shared__ double s_mean[EB], s_tw[N], s_txi[N];  // + the weights and nodes
+    __shared__ double s_mean[EB], s_tw[N], s_txi[N], s_lam[N];  // + weights, nodes, barycentric weights
     __shared__ int s_flag;
     const int t = threadIdx.x;
     const int e0 = blockIdx.x * EB;
@@ -1899,6 +1909,7 @@ __global__ __launch_bounds__(kBlock2, 3) void k_targets2d(Step2DArgs A)
     if (t < N) {
         s_tw[t] = A.tab[O::W + t];
         s_txi[t] = A.tab[O::XI + t];
+        s_lam[t] = A.tab[O::LAM + t];
     }
     const size_t KND = (size_t)A.K * ND;
     for (int k = t; k < EB * ND; k += kBlock2) {
@@ -1965,7 +1976,8 @@ __global__ __launch_bounds__(kBlock2, 3) void k_targets2d(Step2DArgs A)
                     // no LDS value is kept in registers from one trace to
                     // the next (they would be held through all of them)
                     __asm__ __volatile__("" ::: "memory");
-                    const double v = backtrace2<N>(A, s_cu[le], s_cv[le], s_cd[le], s_f[le], T.cu[c] * A.dt, s, r, out);
+                    const double v = backtrace2<N>(A, s_cu[le], s_cv[le], s_cd[le], s_f[le], T.cu[c] * A.dt, s, r,
+                                                   out, s_txi, s_lam);
                     const double dv = v - cmean;
                     vm = fma(T.bu[c], v, vm);
                     vd = fma(T.bu[c], dv, vd);
