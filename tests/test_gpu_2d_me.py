@@ -182,6 +182,26 @@ def test_full_size_c3_with_mass_sampled():
     assert_parity(w, g, o, elems=elems)
 
 
+@pytest.mark.parametrize("cmask", [B | M, B | M | E])
+def test_full_size_c3_bench_options_sampled(cmask):
+    """The options `bench.py --workload c3 --constraints bm` / `bme` times:
+    full C3 size, the flow's exact divergence (zero) handed to both sides,
+    HARD, the energy stop 1e-8 with up to 50 sweeps; one step, sampled
+    elements against the oracle computed for those elements only."""
+    w = W.c3(nsteps=1)
+    w.cmask = cmask
+    div = w.velocity()[1]
+    announce(f"c3 full size, bench options cmask={cmask}, sampled")
+    g, st, rc = run_gpu(w, div=div)
+    rng = np.random.default_rng(11)
+    elems = np.unique(np.concatenate([rng.choice(w.K, 48, replace=False), [0, 255, w.K - 256, w.K - 1]]))
+    want = np.zeros(w.K, dtype=np.uint8)
+    want[elems] = 1
+    o, ost = run_oracle(w, want=want, div=div)
+    assert rc == 0 and st.flags == 0, (rc, st.flags)
+    assert_parity(w, g, o, elems=elems)
+
+
 @pytest.mark.parametrize("n,cmask,ok", [(2, B | M, False), (3, B | M, True), (3, B | M | E, False),
                                         (4, B | M | E, True)])
 def test_hard_rows_beyond_boundary_null_space_rejected(n, cmask, ok):
